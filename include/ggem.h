@@ -1,0 +1,131 @@
+/*
+ * ggem.h -- GGEM evaluation of Stokes flow driven by point forces in a planar
+ * slit on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Kumar & Graham, "Accelerated boundary integral method for
+ * multiphase flow in non-periodic geometries" -- the General Geometry
+ * Ewald-like Method of Sec. 3.2 (density split Eq. rho_l_g, local solution
+ * Eq. local / Eq. u_loc, global spectral slit solver of Appendix C) applied to
+ * the single layer (Eq. u_g a) and to the double layer written as the traction
+ * n . sigma at targets (Eq. wdbl, Eq. vsigma).
+ *
+ * Geometry: periodic in x (period Lx) and z (period Lz); no-slip walls at
+ * y = -H and y = +H (H is the half-gap).  Viscosity is 1.
+ *
+ * Conventions shared by every entry point
+ *  - Position, strength, normal and output arrays are caller-owned DEVICE
+ *    buffers (hipMalloc'd or torch tensors), contiguous, row-major (n, 3)
+ *    float64: x, y, z components of one point per row.
+ *  - All work is enqueued on the plan's HIP stream; no call after
+ *    ggem_plan_create allocates device memory.  Outputs are overwritten.
+ *  - x and z are wrapped into [0, L); they are not rejected.
+ *  - Status codes are returned; ggem_last_error() gives a thread-local
+ *    message for the last failing call on the calling thread.
+ *  - Domain checks (|y| of a source >= H, |y| of a target > H, non-finite
+ *    positions) are evaluated on the device.  With sync_checks = 1 the call
+ *    waits for its stream and returns GGEM_E_DOMAIN; with sync_checks = 0 it
+ *    returns immediately and the flag is read by ggem_plan_status().
+ *    Offending points are clamped inside the kernels, so no access ever
+ *    leaves the workspace; their outputs are meaningless.
+ *  - Calls on one plan must not overlap (they share the plan's workspace).
+ */
+#ifndef GGEM_H
+#define GGEM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ggem_plan_s* ggem_plan_t;
+
+enum ggem_precision {
+  GGEM_FP64 = 0,   /* every stage in double precision                       */
+  GGEM_MIXED = 1   /* FP32 near field, spread, FFT, interpolation; FP32 MFMA
+                      Chebyshev transforms; FP64 tau solves                   */
+};
+
+enum ggem_status {
+  GGEM_OK = 0,
+  GGEM_E_ARG = -1,       /* invalid parameter or null pointer                 */
+  GGEM_E_DOMAIN = -2,    /* a point outside the slit, or a non-finite value   */
+  GGEM_E_CAPACITY = -3,  /* more points than reserved at plan creation        */
+  GGEM_E_NOMEM = -4,     /* device allocation failed at plan creation         */
+  GGEM_E_DEVICE = -5     /* a HIP runtime call failed                         */
+};
+
+/* Which parts of the GGEM sum to evaluate (test hook; ALL is the method). */
+enum ggem_parts {
+  GGEM_PART_LOCAL = 1,   /* local sum of Eq. u_loc including the self rule    */
+  GGEM_PART_GLOBAL = 2,  /* global spectral solution interpolated to targets  */
+  GGEM_PART_ALL = 3
+};
+
+typedef struct {
+  double Lx, Lz;        /* periodic box lengths                               */
+  double H;             /* wall half-gap: walls at y = -H and y = +H          */
+  double alpha;         /* GGEM split parameter (Eq. rho_l_g)                 */
+  double rc;            /* cutoff of the local sum and of the global density;
+                           0 selects 4/alpha (Sec. 3.2.2).  Must satisfy
+                           rc < min(Lx, Lz)/2 (the paper's alpha L > 8)        */
+  int Nx, Nz;           /* Fourier nodes in x and z: even, 8..512, products of
+                           2, 3 and 5                                          */
+  int Ny;               /* Chebyshev Gauss-Lobatto nodes in y: 5..129          */
+  int precision;        /* GGEM_FP64 or GGEM_MIXED                            */
+  int sync_checks;      /* 1: wait and report domain errors; 0: asynchronous  */
+  long long max_src;    /* capacity reserved at plan time (sources)           */
+  long long max_tgt;    /* capacity reserved at plan time (targets)           */
+} ggem_params;
+
+/* Create a plan: validates the parameters, precomputes the Gauss-Lobatto
+ * nodes, Chebyshev transform matrices, FFT twiddles and, for every Fourier
+ * mode, the 2x2 influence matrix of Appendix C (the homogeneous problems (b)
+ * and (c) are solved once per plan), and reserves all workspace.
+ * hip_stream: a hipStream_t (NULL = default stream).
+ * Errors: GGEM_E_ARG (bad parameter, null out), GGEM_E_NOMEM, GGEM_E_DEVICE.
+ * The plan owns its workspace; release it with ggem_plan_destroy. */
+int ggem_plan_create(const ggem_params* params, void* hip_stream, ggem_plan_t* out);
+
+/* Release a plan and its workspace (waits for the plan's stream). */
+int ggem_plan_destroy(ggem_plan_t plan);
+
+/* Rebind the plan to another HIP stream. */
+int ggem_plan_set_stream(ggem_plan_t plan, void* hip_stream);
+
+/* Status of the last evaluation's device-side domain check (waits for the
+ * plan's stream): GGEM_OK or GGEM_E_DOMAIN. */
+int ggem_plan_status(ggem_plan_t plan);
+
+/* Single layer (Eq. u_g a, evaluated by the GGEM split of Sec. 3.2):
+ *   u[t] = (1/8 pi) sum_s G^slit(x_t, x_s) f_s
+ * ns sources xs (ns,3) with strengths f (ns,3); nt targets xt (nt,3); output
+ * u (nt,3).  A target that coincides with a source receives the regular part
+ * of the slit Green's function for that pair (the free-space singular part
+ * is omitted).  parts selects local / global / both.  ns = 0 or nt = 0 is
+ * allowed.  Errors: GGEM_E_ARG, GGEM_E_CAPACITY, GGEM_E_DOMAIN, GGEM_E_DEVICE. */
+int ggem_single_layer(ggem_plan_t plan, long long ns, const double* xs, const double* f,
+                      long long nt, const double* xt, double* u, int parts);
+
+/* Double layer in adjoint form (Eq. wdbl with Eq. vsigma):
+ *   v[t]_j = n_k(x_t) sigma_jk(x_t),  sigma the stress of the point forces q
+ *   sigma_jk(x) = (1/8 pi) sum_s T^slit_jik(x, x_s) q_s,i
+ * The normal belongs to the TARGET (nrm (nt,3), not renormalised).  The
+ * pressure gauge makes the lateral mean of the total pressure vanish at
+ * y = -H.  Same sizes, errors and parts as ggem_single_layer. */
+int ggem_double_layer(ggem_plan_t plan, long long ns, const double* xs, const double* q,
+                      long long nt, const double* xt, const double* nrm, double* v,
+                      int parts);
+
+/* Diagnostic: the global force density of Sec. 3.2.2 on the grid,
+ *   F(node) = sum_s f_s rho_g(node - x_s)   over |node - x_s| <= rc,
+ * written as float64 (3, Ny, Nx, Nz) with y_j = H cos(pi j/(Ny-1)),
+ * x_i = i Lx/Nx, z_k = k Lz/Nz.  Errors as above. */
+int ggem_spread_grid(ggem_plan_t plan, long long ns, const double* xs, const double* f,
+                     double* grid);
+
+/* Thread-local description of the last error on the calling thread. */
+const char* ggem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GGEM_H */

@@ -1,0 +1,109 @@
+// Internal declarations of the GGEM slit library (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ggem.h"
+
+namespace ggem {
+
+constexpr int kMaxCells = 16384;     // cell-list size (LDS histograms)
+constexpr int kBinChunk = 2048;      // points per counting-sort chunk
+constexpr int kNearBlock = 128;      // targets per near-field work item
+constexpr int kMaxNy = 129;
+constexpr int kMaxFFT = 512;
+
+// Domain flags raised on the device.
+enum : unsigned { kFlagNonFinite = 1u, kFlagOutside = 2u };
+
+// Geometry of the cell list: cells of size >= rc in x, y (over [-H, H]) and z.
+struct CellGeom {
+  double Lx, Lz, H;
+  double invLx, invLz;
+  double icx, icy, icz;   // inverse cell sizes
+  int ncx, ncy, ncz;
+  int ncells;
+};
+
+// A binned point set: sorted positions (wrapped) and cell ranges.
+struct Binned {
+  int n;
+  int nchunks;
+  int* keys;         // cell key per original point
+  int* counts;       // [cell][chunk]
+  int* offs;         // [cell][chunk] exclusive offsets inside the cell
+  int* cell_start;   // ncells + 1
+  int* item_start;   // ncells + 1: near-field work items per cell (prefix)
+  int* perm;         // sorted position -> original index
+  double* x;         // sorted wrapped positions (SoA)
+  double* y;
+  double* z;
+  void* s;           // sorted strengths or normals (3 x n, element type T)
+  void* s2;          // second sorted vector field (normals for targets)
+};
+
+struct Plan {
+  ggem_params p;
+  hipStream_t stream;
+  int device;
+  bool fp64;
+  double rc, rc2;
+  double dx, dz;
+  int Nzh;           // Nz/2 + 1
+  int nmodes;        // Nx * Nzh
+  CellGeom cg;
+  int nradx, nradz;
+  int radx[12], radz[12];
+
+  // plan-time constants on the device
+  double* y;          // Gauss-Lobatto nodes (Ny)
+  double* cf64;       // forward Chebyshev (Ny x Ny), scaled by 1/(Nx Nz)
+  double* ci64;       // inverse Chebyshev (Ny x Ny)
+  float* cf32;
+  float* ci32;
+  void* twx;          // twiddles exp(-2 pi i t/Nx), complex T
+  void* twz;
+  double* infl;       // per mode: 2x2 inverse influence matrix (4 doubles)
+
+  // workspace
+  Binned src, tgt;
+  void* ul;           // local result at sorted targets (3 x max_tgt, T)
+  void* phys;         // physical grid fields (6 x Ny x Nx x Nz, T)
+  void* specA;        // spectral fields (6 x Ny x Nx x Nzh, complex T)
+  void* specB;
+  void* wall_phys;    // wall velocities (2 x 3 x Nx x Nz, T)
+  void* wall_spec;    // (2 x 3 x Nx x Nzh, complex T)
+  double* tau_scr;    // tau scratch (7 x Ny x nmodes, complex FP64)
+  double* gauge;      // gauge partial sums and value
+  unsigned* flags;    // device domain flags
+  unsigned* flags_host;  // pinned host copy
+  int* item_count;    // scratch
+};
+
+// ---- kernel launchers (each enqueues on p.stream) -------------------------
+hipError_t launch_bin(Plan& p, Binned& b, long long n, const double* x, const double* s,
+                      const double* s2, bool is_source);
+template <typename T>
+hipError_t launch_near_sl(Plan& p, int nt);
+template <typename T>
+hipError_t launch_near_dl(Plan& p, int nt);
+template <typename T>
+hipError_t launch_wall(Plan& p);
+hipError_t launch_gauge(Plan& p);
+template <typename T>
+hipError_t launch_spread(Plan& p, int ncomp_offset);
+template <typename T>
+hipError_t launch_fft_forward(Plan& p, void* phys, void* spec, int nplanes);
+template <typename T>
+hipError_t launch_fft_inverse(Plan& p, void* spec, void* phys, int nplanes);
+template <typename T>
+hipError_t launch_cheb(Plan& p, const void* in, void* out, int nfields, bool forward);
+template <typename T>
+hipError_t launch_tau(Plan& p, bool stress);
+hipError_t launch_influence(Plan& p);
+template <typename T>
+hipError_t launch_interp(Plan& p, int nt, double* out, bool stress, bool with_global);
+template <typename T>
+hipError_t launch_grid_to_f64(Plan& p, double* out);
+
+}  // namespace ggem

@@ -1,0 +1,215 @@
+// Cell-list binning by a deterministic, stable counting sort (Sec. 3.2.1:
+// neighbours within r_c are found through a cell-linked list; here the list is
+// a sorted order plus per-cell ranges, so later kernels read contiguous runs).
+//
+//   bin_keys     wrap x,z into [0,L), check the slab, cell key per point
+//   bin_count    per-chunk histogram in LDS             -> counts[cell][chunk]
+//   bin_cellscan per-cell running sum over chunks       -> offs[cell][chunk]
+//   bin_scan     exclusive scan over cells              -> cell_start, item_start
+//   bin_scatter  one wave per chunk, stable ranks by wave match -> sorted SoA
+//
+// Points keep their input order inside a cell, so every later sum over a
+// cell's points has a fixed order and results are bitwise reproducible.
+#include "ggem_internal.h"
+
+namespace ggem {
+
+__device__ inline double wrap_periodic(double v, double L) {
+  double r = fmod(v, L);
+  if (r < 0.0) r += L;
+  if (r >= L) r = 0.0;
+  return r;
+}
+
+__device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Cell key of a (wrapped, finite) position; y is clamped into the slab.
+__device__ inline int cell_key(const CellGeom& g, double x, double y, double z) {
+  int ix = clampi((int)floor(x * g.icx), 0, g.ncx - 1);
+  int iy = clampi((int)floor((y + g.H) * g.icy), 0, g.ncy - 1);
+  int iz = clampi((int)floor(z * g.icz), 0, g.ncz - 1);
+  return (iy * g.ncx + ix) * g.ncz + iz;
+}
+
+__global__ void bin_keys(int n, const double* __restrict__ x, CellGeom g, int is_source,
+                         int* __restrict__ keys, unsigned* __restrict__ flags) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double px = x[3 * (size_t)i], py = x[3 * (size_t)i + 1], pz = x[3 * (size_t)i + 2];
+  unsigned f = 0;
+  if (!(isfinite(px) && isfinite(py) && isfinite(pz))) {
+    f |= kFlagNonFinite;
+    px = py = pz = 0.0;
+  }
+  if (is_source ? !(fabs(py) < g.H) : !(fabs(py) <= g.H)) f |= kFlagOutside;
+  px = wrap_periodic(px, g.Lx);
+  pz = wrap_periodic(pz, g.Lz);
+  keys[i] = cell_key(g, px, py, pz);
+  if (f) atomicOr(flags, f);
+}
+
+__global__ void bin_count(int n, int nchunks, int ncells, const int* __restrict__ keys,
+                          int* __restrict__ counts) {
+  extern __shared__ int hist[];
+  int chunk = blockIdx.x;
+  for (int c = threadIdx.x; c < ncells; c += blockDim.x) hist[c] = 0;
+  __syncthreads();
+  int i0 = chunk * kBinChunk;
+  int i1 = min(n, i0 + kBinChunk);
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) atomicAdd(&hist[keys[i]], 1);
+  __syncthreads();
+  for (int c = threadIdx.x; c < ncells; c += blockDim.x) counts[(size_t)c * nchunks + chunk] = hist[c];
+}
+
+__global__ void bin_cellscan(int nchunks, int ncells, const int* __restrict__ counts,
+                             int* __restrict__ offs, int* __restrict__ totals) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncells) return;
+  int s = 0;
+  const int* row = counts + (size_t)c * nchunks;
+  int* orow = offs + (size_t)c * nchunks;
+  for (int k = 0; k < nchunks; ++k) {
+    orow[k] = s;
+    s += row[k];
+  }
+  totals[c] = s;
+}
+
+// Single block: exclusive scans of per-cell totals (in cell_start) and of
+// per-cell near-field work items ceil(total / kNearBlock).
+__global__ void __launch_bounds__(1024) bin_scan(int ncells, int* __restrict__ cell_start,
+                                                 int* __restrict__ item_start) {
+  __shared__ int sa[1024], sb[1024];
+  const int per = (ncells + 1023) / 1024;
+  int t = threadIdx.x;
+  int c0 = t * per, c1 = min(ncells, c0 + per);
+  int la = 0, lb = 0;
+  for (int c = c0; c < c1; ++c) {
+    int v = cell_start[c];
+    la += v;
+    lb += (v + kNearBlock - 1) / kNearBlock;
+  }
+  sa[t] = la;
+  sb[t] = lb;
+  __syncthreads();
+  // Hillis-Steele inclusive scan over 1024 partial sums
+  for (int o = 1; o < 1024; o <<= 1) {
+    int va = t >= o ? sa[t - o] : 0;
+    int vb = t >= o ? sb[t - o] : 0;
+    __syncthreads();
+    sa[t] += va;
+    sb[t] += vb;
+    __syncthreads();
+  }
+  int ra = sa[t] - la, rb = sb[t] - lb;
+  for (int c = c0; c < c1; ++c) {
+    int v = cell_start[c];
+    cell_start[c] = ra;
+    item_start[c] = rb;
+    ra += v;
+    rb += (v + kNearBlock - 1) / kNearBlock;
+  }
+  if (t == 1023) {
+    cell_start[ncells] = sa[1023];
+    item_start[ncells] = sb[1023];
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) bin_scatter(int n, int nchunks, int ncells, CellGeom g,
+                                                  const int* __restrict__ keys,
+                                                  const double* __restrict__ x,
+                                                  const double* __restrict__ s,
+                                                  const int* __restrict__ cell_start,
+                                                  const int* __restrict__ offs,
+                                                  int* __restrict__ perm, double* __restrict__ sx,
+                                                  double* __restrict__ sy, double* __restrict__ sz,
+                                                  T* __restrict__ ss, size_t cap) {
+  extern __shared__ int cnt[];
+  const int lane = threadIdx.x;
+  const int chunk = blockIdx.x;
+  for (int c = lane; c < ncells; c += 64) cnt[c] = 0;
+  __syncthreads();
+  const int i0 = chunk * kBinChunk;
+  const int i1 = min(n, i0 + kBinChunk);
+  const unsigned long long lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+  for (int base = i0; base < i1; base += 64) {
+    int i = base + lane;
+    bool valid = i < i1;
+    int key = valid ? keys[i] : -1;
+    unsigned long long active = __ballot(valid);
+    int rank = 0, before = 0;
+    while (active) {
+      int leader = __ffsll((long long)active) - 1;
+      int lk = __shfl(key, leader);
+      unsigned long long m = __ballot(key == lk) & active;
+      int cur = cnt[lk];
+      if (key == lk) {
+        rank = __popcll(m & lt);
+        before = cur;
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (lane == leader) cnt[lk] = cur + __popcll(m);
+      __builtin_amdgcn_wave_barrier();
+      active &= ~m;
+    }
+    if (valid) {
+      int pos = cell_start[key] + offs[(size_t)key * nchunks + chunk] + before + rank;
+      double px = x[3 * (size_t)i], py = x[3 * (size_t)i + 1], pz = x[3 * (size_t)i + 2];
+      if (!(isfinite(px) && isfinite(py) && isfinite(pz))) px = py = pz = 0.0;
+      py = fmin(fmax(py, -g.H), g.H);
+      perm[pos] = i;
+      sx[pos] = wrap_periodic(px, g.Lx);
+      sy[pos] = py;
+      sz[pos] = wrap_periodic(pz, g.Lz);
+      if (s) {
+        ss[pos] = (T)s[3 * (size_t)i];
+        ss[cap + pos] = (T)s[3 * (size_t)i + 1];
+        ss[2 * cap + pos] = (T)s[3 * (size_t)i + 2];
+      }
+    }
+  }
+}
+
+__global__ void zero_ints(int* p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+static hipError_t bin_impl(Plan& p, Binned& b, long long n, const double* x, const double* s,
+                           bool is_source, size_t cap) {
+  hipStream_t st = p.stream;
+  const CellGeom& g = p.cg;
+  b.n = (int)n;
+  b.nchunks = (int)((n + kBinChunk - 1) / kBinChunk);
+  if (n > 0) {
+    bin_keys<<<(unsigned)((n + 255) / 256), 256, 0, st>>>((int)n, x, g, is_source ? 1 : 0, b.keys,
+                                                          p.flags);
+    bin_count<<<b.nchunks, 256, g.ncells * sizeof(int), st>>>((int)n, b.nchunks, g.ncells, b.keys,
+                                                               b.counts);
+    bin_cellscan<<<(g.ncells + 255) / 256, 256, 0, st>>>(b.nchunks, g.ncells, b.counts, b.offs,
+                                                         b.cell_start);
+  } else {
+    zero_ints<<<(g.ncells + 1 + 255) / 256, 256, 0, st>>>(b.cell_start, g.ncells + 1);
+  }
+  bin_scan<<<1, 1024, 0, st>>>(g.ncells, b.cell_start, b.item_start);
+  if (n > 0) {
+    if (p.fp64)
+      bin_scatter<double><<<b.nchunks, 64, g.ncells * sizeof(int), st>>>(
+          (int)n, b.nchunks, g.ncells, g, b.keys, x, s, b.cell_start, b.offs, b.perm, b.x, b.y,
+          b.z, (double*)b.s, cap);
+    else
+      bin_scatter<float><<<b.nchunks, 64, g.ncells * sizeof(int), st>>>(
+          (int)n, b.nchunks, g.ncells, g, b.keys, x, s, b.cell_start, b.offs, b.perm, b.x, b.y,
+          b.z, (float*)b.s, cap);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_bin(Plan& p, Binned& b, long long n, const double* x, const double* s,
+                      const double* /*s2*/, bool is_source) {
+  size_t cap = is_source ? (size_t)p.p.max_src : (size_t)p.p.max_tgt;
+  return bin_impl(p, b, n, x, s, is_source, cap);
+}
+
+}  // namespace ggem

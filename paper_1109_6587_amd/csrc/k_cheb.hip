@@ -1,0 +1,124 @@
+// Chebyshev transforms in y as dense GEMMs on the matrix cores.
+//
+// Forward (Gauss-Lobatto values -> coefficients, Sec. 3.2.2):
+//   a_n = 2/(N cbar_n) sum_j u_j cos(pi n j/N)/cbar_j,  cbar_0 = cbar_N = 2,
+// scaled here by 1/(Nx Nz) (the DFT normalisation).  Inverse:
+//   u_j = sum_n a_n cos(pi n j/N).
+// The paper evaluates these with FFTs; at N_y <= 129 a dense (Ny x Ny) times
+// (Ny x columns) product is cheap on MFMA and keeps the data in one pass.
+//
+// Data: [field][row][col] with col over the real view of the half spectrum
+// (2 * Nx * Nzh reals per row).  Block: 4 waves, each wave two 16-column
+// tiles and every 16-row tile of the (padded) output; A fragments come from a
+// zero-padded copy of the matrix (MP x KP), B fragments straight from HBM.
+#include "ggem_internal.h"
+
+namespace ggem {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMaxRowTiles = 9;   // Ny <= 129 -> 144 padded rows
+constexpr int kColTiles = 2;      // column tiles per wave
+
+__device__ inline d4 mfma16x16x4(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline f4 mfma16x16x4(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename T>
+struct Acc;
+template <>
+struct Acc<double> {
+  using t = d4;
+};
+template <>
+struct Acc<float> {
+  using t = f4;
+};
+
+// out[f][r][c] = sum_k A[r][k] in[f][k][c];  A is MP x KP, zero padded.
+template <typename T, int RT>
+__global__ void __launch_bounds__(256) cheb_gemm(const T* __restrict__ A, int MP, int KP, int Ny,
+                                                 const T* __restrict__ in, T* __restrict__ out,
+                                                 long ncols) {
+  using V = typename Acc<T>::t;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const size_t fstride = (size_t)Ny * ncols;
+  const T* src = in + blockIdx.y * fstride;
+  T* dst = out + blockIdx.y * fstride;
+  const long col0 = (long)blockIdx.x * (4 * 16 * kColTiles) + wave * 16 * kColTiles;
+  const int li = lane & 15, lk = lane >> 4;
+  V acc[RT][kColTiles];
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int c = 0; c < kColTiles; ++c) acc[t][c] = (V)0;
+  for (int kk = 0; kk < KP; kk += 4) {
+    const int k = kk + lk;
+    T b[kColTiles];
+#pragma unroll
+    for (int c = 0; c < kColTiles; ++c) {
+      const long col = col0 + c * 16 + li;
+      b[c] = (k < Ny && col < ncols) ? src[(size_t)k * ncols + col] : (T)0;
+    }
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const T a = A[(size_t)(t * 16 + li) * KP + k];
+#pragma unroll
+      for (int c = 0; c < kColTiles; ++c) acc[t][c] = mfma16x16x4(a, b[c], acc[t][c]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int c = 0; c < kColTiles; ++c) {
+      const long col = col0 + c * 16 + li;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        // accumulator layout: FP32 16x16x4 holds rows 4*(lane/16)+v of column
+        // lane%16; FP64 16x16x4 holds rows lane/16 + 4*v.
+        const int row = t * 16 + (sizeof(T) == 8 ? lk + 4 * v : 4 * lk + v);
+        if (row < Ny && col < ncols) dst[(size_t)row * ncols + col] = acc[t][c][v];
+      }
+    }
+}
+
+template <typename T>
+hipError_t launch_cheb(Plan& p, const void* in, void* out, int nfields, bool forward) {
+  const int Ny = p.p.Ny;
+  const int MP = ((Ny + 15) / 16) * 16;
+  const int KP = ((Ny + 3) / 4) * 4;
+  const long ncols = 2L * p.p.Nx * p.Nzh;
+  const T* A;
+  if (sizeof(T) == 8) A = (const T*)(forward ? (const void*)p.cf64 : (const void*)p.ci64);
+  else A = (const T*)(forward ? (const void*)p.cf32 : (const void*)p.ci32);
+  dim3 grid((unsigned)((ncols + 4 * 16 * kColTiles - 1) / (4 * 16 * kColTiles)), nfields);
+  const int rt = MP / 16;
+  switch (rt) {
+#define GGEM_CASE(R)                                                                            \
+  case R:                                                                                       \
+    cheb_gemm<T, R><<<grid, 256, 0, p.stream>>>(A, MP, KP, Ny, (const T*)in, (T*)out, ncols); \
+    break;
+    GGEM_CASE(1)
+    GGEM_CASE(2)
+    GGEM_CASE(3)
+    GGEM_CASE(4)
+    GGEM_CASE(5)
+    GGEM_CASE(6)
+    GGEM_CASE(7)
+    GGEM_CASE(8)
+    GGEM_CASE(9)
+#undef GGEM_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_cheb<double>(Plan&, const void*, void*, int, bool);
+template hipError_t launch_cheb<float>(Plan&, const void*, void*, int, bool);
+
+}  // namespace ggem

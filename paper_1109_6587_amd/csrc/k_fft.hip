@@ -1,0 +1,310 @@
+// Fourier transforms in the periodic directions (Eq. fourier, Appendix C).
+// Physical fields are stored [plane][x][z] (z contiguous); spectra are
+// [plane][l][m] with the half spectrum m = 0..Nz/2 contiguous.
+//
+//   forward:  real z-lines -> complex (R2C), then complex x-columns (C2C)
+//   inverse:  complex x-columns (C2C), then Hermitian z-lines -> real (C2R)
+//
+// Each 1-D transform is a mixed-radix (2, 3, 4, 5) Stockham autosort FFT in
+// LDS with twiddles from a table computed once per plan in FP64.  The
+// 1/(Nx Nz) normalisation of the forward transform is folded into the
+// Chebyshev forward matrix.
+#include "ggem_internal.h"
+
+namespace ggem {
+
+template <typename T>
+struct Cx;
+template <>
+struct Cx<double> {
+  using t = double2;
+};
+template <>
+struct Cx<float> {
+  using t = float2;
+};
+
+template <typename C>
+__device__ inline C cmul(C a, C b) {
+  C r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+template <typename C>
+__device__ inline C cadd(C a, C b) {
+  C r;
+  r.x = a.x + b.x;
+  r.y = a.y + b.y;
+  return r;
+}
+template <typename C>
+__device__ inline C csub(C a, C b) {
+  C r;
+  r.x = a.x - b.x;
+  r.y = a.y - b.y;
+  return r;
+}
+
+struct Radices {
+  int n;
+  int r[12];
+};
+
+// In-register DFT of length R (2..5), sign -1 forward, +1 inverse.
+template <typename T, int SIGN>
+__device__ inline void small_dft(typename Cx<T>::t* v, int R) {
+  using C = typename Cx<T>::t;
+  if (R == 2) {
+    C a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  } else if (R == 4) {
+    C s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+    C s13 = cadd(v[1], v[3]), d13 = csub(v[1], v[3]);
+    // multiply d13 by SIGN * i
+    C jd;
+    jd.x = -(T)SIGN * d13.y;
+    jd.y = (T)SIGN * d13.x;
+    v[0] = cadd(s02, s13);
+    v[2] = csub(s02, s13);
+    v[1] = cadd(d02, jd);
+    v[3] = csub(d02, jd);
+  } else if (R == 3) {
+    const T c1 = (T)-0.5, s1 = (T)SIGN * (T)0.86602540378443864676;
+    C y0 = cadd(v[0], cadd(v[1], v[2]));
+    C t;
+    t.x = v[0].x + c1 * (v[1].x + v[2].x);
+    t.y = v[0].y + c1 * (v[1].y + v[2].y);
+    C d = csub(v[1], v[2]);
+    C y1, y2;
+    y1.x = t.x - s1 * d.y;
+    y1.y = t.y + s1 * d.x;
+    y2.x = t.x + s1 * d.y;
+    y2.y = t.y - s1 * d.x;
+    v[0] = y0;
+    v[1] = y1;
+    v[2] = y2;
+  } else {  // R == 5
+    const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;
+    const T s1 = (T)SIGN * (T)0.95105651629515357212, s2 = (T)SIGN * (T)0.58778525229247312917;
+    C a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+    C a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+    C y0 = cadd(v[0], cadd(a1, a2));
+    C t1, t2;
+    t1.x = v[0].x + c1 * a1.x + c2 * a2.x;
+    t1.y = v[0].y + c1 * a1.y + c2 * a2.y;
+    t2.x = v[0].x + c2 * a1.x + c1 * a2.x;
+    t2.y = v[0].y + c2 * a1.y + c1 * a2.y;
+    // i * (s1 b1 + s2 b2) and i * (s2 b1 - s1 b2)
+    C u1, u2;
+    u1.x = -(s1 * b1.y + s2 * b2.y);
+    u1.y = s1 * b1.x + s2 * b2.x;
+    u2.x = -(s2 * b1.y - s1 * b2.y);
+    u2.y = s2 * b1.x - s1 * b2.x;
+    v[0] = y0;
+    v[1] = cadd(t1, u1);
+    v[4] = csub(t1, u1);
+    v[2] = cadd(t2, u2);
+    v[3] = csub(t2, u2);
+  }
+}
+
+// One Stockham pass over a line of length N with radix R; workers j run
+// from `start` with step `stride` (tw: exp(-2 pi i t/N), conjugated for the
+// inverse).
+template <typename T, int SIGN>
+__device__ inline void stockham_pass(const typename Cx<T>::t* __restrict__ src,
+                                     typename Cx<T>::t* __restrict__ dst, int N, int R, int Ns,
+                                     const typename Cx<T>::t* __restrict__ tw, int start,
+                                     int stride) {
+  using C = typename Cx<T>::t;
+  const int NR = N / R;
+  const int tstep = N / (Ns * R);
+  for (int j = start; j < NR; j += stride) {
+    const int k = j % Ns;
+    C v[5];
+    for (int r = 0; r < R; ++r) {
+      C a = src[j + r * NR];
+      if (r > 0 && k > 0) {
+        C w = tw[(k * r * tstep) % N];
+        if (SIGN > 0) w.y = -w.y;
+        a = cmul(a, w);
+      }
+      v[r] = a;
+    }
+    small_dft<T, SIGN>(v, R);
+    const int base = (j / Ns) * Ns * R + k;
+    for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[r];
+  }
+}
+
+// Forward R2C along z: one wave per line, 4 lines per block.
+template <typename T>
+__global__ void __launch_bounds__(256) fft_z_r2c(const T* __restrict__ in,
+                                                 typename Cx<T>::t* __restrict__ out, int nlines,
+                                                 int Nz, Radices rz,
+                                                 const typename Cx<T>::t* __restrict__ tw) {
+  using C = typename Cx<T>::t;
+  extern __shared__ unsigned char smem_raw[];
+  C* smem = (C*)smem_raw;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int line = blockIdx.x * 4 + wave;
+  C* b0 = smem + wave * 2 * Nz;
+  C* b1 = b0 + Nz;
+  const bool ok = line < nlines;
+  if (ok)
+    for (int n = lane; n < Nz; n += 64) {
+      C v;
+      v.x = in[(size_t)line * Nz + n];
+      v.y = (T)0;
+      b0[n] = v;
+    }
+  __syncthreads();
+  int Ns = 1;
+  for (int s = 0; s < rz.n; ++s) {
+    if (ok) stockham_pass<T, -1>(b0, b1, Nz, rz.r[s], Ns, tw, lane, 64);
+    __syncthreads();
+    C* t = b0;
+    b0 = b1;
+    b1 = t;
+    Ns *= rz.r[s];
+  }
+  const int Nzh = Nz / 2 + 1;
+  if (ok)
+    for (int m = lane; m < Nzh; m += 64) out[(size_t)line * Nzh + m] = b0[m];
+}
+
+// Inverse C2R along z: rebuild the Hermitian line, inverse FFT, real part.
+template <typename T>
+__global__ void __launch_bounds__(256) fft_z_c2r(const typename Cx<T>::t* __restrict__ in,
+                                                 T* __restrict__ out, int nlines, int Nz,
+                                                 Radices rz,
+                                                 const typename Cx<T>::t* __restrict__ tw) {
+  using C = typename Cx<T>::t;
+  extern __shared__ unsigned char smem_raw[];
+  C* smem = (C*)smem_raw;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int line = blockIdx.x * 4 + wave;
+  C* b0 = smem + wave * 2 * Nz;
+  C* b1 = b0 + Nz;
+  const bool ok = line < nlines;
+  const int Nzh = Nz / 2 + 1;
+  if (ok)
+    for (int m = lane; m < Nzh; m += 64) {
+      C v = in[(size_t)line * Nzh + m];
+      b0[m] = v;
+      if (m > 0 && m < Nz / 2) {
+        v.y = -v.y;
+        b0[Nz - m] = v;
+      }
+    }
+  __syncthreads();
+  int Ns = 1;
+  for (int s = 0; s < rz.n; ++s) {
+    if (ok) stockham_pass<T, 1>(b0, b1, Nz, rz.r[s], Ns, tw, lane, 64);
+    __syncthreads();
+    C* t = b0;
+    b0 = b1;
+    b1 = t;
+    Ns *= rz.r[s];
+  }
+  if (ok)
+    for (int n = lane; n < Nz; n += 64) out[(size_t)line * Nz + n] = b0[n].x;
+}
+
+// C2C along x on [plane][l][m] data, in place: CB columns per block.
+template <typename T, int SIGN>
+__global__ void __launch_bounds__(256) fft_x(typename Cx<T>::t* __restrict__ data, int Nx,
+                                             int Nzh, int CB, Radices rx,
+                                             const typename Cx<T>::t* __restrict__ tw) {
+  using C = typename Cx<T>::t;
+  extern __shared__ unsigned char smem_raw[];
+  C* smem = (C*)smem_raw;
+  const int plane = blockIdx.y;
+  const int m0 = blockIdx.x * CB;
+  C* b0 = smem;
+  C* b1 = smem + CB * Nx;
+  C* base = data + (size_t)plane * Nx * Nzh;
+  for (int idx = threadIdx.x; idx < CB * Nx; idx += 256) {
+    const int i = idx / CB, c = idx - (idx / CB) * CB;
+    const int m = m0 + c;
+    C v;
+    v.x = (T)0;
+    v.y = (T)0;
+    if (m < Nzh) v = base[(size_t)i * Nzh + m];
+    b0[c * Nx + i] = v;
+  }
+  __syncthreads();
+  int Ns = 1;
+  for (int s = 0; s < rx.n; ++s) {
+    const int R = rx.r[s];
+    const int NR = Nx / R;
+    // spread the CB lines' butterflies over the block
+    for (int w = threadIdx.x; w < CB * NR; w += 256) {
+      const int c = w / NR, j = w - (w / NR) * NR;
+      stockham_pass<T, SIGN>(b0 + c * Nx, b1 + c * Nx, Nx, R, Ns, tw, j, NR + 1);
+    }
+    __syncthreads();
+    C* t = b0;
+    b0 = b1;
+    b1 = t;
+    Ns *= R;
+  }
+  for (int idx = threadIdx.x; idx < CB * Nx; idx += 256) {
+    const int i = idx / CB, c = idx - (idx / CB) * CB;
+    const int m = m0 + c;
+    if (m < Nzh) base[(size_t)i * Nzh + m] = b0[c * Nx + i];
+  }
+}
+
+static Radices radices(const int* r, int n) {
+  Radices R;
+  R.n = n;
+  for (int i = 0; i < 12; ++i) R.r[i] = i < n ? r[i] : 1;
+  return R;
+}
+
+static int cols_per_block(int Nx, size_t elt) {
+  int cb = (int)(32768 / ((size_t)Nx * elt));  // ping-pong buffers of <= 64 KB
+  if (cb < 1) cb = 1;
+  if (cb > 16) cb = 16;
+  return cb;
+}
+
+template <typename T>
+hipError_t launch_fft_forward(Plan& p, void* phys, void* spec, int nplanes) {
+  using C = typename Cx<T>::t;
+  const int Nx = p.p.Nx, Nz = p.p.Nz, Nzh = p.Nzh;
+  const int nlines = nplanes * Nx;
+  Radices rz = radices(p.radz, p.nradz), rx = radices(p.radx, p.nradx);
+  fft_z_r2c<T><<<(nlines + 3) / 4, 256, 4 * 2 * Nz * sizeof(C), p.stream>>>(
+      (const T*)phys, (C*)spec, nlines, Nz, rz, (const C*)p.twz);
+  const int CB = cols_per_block(Nx, sizeof(C));
+  dim3 g((Nzh + CB - 1) / CB, nplanes);
+  fft_x<T, -1><<<g, 256, 2 * CB * Nx * sizeof(C), p.stream>>>((C*)spec, Nx, Nzh, CB, rx,
+                                                              (const C*)p.twx);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fft_inverse(Plan& p, void* spec, void* phys, int nplanes) {
+  using C = typename Cx<T>::t;
+  const int Nx = p.p.Nx, Nz = p.p.Nz, Nzh = p.Nzh;
+  const int nlines = nplanes * Nx;
+  Radices rz = radices(p.radz, p.nradz), rx = radices(p.radx, p.nradx);
+  const int CB = cols_per_block(Nx, sizeof(C));
+  dim3 g((Nzh + CB - 1) / CB, nplanes);
+  fft_x<T, 1><<<g, 256, 2 * CB * Nx * sizeof(C), p.stream>>>((C*)spec, Nx, Nzh, CB, rx,
+                                                             (const C*)p.twx);
+  fft_z_c2r<T><<<(nlines + 3) / 4, 256, 4 * 2 * Nz * sizeof(C), p.stream>>>(
+      (const C*)spec, (T*)phys, nlines, Nz, rz, (const C*)p.twz);
+  return hipGetLastError();
+}
+
+template hipError_t launch_fft_forward<double>(Plan&, void*, void*, int);
+template hipError_t launch_fft_forward<float>(Plan&, void*, void*, int);
+template hipError_t launch_fft_inverse<double>(Plan&, void*, void*, int);
+template hipError_t launch_fft_inverse<float>(Plan&, void*, void*, int);
+
+}  // namespace ggem

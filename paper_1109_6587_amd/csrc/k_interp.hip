@@ -1,0 +1,150 @@
+// Interpolation of the global solution to the targets with 4th-order
+// Lagrange polynomials, 5 nodes per axis (Sec. 3.2.2: error ~ h^5), and the
+// local + global combination (Eq. tot_l_g; Eq. vsigma for the double layer).
+//
+// Stencil: x nodes i0-2..i0+2 (periodic) with i0 = floor(x/dx + 1/2), z
+// likewise; y nodes j0-2..j0+2 of the Gauss-Lobatto grid with
+// j0 = clamp(rint(arccos(y/H) (Ny-1)/pi), 2, Ny-3).  Indices and weights are
+// formed in FP64 from FP64 positions in both precision modes.
+#include "ggem_internal.h"
+
+namespace ggem {
+
+__device__ inline void lagrange5_uniform(double t, double* w) {
+  // nodes at -2..2
+  for (int q = 0; q < 5; ++q) {
+    double v = 1.0;
+    for (int p = 0; p < 5; ++p)
+      if (p != q) v *= (t - (double)(p - 2)) / (double)(q - p);
+    w[q] = v;
+  }
+}
+
+__device__ inline void lagrange5(double t, const double* nd, double* w) {
+  for (int q = 0; q < 5; ++q) {
+    double v = 1.0;
+    for (int p = 0; p < 5; ++p)
+      if (p != q) v *= (t - nd[p]) / (nd[q] - nd[p]);
+    w[q] = v;
+  }
+}
+
+struct InterpArgs {
+  int nt, Nx, Nz, Ny;
+  double dx, dz, H;
+  const double* y;
+  const int* perm;
+  const double *tx, *ty, *tz;
+  const void* tn;      // sorted normals (T, SoA) for the double layer
+  size_t tcap;
+  const void* ul;      // local part at sorted targets (T, SoA)
+  const void* grid;    // [ncomp][Ny][Nx][Nz] T
+  double* out;         // (nt, 3) in input order
+};
+
+template <typename T, bool STRESS, bool GLOBAL>
+__global__ void __launch_bounds__(256) interp_combine(InterpArgs a) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.nt) return;
+  const T* ul = (const T*)a.ul;
+  double r[3] = {(double)ul[t], (double)ul[a.tcap + t], (double)ul[2 * a.tcap + t]};
+  if (GLOBAL) {
+    constexpr int NC = STRESS ? 6 : 3;
+    const double x = a.tx[t], y = a.ty[t], z = a.tz[t];
+    const double fx = floor(x / a.dx + 0.5), fz = floor(z / a.dz + 0.5);
+    double wx[5], wz[5], wy[5], ny[5];
+    lagrange5_uniform(x / a.dx - fx, wx);
+    lagrange5_uniform(z / a.dz - fz, wz);
+    const int N = a.Ny - 1;
+    int j0 = (int)rint(acos(y / a.H) * N / 3.141592653589793);
+    j0 = j0 < 2 ? 2 : (j0 > a.Ny - 3 ? a.Ny - 3 : j0);
+    for (int q = 0; q < 5; ++q) ny[q] = a.y[j0 - 2 + q];
+    lagrange5(y, ny, wy);
+    const int i0 = (int)fx, k0 = (int)fz;
+    int ii[5], kk[5];
+    for (int q = 0; q < 5; ++q) {
+      ii[q] = ((i0 - 2 + q) % a.Nx + a.Nx) % a.Nx;
+      kk[q] = ((k0 - 2 + q) % a.Nz + a.Nz) % a.Nz;
+    }
+    const T* g = (const T*)a.grid;
+    const size_t fs = (size_t)a.Ny * a.Nx * a.Nz;
+    double acc[NC];
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    for (int qa = 0; qa < 5; ++qa) {
+      const size_t jrow = (size_t)(j0 - 2 + qa) * a.Nx;
+      for (int qb = 0; qb < 5; ++qb) {
+        const size_t row = (jrow + ii[qb]) * a.Nz;
+        const double wab = wy[qa] * wx[qb];
+        for (int qc = 0; qc < 5; ++qc) {
+          const double w = wab * wz[qc];
+          const size_t idx = row + kk[qc];
+          for (int c = 0; c < NC; ++c) acc[c] += w * (double)g[c * fs + idx];
+        }
+      }
+    }
+    if (!STRESS) {
+      r[0] += acc[0];
+      r[1] += acc[1];
+      r[2] += acc[2];
+    } else {
+      const T* tn = (const T*)a.tn;
+      const double nx = tn[t], nyv = tn[a.tcap + t], nz = tn[2 * a.tcap + t];
+      // acc: xx, yy, zz, xy, xz, yz
+      r[0] += acc[0] * nx + acc[3] * nyv + acc[4] * nz;
+      r[1] += acc[3] * nx + acc[1] * nyv + acc[5] * nz;
+      r[2] += acc[4] * nx + acc[5] * nyv + acc[2] * nz;
+    }
+  }
+  const size_t o = 3 * (size_t)a.perm[t];
+  a.out[o] = r[0];
+  a.out[o + 1] = r[1];
+  a.out[o + 2] = r[2];
+}
+
+template <typename T>
+hipError_t launch_interp(Plan& p, int nt, double* out, bool stress, bool with_global) {
+  if (nt <= 0) return hipSuccess;
+  InterpArgs a;
+  a.nt = nt;
+  a.Nx = p.p.Nx;
+  a.Nz = p.p.Nz;
+  a.Ny = p.p.Ny;
+  a.dx = p.dx;
+  a.dz = p.dz;
+  a.H = p.p.H;
+  a.y = p.y;
+  a.perm = p.tgt.perm;
+  a.tx = p.tgt.x;
+  a.ty = p.tgt.y;
+  a.tz = p.tgt.z;
+  a.tn = p.tgt.s;
+  a.tcap = (size_t)p.p.max_tgt;
+  a.ul = p.ul;
+  a.grid = p.phys;
+  a.out = out;
+  const unsigned nb = (unsigned)((nt + 255) / 256);
+  if (!with_global) interp_combine<T, false, false><<<nb, 256, 0, p.stream>>>(a);
+  else if (stress) interp_combine<T, true, true><<<nb, 256, 0, p.stream>>>(a);
+  else interp_combine<T, false, true><<<nb, 256, 0, p.stream>>>(a);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void to_f64(const T* __restrict__ in, double* __restrict__ out, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (double)in[i];
+}
+
+template <typename T>
+hipError_t launch_grid_to_f64(Plan& p, double* out) {
+  const size_t n = (size_t)3 * p.p.Ny * p.p.Nx * p.p.Nz;
+  to_f64<T><<<(unsigned)((n + 255) / 256), 256, 0, p.stream>>>((const T*)p.phys, out, n);
+  return hipGetLastError();
+}
+
+template hipError_t launch_interp<double>(Plan&, int, double*, bool, bool);
+template hipError_t launch_interp<float>(Plan&, int, double*, bool, bool);
+template hipError_t launch_grid_to_f64<double>(Plan&, double*);
+template hipError_t launch_grid_to_f64<float>(Plan&, double*);
+
+}  // namespace ggem

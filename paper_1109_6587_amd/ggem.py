@@ -1,0 +1,171 @@
+"""ctypes binding of libggem (the C-ABI in include/ggem.h).
+
+Argument marshalling only: torch tensors provide device memory and the HIP
+stream; every step of the evaluation runs in the library's HIP kernels.  If
+the shared library has not been built, importing works but creating a plan
+raises, so no evaluation can silently fall back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libggem.so")
+
+FP64 = 0
+MIXED = 1
+PART_LOCAL = 1
+PART_GLOBAL = 2
+PART_ALL = 3
+
+OK = 0
+E_ARG = -1
+E_DOMAIN = -2
+E_CAPACITY = -3
+E_NOMEM = -4
+E_DEVICE = -5
+
+EXPORTS = (
+    "ggem_plan_create", "ggem_plan_destroy", "ggem_plan_set_stream", "ggem_plan_status",
+    "ggem_single_layer", "ggem_double_layer", "ggem_spread_grid", "ggem_last_error",
+)
+
+
+class GGEMError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ggem error {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("Lx", ctypes.c_double), ("Lz", ctypes.c_double), ("H", ctypes.c_double),
+        ("alpha", ctypes.c_double), ("rc", ctypes.c_double),
+        ("Nx", ctypes.c_int), ("Nz", ctypes.c_int), ("Ny", ctypes.c_int),
+        ("precision", ctypes.c_int), ("sync_checks", ctypes.c_int),
+        ("max_src", ctypes.c_longlong), ("max_tgt", ctypes.c_longlong),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libggem.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_1109_6587_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    vp, ll, dp, ip = ctypes.c_void_p, ctypes.c_longlong, ctypes.c_void_p, ctypes.c_int
+    lib.ggem_plan_create.argtypes = [ctypes.POINTER(Params), vp, ctypes.POINTER(vp)]
+    lib.ggem_plan_destroy.argtypes = [vp]
+    lib.ggem_plan_set_stream.argtypes = [vp, vp]
+    lib.ggem_plan_status.argtypes = [vp]
+    lib.ggem_single_layer.argtypes = [vp, ll, dp, dp, ll, dp, dp, ip]
+    lib.ggem_double_layer.argtypes = [vp, ll, dp, dp, ll, dp, dp, dp, ip]
+    lib.ggem_spread_grid.argtypes = [vp, ll, dp, dp, dp]
+    lib.ggem_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name != "ggem_last_error":
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(code: int):
+    if code != OK:
+        msg = _lib.ggem_last_error()
+        raise GGEMError(code, msg.decode() if msg else "")
+
+
+def _dev_ptr(t, name, n=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if t.dim() != 2 or t.shape[1] != 3 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous (n, 3) tensor")
+    if n is not None and t.shape[0] != n:
+        raise ValueError(f"{name} must have {n} rows")
+    return t.data_ptr()
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """A GGEM plan: box, split parameter, grid, precision and capacities."""
+
+    def __init__(self, Lx, Lz, H, alpha, Nx, Nz, Ny, rc=0.0, precision="fp64",
+                 max_src=1, max_tgt=1, sync_checks=True, stream=None):
+        lib = load_library()
+        prec = {"fp64": FP64, "mixed": MIXED}[precision] if isinstance(precision, str) else int(precision)
+        self.params = Params(float(Lx), float(Lz), float(H), float(alpha), float(rc),
+                             int(Nx), int(Nz), int(Ny), prec, 1 if sync_checks else 0,
+                             int(max_src), int(max_tgt))
+        self.Nx, self.Nz, self.Ny = int(Nx), int(Nz), int(Ny)
+        self._h = ctypes.c_void_p()
+        _check(lib.ggem_plan_create(ctypes.byref(self.params), _stream_handle(stream),
+                                    ctypes.byref(self._h)))
+
+    @classmethod
+    def from_case(cls, c, precision="fp64", max_src=None, max_tgt=None, **kw):
+        return cls(c.Lx, c.Lz, c.H, c.alpha, c.Nx, c.Nz, c.Ny, rc=c.rc, precision=precision,
+                   max_src=max_src if max_src is not None else max(c.ns, 1),
+                   max_tgt=max_tgt if max_tgt is not None else max(c.nt, 1), **kw)
+
+    def close(self):
+        if self._h:
+            _check(_lib.ggem_plan_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            if self._h and _lib is not None:
+                _lib.ggem_plan_destroy(self._h)
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        _check(_lib.ggem_plan_set_stream(self._h, _stream_handle(stream)))
+
+    def status(self):
+        _check(_lib.ggem_plan_status(self._h))
+
+    def single_layer(self, xs, f, xt, parts=PART_ALL, out=None):
+        import torch
+        ns, nt = xs.shape[0], xt.shape[0]
+        if out is None:
+            out = torch.empty((nt, 3), dtype=torch.float64, device=xt.device)
+        _check(_lib.ggem_single_layer(self._h, ns, _dev_ptr(xs, "xs"), _dev_ptr(f, "f", ns), nt,
+                                      _dev_ptr(xt, "xt"), _dev_ptr(out, "out", nt), int(parts)))
+        return out
+
+    def double_layer(self, xs, q, xt, nrm, parts=PART_ALL, out=None):
+        import torch
+        ns, nt = xs.shape[0], xt.shape[0]
+        if out is None:
+            out = torch.empty((nt, 3), dtype=torch.float64, device=xt.device)
+        _check(_lib.ggem_double_layer(self._h, ns, _dev_ptr(xs, "xs"), _dev_ptr(q, "q", ns), nt,
+                                      _dev_ptr(xt, "xt"), _dev_ptr(nrm, "nrm", nt),
+                                      _dev_ptr(out, "out", nt), int(parts)))
+        return out
+
+    def spread_grid(self, xs, f, out=None):
+        import torch
+        ns = xs.shape[0]
+        if out is None:
+            out = torch.empty((3, self.Ny, self.Nx, self.Nz), dtype=torch.float64, device=xs.device)
+        if not (out.is_cuda and out.dtype == torch.float64 and out.is_contiguous()
+                and out.numel() == 3 * self.Ny * self.Nx * self.Nz):
+            raise ValueError("out must be a contiguous float64 (3, Ny, Nx, Nz) device tensor")
+        _check(_lib.ggem_spread_grid(self._h, ns, _dev_ptr(xs, "xs"), _dev_ptr(f, "f", ns),
+                                     out.data_ptr()))
+        return out
