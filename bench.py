@@ -1,0 +1,218 @@
+"""Throughput of the GGEM slit evaluation on one MI355X.
+
+Workload (default): single layer on 50 capsule meshes (unit spheres, 642 nodes
+each, 32,100 nodal point forces, force-free per capsule) in a 20 x 10 x 20
+slit (walls at y = +-5), alpha = 2, r_c = 2, grid 128 x 128 Fourier x 65
+Chebyshev; targets = sources.  A step is one full evaluation (binning, local
+sum, wall data, spread, forward FFT + Chebyshev, tau solves, inverse
+transforms, interpolation) on inputs resident in device memory.
+
+Prints one JSON line: throughput in Mpoints/s (points = targets) for the
+mixed-precision path, with its error against the FP64 path on the same GPU,
+the FP64 path's throughput, the dominant kernel's roofline and the CPU oracle
+timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import resource
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Published MI355X peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
+
+# Algorithmic work per unit (flops), counted per pair within r_c (local sum)
+# and per (source, grid node within r_c) update (spread).
+FLOP_NEAR_SL = 50.0
+FLOP_NEAR_DL = 65.0
+FLOP_SPREAD = 12.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--workload", choices=["capsules_sl", "capsules_dl"], default="capsules_sl")
+    ap.add_argument("--roofline-stage", default="auto")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-capsules", type=int, default=5)
+    return ap.parse_args()
+
+
+def pair_counts(c):
+    """Pairs within r_c among the targets/sources and (source, node) pairs
+    within r_c, by a periodic k-d tree (work counts for the roofline)."""
+    import numpy as np
+    from scipy.spatial import cKDTree
+    box = np.array([c.Lx, 1e9, c.Lz])
+
+    def shift(x):
+        y = x.copy()
+        y[:, 1] += c.H
+        y[:, 0] = np.mod(y[:, 0], c.Lx)
+        y[:, 2] = np.mod(y[:, 2], c.Lz)
+        y[y[:, 0] >= c.Lx, 0] = 0.0
+        y[y[:, 2] >= c.Lz, 2] = 0.0
+        return y
+
+    ts = cKDTree(shift(c.xs), boxsize=box)
+    tt = cKDTree(shift(c.xt), boxsize=box)
+    near = int(tt.count_neighbors(ts, c.rc)) - int(tt.count_neighbors(ts, 0.0))
+    x = np.arange(c.Nx) * c.Lx / c.Nx
+    z = np.arange(c.Nz) * c.Lz / c.Nz
+    y = c.H * np.cos(np.pi * np.arange(c.Ny) / (c.Ny - 1)) + c.H
+    Y, X, Z = np.meshgrid(y, x, z, indexing="ij")
+    nodes = cKDTree(np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1), boxsize=box)
+    spread = int(nodes.count_neighbors(ts, c.rc))
+    return near, spread
+
+
+def time_steps(plan, call, steps, warmup, stage=None):
+    import torch
+    for _ in range(warmup):
+        call()
+    torch.cuda.synchronize()
+    if stage is not None:
+        plan.time_stage(stage, steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        call()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plan.status()
+    stage_ms = None
+    if stage is not None:
+        tot, n = plan.stage_time()
+        stage_ms = tot / max(n, 1)
+        plan.time_stage(-1, 1)
+    return (t1 - t0) * 1e3 / steps, stage_ms
+
+
+def cpu_baseline(c, ncap):
+    """FP64 oracle on the first `ncap` capsules (same box and grid)."""
+    import oracle as O
+    nv = c.meta.get("nv") or c.meta.get("ng")
+    n = ncap * nv
+    g = O.SlitGrid.from_case(c)
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    t0 = time.perf_counter()
+    if c.normals is None:
+        O.single_layer(g, c.xs[:n], c.f[:n], c.xt[:n])
+    else:
+        O.double_layer(g, c.xs[:n], c.f[:n], c.xt[:n], c.normals[:n])
+    wall = time.perf_counter() - t0
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    return {
+        "value": n / wall / 1e6,
+        "unit": "Mpoints/s",
+        "cores": max(1, int(round(cpu / wall))),
+        "kind": "oracle",
+        "sample": f"{ncap} of {c.meta['ncap']} capsules ({n} points as sources and targets) on "
+                  f"the full {c.Nx}x{c.Nz}x{c.Ny} grid, FP64 NumPy oracle, wall {wall:.1f} s, "
+                  f"cpu {cpu:.1f} s",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "design is described but not built", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1109_6587_amd as G
+    from workloads import case_capsules_dl, case_capsules_sl
+
+    dev = torch.device("cuda:0")
+    c = case_capsules_sl(1) if args.workload == "capsules_sl" else case_capsules_dl(2)
+    dl = c.normals is not None
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)  # noqa: E731
+    xs, f, xt = t(c.xs), t(c.f), t(c.xt)
+    nrm = t(c.normals) if dl else None
+    out = torch.empty((c.nt, 3), dtype=torch.float64, device=dev)
+
+    plans = {p: G.Plan.from_case(c, precision=p, sync_checks=False) for p in ("mixed", "fp64")}
+
+    def caller(plan):
+        if dl:
+            return lambda: plan.double_layer(xs, f, xt, nrm, out=out)
+        return lambda: plan.single_layer(xs, f, xt, out=out)
+
+    # accuracy of the mixed path against the FP64 path (same inputs)
+    caller(plans["fp64"])()
+    ref = out.clone()
+    caller(plans["mixed"])()
+    torch.cuda.synchronize()
+    err_l2 = float(torch.linalg.norm(out - ref) / torch.linalg.norm(ref))
+    err_max = float((out - ref).abs().max() / ref.abs().max())
+
+    near_pairs, spread_pairs = pair_counts(c)
+    stage = args.roofline_stage
+    if stage == "auto":
+        stage = "near"
+    plan = plans[args.precision]
+    ms, stage_ms = time_steps(plan, caller(plan), args.steps, args.warmup, stage=stage)
+    other = "fp64" if args.precision == "mixed" else "mixed"
+    ms_other, _ = time_steps(plans[other], caller(plans[other]), max(10, args.steps // 4),
+                             args.warmup)
+    value = c.nt / (ms * 1e-3) / 1e6
+
+    if stage == "near":
+        flops = near_pairs * (FLOP_NEAR_DL if dl else FLOP_NEAR_SL)
+    elif stage == "spread":
+        flops = spread_pairs * FLOP_SPREAD
+    else:
+        flops = None
+    peak = PEAK_FP32_TFLOPS if args.precision == "mixed" else PEAK_FP64_TFLOPS
+    roof = None
+    if flops is not None and stage_ms:
+        ach = flops / (stage_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(ach / peak, 4), "traffic": None, "kernel": stage,
+                "kernel_ms": round(stage_ms, 5), "work_units": near_pairs if stage == "near" else spread_pairs}
+
+    line = {
+        "metric": "GGEM Mpoints/s (mixed vs FP64, rel err 1e-5); Fredholm solve s to 1e-6",
+        "value": round(value, 3),
+        "unit": "Mpoints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if args.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": c.name, "points": c.nt, "sources": c.ns,
+                   "grid": [c.Nx, c.Nz, c.Ny], "alpha": c.alpha, "rc": c.rc,
+                   "box": [c.Lx, 2 * c.H, c.Lz], "precision": args.precision,
+                   "layer": "double" if dl else "single"},
+        "err_vs_fp64": {"rel_l2": err_l2, "rel_max": err_max},
+        f"{other}_mpoints_per_s": round(c.nt / (ms_other * 1e-3) / 1e6, 3),
+        f"{other}_ms_per_step": round(ms_other, 5),
+        "work": {"near_pairs": near_pairs, "spread_updates": spread_pairs},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(c, args.cpu_capsules)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

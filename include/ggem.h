@@ -122,6 +122,33 @@ int ggem_double_layer(ggem_plan_t plan, long long ns, const double* xs, const do
 int ggem_spread_grid(ggem_plan_t plan, long long ns, const double* xs, const double* f,
                      double* grid);
 
+/* Pipeline stages, for the timing hook below. */
+enum ggem_stage {
+  GGEM_STAGE_BIN = 0,       /* cell binning of sources and targets           */
+  GGEM_STAGE_NEAR = 1,      /* local sum at the targets                      */
+  GGEM_STAGE_WALL = 2,      /* wall data u^g = -u^l (and the pressure gauge) */
+  GGEM_STAGE_SPREAD = 3,    /* global density on the grid                    */
+  GGEM_STAGE_FFT_FWD = 4,   /* forward x-z FFTs of the grid and wall planes  */
+  GGEM_STAGE_CHEB_FWD = 5,  /* forward Chebyshev transform                   */
+  GGEM_STAGE_TAU = 6,       /* per-mode tau / influence-matrix solves        */
+  GGEM_STAGE_CHEB_INV = 7,  /* inverse Chebyshev transform                   */
+  GGEM_STAGE_FFT_INV = 8,   /* inverse x-z FFTs                              */
+  GGEM_STAGE_INTERP = 9,    /* interpolation and local + global combination  */
+  GGEM_NUM_STAGES = 10
+};
+
+/* Timing hook: from now on, record HIP events on the plan's stream around
+ * the launches of `stage` in each of the next max_calls evaluations (no host
+ * synchronisation is added).  stage < 0 switches timing off.  The events are
+ * created here, on the host side of the runtime; no device buffer is
+ * allocated.  Errors: GGEM_E_ARG, GGEM_E_DEVICE. */
+int ggem_plan_time_stage(ggem_plan_t plan, int stage, int max_calls);
+
+/* Waits for the plan's stream and returns the summed duration (ms) of the
+ * timed stage over the evaluations recorded since ggem_plan_time_stage, and
+ * their number. */
+int ggem_plan_stage_time(ggem_plan_t plan, double* total_ms, int* calls);
+
 /* Thread-local description of the last error on the calling thread. */
 const char* ggem_last_error(void);
 

@@ -71,14 +71,22 @@ void free_plan(Plan& p) {
                   p.src.offs,  p.src.cell_start, p.src.item_start, p.src.perm, p.src.x,
                   p.src.y,     p.src.z,       p.src.s,       p.tgt.keys,   p.tgt.counts,
                   p.tgt.offs,  p.tgt.cell_start, p.tgt.item_start, p.tgt.perm, p.tgt.x,
-                  p.tgt.y,     p.tgt.z,       p.tgt.s};
+                  p.tgt.y,     p.tgt.z,       p.tgt.s,       p.nconst,     p.sweep,
+                  p.wall.keys, p.wall.counts, p.wall.offs,   p.wall.cell_start,
+                  p.wall.item_start, p.wall.perm, p.wall.x,  p.wall.y,     p.wall.z,
+                  p.wall.s};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (p.flags_host) (void)hipHostFree(p.flags_host);
+  if (p.timed_ev) {
+    for (int i = 0; i < 2 * p.timed_max; ++i) (void)hipEventDestroy(p.timed_ev[i]);
+    delete[] p.timed_ev;
+    p.timed_ev = nullptr;
+  }
 }
 
 bool alloc_binned(Binned& b, long long cap, int ncells, size_t elt) {
-  const long long nch = (cap + kBinChunk - 1) / kBinChunk;
+  const long long nch = kMaxChunks + 1;
   return dev_alloc(&b.keys, (size_t)cap) && dev_alloc(&b.counts, (size_t)ncells * (nch + 1)) &&
          dev_alloc(&b.offs, (size_t)ncells * (nch + 1)) && dev_alloc(&b.cell_start, ncells + 1) &&
          dev_alloc(&b.item_start, ncells + 1) && dev_alloc(&b.perm, (size_t)cap) &&
@@ -105,6 +113,18 @@ double cospi_frac(long m, int N) {
 __global__ void fill_u32(unsigned* p, unsigned v, size_t n) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
+}
+
+// normals of coinciding targets, in the sources' sorted order
+template <typename T>
+__global__ void gather_normals(int n, const int* __restrict__ perm, const double* __restrict__ nrm,
+                               T* __restrict__ out, size_t cap) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const size_t j = 3 * (size_t)perm[i];
+  out[i] = (T)nrm[j];
+  out[cap + i] = (T)nrm[j + 1];
+  out[2 * cap + i] = (T)nrm[j + 2];
 }
 
 template <typename T>
@@ -152,7 +172,34 @@ int plan_constants(Plan& p) {
       HIP_TRY(hipMemcpy(dst, tf.data(), tf.size() * 4, hipMemcpyHostToDevice));
     }
   }
+  std::vector<double> nc(3 * (size_t)Ny, 0.0);
+  for (int n = 2; n < Ny; ++n) {
+    nc[n] = 1.0 / (4.0 * n * (n - 1));
+    nc[Ny + n] = 1.0 / (2.0 * ((double)n * n - 1.0));
+    nc[2 * Ny + n] = 1.0 / (4.0 * n * (n + 1));
+  }
+  HIP_TRY(hipMemcpy(p.nconst, nc.data(), nc.size() * 8, hipMemcpyHostToDevice));
   HIP_TRY(launch_influence(p));
+  {
+    // wall nodes (x_i, -H, z_k) then (x_i, +H, z_k), binned once
+    const size_t nw = 2 * (size_t)Nx * Nz;
+    std::vector<double> wpos(3 * nw);
+    for (int w = 0; w < 2; ++w)
+      for (int i = 0; i < Nx; ++i)
+        for (int k = 0; k < Nz; ++k) {
+          const size_t r = (size_t)w * Nx * Nz + (size_t)i * Nz + k;
+          wpos[3 * r] = i * p.dx;
+          wpos[3 * r + 1] = w ? p.p.H : -p.p.H;
+          wpos[3 * r + 2] = k * p.dz;
+        }
+    double* dpos = nullptr;
+    HIP_TRY(hipMalloc((void**)&dpos, wpos.size() * sizeof(double)));
+    hipError_t e = hipMemcpy(dpos, wpos.data(), wpos.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_bin(p, p.wall, (long long)nw, dpos, nullptr, nullptr, false);
+    if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
+    (void)hipFree(dpos);
+    HIP_TRY(e);
+  }
   HIP_TRY(hipStreamSynchronize(p.stream));
   return GGEM_OK;
 }
@@ -180,14 +227,56 @@ int finish(Plan& p) {
   return GGEM_OK;
 }
 
+// Timing hook: events around the launches of the selected stage.
+struct StageScope {
+  Plan& p;
+  bool on;
+  StageScope(Plan& pp, int stage) : p(pp), on(pp.timed_stage == stage && pp.timed_calls < pp.timed_max) {
+    if (on) (void)hipEventRecord(p.timed_ev[2 * p.timed_calls], p.stream);
+  }
+  ~StageScope() {
+    if (on) {
+      (void)hipEventRecord(p.timed_ev[2 * p.timed_calls + 1], p.stream);
+      ++p.timed_calls;
+    }
+  }
+};
+
+void destroy_timer(Plan& p) {
+  if (p.timed_ev) {
+    for (int i = 0; i < 2 * p.timed_max; ++i) (void)hipEventDestroy(p.timed_ev[i]);
+    delete[] p.timed_ev;
+  }
+  p.timed_ev = nullptr;
+  p.timed_max = 0;
+  p.timed_calls = 0;
+  p.timed_stage = -1;
+}
+
 template <typename T>
 int evaluate(Plan& p, long long ns, const double* xs, const double* f, long long nt,
              const double* xt, const double* nrm, double* out, int parts, bool dl) {
   fill_u32<<<1, 64, 0, p.stream>>>(p.flags, 0u, 1);
   HIP_TRY(hipGetLastError());
-  HIP_TRY(launch_bin(p, p.src, ns, xs, f, nullptr, true));
-  HIP_TRY(launch_bin(p, p.tgt, nt, xt, dl ? nrm : nullptr, nullptr, false));
+  {
+    StageScope s(p, GGEM_STAGE_BIN);
+    HIP_TRY(launch_bin(p, p.src, ns, xs, f, nullptr, true));
+    if (xt == xs && nt == ns) {
+      // targets coincide with the sources: reuse their binning
+      p.tview = &p.src;
+      if (dl && nt > 0) {
+        gather_normals<T><<<(unsigned)((nt + 255) / 256), 256, 0, p.stream>>>(
+            (int)nt, p.src.perm, nrm, (T*)p.tgt.s, (size_t)p.p.max_tgt);
+        HIP_TRY(hipGetLastError());
+      }
+    } else {
+      HIP_TRY(launch_bin(p, p.tgt, nt, xt, dl ? nrm : nullptr, nullptr, false));
+      p.tview = &p.tgt;
+    }
+    p.tnrm = p.tgt.s;
+  }
   if (parts & GGEM_PART_LOCAL) {
+    StageScope s(p, GGEM_STAGE_NEAR);
     if (dl) HIP_TRY(launch_near_dl<T>(p, (int)nt));
     else HIP_TRY(launch_near_sl<T>(p, (int)nt));
   } else {
@@ -197,18 +286,42 @@ int evaluate(Plan& p, long long ns, const double* xs, const double* f, long long
   const bool glob = (parts & GGEM_PART_GLOBAL) != 0;
   if (glob && nt > 0) {
     const int Ny = p.p.Ny;
-    HIP_TRY(launch_wall<T>(p));
-    if (dl) HIP_TRY(launch_gauge(p));
-    HIP_TRY(launch_spread<T>(p, 0));
-    HIP_TRY(launch_fft_forward<T>(p, p.phys, p.specA, 3 * Ny));
-    HIP_TRY(launch_fft_forward<T>(p, p.wall_phys, p.wall_spec, 6));
-    HIP_TRY(launch_cheb<T>(p, p.specA, p.specB, 3, true));
-    HIP_TRY(launch_tau<T>(p, dl));
+    {
+      StageScope s(p, GGEM_STAGE_WALL);
+      HIP_TRY(launch_wall<T>(p));
+      if (dl) HIP_TRY(launch_gauge(p));
+    }
+    {
+      StageScope s(p, GGEM_STAGE_SPREAD);
+      HIP_TRY(launch_spread<T>(p, 0));
+    }
+    {
+      StageScope s(p, GGEM_STAGE_FFT_FWD);
+      HIP_TRY(launch_fft_forward<T>(p, p.phys, p.specA, 3 * Ny));
+      HIP_TRY(launch_fft_forward<T>(p, p.wall_phys, p.wall_spec, 6));
+    }
+    {
+      StageScope s(p, GGEM_STAGE_CHEB_FWD);
+      HIP_TRY(launch_cheb<T>(p, p.specA, p.specB, 3, true));
+    }
+    {
+      StageScope s(p, GGEM_STAGE_TAU);
+      HIP_TRY(launch_tau<T>(p, dl));
+    }
     const int nf = dl ? 6 : 3;
-    HIP_TRY(launch_cheb<T>(p, p.specA, p.specB, nf, false));
-    HIP_TRY(launch_fft_inverse<T>(p, p.specB, p.phys, nf * Ny));
+    {
+      StageScope s(p, GGEM_STAGE_CHEB_INV);
+      HIP_TRY(launch_cheb<T>(p, p.specA, p.specB, nf, false));
+    }
+    {
+      StageScope s(p, GGEM_STAGE_FFT_INV);
+      HIP_TRY(launch_fft_inverse<T>(p, p.specB, p.phys, nf * Ny));
+    }
   }
-  HIP_TRY(launch_interp<T>(p, (int)nt, out, dl, glob));
+  {
+    StageScope s(p, GGEM_STAGE_INTERP);
+    HIP_TRY(launch_interp<T>(p, (int)nt, out, dl, glob));
+  }
   return finish(p);
 }
 
@@ -256,6 +369,7 @@ extern "C" int ggem_plan_create(const ggem_params* prm, void* hip_stream, ggem_p
   p.stream = (hipStream_t)hip_stream;
   (void)hipGetDevice(&p.device);
   p.fp64 = q.precision == GGEM_FP64;
+  p.timed_stage = -1;
   p.rc = q.rc;
   p.rc2 = q.rc * q.rc;
   p.dx = q.Lx / q.Nx;
@@ -306,12 +420,15 @@ extern "C" int ggem_plan_create(const ggem_params* prm, void* hip_stream, ggem_p
             hipMalloc(&p.specB, 6 * Ny * p.nmodes * 2 * elt) == hipSuccess &&
             hipMalloc(&p.wall_phys, 6 * Nx * Nz * elt) == hipSuccess &&
             hipMalloc(&p.wall_spec, 6 * (size_t)p.nmodes * 2 * elt) == hipSuccess &&
-            dev_alloc(&p.tau_scr, 2 * 7 * Ny * (size_t)p.nmodes) &&
+            dev_alloc(&p.tau_scr, 2 * 9 * Ny * (size_t)p.nmodes) &&
+            dev_alloc(&p.nconst, 3 * Ny) &&
+            dev_alloc(&p.sweep, (6 * Ny + 2) * (size_t)p.nmodes) &&
             dev_alloc(&p.gauge, (size_t)(q.max_src / 256 + 4)) && dev_alloc(&p.flags, 1) &&
             dev_alloc(&p.item_count, 4) &&
             hipHostMalloc((void**)&p.flags_host, sizeof(unsigned), 0) == hipSuccess &&
             alloc_binned(p.src, q.max_src, g.ncells, elt) &&
-            alloc_binned(p.tgt, q.max_tgt, g.ncells, elt);
+            alloc_binned(p.tgt, q.max_tgt, g.ncells, elt) &&
+            alloc_binned(p.wall, 2LL * q.Nx * q.Nz, g.ncells, elt);
   if (!ok) {
     free_plan(p);
     delete h;
@@ -389,4 +506,44 @@ extern "C" int ggem_spread_grid(ggem_plan_t plan, long long ns, const double* xs
     HIP_TRY(launch_grid_to_f64<float>(p, grid));
   }
   return finish(p);
+}
+
+extern "C" int ggem_plan_time_stage(ggem_plan_t plan, int stage, int max_calls) {
+  if (int rc = check_plan(plan)) return rc;
+  Plan& p = plan->p;
+  if (stage >= GGEM_NUM_STAGES) return fail(GGEM_E_ARG, "unknown stage %d", stage);
+  HIP_TRY(hipStreamSynchronize(p.stream));
+  destroy_timer(p);
+  if (stage < 0) return GGEM_OK;
+  if (max_calls < 1 || max_calls > 1000000) return fail(GGEM_E_ARG, "max_calls out of range");
+  p.timed_ev = new (std::nothrow) hipEvent_t[2 * (size_t)max_calls];
+  if (!p.timed_ev) return fail(GGEM_E_NOMEM, "host allocation failed");
+  for (int i = 0; i < 2 * max_calls; ++i) {
+    hipError_t e = hipEventCreate(&p.timed_ev[i]);
+    if (e != hipSuccess) {
+      p.timed_max = i / 2;
+      destroy_timer(p);
+      return fail(GGEM_E_DEVICE, "hipEventCreate failed: %s", hipGetErrorString(e));
+    }
+  }
+  p.timed_max = max_calls;
+  p.timed_calls = 0;
+  p.timed_stage = stage;
+  return GGEM_OK;
+}
+
+extern "C" int ggem_plan_stage_time(ggem_plan_t plan, double* total_ms, int* calls) {
+  if (int rc = check_plan(plan)) return rc;
+  if (!total_ms || !calls) return fail(GGEM_E_ARG, "null output");
+  Plan& p = plan->p;
+  HIP_TRY(hipStreamSynchronize(p.stream));
+  double sum = 0.0;
+  for (int i = 0; i < p.timed_calls; ++i) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, p.timed_ev[2 * i], p.timed_ev[2 * i + 1]));
+    sum += ms;
+  }
+  *total_ms = sum;
+  *calls = p.timed_calls;
+  return GGEM_OK;
 }

@@ -8,8 +8,8 @@
 namespace ggem {
 
 constexpr int kMaxCells = 16384;     // cell-list size (LDS histograms)
-constexpr int kBinChunk = 2048;      // points per counting-sort chunk
-constexpr int kNearBlock = 128;      // targets per near-field work item
+constexpr int kMaxChunks = 512;      // counting-sort chunks per point set (at most)
+constexpr int kNearBlock = 64;       // targets per near-field work item
 constexpr int kMaxNy = 129;
 constexpr int kMaxFFT = 512;
 
@@ -28,6 +28,7 @@ struct CellGeom {
 // A binned point set: sorted positions (wrapped) and cell ranges.
 struct Binned {
   int n;
+  int chunk;         // points per counting-sort chunk
   int nchunks;
   int* keys;         // cell key per original point
   int* counts;       // [cell][chunk]
@@ -64,20 +65,31 @@ struct Plan {
   void* twx;          // twiddles exp(-2 pi i t/Nx), complex T
   void* twz;
   double* infl;       // per mode: 2x2 inverse influence matrix (4 doubles)
+  double* nconst;     // per Chebyshev index: 1/(4n(n-1)), 1/(2(n^2-1)), 1/(4n(n+1))
+  double* sweep;      // per mode: tau sweep factors and (b) profiles ((6 Ny + 2) x nmodes)
 
   // workspace
   Binned src, tgt;
+  Binned wall;        // wall nodes of y = -H and y = +H, binned once per plan
+  Binned* tview;      // targets of the current call (tgt, or src when they coincide)
+  void* tnrm;         // sorted target normals of the current call (3 x max_tgt, T)
   void* ul;           // local result at sorted targets (3 x max_tgt, T)
   void* phys;         // physical grid fields (6 x Ny x Nx x Nz, T)
   void* specA;        // spectral fields (6 x Ny x Nx x Nzh, complex T)
   void* specB;
   void* wall_phys;    // wall velocities (2 x 3 x Nx x Nz, T)
   void* wall_spec;    // (2 x 3 x Nx x Nzh, complex T)
-  double* tau_scr;    // tau scratch (7 x Ny x nmodes, complex FP64)
+  double* tau_scr;    // tau scratch (9 x Ny x nmodes, complex FP64)
   double* gauge;      // gauge partial sums and value
   unsigned* flags;    // device domain flags
   unsigned* flags_host;  // pinned host copy
   int* item_count;    // scratch
+
+  // stage timing hook (host side)
+  int timed_stage;    // -1: off
+  int timed_max;
+  int timed_calls;
+  hipEvent_t* timed_ev;  // 2 * timed_max events
 };
 
 // ---- kernel launchers (each enqueues on p.stream) -------------------------

@@ -3,8 +3,8 @@
 // a sorted order plus per-cell ranges, so later kernels read contiguous runs).
 //
 //   bin_keys     wrap x,z into [0,L), check the slab, cell key per point
-//   bin_count    per-chunk histogram in LDS             -> counts[cell][chunk]
-//   bin_cellscan per-cell running sum over chunks       -> offs[cell][chunk]
+//   bin_count    per-chunk histogram in LDS             -> counts[chunk][cell]
+//   bin_cellscan per-cell running sum over chunks       -> offs[chunk][cell]
 //   bin_scan     exclusive scan over cells              -> cell_start, item_start
 //   bin_scatter  one wave per chunk, stable ranks by wave match -> sorted SoA
 //
@@ -48,29 +48,31 @@ __global__ void bin_keys(int n, const double* __restrict__ x, CellGeom g, int is
   if (f) atomicOr(flags, f);
 }
 
-__global__ void bin_count(int n, int nchunks, int ncells, const int* __restrict__ keys,
-                          int* __restrict__ counts) {
+__global__ void bin_count(int n, int chunk_size, int nchunks, int ncells,
+                          const int* __restrict__ keys, int* __restrict__ counts) {
   extern __shared__ int hist[];
   int chunk = blockIdx.x;
   for (int c = threadIdx.x; c < ncells; c += blockDim.x) hist[c] = 0;
   __syncthreads();
-  int i0 = chunk * kBinChunk;
-  int i1 = min(n, i0 + kBinChunk);
+  int i0 = chunk * chunk_size;
+  int i1 = min(n, i0 + chunk_size);
   for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) atomicAdd(&hist[keys[i]], 1);
   __syncthreads();
-  for (int c = threadIdx.x; c < ncells; c += blockDim.x) counts[(size_t)c * nchunks + chunk] = hist[c];
+  for (int c = threadIdx.x; c < ncells; c += blockDim.x) counts[(size_t)chunk * ncells + c] = hist[c];
 }
 
+// counts and offsets are chunk-major ([chunk][cell]): a thread per cell walks
+// the chunks with coalesced, independent loads.
 __global__ void bin_cellscan(int nchunks, int ncells, const int* __restrict__ counts,
                              int* __restrict__ offs, int* __restrict__ totals) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncells) return;
   int s = 0;
-  const int* row = counts + (size_t)c * nchunks;
-  int* orow = offs + (size_t)c * nchunks;
+#pragma unroll 8
   for (int k = 0; k < nchunks; ++k) {
-    orow[k] = s;
-    s += row[k];
+    const int v = counts[(size_t)k * ncells + c];
+    offs[(size_t)k * ncells + c] = s;
+    s += v;
   }
   totals[c] = s;
 }
@@ -116,7 +118,8 @@ __global__ void __launch_bounds__(1024) bin_scan(int ncells, int* __restrict__ c
 }
 
 template <typename T>
-__global__ void __launch_bounds__(64) bin_scatter(int n, int nchunks, int ncells, CellGeom g,
+__global__ void __launch_bounds__(64) bin_scatter(int n, int chunk_size, int nchunks, int ncells,
+                                                  CellGeom g,
                                                   const int* __restrict__ keys,
                                                   const double* __restrict__ x,
                                                   const double* __restrict__ s,
@@ -130,8 +133,8 @@ __global__ void __launch_bounds__(64) bin_scatter(int n, int nchunks, int ncells
   const int chunk = blockIdx.x;
   for (int c = lane; c < ncells; c += 64) cnt[c] = 0;
   __syncthreads();
-  const int i0 = chunk * kBinChunk;
-  const int i1 = min(n, i0 + kBinChunk);
+  const int i0 = chunk * chunk_size;
+  const int i1 = min(n, i0 + chunk_size);
   const unsigned long long lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
   for (int base = i0; base < i1; base += 64) {
     int i = base + lane;
@@ -154,7 +157,7 @@ __global__ void __launch_bounds__(64) bin_scatter(int n, int nchunks, int ncells
       active &= ~m;
     }
     if (valid) {
-      int pos = cell_start[key] + offs[(size_t)key * nchunks + chunk] + before + rank;
+      int pos = cell_start[key] + offs[(size_t)chunk * ncells + key] + before + rank;
       double px = x[3 * (size_t)i], py = x[3 * (size_t)i + 1], pz = x[3 * (size_t)i + 2];
       if (!(isfinite(px) && isfinite(py) && isfinite(pz))) px = py = pz = 0.0;
       py = fmin(fmax(py, -g.H), g.H);
@@ -181,12 +184,15 @@ static hipError_t bin_impl(Plan& p, Binned& b, long long n, const double* x, con
   hipStream_t st = p.stream;
   const CellGeom& g = p.cg;
   b.n = (int)n;
-  b.nchunks = (int)((n + kBinChunk - 1) / kBinChunk);
+  // at most kMaxChunks chunks, at least 256 points each (multiple of 64)
+  const long long per = (n + kMaxChunks - 1) / kMaxChunks;
+  b.chunk = (int)(per < 256 ? 256 : ((per + 63) / 64) * 64);
+  b.nchunks = (int)((n + b.chunk - 1) / b.chunk);
   if (n > 0) {
     bin_keys<<<(unsigned)((n + 255) / 256), 256, 0, st>>>((int)n, x, g, is_source ? 1 : 0, b.keys,
                                                           p.flags);
-    bin_count<<<b.nchunks, 256, g.ncells * sizeof(int), st>>>((int)n, b.nchunks, g.ncells, b.keys,
-                                                               b.counts);
+    bin_count<<<b.nchunks, 256, g.ncells * sizeof(int), st>>>((int)n, b.chunk, b.nchunks, g.ncells,
+                                                               b.keys, b.counts);
     bin_cellscan<<<(g.ncells + 255) / 256, 256, 0, st>>>(b.nchunks, g.ncells, b.counts, b.offs,
                                                          b.cell_start);
   } else {
@@ -196,12 +202,12 @@ static hipError_t bin_impl(Plan& p, Binned& b, long long n, const double* x, con
   if (n > 0) {
     if (p.fp64)
       bin_scatter<double><<<b.nchunks, 64, g.ncells * sizeof(int), st>>>(
-          (int)n, b.nchunks, g.ncells, g, b.keys, x, s, b.cell_start, b.offs, b.perm, b.x, b.y,
-          b.z, (double*)b.s, cap);
+          (int)n, b.chunk, b.nchunks, g.ncells, g, b.keys, x, s, b.cell_start, b.offs, b.perm,
+          b.x, b.y, b.z, (double*)b.s, cap);
     else
       bin_scatter<float><<<b.nchunks, 64, g.ncells * sizeof(int), st>>>(
-          (int)n, b.nchunks, g.ncells, g, b.keys, x, s, b.cell_start, b.offs, b.perm, b.x, b.y,
-          b.z, (float*)b.s, cap);
+          (int)n, b.chunk, b.nchunks, g.ncells, g, b.keys, x, s, b.cell_start, b.offs, b.perm,
+          b.x, b.y, b.z, (float*)b.s, cap);
   }
   return hipGetLastError();
 }
@@ -209,6 +215,7 @@ static hipError_t bin_impl(Plan& p, Binned& b, long long n, const double* x, con
 hipError_t launch_bin(Plan& p, Binned& b, long long n, const double* x, const double* s,
                       const double* /*s2*/, bool is_source) {
   size_t cap = is_source ? (size_t)p.p.max_src : (size_t)p.p.max_tgt;
+  if (&b == &p.wall) cap = 2 * (size_t)p.p.Nx * p.p.Nz;
   return bin_impl(p, b, n, x, s, is_source, cap);
 }
 

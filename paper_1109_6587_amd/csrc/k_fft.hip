@@ -52,14 +52,14 @@ struct Radices {
 };
 
 // In-register DFT of length R (2..5), sign -1 forward, +1 inverse.
-template <typename T, int SIGN>
-__device__ inline void small_dft(typename Cx<T>::t* v, int R) {
+template <typename T, int SIGN, int R>
+__device__ inline void small_dft(typename Cx<T>::t* v) {
   using C = typename Cx<T>::t;
-  if (R == 2) {
+  if constexpr (R == 2) {
     C a = v[0], b = v[1];
     v[0] = cadd(a, b);
     v[1] = csub(a, b);
-  } else if (R == 4) {
+  } else if constexpr (R == 4) {
     C s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
     C s13 = cadd(v[1], v[3]), d13 = csub(v[1], v[3]);
     // multiply d13 by SIGN * i
@@ -70,7 +70,7 @@ __device__ inline void small_dft(typename Cx<T>::t* v, int R) {
     v[2] = csub(s02, s13);
     v[1] = cadd(d02, jd);
     v[3] = csub(d02, jd);
-  } else if (R == 3) {
+  } else if constexpr (R == 3) {
     const T c1 = (T)-0.5, s1 = (T)SIGN * (T)0.86602540378443864676;
     C y0 = cadd(v[0], cadd(v[1], v[2]));
     C t;
@@ -110,32 +110,53 @@ __device__ inline void small_dft(typename Cx<T>::t* v, int R) {
   }
 }
 
-// One Stockham pass over a line of length N with radix R; workers j run
-// from `start` with step `stride` (tw: exp(-2 pi i t/N), conjugated for the
-// inverse).
+// One butterfly of a Stockham pass over a line of length N with radix R
+// (tw: exp(-2 pi i t/N), conjugated for the inverse).
+template <typename T, int SIGN, int R>
+__device__ inline void stockham_bfly(const typename Cx<T>::t* __restrict__ src,
+                                     typename Cx<T>::t* __restrict__ dst, int N, int Ns, int j,
+                                     const typename Cx<T>::t* __restrict__ tw) {
+  using C = typename Cx<T>::t;
+  const int NR = N / R;
+  const int k = j % Ns;
+  const int tstep = N / (Ns * R);
+  C v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    C a = src[j + r * NR];
+    if (r > 0 && k > 0) {
+      C w = tw[k * r * tstep];
+      if (SIGN > 0) w.y = -w.y;
+      a = cmul(a, w);
+    }
+    v[r] = a;
+  }
+  small_dft<T, SIGN, R>(v);
+  const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+  for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[r];
+}
+
+// Stockham pass: workers j run from `start` with step `stride`.
 template <typename T, int SIGN>
 __device__ inline void stockham_pass(const typename Cx<T>::t* __restrict__ src,
                                      typename Cx<T>::t* __restrict__ dst, int N, int R, int Ns,
                                      const typename Cx<T>::t* __restrict__ tw, int start,
                                      int stride) {
-  using C = typename Cx<T>::t;
   const int NR = N / R;
-  const int tstep = N / (Ns * R);
-  for (int j = start; j < NR; j += stride) {
-    const int k = j % Ns;
-    C v[5];
-    for (int r = 0; r < R; ++r) {
-      C a = src[j + r * NR];
-      if (r > 0 && k > 0) {
-        C w = tw[(k * r * tstep) % N];
-        if (SIGN > 0) w.y = -w.y;
-        a = cmul(a, w);
-      }
-      v[r] = a;
-    }
-    small_dft<T, SIGN>(v, R);
-    const int base = (j / Ns) * Ns * R + k;
-    for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[r];
+  switch (R) {
+    case 2:
+      for (int j = start; j < NR; j += stride) stockham_bfly<T, SIGN, 2>(src, dst, N, Ns, j, tw);
+      break;
+    case 3:
+      for (int j = start; j < NR; j += stride) stockham_bfly<T, SIGN, 3>(src, dst, N, Ns, j, tw);
+      break;
+    case 4:
+      for (int j = start; j < NR; j += stride) stockham_bfly<T, SIGN, 4>(src, dst, N, Ns, j, tw);
+      break;
+    default:
+      for (int j = start; j < NR; j += stride) stockham_bfly<T, SIGN, 5>(src, dst, N, Ns, j, tw);
+      break;
   }
 }
 

@@ -113,11 +113,11 @@ hipError_t launch_interp(Plan& p, int nt, double* out, bool stress, bool with_gl
   a.dz = p.dz;
   a.H = p.p.H;
   a.y = p.y;
-  a.perm = p.tgt.perm;
-  a.tx = p.tgt.x;
-  a.ty = p.tgt.y;
-  a.tz = p.tgt.z;
-  a.tn = p.tgt.s;
+  a.perm = p.tview->perm;
+  a.tx = p.tview->x;
+  a.ty = p.tview->y;
+  a.tz = p.tview->z;
+  a.tn = p.tnrm;
   a.tcap = (size_t)p.p.max_tgt;
   a.ul = p.ul;
   a.grid = p.phys;

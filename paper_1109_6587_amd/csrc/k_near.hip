@@ -1,8 +1,9 @@
 // Local (near-field) part of the GGEM sum, Eq. u_loc with the kernels of
 // Eq. local, truncated at r_c and periodic in x, z by the minimum image
-// (Sec. 3.2.2).  One work item = up to kNearBlock sorted targets of one cell;
-// the sources of each neighbour cell are staged through LDS and every thread
-// accumulates its own target in registers (no atomics, fixed order).
+// (Sec. 3.2.2).  One work item = up to 64 sorted targets of one cell; the
+// neighbour cells are shared out among the waves of the block, their sources
+// staged through LDS, and every lane accumulates its own target in registers
+// (no atomics, fixed order of summation).
 //
 // Displacements and the cutoff test are always formed in FP64 (so the set of
 // interacting pairs does not depend on the precision mode); the kernel values
@@ -30,12 +31,6 @@ __host__ Kc<T> make_kc(double alpha) {
   return k;
 }
 
-__device__ inline double t_erfc(double v) { return erfc(v); }
-__device__ inline float t_erfc(float v) { return erfcf(v); }
-__device__ inline double t_exp(double v) { return exp(v); }
-__device__ inline float t_exp(float v) { return expf(v); }
-__device__ inline double t_sqrt(double v) { return sqrt(v); }
-__device__ inline float t_sqrt(float v) { return sqrtf(v); }
 
 // d - L rint(d/L) using a multiply by 1/L: for every pair within r_c < L/2
 // the rounding picks the same image as the division would.
@@ -48,18 +43,40 @@ __device__ inline double dist2(double dx, double dy, double dz) {
   return (dx * dx + dy * dy) + dz * dz;
 }
 
-// G^l(d) f accumulated (without the 1/8pi factor).
+// erfc and exp(-x^2) for the pair kernels.  FP64: the device library.  FP32:
+// exp(-x^2) once, shared with the Gaussian terms, and erfc(x) =
+// t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2), t = 1/(1 + p x), the
+// approximation 7.1.26 of Abramowitz & Stegun (absolute error <= 1.5e-7).
+__device__ inline void erfc_exp(double x, double x2, double& ec, double& ex) {
+  ec = erfc(x);
+  ex = exp(-x2);
+}
+__device__ inline void erfc_exp(float x, float x2, float& ec, float& ex) {
+  ex = __builtin_amdgcn_exp2f(-1.44269504088896341f * x2);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
+  float p = fmaf(1.061405429f, t, -1.453152027f);
+  p = fmaf(p, t, 1.421413741f);
+  p = fmaf(p, t, -0.284496736f);
+  p = fmaf(p, t, 0.254829592f);
+  ec = p * t * ex;
+}
+__device__ inline double t_rsqrt(double v) { return 1.0 / sqrt(v); }
+__device__ inline float t_rsqrt(float v) { return __builtin_amdgcn_rsqf(v); }
+
+// G^l(d) f accumulated (without the 1/8pi factor):
+// G^l f = f (erfc/r - c e) + d (d.f) (erfc/r + c e)/r^2,  c = 2 alpha/sqrt(pi).
 template <typename T>
 __device__ inline void stokeslet_acc(T dx, T dy, T dz, T r2, T fx, T fy, T fz, const Kc<T>& k,
                                      T& ux, T& uy, T& uz) {
-  T r = t_sqrt(r2);
-  T ir = (T)1 / r;
-  T ec = t_erfc(k.alpha * r);
-  T ex = t_exp(-k.a2 * r2);
-  T A = ec * ir - k.c2a * ex;
-  T B = (ec * ir + k.c2a * ex) * (ir * ir);
-  T df = dx * fx + dy * fy + dz * fz;
-  T Bdf = B * df;
+  const T ir = t_rsqrt(r2);
+  const T r = r2 * ir;
+  T ec, ex;
+  erfc_exp(k.alpha * r, k.a2 * r2, ec, ex);
+  const T er = ec * ir;
+  const T A = er - k.c2a * ex;
+  const T B = (er + k.c2a * ex) * (ir * ir);
+  const T df = dx * fx + dy * fy + dz * fz;
+  const T Bdf = B * df;
   ux += A * fx + Bdf * dx;
   uy += A * fy + Bdf * dy;
   uz += A * fz + Bdf * dz;
@@ -70,19 +87,19 @@ __device__ inline void stokeslet_acc(T dx, T dy, T dz, T r2, T fx, T fy, T fz, c
 template <typename T>
 __device__ inline void stresslet_acc(T dx, T dy, T dz, T r2, T qx, T qy, T qz, T nx, T ny, T nz,
                                      const Kc<T>& k, T& vx, T& vy, T& vz) {
-  T r = t_sqrt(r2);
-  T ir = (T)1 / r;
-  T ir2 = ir * ir;
-  T ec = t_erfc(k.alpha * r);
-  T ex = t_exp(-k.a2 * r2);
-  T ir4 = ir2 * ir2;
-  T A = -(T)6 * ec * ir4 * ir - k.c12a * ex * ir4 - k.c8a3 * ex * ir2;
-  T B = k.c4a3 * ex;
-  T dq = dx * qx + dy * qy + dz * qz;
-  T dn = dx * nx + dy * ny + dz * nz;
-  T qn = qx * nx + qy * ny + qz * nz;
-  T Ad = A * dq * dn;
-  T Bqn = B * qn, Bdn = B * dn, Bdq = B * dq;
+  const T ir = t_rsqrt(r2);
+  const T r = r2 * ir;
+  const T ir2 = ir * ir;
+  T ec, ex;
+  erfc_exp(k.alpha * r, k.a2 * r2, ec, ex);
+  const T ir4 = ir2 * ir2;
+  const T A = -(T)6 * ec * ir4 * ir - k.c12a * ex * ir4 - k.c8a3 * ex * ir2;
+  const T B = k.c4a3 * ex;
+  const T dq = dx * qx + dy * qy + dz * qz;
+  const T dn = dx * nx + dy * ny + dz * nz;
+  const T qn = qx * nx + qy * ny + qz * nz;
+  const T Ad = A * dq * dn;
+  const T Bqn = B * qn, Bdn = B * dn, Bdq = B * dq;
   vx += Ad * dx + Bdn * qx + Bdq * nx + Bqn * dx;
   vy += Ad * dy + Bdn * qy + Bdq * ny + Bqn * dy;
   vz += Ad * dz + Bdn * qz + Bdq * nz + Bqn * dz;
@@ -100,7 +117,11 @@ struct NearArgs {
   const double *sx, *sy, *sz;
   const void* sf;          // sorted strengths (T, SoA)
   size_t scap;
-  void* out;               // (3 x tcap, T) at sorted targets
+  void* out;               // (3 x ostride, T)
+  size_t ostride;
+  const int* tperm;        // wall mode: sorted target -> wall node index
+  int nplane;              // wall mode: nodes per wall plane (0 = ordinary targets)
+  double scale;            // output factor
 };
 
 __device__ inline int find_cell(const int* __restrict__ start, int ncells, int item) {
@@ -113,19 +134,42 @@ __device__ inline int find_cell(const int* __restrict__ start, int ncells, int i
   return lo;
 }
 
-template <typename T, bool DL>
-__global__ void __launch_bounds__(kNearBlock) near_field(NearArgs a, Kc<T> k) {
-  __shared__ double lx[kNearBlock], ly[kNearBlock], lz[kNearBlock];
-  __shared__ T lf[3][kNearBlock];
+constexpr int kNearWaves = 4;
+
+// Work item: up to 64 sorted targets of one cell (one per lane).  The four
+// waves of the block take disjoint subsets of the neighbour cells (cell k of
+// the list goes to wave k mod 4), stage each cell's sources through their own
+// LDS slice, and the four partial sums are added in wave order at the end.
+//
+// Pass 1 tests every staged source against the lane's target and keeps a bit
+// mask of the pairs within r_c; pass 2 evaluates the kernel only for those.
+// FAST (mixed precision, >= 3 cells per periodic direction): sources are
+// staged shifted into the target cell's periodic image, pass 1 compares in
+// FP32 relative to the cell corner and pass 2 forms the displacement in FP64
+// without a per-pair image search.  Otherwise every displacement is the FP64
+// minimum image and the cutoff is decided in FP64.
+template <typename T, bool DL, bool FAST>
+__global__ void __launch_bounds__(64 * kNearWaves) near_field(NearArgs a, Kc<T> k) {
+  __shared__ double lx[kNearWaves][64], ly[kNearWaves][64], lz[kNearWaves][64];
+  __shared__ float4 lr[kNearWaves][64];
+  __shared__ T lf[kNearWaves][3][64];
+  __shared__ T part[kNearWaves][3][64];
   const CellGeom& g = a.g;
   const int item = blockIdx.x;
   const int nitems = a.item_start[g.ncells];
   if (item >= nitems) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int c = find_cell(a.item_start, g.ncells, item);
-  const int t0 = a.tcell[c] + (item - a.item_start[c]) * kNearBlock;
-  const int t1 = min(a.tcell[c + 1], t0 + kNearBlock);
-  const int t = t0 + threadIdx.x;
+  const int t0 = a.tcell[c] + (item - a.item_start[c]) * 64;
+  const int t1 = min(a.tcell[c + 1], t0 + 64);
+  const int t = t0 + lane;
   const bool active = t < t1;
+  const int iz = c % g.ncz;
+  const int ix = (c / g.ncz) % g.ncx;
+  const int iy = c / (g.ncz * g.ncx);
+  // target cell corner (FAST path reference point)
+  const double ox = ix / g.icx, oy = iy / g.icy - g.H, oz = iz / g.icz;
   double px = 0, py = 0, pz = 0;
   T nx = 0, ny = 0, nz = 0;
   if (active) {
@@ -139,117 +183,142 @@ __global__ void __launch_bounds__(kNearBlock) near_field(NearArgs a, Kc<T> k) {
       nz = tn[2 * a.tcap + t];
     }
   }
+  const float prx = (float)(px - ox), pry = (float)(py - oy), prz = (float)(pz - oz);
+  const float rc2f = (float)a.rc2;
   const T* sf = (const T*)a.sf;
   T ux = 0, uy = 0, uz = 0;
   T sfx = 0, sfy = 0, sfz = 0;  // self contributions
-  const int iz = c % g.ncz;
-  const int ix = (c / g.ncz) % g.ncx;
-  const int iy = c / (g.ncz * g.ncx);
-  const int xa = g.ncx >= 3 ? -1 : 0, xb = g.ncx >= 3 ? 1 : g.ncx - 1;
-  const int za = g.ncz >= 3 ? -1 : 0, zb = g.ncz >= 3 ? 1 : g.ncz - 1;
-  for (int oy = -1; oy <= 1; ++oy) {
-    const int cy = iy + oy;
+  const int nxo = g.ncx >= 3 ? 3 : g.ncx, nzo = g.ncz >= 3 ? 3 : g.ncz;
+  // wall targets only see the wall cell layer (cells are at least r_c high)
+  const int oy0 = a.nplane ? 1 : 0, noy = a.nplane ? 1 : 3;
+  const int ncand = noy * nxo * nzo;
+  for (int kc = wave; kc < ncand; kc += kNearWaves) {
+    const int oyi = kc / (nxo * nzo) + oy0 - 1;
+    const int oxi = (kc / nzo) % nxo, ozi = kc % nzo;
+    const int cy = iy + oyi;
     if (cy < 0 || cy >= g.ncy) continue;
-    for (int ox = xa; ox <= xb; ++ox) {
-      const int cx = g.ncx >= 3 ? (ix + ox + g.ncx) % g.ncx : ox;
-      for (int oz = za; oz <= zb; ++oz) {
-        const int cz = g.ncz >= 3 ? (iz + oz + g.ncz) % g.ncz : oz;
-        const int nc = (cy * g.ncx + cx) * g.ncz + cz;
-        const int s0 = a.scell[nc], s1 = a.scell[nc + 1];
-        for (int b = s0; b < s1; b += kNearBlock) {
-          __syncthreads();
-          const int si = b + threadIdx.x;
-          if (si < s1) {
-            lx[threadIdx.x] = a.sx[si];
-            ly[threadIdx.x] = a.sy[si];
-            lz[threadIdx.x] = a.sz[si];
-            lf[0][threadIdx.x] = sf[si];
-            lf[1][threadIdx.x] = sf[a.scap + si];
-            lf[2][threadIdx.x] = sf[2 * a.scap + si];
+    int cx, cz;
+    double shx = 0.0, shz = 0.0;
+    if (g.ncx >= 3) {
+      const int u = ix + oxi - 1;
+      cx = u < 0 ? u + g.ncx : (u >= g.ncx ? u - g.ncx : u);
+      shx = u < 0 ? -g.Lx : (u >= g.ncx ? g.Lx : 0.0);
+    } else {
+      cx = oxi;
+    }
+    if (g.ncz >= 3) {
+      const int u = iz + ozi - 1;
+      cz = u < 0 ? u + g.ncz : (u >= g.ncz ? u - g.ncz : u);
+      shz = u < 0 ? -g.Lz : (u >= g.ncz ? g.Lz : 0.0);
+    } else {
+      cz = ozi;
+    }
+    const int nc = (cy * g.ncx + cx) * g.ncz + cz;
+    const int s0 = a.scell[nc], s1 = a.scell[nc + 1];
+    for (int b = s0; b < s1; b += 64) {
+      const int si = b + lane;
+      __builtin_amdgcn_wave_barrier();
+      if (si < s1) {
+        double qx = a.sx[si], qy = a.sy[si], qz = a.sz[si];
+        if (FAST) {
+          qx += shx;
+          qz += shz;
+          lr[wave][lane] = make_float4((float)(qx - ox), (float)(qy - oy), (float)(qz - oz), 0.f);
+        }
+        lx[wave][lane] = qx;
+        ly[wave][lane] = qy;
+        lz[wave][lane] = qz;
+        lf[wave][0][lane] = sf[si];
+        lf[wave][1][lane] = sf[a.scap + si];
+        lf[wave][2][lane] = sf[2 * a.scap + si];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const int cnt = min(64, s1 - b);
+      // pass 1: this lane's in-range sources of the batch as a bit mask
+      unsigned long long mask = 0;
+      if (active) {
+        for (int j = 0; j < cnt; ++j) {
+          bool in, self;
+          if (FAST) {
+            const float4 q = lr[wave][j];
+            const float dx = prx - q.x, dy = pry - q.y, dz = prz - q.z;
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            in = r2 <= rc2f;
+            self = r2 == 0.f;
+          } else {
+            const double dx = min_image(px - lx[wave][j], g.Lx, g.invLx);
+            const double dy = py - ly[wave][j];
+            const double dz = min_image(pz - lz[wave][j], g.Lz, g.invLz);
+            const double r2 = dist2(dx, dy, dz);
+            in = r2 <= a.rc2;
+            self = r2 == 0.0;
           }
-          __syncthreads();
-          const int cnt = min(kNearBlock, s1 - b);
-          if (active) {
-            for (int j = 0; j < cnt; ++j) {
-              const double dx = min_image(px - lx[j], g.Lx, g.invLx);
-              const double dy = py - ly[j];
-              const double dz = min_image(pz - lz[j], g.Lz, g.invLz);
-              const double r2 = dist2(dx, dy, dz);
-              if (r2 <= a.rc2) {
-                if (r2 > 0.0) {
-                  if (DL)
-                    stresslet_acc<T>((T)dx, (T)dy, (T)dz, (T)r2, lf[0][j], lf[1][j], lf[2][j], nx,
-                                     ny, nz, k, ux, uy, uz);
-                  else
-                    stokeslet_acc<T>((T)dx, (T)dy, (T)dz, (T)r2, lf[0][j], lf[1][j], lf[2][j], k,
-                                     ux, uy, uz);
-                } else if (!DL) {
-                  sfx += lf[0][j];
-                  sfy += lf[1][j];
-                  sfz += lf[2][j];
-                }
-              }
+          if (in) {
+            if (!self) {
+              mask |= 1ull << j;
+            } else if (!DL) {
+              sfx += lf[wave][0][j];
+              sfy += lf[wave][1][j];
+              sfz += lf[wave][2][j];
             }
           }
         }
       }
-    }
-  }
-  if (active) {
-    const T s = (T)0.039788735772973833942;  // 1/(8 pi)
-    T* out = (T*)a.out;
-    out[t] = s * (ux + k.selfc * sfx);
-    out[a.tcap + t] = s * (uy + k.selfc * sfy);
-    out[2 * a.tcap + t] = s * (uz + k.selfc * sfz);
-  }
-}
-
-// Wall data of the global problem: u^g = -u^l at the wall nodes (Sec. 3.2.2).
-// One thread per node of the planes y = -H (w = 0) and y = +H (w = 1).  The
-// cells have height >= r_c, so only the wall-adjacent cell layer contributes.
-template <typename T>
-__global__ void wall_velocity(CellGeom g, double rc2, int Nx, int Nz, double dx, double dz,
-                              const int* __restrict__ scell, const double* __restrict__ sx,
-                              const double* __restrict__ sy, const double* __restrict__ sz,
-                              const T* __restrict__ sf, size_t scap, Kc<T> k,
-                              T* __restrict__ wall) {
-  const int nplane = Nx * Nz;
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= 2 * nplane) return;
-  const int w = gid / nplane;
-  const int r = gid - w * nplane;
-  const int i = r / Nz, kk = r - (r / Nz) * Nz;
-  const double px = i * dx, pz = kk * dz, py = w ? g.H : -g.H;
-  const int ix = min((int)floor(px * g.icx), g.ncx - 1);
-  const int iz = min((int)floor(pz * g.icz), g.ncz - 1);
-  const int cy = w ? g.ncy - 1 : 0;
-  const int xa = g.ncx >= 3 ? -1 : 0, xb = g.ncx >= 3 ? 1 : g.ncx - 1;
-  const int za = g.ncz >= 3 ? -1 : 0, zb = g.ncz >= 3 ? 1 : g.ncz - 1;
-  T ux = 0, uy = 0, uz = 0;
-  for (int ox = xa; ox <= xb; ++ox) {
-    const int cx = g.ncx >= 3 ? (ix + ox + g.ncx) % g.ncx : ox;
-    for (int oz = za; oz <= zb; ++oz) {
-      const int cz = g.ncz >= 3 ? (iz + oz + g.ncz) % g.ncz : oz;
-      const int nc = (cy * g.ncx + cx) * g.ncz + cz;
-      const int s1 = scell[nc + 1];
-      for (int s = scell[nc]; s < s1; ++s) {
-        const double ddx = min_image(px - sx[s], g.Lx, g.invLx);
-        const double ddy = py - sy[s];
-        const double ddz = min_image(pz - sz[s], g.Lz, g.invLz);
-        const double r2 = dist2(ddx, ddy, ddz);
-        if (r2 <= rc2 && r2 > 0.0)
-          stokeslet_acc<T>((T)ddx, (T)ddy, (T)ddz, (T)r2, sf[s], sf[scap + s], sf[2 * scap + s],
-                           k, ux, uy, uz);
+      // pass 2: kernel evaluations only for in-range pairs, in source order
+      while (mask) {
+        const int j = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        double dx, dy, dz;
+        if (FAST) {
+          dx = px - lx[wave][j];
+          dy = py - ly[wave][j];
+          dz = pz - lz[wave][j];
+        } else {
+          dx = min_image(px - lx[wave][j], g.Lx, g.invLx);
+          dy = py - ly[wave][j];
+          dz = min_image(pz - lz[wave][j], g.Lz, g.invLz);
+        }
+        const double r2 = dist2(dx, dy, dz);
+        if (DL)
+          stresslet_acc<T>((T)dx, (T)dy, (T)dz, (T)r2, lf[wave][0][j], lf[wave][1][j],
+                           lf[wave][2][j], nx, ny, nz, k, ux, uy, uz);
+        else
+          stokeslet_acc<T>((T)dx, (T)dy, (T)dz, (T)r2, lf[wave][0][j], lf[wave][1][j],
+                           lf[wave][2][j], k, ux, uy, uz);
       }
     }
   }
-  // -1/(8 pi), times the 1/(Nx Nz) of the forward DFT: the wall planes are
-  // transformed in x, z only (the grid fields get that factor through the
-  // Chebyshev forward matrix)
-  const T s = (T)(-0.039788735772973833942 / ((double)Nx * (double)Nz));
-  wall[(size_t)(w * 3 + 0) * nplane + r] = s * ux;
-  wall[(size_t)(w * 3 + 1) * nplane + r] = s * uy;
-  wall[(size_t)(w * 3 + 2) * nplane + r] = s * uz;
+  part[wave][0][lane] = ux + k.selfc * sfx;
+  part[wave][1][lane] = uy + k.selfc * sfy;
+  part[wave][2][lane] = uz + k.selfc * sfz;
+  __syncthreads();
+  if (wave == 0 && active) {
+    T v[3];
+    for (int d = 0; d < 3; ++d) {
+      T acc = part[0][d][lane];
+      for (int w = 1; w < kNearWaves; ++w) acc += part[w][d][lane];
+      v[d] = (T)a.scale * acc;
+    }
+    T* out = (T*)a.out;
+    size_t o = (size_t)t;
+    if (a.nplane) {
+      const int r = a.tperm[t];
+      const int wall = r / a.nplane;
+      o = (size_t)wall * 3 * a.nplane + (r - wall * a.nplane);
+    }
+    out[o] = v[0];
+    out[a.ostride + o] = v[1];
+    out[2 * a.ostride + o] = v[2];
+  }
+}
+
+template <typename T, bool DL>
+static void launch_near_kernel(Plan& p, const NearArgs& a, unsigned grid) {
+  const bool fast = sizeof(T) == 4 && p.cg.ncx >= 3 && p.cg.ncz >= 3;
+  if (fast) near_field<T, DL, true><<<grid, 64 * kNearWaves, 0, p.stream>>>(a, make_kc<T>(p.p.alpha));
+  else near_field<T, DL, false><<<grid, 64 * kNearWaves, 0, p.stream>>>(a, make_kc<T>(p.p.alpha));
 }
 
 // Pressure gauge of the double layer: the k = 0 pressure at y = -H equals
@@ -293,53 +362,64 @@ __global__ void __launch_bounds__(256) gauge_final(int nblk, double scale, doubl
   if (threadIdx.x == 0) part[0] = red[0] * scale;
 }
 
-static NearArgs near_args(Plan& p) {
+static NearArgs near_args(Plan& p, const Binned& tg, void* out, size_t ostride) {
   NearArgs a;
   a.g = p.cg;
   a.rc2 = p.rc2;
-  a.item_start = p.tgt.item_start;
-  a.tcell = p.tgt.cell_start;
-  a.tx = p.tgt.x;
-  a.ty = p.tgt.y;
-  a.tz = p.tgt.z;
-  a.tn = p.tgt.s;
-  a.tcap = (size_t)p.p.max_tgt;
+  a.item_start = tg.item_start;
+  a.tcell = tg.cell_start;
+  a.tx = tg.x;
+  a.ty = tg.y;
+  a.tz = tg.z;
+  a.tn = tg.s;
+  a.tcap = ostride;
   a.scell = p.src.cell_start;
   a.sx = p.src.x;
   a.sy = p.src.y;
   a.sz = p.src.z;
   a.sf = p.src.s;
   a.scap = (size_t)p.p.max_src;
-  a.out = p.ul;
+  a.out = out;
+  a.ostride = ostride;
+  a.tperm = tg.perm;
+  a.nplane = 0;
+  a.scale = 0.039788735772973833942;  // 1/(8 pi)
   return a;
 }
 
-static unsigned near_grid(Plan& p, int nt) {
-  return (unsigned)((nt + kNearBlock - 1) / kNearBlock + p.cg.ncells);
-}
+static unsigned near_grid(Plan& p, int nt) { return (unsigned)((nt + 63) / 64 + p.cg.ncells); }
 
 template <typename T>
 hipError_t launch_near_sl(Plan& p, int nt) {
   if (nt <= 0) return hipSuccess;
-  near_field<T, false><<<near_grid(p, nt), kNearBlock, 0, p.stream>>>(near_args(p),
-                                                                      make_kc<T>(p.p.alpha));
+  NearArgs a = near_args(p, *p.tview, p.ul, (size_t)p.p.max_tgt);
+  a.tcap = (size_t)p.p.max_tgt;
+  launch_near_kernel<T, false>(p, a, near_grid(p, nt));
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_near_dl(Plan& p, int nt) {
   if (nt <= 0) return hipSuccess;
-  near_field<T, true><<<near_grid(p, nt), kNearBlock, 0, p.stream>>>(near_args(p),
-                                                                     make_kc<T>(p.p.alpha));
+  NearArgs a = near_args(p, *p.tview, p.ul, (size_t)p.p.max_tgt);
+  a.tn = p.tnrm;
+  a.tcap = (size_t)p.p.max_tgt;
+  launch_near_kernel<T, true>(p, a, near_grid(p, nt));
   return hipGetLastError();
 }
 
+// Wall data of the global problem: u^g = -u^l at the wall nodes (Sec. 3.2.2),
+// the local sum evaluated at the nodes of y = -H and y = +H (a target set
+// binned once per plan), written as -u^l/(Nx Nz) into [wall][component][x][z]:
+// the wall planes are transformed in x, z only, while the grid fields get the
+// 1/(Nx Nz) of the forward DFT through the Chebyshev forward matrix.
 template <typename T>
 hipError_t launch_wall(Plan& p) {
-  const int n = 2 * p.p.Nx * p.p.Nz;
-  wall_velocity<T><<<(n + 255) / 256, 256, 0, p.stream>>>(
-      p.cg, p.rc2, p.p.Nx, p.p.Nz, p.dx, p.dz, p.src.cell_start, p.src.x, p.src.y, p.src.z,
-      (const T*)p.src.s, (size_t)p.p.max_src, make_kc<T>(p.p.alpha), (T*)p.wall_phys);
+  const int nplane = p.p.Nx * p.p.Nz;
+  NearArgs a = near_args(p, p.wall, p.wall_phys, (size_t)nplane);
+  a.nplane = nplane;
+  a.scale = -0.039788735772973833942 / ((double)p.p.Nx * (double)p.p.Nz);
+  launch_near_kernel<T, false>(p, a, near_grid(p, 2 * nplane));
   return hipGetLastError();
 }
 

@@ -21,7 +21,7 @@ __device__ inline double dist2_s(double dx, double dy, double dz) {
 }
 
 __device__ inline double t_exp_s(double v) { return exp(v); }
-__device__ inline float t_exp_s(float v) { return expf(v); }
+__device__ inline float t_exp_s(float v) { return __builtin_amdgcn_exp2f(1.44269504088896341f * v); }
 
 // distance from v to the interval [lo, hi] along a periodic axis
 __device__ inline double box_gap_periodic(double v, double lo, double hi, double L, double invL) {
@@ -42,12 +42,29 @@ struct SpreadArgs {
   void* out;           // (3, Ny, Nx, Nz) T
 };
 
+// Tile of TJ (y) x TI (x) x TK (z) nodes, one node per thread.
 constexpr int TJ = 4, TI = 8, TK = 8, TB = TJ * TI * TK;
 
 template <typename T>
+struct V4;
+template <>
+struct V4<double> {
+  using t = double4;
+};
+template <>
+struct V4<float> {
+  using t = float4;
+};
+
+// REL: sources staged relative to the tile corner in T (mixed mode: the
+// displacement is formed once per source in FP64, the pair test in FP32);
+// otherwise every pair displacement is formed in FP64 with the minimum image.
+template <typename T, bool REL>
 __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
-  __shared__ double lx[TB], ly[TB], lz[TB];
-  __shared__ T lf[3][TB];
+  using Q = typename V4<T>::t;
+  __shared__ double lx[REL ? 1 : TB], ly[REL ? 1 : TB], lz[REL ? 1 : TB];
+  __shared__ Q lr[REL ? TB : 1];
+  __shared__ Q lf[TB];
   __shared__ int wave_cnt[TB / 64];
   const CellGeom& g = a.g;
   const int tid = threadIdx.x;
@@ -65,6 +82,9 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
   const double px = valid ? i * a.dx : 0.0;
   const double pz = valid ? k * a.dz : 0.0;
   const double py = valid ? a.y[j] : 0.0;
+  // node relative to the tile corner
+  const T nrx = (T)(px - bx0), nry = (T)(py - by0), nrz = (T)(pz - bz0);
+  const T rc2t = (T)a.rc2;
   const double eps = 1e-9 * (g.Lx + g.Lz);
   // cell ranges (unwrapped in x, z; clamped in y)
   int cx0 = (int)floor((bx0 - a.rc - eps) * g.icx), cx1 = (int)floor((bx1 + a.rc + eps) * g.icx);
@@ -109,27 +129,48 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
           for (int w = 0; w < TB / 64; ++w) total += wave_cnt[w];
           if (keep) {
             const int slot = off + __popcll(m & lt);
-            lx[slot] = qx;
-            ly[slot] = qy;
-            lz[slot] = qz;
-            lf[0][slot] = sf[si];
-            lf[1][slot] = sf[a.scap + si];
-            lf[2][slot] = sf[2 * a.scap + si];
+            if (REL) {
+              Q r;
+              r.x = (T)min_image_s(qx - bx0, g.Lx, g.invLx);
+              r.y = (T)(qy - by0);
+              r.z = (T)min_image_s(qz - bz0, g.Lz, g.invLz);
+              r.w = (T)0;
+              lr[slot] = r;
+            } else {
+              lx[slot] = qx;
+              ly[slot] = qy;
+              lz[slot] = qz;
+            }
+            Q f;
+            f.x = sf[si];
+            f.y = sf[a.scap + si];
+            f.z = sf[2 * a.scap + si];
+            f.w = (T)0;
+            lf[slot] = f;
           }
           __syncthreads();
           if (valid) {
             for (int s = 0; s < total; ++s) {
-              const double dx = min_image_s(px - lx[s], g.Lx, g.invLx);
-              const double dy = py - ly[s];
-              const double dz = min_image_s(pz - lz[s], g.Lz, g.invLz);
-              const double r2 = dist2_s(dx, dy, dz);
-              if (r2 <= a.rc2) {
-                const T ar = a2 * (T)r2;
-                const T w = t_exp_s(-ar) * ((T)2.5 - ar);
-                fx += w * lf[0][s];
-                fy += w * lf[1][s];
-                fz += w * lf[2][s];
+              T r2;
+              if (REL) {
+                const Q q = lr[s];
+                const T dx = nrx - q.x, dy = nry - q.y, dz = nrz - q.z;
+                r2 = dx * dx + dy * dy + dz * dz;
+                if (!(r2 <= rc2t)) continue;
+              } else {
+                const double dx = min_image_s(px - lx[s], g.Lx, g.invLx);
+                const double dy = py - ly[s];
+                const double dz = min_image_s(pz - lz[s], g.Lz, g.invLz);
+                const double d2 = dist2_s(dx, dy, dz);
+                if (!(d2 <= a.rc2)) continue;
+                r2 = (T)d2;
               }
+              const T ar = a2 * r2;
+              const T w = t_exp_s(-ar) * ((T)2.5 - ar);
+              const Q f = lf[s];
+              fx += w * f.x;
+              fy += w * f.y;
+              fz += w * f.z;
             }
           }
         }
@@ -167,7 +208,10 @@ hipError_t launch_spread(Plan& p, int /*unused*/) {
   a.scap = (size_t)p.p.max_src;
   a.out = p.phys;
   dim3 grid((p.p.Nz + TK - 1) / TK, (p.p.Nx + TI - 1) / TI, (p.p.Ny + TJ - 1) / TJ);
-  spread_tile<T><<<grid, TB, 0, p.stream>>>(a);
+  // tile-relative staging needs one periodic image per (tile, source) pair
+  const bool rel = sizeof(T) == 4 && TI * p.dx + p.rc < 0.5 * p.p.Lx && TK * p.dz + p.rc < 0.5 * p.p.Lz;
+  if (rel) spread_tile<T, true><<<grid, TB, 0, p.stream>>>(a);
+  else spread_tile<T, false><<<grid, TB, 0, p.stream>>>(a);
   return hipGetLastError();
 }
 

@@ -2,142 +2,64 @@
 //
 // For mode (k_x, k_z), lam = k_x^2 + k_z^2, with F the Chebyshev
 // coefficients of the global force density (momentum: -grad p + lap u + F = 0)
-// and g-, g+ the wall velocities (u^g = -u^l at y = -H, +H):
-//   p'' - lam p = i k_x F_x + F_y' + i k_z F_z,   p(-H) = p1, p(+H) = p2
-//   u'' - lam u = i k_x p - F_x   (v: p' - F_y,  w: i k_z p - F_z)
-// and p1, p2 make the velocity divergence-free at both walls (the influence
-// matrix of Eq. inf_mat).  The 2x2 influence matrix depends only on lam and
-// is inverted once per plan; u, w meet their wall values exactly, so the
-// wall divergence of problem (a) needs only the v solve.  The final fields
-// are obtained by solving again with the wall pressures p1, p2 (the same
-// superposition as Eq. cheb_sol).
+// and g-, g+ the wall velocities (u^g = -u^l at y = -H, +H), the influence
+// matrix method solves
+//   (a) p_a'' - lam p_a = i k_x F_x + F_y' + i k_z F_z,  p_a(+-H) = 0,
+//       u_a'' - lam u_a = i k_x p_a - F_x, u_a(+-H) = g_x+-  (v_a: p_a' - F_y,
+//       w_a: i k_z p_a - F_z),
+//   (b), (c) the same with no forcing, no-slip, and p = 1 at y = -H resp. +H,
+// and superposes u = u_a + p1 u_b + p2 u_c (Eq. cheb_sol) with p1, p2 chosen
+// so that the velocity is divergence-free at both walls (Eq. inf_mat).
+// (b) and (c) depend only on lam and are solved once per plan; (c) is the
+// mirror image of (b) (coefficients times (-1)^n, v also changes sign).  u_b
+// and w_b are i k_x and i k_z times one real profile; u and w meet their wall
+// values exactly, so the wall divergence needs only v'.
 //
 // Each Helmholtz problem is the tau system: rows 0..N-2 of
-// (D^2/H^2 - lam) a = r plus the two wall rows.  Substituting the Chebyshev
-// recurrence that expresses a_n (n >= 2) through the coefficients of a''
-// turns it into two tridiagonal systems (even and odd n) bordered by one full
-// row each (the wall conditions); each is solved by a backward sweep that
-// writes a_n = P_n + Q_n a_{0|1} and one full-row solve, O(N) per problem.
+// (D^2/H^2 - lam) a = r plus the two wall rows.  The Chebyshev recurrence
+// that expresses a_n (n >= 2) through the coefficients of a'' splits it into
+// two independent tridiagonal systems (even and odd n), each bordered by one
+// full row (the wall value of that parity).  Writing a_n = P_n + Q_n a_{0|1},
+// a backward sweep gives P and the full row gives a_{0|1}; the lam-only
+// factors (1/pivot, multiplier, Q and its sum) are computed once per plan.
 //
-// One thread per mode; per-mode work arrays live in a strided scratch buffer
-// so that a wave's accesses are coalesced.
+// Kernels of one evaluation:
+//   A  one thread per (mode, parity): p_a
+//   B  one thread per (mode, parity, component): u_a, v_a, w_a and the
+//      parity's share of the wall slopes of v_a
+//   D  one thread per (mode, n): p1, p2, superposition, output (and, for the
+//      double layer, the stress components that need no y-derivative)
+//   E  double layer: one thread per (mode, component) for the stress
+//      components with a y-derivative.
+// Vectors are stored [n][mode] so a wave's accesses are coalesced.
 #include "ggem_internal.h"
 
 namespace ggem {
-
-struct Col {
-  double2* p;
-  size_t s;
-  __device__ double2& operator[](int n) const { return p[(size_t)n * s]; }
-};
-
-struct RCol {
-  double* p;
-  size_t s;
-  __device__ double& operator[](int n) const { return p[(size_t)n * s]; }
-};
 
 __device__ inline double2 z2(double a, double b) { return make_double2(a, b); }
 __device__ inline double2 zadd(double2 a, double2 b) { return z2(a.x + b.x, a.y + b.y); }
 __device__ inline double2 zsub(double2 a, double2 b) { return z2(a.x - b.x, a.y - b.y); }
 __device__ inline double2 zscale(double s, double2 a) { return z2(s * a.x, s * a.y); }
+__device__ inline double2 zfma(double s, double2 a, double2 b) {
+  return z2(fma(s, a.x, b.x), fma(s, a.y, b.y));
+}
 __device__ inline double2 zi(double k, double2 a) { return z2(-k * a.y, k * a.x); }  // i k a
-
-// Tau solution of a'' - lam a = r on [-H, H] with a(-H) = gm, a(+H) = gp.
-// r and out must not alias; beta is real scratch.
-__device__ void hel_tau(int N, double lam, double H, Col r, double2 gm, double2 gp, Col out,
-                        RCol beta) {
-  const double h2 = H * H;
-  const double h2l = h2 * lam;
-  for (int par = 0; par < 2; ++par) {
-    const int M = (N - par) / 2;
-    double2 an = z2(0, 0);
-    double bn = 0.0;
-    for (int i = M; i >= 1; --i) {
-      const int n = par + 2 * i;
-      const double cm2 = (n == 2) ? 2.0 : 1.0;
-      const double q1 = 1.0 / (4.0 * n * (n - 1));
-      const double q2 = 1.0 / (2.0 * ((double)n * n - 1.0));
-      const double q3 = 1.0 / (4.0 * n * (n + 1));
-      const bool en = n <= N - 2, ep = n + 2 <= N - 2;
-      const double l = -h2l * cm2 * q1;
-      const double d = 1.0 + (en ? h2l * q2 : 0.0);
-      const double u = ep ? -h2l * q3 : 0.0;
-      double2 s = zscale(cm2 * q1, r[n - 2]);
-      if (en) s = zsub(s, zscale(q2, r[n]));
-      if (ep) s = zadd(s, zscale(q3, r[n + 2]));
-      s = zscale(h2, s);
-      const double den = d + u * bn;
-      const double inv = 1.0 / den;
-      const double bi = -l * inv;
-      const double2 ai = zscale(inv, zsub(s, zscale(u, an)));
-      out[n] = ai;
-      beta[n] = bi;
-      an = ai;
-      bn = bi;
-    }
-    double2 P = z2(0, 0), SP = z2(0, 0);
-    double Q = 1.0, SQ = 1.0;
-    for (int i = 1; i <= M; ++i) {
-      const int n = par + 2 * i;
-      const double b = beta[n];
-      P = zadd(out[n], zscale(b, P));
-      Q = b * Q;
-      out[n] = P;
-      beta[n] = Q;
-      SP = zadd(SP, P);
-      SQ += Q;
-    }
-    const double2 g = par == 0 ? zscale(0.5, zadd(gp, gm)) : zscale(0.5, zsub(gp, gm));
-    const double2 x0 = zscale(1.0 / SQ, zsub(g, SP));
-    out[par] = x0;
-    for (int i = 1; i <= M; ++i) {
-      const int n = par + 2 * i;
-      out[n] = zadd(out[n], zscale(beta[n], x0));
-    }
-  }
-}
-
-// b = d/d(ybar) a on coefficients: c_n b_n = b_{n+2} + 2 (n+1) a_{n+1}.
-__device__ void cheb_deriv(int N, Col a, Col b) {
-  double2 b2 = z2(0, 0), b1 = z2(0, 0);
-  b[N] = b1;
-  for (int n = N - 1; n >= 0; --n) {
-    double2 v = zadd(b2, zscale(2.0 * (n + 1), a[n + 1]));
-    if (n == 0) v = zscale(0.5, v);
-    b[n] = v;
-    b2 = b1;
-    b1 = v;
-  }
-}
-
-// wall slopes: a'(-1) = sum (-1)^(n+1) n^2 a_n, a'(+1) = sum n^2 a_n
-__device__ inline void wall_slopes(int N, Col a, double2& dm, double2& dp) {
-  dm = z2(0, 0);
-  dp = z2(0, 0);
-  for (int n = 1; n <= N; ++n) {
-    const double w = (double)n * n;
-    const double2 v = zscale(w, a[n]);
-    dp = zadd(dp, v);
-    dm = (n & 1) ? zadd(dm, v) : zsub(dm, v);
-  }
-}
 
 struct TauArgs {
   int N, Nx, Nz, Nzh, nmodes;
   double H, Lx, Lz;
-  const double* infl;
-  const void* in;      // [3][Ny][nmodes] complex T
-  const void* wall;    // [2][3][nmodes] complex T
-  void* out;           // [3|6][Ny][nmodes] complex T
-  double2* scr;        // [6][Ny][nmodes] complex + [Ny][nmodes] real
+  const double* nconst;  // per n: 1/(4n(n-1)), 1/(2(n^2-1)), 1/(4n(n+1))  [3][Ny]
+  double* pre;           // per mode: [1/pivot, multiplier, Q][Ny], sum Q [2], [p_b, u_b, v_b][Ny]
+  double* infl;          // per mode: 2x2 inverse influence matrix (4 doubles)
+  const void* in;        // [3][Ny][nmodes] complex T
+  const void* wall;      // [2][3][nmodes] complex T
+  void* out;             // [3|6][Ny][nmodes] complex T
+  double2* scr;          // [8][Ny][nmodes] complex + wall slopes [2][2][nmodes]
   const double* gauge;
 };
 
-template <typename C>
-__device__ inline double2 to_z(C v) {
-  return z2((double)v.x, (double)v.y);
-}
+// scratch slots
+enum { kPA = 0, kUA = 1, kVA = 2, kWA = 3, kU = 4, kV = 5, kW = 6, kP = 7, kSlope = 8 };
 
 template <typename T>
 struct CT;
@@ -149,7 +71,10 @@ template <>
 struct CT<float> {
   using t = float2;
 };
-
+template <typename C>
+__device__ inline double2 to_z(C v) {
+  return z2((double)v.x, (double)v.y);
+}
 template <typename T>
 __device__ inline typename CT<T>::t from_z(double2 v) {
   typename CT<T>::t r;
@@ -158,169 +83,390 @@ __device__ inline typename CT<T>::t from_z(double2 v) {
   return r;
 }
 
-__device__ inline void mode_k(const TauArgs& a, int q, int& l, int& m, double& kx, double& kz) {
-  l = q / a.Nzh;
-  m = q - l * a.Nzh;
-  const int ls = l < a.Nx / 2 ? l : l - a.Nx;
-  kx = 6.283185307179586477 * ls / a.Lx;
-  kz = 6.283185307179586477 * m / a.Lz;
+struct Mode {
+  int q, l, m;
+  double kx, kz, lam;
+  bool nyquist;
+};
+
+__device__ inline Mode mode_of(const TauArgs& a, int q) {
+  Mode md;
+  md.q = q;
+  md.l = q / a.Nzh;
+  md.m = q - md.l * a.Nzh;
+  const int ls = md.l < a.Nx / 2 ? md.l : md.l - a.Nx;
+  md.kx = 6.283185307179586477 * ls / a.Lx;
+  md.kz = 6.283185307179586477 * md.m / a.Lz;
+  md.lam = md.kx * md.kx + md.kz * md.kz;
+  md.nyquist = md.l == a.Nx / 2 || md.m == a.Nz / 2;
+  return md;
 }
 
-template <typename T, bool STRESS>
-__global__ void __launch_bounds__(64) tau_modes(TauArgs a) {
+struct Sweep {
+  int N;
+  double h2, h2l;
+  const double* nc;
+  const double* pre;  // this mode's factor column (stride S)
+  size_t S, NyS;
+};
+
+__device__ inline Sweep make_sweep(const TauArgs& a, int q, double lam) {
+  Sweep w;
+  w.N = a.N;
+  w.h2 = a.H * a.H;
+  w.h2l = w.h2 * lam;
+  w.nc = a.nconst;
+  w.S = (size_t)a.nmodes;
+  w.NyS = (size_t)(a.N + 1) * w.S;
+  w.pre = a.pre + q;
+  return w;
+}
+
+// Tau Helmholtz solve restricted to the coefficients n = par, par+2, ...:
+// on entry lds[i] (stride 64) holds r(par + 2i) for par + 2i <= N-2; g is the
+// parity's share of the wall values ((g+ + g-)/2 even, (g+ - g-)/2 odd);
+// dst(n, a_n) receives the solution.
+template <class DST>
+__device__ inline void hel_par(const Sweep& w, int par, double2* lds, double2 g, DST dst) {
+  const int N = w.N;
+  const int M = (N - par) / 2;
+  const int Nc = N + 1;
+  // row right-hand sides s_i = h2 (c_{n-2} q1 r_{n-2} - q2 r_n + q3 r_{n+2}), in place
+  double2 rprev = lds[0];
+  for (int i = 1; i <= M; ++i) {
+    const int n = par + 2 * i;
+    const double2 ri = (n <= N - 2) ? lds[i * 64] : z2(0, 0);
+    const double2 rn = (n + 2 <= N - 2) ? lds[(i + 1) * 64] : z2(0, 0);
+    double2 s = zscale((n == 2 ? 2.0 : 1.0) * w.nc[n], rprev);
+    s = zfma(-w.nc[Nc + n], ri, s);
+    s = zfma(w.nc[2 * Nc + n], rn, s);
+    lds[i * 64] = zscale(w.h2, s);
+    rprev = ri;
+  }
+  // backward: alpha_i = (s_i - u_i alpha_{i+1}) / pivot_i
+  double2 an = z2(0, 0);
+#pragma unroll 4
+  for (int i = M; i >= 1; --i) {
+    const int n = par + 2 * i;
+    const double u = (n + 2 <= N - 2) ? -w.h2l * w.nc[2 * Nc + n] : 0.0;
+    an = zscale(w.pre[(size_t)n * w.S], zfma(-u, an, lds[i * 64]));
+    lds[i * 64] = an;
+  }
+  // forward: P_i = alpha_i + beta_i P_{i-1}
+  double2 P = z2(0, 0), SP = z2(0, 0);
+#pragma unroll 4
+  for (int i = 1; i <= M; ++i) {
+    const int n = par + 2 * i;
+    P = zfma(w.pre[w.NyS + (size_t)n * w.S], P, lds[i * 64]);
+    lds[i * 64] = P;
+    SP = zadd(SP, P);
+  }
+  const double2 x0 = zscale(1.0 / w.pre[3 * w.NyS + par * w.S], zsub(g, SP));
+  dst(par, x0);
+#pragma unroll 4
+  for (int i = 1; i <= M; ++i) {
+    const int n = par + 2 * i;
+    dst(n, zfma(w.pre[2 * w.NyS + (size_t)n * w.S], x0, lds[i * 64]));
+  }
+}
+
+// Fill lds[i] = rhs(m, D_m) for m = par + 2i <= N-2, descending, where D_m is
+// the y-derivative coefficient (d/dybar) of the vector `a` at index m:
+// c_m D_m = 2 sum_{p > m, p + m odd} p a_p.
+template <class SRC, class RHS>
+__device__ inline void fill_rhs_deriv(int N, int par, double2* lds, SRC a, RHS rhs) {
+  int mt = N - 2;
+  if ((mt & 1) != par) --mt;
+  double2 S = z2(0, 0);
+  // contributions of p > mt + 1 of the opposite parity
+  for (int p = N - ((N & 1) == par ? 1 : 0); p > mt + 1; p -= 2) S = zfma((double)p, a(p), S);
+  for (int m = mt; m >= par; m -= 2) {
+    S = zfma((double)(m + 1), a(m + 1), S);
+    const double2 D = zscale(m == 0 ? 1.0 : 2.0, S);
+    lds[((m - par) / 2) * 64] = rhs(m, D);
+  }
+}
+
+template <class RHS>
+__device__ inline void fill_rhs(int N, int par, double2* lds, RHS rhs) {
+  for (int m = par; m <= N - 2; m += 2) lds[((m - par) / 2) * 64] = rhs(m);
+}
+
+// ---- A: p_a, one thread per (mode, parity) ---------------------------------
+template <typename T>
+__global__ void __launch_bounds__(64) tau_pressure(TauArgs a) {
   using C = typename CT<T>::t;
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  extern __shared__ double2 tau_lds[];
+  const int q = blockIdx.x * 64 + threadIdx.x;
+  const int par = blockIdx.y;
   if (q >= a.nmodes) return;
+  const Mode md = mode_of(a, q);
+  if (md.nyquist) return;
   const int N = a.N, Ny = N + 1;
   const size_t S = (size_t)a.nmodes;
-  int l, m;
-  double kx, kz;
-  mode_k(a, q, l, m, kx, kz);
-  const int nout = STRESS ? 6 : 3;
-  C* out = (C*)a.out;
-  if (l == a.Nx / 2 || m == a.Nz / 2) {
-    C zero;
-    zero.x = (T)0;
-    zero.y = (T)0;
-    for (int f = 0; f < nout; ++f)
-      for (int n = 0; n < Ny; ++n) out[((size_t)f * Ny + n) * S + q] = zero;
+  const C* in = (const C*)a.in;
+  auto F = [&](int c, int n) { return to_z(in[((size_t)c * Ny + n) * S + q]); };
+  double2* PA = a.scr + (size_t)kPA * Ny * S + q;
+  if (q == 0) {
+    // k = 0: p' = F_y (rows 0..N-1) with p(-H) = gauge; integrate b = H F_y:
+    // 2n p_n = c_{n-1} b_{n-1} - b_{n+1}.  Written by the even-parity thread.
+    if (par) return;
+    double2 s = z2(0, 0);
+    for (int n = 1; n <= N; ++n) {
+      const double2 bm = zscale(a.H * (n == 1 ? 2.0 : 1.0), F(1, n - 1));
+      const double2 bp = (n + 1 <= N - 1) ? zscale(a.H, F(1, n + 1)) : z2(0, 0);
+      const double2 pn = zscale(1.0 / (2.0 * n), zsub(bm, bp));
+      PA[(size_t)n * S] = pn;
+      s = (n & 1) ? zsub(s, pn) : zadd(s, pn);
+    }
+    PA[0] = zsub(z2(a.gauge[0], 0.0), s);
     return;
   }
-  const double lam = kx * kx + kz * kz;
-  const double H = a.H;
+  double2* lds = tau_lds + threadIdx.x;
+  const double iH = 1.0 / a.H;
+  fill_rhs_deriv(N, par, lds, [&](int p) { return F(1, p); }, [&](int m, double2 dfy) {
+    return zadd(zadd(zi(md.kx, F(0, m)), zscale(iH, dfy)), zi(md.kz, F(2, m)));
+  });
+  hel_par(make_sweep(a, q, md.lam), par, lds, z2(0, 0),
+          [&](int n, double2 v) { PA[(size_t)n * S] = v; });
+}
+
+// ---- B: u_a, v_a, w_a, one thread per (mode, parity, component) -----------
+template <typename T>
+__global__ void __launch_bounds__(64) tau_velocity(TauArgs a) {
+  using C = typename CT<T>::t;
+  extern __shared__ double2 tau_lds[];
+  const int q = blockIdx.x * 64 + threadIdx.x;
+  const int par = blockIdx.y, comp = blockIdx.z;
+  if (q >= a.nmodes) return;
+  const Mode md = mode_of(a, q);
+  if (md.nyquist) return;
+  const int N = a.N, Ny = N + 1;
+  const size_t S = (size_t)a.nmodes;
   const C* in = (const C*)a.in;
   const C* wall = (const C*)a.wall;
-  const size_t FS = (size_t)Ny * S;
-  Col R{a.scr + 0 * FS + q, S}, P{a.scr + 1 * FS + q, S}, U{a.scr + 2 * FS + q, S},
-      V{a.scr + 3 * FS + q, S}, W{a.scr + 4 * FS + q, S}, X{a.scr + 5 * FS + q, S};
-  RCol B{(double*)(a.scr + 6 * FS) + q, S};
-  for (int n = 0; n < Ny; ++n) {
-    U[n] = to_z(in[(0 * (size_t)Ny + n) * S + q]);
-    V[n] = to_z(in[(1 * (size_t)Ny + n) * S + q]);
-    W[n] = to_z(in[(2 * (size_t)Ny + n) * S + q]);
-  }
-  const double2 gxm = to_z(wall[0 * S + q]), gym = to_z(wall[1 * S + q]),
-                gzm = to_z(wall[2 * S + q]);
-  const double2 gxp = to_z(wall[3 * S + q]), gyp = to_z(wall[4 * S + q]),
-                gzp = to_z(wall[5 * S + q]);
-  const double iH = 1.0 / H;
-  if (q == 0) {
-    // k = 0: u'' = -F_x, w'' = -F_z, v'' = 0 between the wall values;
-    // p' = F_y (rows 0..N-1), p(-H) = gauge.
-    for (int n = 0; n < Ny; ++n) R[n] = zscale(-1.0, U[n]);
-    hel_tau(N, 0.0, H, R, gxm, gxp, X, B);
-    for (int n = 0; n < Ny; ++n) U[n] = X[n];
-    for (int n = 0; n < Ny; ++n) R[n] = zscale(-1.0, W[n]);
-    hel_tau(N, 0.0, H, R, gzm, gzp, X, B);
-    for (int n = 0; n < Ny; ++n) W[n] = X[n];
-    if (STRESS) {
-      // integrate b = H F_y: 2n p_n = c_{n-1} b_{n-1} - b_{n+1}
-      for (int n = 1; n <= N; ++n) {
-        const double2 bm = zscale(H * (n - 1 == 0 ? 2.0 : 1.0), V[n - 1]);
-        const double2 bp = (n + 1 <= N - 1) ? zscale(H, V[n + 1]) : z2(0, 0);
-        P[n] = zscale(1.0 / (2.0 * n), zsub(bm, bp));
-      }
-      double2 s = z2(0, 0);
-      for (int n = 1; n <= N; ++n) s = (n & 1) ? zsub(s, P[n]) : zadd(s, P[n]);
-      P[0] = zsub(z2(a.gauge[0], 0.0), s);
-    }
-    for (int n = 0; n < Ny; ++n) R[n] = z2(0, 0);
-    hel_tau(N, 0.0, H, R, gym, gyp, V, B);
+  auto F = [&](int c, int n) { return to_z(in[((size_t)c * Ny + n) * S + q]); };
+  const double2* PA = a.scr + (size_t)kPA * Ny * S + q;
+  double2* dst = a.scr + (size_t)(kUA + comp) * Ny * S + q;
+  const double2 gm = to_z(wall[(size_t)comp * S + q]);
+  const double2 gp = to_z(wall[(size_t)(3 + comp) * S + q]);
+  const double2 g = par == 0 ? zscale(0.5, zadd(gp, gm)) : zscale(0.5, zsub(gp, gm));
+  double2* lds = tau_lds + threadIdx.x;
+  const double iH = 1.0 / a.H;
+  const bool zero = q == 0;  // k = 0: no pressure coupling, v'' = 0
+  if (comp == 1) {
+    if (zero) fill_rhs(N, par, lds, [](int) { return z2(0, 0); });
+    else
+      fill_rhs_deriv(N, par, lds, [&](int p) { return PA[(size_t)p * S]; },
+                     [&](int m, double2 dp) { return zsub(zscale(iH, dp), F(1, m)); });
+    double2 dm = z2(0, 0), dpl = z2(0, 0);
+    hel_par(make_sweep(a, q, md.lam), par, lds, g, [&](int n, double2 v) {
+      dst[(size_t)n * S] = v;
+      const double2 t = zscale((double)n * n, v);
+      dpl = zadd(dpl, t);
+      dm = (n & 1) ? zadd(dm, t) : zsub(dm, t);
+    });
+    double2* sl = a.scr + (size_t)kSlope * Ny * S + q;
+    sl[(size_t)(2 * par) * S] = dm;
+    sl[(size_t)(2 * par + 1) * S] = dpl;
   } else {
-    // (a): pressure with zero wall values, then v for the wall divergence
-    cheb_deriv(N, V, X);
-    for (int n = 0; n < Ny; ++n) R[n] = zadd(zadd(zi(kx, U[n]), zscale(iH, X[n])), zi(kz, W[n]));
-    hel_tau(N, lam, H, R, z2(0, 0), z2(0, 0), P, B);
-    cheb_deriv(N, P, X);
-    for (int n = 0; n < Ny; ++n) R[n] = zsub(zscale(iH, X[n]), V[n]);
-    hel_tau(N, lam, H, R, gym, gyp, X, B);
-    double2 dm, dp;
-    wall_slopes(N, X, dm, dp);
-    const double2 cam = zadd(zadd(zi(kx, gxm), zscale(iH, dm)), zi(kz, gzm));
-    const double2 cap = zadd(zadd(zi(kx, gxp), zscale(iH, dp)), zi(kz, gzp));
+    const double k = comp == 0 ? md.kx : md.kz;
+    if (zero) fill_rhs(N, par, lds, [&](int m) { return zscale(-1.0, F(comp, m)); });
+    else
+      fill_rhs(N, par, lds,
+               [&](int m) { return zsub(zi(k, PA[(size_t)m * S]), F(comp, m)); });
+    hel_par(make_sweep(a, q, md.lam), par, lds, g,
+            [&](int n, double2 v) { dst[(size_t)n * S] = v; });
+  }
+}
+
+// ---- D: wall pressures and superposition, one thread per (mode, n) --------
+template <typename T, bool STRESS>
+__global__ void __launch_bounds__(256) tau_combine(TauArgs a) {
+  using C = typename CT<T>::t;
+  const size_t S = (size_t)a.nmodes;
+  const int Ny = a.N + 1;
+  const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (size_t)Ny * S) return;
+  const int n = (int)(idx / S);
+  const int q = (int)(idx - (size_t)n * S);
+  const Mode md = mode_of(a, q);
+  C* out = (C*)a.out;
+  auto put = [&](int f, double2 v) { out[((size_t)f * Ny + n) * S + q] = from_z<T>(v); };
+  if (md.nyquist) {
+    for (int f = 0; f < (STRESS ? 6 : 3); ++f) put(f, z2(0, 0));
+    return;
+  }
+  const double2* scr = a.scr + q;
+  auto at = [&](int slot) { return scr[((size_t)slot * Ny + n) * S]; };
+  double2 u = at(kUA), v = at(kVA), w = at(kWA), p = at(kPA);
+  if (q != 0) {
+    const C* wall = (const C*)a.wall;
+    const double2* sl = scr + (size_t)kSlope * Ny * S;
+    const double iH = 1.0 / a.H;
+    const double2 dm = zadd(sl[0], sl[2 * S]), dp = zadd(sl[S], sl[3 * S]);
+    const double2 cam = zadd(zadd(zi(md.kx, to_z(wall[q])), zscale(iH, dm)),
+                             zi(md.kz, to_z(wall[2 * S + q])));
+    const double2 cap = zadd(zadd(zi(md.kx, to_z(wall[3 * S + q])), zscale(iH, dp)),
+                             zi(md.kz, to_z(wall[5 * S + q])));
     const double* mi = a.infl + 4 * (size_t)q;
     const double2 p1 = zscale(-1.0, zadd(zscale(mi[0], cam), zscale(mi[1], cap)));
     const double2 p2 = zscale(-1.0, zadd(zscale(mi[2], cam), zscale(mi[3], cap)));
-    // final pressure with wall values p1 (y = -H), p2 (y = +H)
-    cheb_deriv(N, V, X);
-    for (int n = 0; n < Ny; ++n) R[n] = zadd(zadd(zi(kx, U[n]), zscale(iH, X[n])), zi(kz, W[n]));
-    hel_tau(N, lam, H, R, p1, p2, P, B);
-    // velocities
-    for (int n = 0; n < Ny; ++n) R[n] = zsub(zi(kx, P[n]), U[n]);
-    hel_tau(N, lam, H, R, gxm, gxp, U, B);
-    for (int n = 0; n < Ny; ++n) R[n] = zsub(zi(kz, P[n]), W[n]);
-    hel_tau(N, lam, H, R, gzm, gzp, W, B);
-    cheb_deriv(N, P, X);
-    for (int n = 0; n < Ny; ++n) R[n] = zsub(zscale(iH, X[n]), V[n]);
-    hel_tau(N, lam, H, R, gym, gyp, V, B);
+    // (c) mirrors (b): coefficient n times (-1)^n, v also changes sign
+    const double sg = (n & 1) ? -1.0 : 1.0;
+    const double2 ps = zfma(sg, p2, p1), pd = zfma(-sg, p2, p1);
+    const size_t NyS = (size_t)Ny * S;
+    const double pb = a.pre[3 * NyS + 2 * S + (size_t)n * S + q];
+    const double ub = a.pre[4 * NyS + 2 * S + (size_t)n * S + q];
+    const double vb = a.pre[5 * NyS + 2 * S + (size_t)n * S + q];
+    u = zadd(u, zi(md.kx, zscale(ub, ps)));
+    w = zadd(w, zi(md.kz, zscale(ub, ps)));
+    v = zfma(vb, pd, v);
+    p = zfma(pb, ps, p);
   }
   if (!STRESS) {
-    for (int n = 0; n < Ny; ++n) {
-      out[((size_t)0 * Ny + n) * S + q] = from_z<T>(U[n]);
-      out[((size_t)1 * Ny + n) * S + q] = from_z<T>(V[n]);
-      out[((size_t)2 * Ny + n) * S + q] = from_z<T>(W[n]);
+    put(0, u);
+    put(1, v);
+    put(2, w);
+    return;
+  }
+  double2* o = a.scr + q;
+  o[((size_t)kU * Ny + n) * S] = u;
+  o[((size_t)kV * Ny + n) * S] = v;
+  o[((size_t)kW * Ny + n) * S] = w;
+  o[((size_t)kP * Ny + n) * S] = p;
+  // sigma = -p I + grad u + grad u^T: xx, yy, zz, xy, xz, yz
+  const double2 mp = zscale(-1.0, p);
+  put(0, zadd(mp, zscale(2.0, zi(md.kx, u))));
+  put(2, zadd(mp, zscale(2.0, zi(md.kz, w))));
+  put(4, zadd(zi(md.kz, u), zi(md.kx, w)));
+}
+
+// ---- E: stress components with a y-derivative, per (mode, component) -------
+template <typename T>
+__global__ void __launch_bounds__(64) tau_stress_dy(TauArgs a) {
+  using C = typename CT<T>::t;
+  const int q = blockIdx.x * 64 + threadIdx.x;
+  const int comp = blockIdx.y;  // 0: sigma_yy (v'), 1: sigma_xy (u'), 2: sigma_yz (w')
+  if (q >= a.nmodes) return;
+  const Mode md = mode_of(a, q);
+  if (md.nyquist) return;
+  const int N = a.N, Ny = N + 1;
+  const size_t S = (size_t)a.nmodes;
+  const double2* scr = a.scr + q;
+  const int src = comp == 0 ? kV : (comp == 1 ? kU : kW);
+  auto A = [&](int slot, int n) { return scr[((size_t)slot * Ny + n) * S]; };
+  C* out = (C*)a.out;
+  const int f = comp == 0 ? 1 : (comp == 1 ? 3 : 5);
+  const double iH = 1.0 / a.H;
+  // c_n b_n = b_{n+2} + 2 (n+1) a_{n+1}, from the top
+  double2 b2 = z2(0, 0), b1 = z2(0, 0);
+  for (int n = N; n >= 0; --n) {
+    double2 b = z2(0, 0);
+    if (n < N) {
+      b = zfma(2.0 * (n + 1), A(src, n + 1), b2);
+      if (n == 0) b = zscale(0.5, b);
     }
-  } else {
-    // sigma = -p I + grad u + grad u^T: xx, yy, zz, xy, xz, yz
-    for (int n = 0; n < Ny; ++n) {
-      const double2 mp = zscale(-1.0, P[n]);
-      out[((size_t)0 * Ny + n) * S + q] = from_z<T>(zadd(mp, zscale(2.0, zi(kx, U[n]))));
-      out[((size_t)2 * Ny + n) * S + q] = from_z<T>(zadd(mp, zscale(2.0, zi(kz, W[n]))));
-      out[((size_t)4 * Ny + n) * S + q] = from_z<T>(zadd(zi(kz, U[n]), zi(kx, W[n])));
-    }
-    cheb_deriv(N, V, X);
-    for (int n = 0; n < Ny; ++n)
-      out[((size_t)1 * Ny + n) * S + q] =
-          from_z<T>(zadd(zscale(-1.0, P[n]), zscale(2.0 * iH, X[n])));
-    cheb_deriv(N, U, X);
-    for (int n = 0; n < Ny; ++n)
-      out[((size_t)3 * Ny + n) * S + q] = from_z<T>(zadd(zscale(iH, X[n]), zi(kx, V[n])));
-    cheb_deriv(N, W, X);
-    for (int n = 0; n < Ny; ++n)
-      out[((size_t)5 * Ny + n) * S + q] = from_z<T>(zadd(zi(kz, V[n]), zscale(iH, X[n])));
+    double2 val;
+    if (comp == 0) val = zadd(zscale(-1.0, A(kP, n)), zscale(2.0 * iH, b));
+    else if (comp == 1) val = zadd(zscale(iH, b), zi(md.kx, A(kV, n)));
+    else val = zadd(zi(md.kz, A(kV, n)), zscale(iH, b));
+    out[((size_t)f * Ny + n) * S + q] = from_z<T>(val);
+    b2 = b1;
+    b1 = b;
   }
 }
 
-// Plan time: 2x2 influence matrix of Eq. inf_mat per mode and its inverse.
-// (b): p = 1 at y = -H, (c): p = 1 at y = +H, no forcing, no-slip.  The
-// continuity expression at the walls reduces to v'/H there because u and w
-// vanish at both walls.
-__global__ void __launch_bounds__(64) influence_modes(TauArgs a, double* infl) {
+// ---- plan time ------------------------------------------------------------
+// Step 1: the lam-only factors of the even/odd sweeps per mode.
+__global__ void __launch_bounds__(64) sweep_factors(TauArgs a) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= a.nmodes) return;
-  int l, m;
-  double kx, kz;
-  mode_k(a, q, l, m, kx, kz);
-  double* o = infl + 4 * (size_t)q;
-  if (q == 0 || l == a.Nx / 2 || m == a.Nz / 2) {
+  const Mode md = mode_of(a, q);
+  const int N = a.N, Nc = N + 1;
+  const size_t S = (size_t)a.nmodes, NyS = (size_t)Nc * S;
+  const double h2l = a.H * a.H * md.lam;
+  const double* nc = a.nconst;
+  double* inv = a.pre + q;
+  double* mul = a.pre + NyS + q;
+  double* Qa = a.pre + 2 * NyS + q;
+  double* sq = a.pre + 3 * NyS + q;
+  for (int par = 0; par < 2; ++par) {
+    const int M = (N - par) / 2;
+    double bn = 0.0;
+    for (int i = M; i >= 1; --i) {
+      const int n = par + 2 * i;
+      const double cm2 = (n == 2) ? 2.0 : 1.0;
+      const double lo = -h2l * cm2 * nc[n];
+      const double d = 1.0 + ((n <= N - 2) ? h2l * nc[Nc + n] : 0.0);
+      const double u = (n + 2 <= N - 2) ? -h2l * nc[2 * Nc + n] : 0.0;
+      const double iv = 1.0 / (d + u * bn);
+      bn = -lo * iv;
+      inv[(size_t)n * S] = iv;
+      mul[(size_t)n * S] = bn;
+    }
+    double Q = 1.0, s = 1.0;
+    for (int i = 1; i <= M; ++i) {
+      const int n = par + 2 * i;
+      Q *= mul[(size_t)n * S];
+      Qa[(size_t)n * S] = Q;
+      s += Q;
+    }
+    sq[par * S] = s;
+  }
+}
+
+// Step 2: problem (b) (p = 1 at y = -H): profiles p_b, u_b (u_b = i k_x u_b,
+// w_b = i k_z u_b), v_b, and the 2x2 influence matrix of Eq. inf_mat with its
+// inverse; (c) follows by reflection.
+__global__ void __launch_bounds__(64) influence_modes(TauArgs a) {
+  extern __shared__ double2 tau_lds[];
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= a.nmodes) return;
+  const Mode md = mode_of(a, q);
+  const int N = a.N, Ny = N + 1;
+  const size_t S = (size_t)a.nmodes, NyS = (size_t)Ny * S;
+  double* pb = a.pre + 3 * NyS + 2 * S + q;
+  double* ub = a.pre + 4 * NyS + 2 * S + q;
+  double* vb = a.pre + 5 * NyS + 2 * S + q;
+  double* o = a.infl + 4 * (size_t)q;
+  if (q == 0 || md.nyquist) {
+    for (int n = 0; n < Ny; ++n) pb[(size_t)n * S] = ub[(size_t)n * S] = vb[(size_t)n * S] = 0.0;
     o[0] = o[1] = o[2] = o[3] = 0.0;
     return;
   }
-  const int N = a.N, Ny = N + 1;
-  const size_t S = (size_t)a.nmodes;
-  const size_t FS = (size_t)Ny * S;
-  const double lam = kx * kx + kz * kz, H = a.H, iH = 1.0 / H;
-  Col R{a.scr + 0 * FS + q, S}, P{a.scr + 1 * FS + q, S}, V{a.scr + 3 * FS + q, S},
-      X{a.scr + 5 * FS + q, S};
-  RCol B{(double*)(a.scr + 6 * FS) + q, S};
-  double c[2][2];  // c[wall][problem]
-  for (int prob = 0; prob < 2; ++prob) {
-    for (int n = 0; n < Ny; ++n) R[n] = z2(0, 0);
-    hel_tau(N, lam, H, R, z2(prob == 0 ? 1.0 : 0.0, 0), z2(prob == 1 ? 1.0 : 0.0, 0), P, B);
-    cheb_deriv(N, P, X);
-    for (int n = 0; n < Ny; ++n) R[n] = zscale(iH, X[n]);
-    hel_tau(N, lam, H, R, z2(0, 0), z2(0, 0), V, B);
-    double2 dm, dp;
-    wall_slopes(N, V, dm, dp);
-    c[0][prob] = dm.x * iH;
-    c[1][prob] = dp.x * iH;
+  double2* lds = tau_lds + threadIdx.x;
+  const Sweep w = make_sweep(a, q, md.lam);
+  const double iH = 1.0 / a.H;
+  // p_b: zero forcing, p(-H) = 1, p(+H) = 0
+  for (int par = 0; par < 2; ++par) {
+    fill_rhs(N, par, lds, [](int) { return z2(0, 0); });
+    hel_par(w, par, lds, z2(par == 0 ? 0.5 : -0.5, 0), [&](int n, double2 v) { pb[(size_t)n * S] = v.x; });
   }
-  const double det = c[0][0] * c[1][1] - c[0][1] * c[1][0];
+  double vm = 0.0, vp = 0.0;
+  for (int par = 0; par < 2; ++par) {
+    // u_b profile: u'' - lam u = p_b, no-slip
+    fill_rhs(N, par, lds, [&](int m) { return z2(pb[(size_t)m * S], 0); });
+    hel_par(w, par, lds, z2(0, 0), [&](int n, double2 v) { ub[(size_t)n * S] = v.x; });
+    // v_b: v'' - lam v = p_b', no-slip
+    fill_rhs_deriv(N, par, lds, [&](int p) { return z2(pb[(size_t)p * S], 0); },
+                   [&](int, double2 d) { return zscale(iH, d); });
+    hel_par(w, par, lds, z2(0, 0), [&](int n, double2 v) {
+      vb[(size_t)n * S] = v.x;
+      const double t = (double)n * n * v.x;
+      vp += t;
+      vm += (n & 1) ? t : -t;
+    });
+  }
+  // continuity at the walls: C(y) = v'(y)/H; (c) mirrors (b)
+  const double cbm = vm * iH, cbp = vp * iH;
+  const double ccm = cbp, ccp = cbm;
+  const double det = cbm * ccp - ccm * cbp;
   const double id = 1.0 / det;
-  o[0] = c[1][1] * id;
-  o[1] = -c[0][1] * id;
-  o[2] = -c[1][0] * id;
-  o[3] = c[0][0] * id;
+  o[0] = ccp * id;
+  o[1] = -ccm * id;
+  o[2] = -cbp * id;
+  o[3] = cbm * id;
 }
 
 static TauArgs tau_args(Plan& p) {
@@ -333,6 +479,8 @@ static TauArgs tau_args(Plan& p) {
   a.H = p.p.H;
   a.Lx = p.p.Lx;
   a.Lz = p.p.Lz;
+  a.nconst = p.nconst;
+  a.pre = p.sweep;
   a.infl = p.infl;
   a.in = p.specB;
   a.wall = p.wall_spec;
@@ -342,18 +490,31 @@ static TauArgs tau_args(Plan& p) {
   return a;
 }
 
+static size_t tau_lds_bytes(Plan& p) { return (size_t)((p.p.Ny - 1) / 2 + 2) * 64 * sizeof(double2); }
+
 template <typename T>
 hipError_t launch_tau(Plan& p, bool stress) {
   TauArgs a = tau_args(p);
   const unsigned nb = (unsigned)((p.nmodes + 63) / 64);
-  if (stress) tau_modes<T, true><<<nb, 64, 0, p.stream>>>(a);
-  else tau_modes<T, false><<<nb, 64, 0, p.stream>>>(a);
+  const size_t lds = tau_lds_bytes(p);
+  tau_pressure<T><<<dim3(nb, 2), 64, lds, p.stream>>>(a);
+  tau_velocity<T><<<dim3(nb, 2, 3), 64, lds, p.stream>>>(a);
+  const size_t tot = (size_t)p.p.Ny * p.nmodes;
+  const unsigned nc = (unsigned)((tot + 255) / 256);
+  if (stress) {
+    tau_combine<T, true><<<nc, 256, 0, p.stream>>>(a);
+    tau_stress_dy<T><<<dim3(nb, 3), 64, 0, p.stream>>>(a);
+  } else {
+    tau_combine<T, false><<<nc, 256, 0, p.stream>>>(a);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_influence(Plan& p) {
   TauArgs a = tau_args(p);
-  influence_modes<<<(unsigned)((p.nmodes + 63) / 64), 64, 0, p.stream>>>(a, p.infl);
+  const unsigned nb = (unsigned)((p.nmodes + 63) / 64);
+  sweep_factors<<<nb, 64, 0, p.stream>>>(a);
+  influence_modes<<<nb, 64, tau_lds_bytes(p), p.stream>>>(a);
   return hipGetLastError();
 }
 

@@ -28,8 +28,12 @@ E_DEVICE = -5
 
 EXPORTS = (
     "ggem_plan_create", "ggem_plan_destroy", "ggem_plan_set_stream", "ggem_plan_status",
-    "ggem_single_layer", "ggem_double_layer", "ggem_spread_grid", "ggem_last_error",
+    "ggem_single_layer", "ggem_double_layer", "ggem_spread_grid", "ggem_plan_time_stage",
+    "ggem_plan_stage_time", "ggem_last_error",
 )
+
+STAGES = ("bin", "near", "wall", "spread", "fft_fwd", "cheb_fwd", "tau", "cheb_inv",
+          "fft_inv", "interp")
 
 
 class GGEMError(RuntimeError):
@@ -67,6 +71,9 @@ def load_library(path: str = LIB_PATH):
     lib.ggem_single_layer.argtypes = [vp, ll, dp, dp, ll, dp, dp, ip]
     lib.ggem_double_layer.argtypes = [vp, ll, dp, dp, ll, dp, dp, dp, ip]
     lib.ggem_spread_grid.argtypes = [vp, ll, dp, dp, dp]
+    lib.ggem_plan_time_stage.argtypes = [vp, ip, ip]
+    lib.ggem_plan_stage_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_int)]
     lib.ggem_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name != "ggem_last_error":
@@ -138,6 +145,18 @@ class Plan:
 
     def status(self):
         _check(_lib.ggem_plan_status(self._h))
+
+    def time_stage(self, stage, max_calls):
+        """Record HIP events around one pipeline stage for the next calls."""
+        sid = STAGES.index(stage) if isinstance(stage, str) else int(stage)
+        _check(_lib.ggem_plan_time_stage(self._h, sid, int(max_calls)))
+
+    def stage_time(self):
+        """(total ms, number of evaluations) recorded for the timed stage."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int()
+        _check(_lib.ggem_plan_stage_time(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
     def single_layer(self, xs, f, xt, parts=PART_ALL, out=None):
         import torch

@@ -133,3 +133,27 @@ def test_empty_inputs():
     assert np.all(u == 0.0)
     out = plan.single_layer(dev(c.xs), dev(c.f), xs0)
     assert out.shape == (0, 3)
+
+
+@pytest.mark.parametrize("cfg", DL_CASES + [(13, 300, 100, 5.0, 1.5, 2.0, 2.0, 40, 40, 33, None)])
+def test_double_layer_mixed(cfg):
+    seed, ns, nt, L, H, alpha, rc, Nx, Nz, Ny, Lz = cfg
+    c = random_case(seed, ns, nt, L, H, alpha, rc, Nx, Nz, Ny, Lz=Lz, dl=True)
+    print(f"case {c.name} double layer mixed", flush=True)
+    g = O.SlitGrid.from_case(c)
+    ref = O.double_layer(g, c.xs, c.f, c.xt, c.normals)
+    plan = G.Plan.from_case(c, precision="mixed")
+    v = plan.double_layer(dev(c.xs), dev(c.f), dev(c.xt), dev(c.normals)).cpu().numpy()
+    assert rel_l2(v, ref) < TOLMIX
+
+
+@pytest.mark.parametrize("cfg", SL_CASES)
+def test_single_layer_random_mixed(cfg):
+    seed, ns, nt, L, H, alpha, rc, Nx, Nz, Ny, Lz = cfg
+    c = random_case(seed, ns, nt, L, H, alpha, rc, Nx, Nz, Ny, Lz=Lz)
+    print(f"case {c.name} single layer random mixed", flush=True)
+    g = O.SlitGrid.from_case(c)
+    ref = O.single_layer(g, c.xs, c.f, c.xt)
+    plan = G.Plan.from_case(c, precision="mixed")
+    u = plan.single_layer(dev(c.xs), dev(c.f), dev(c.xt)).cpu().numpy()
+    assert rel_l2(u, ref) < TOLMIX
