@@ -50,34 +50,6 @@ def parse():
     return ap.parse_args()
 
 
-def pair_counts(c):
-    """Pairs within r_c among the targets/sources and (source, node) pairs
-    within r_c, by a periodic k-d tree (work counts for the roofline)."""
-    import numpy as np
-    from scipy.spatial import cKDTree
-    box = np.array([c.Lx, 1e9, c.Lz])
-
-    def shift(x):
-        y = x.copy()
-        y[:, 1] += c.H
-        y[:, 0] = np.mod(y[:, 0], c.Lx)
-        y[:, 2] = np.mod(y[:, 2], c.Lz)
-        y[y[:, 0] >= c.Lx, 0] = 0.0
-        y[y[:, 2] >= c.Lz, 2] = 0.0
-        return y
-
-    ts = cKDTree(shift(c.xs), boxsize=box)
-    tt = cKDTree(shift(c.xt), boxsize=box)
-    near = int(tt.count_neighbors(ts, c.rc)) - int(tt.count_neighbors(ts, 0.0))
-    x = np.arange(c.Nx) * c.Lx / c.Nx
-    z = np.arange(c.Nz) * c.Lz / c.Nz
-    y = c.H * np.cos(np.pi * np.arange(c.Ny) / (c.Ny - 1)) + c.H
-    Y, X, Z = np.meshgrid(y, x, z, indexing="ij")
-    nodes = cKDTree(np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1), boxsize=box)
-    spread = int(nodes.count_neighbors(ts, c.rc))
-    return near, spread
-
-
 def time_steps(plan, call, steps, warmup, stage=None):
     import torch
     for _ in range(warmup):
@@ -161,11 +133,16 @@ def main():
     err_l2 = float(torch.linalg.norm(out - ref) / torch.linalg.norm(ref))
     err_max = float((out - ref).abs().max() / ref.abs().max())
 
-    near_pairs, spread_pairs = pair_counts(c)
+    plan = plans[args.precision]
+    caller(plan)()
+    near_pairs, spread_pairs = plan.work()
     stage = args.roofline_stage
     if stage == "auto":
-        stage = "near"
-    plan = plans[args.precision]
+        # the dominant of the two pair kernels, timed before the measured region
+        per = {}
+        for st in ("near", "spread"):
+            _, per[st] = time_steps(plan, caller(plan), 10, 2, stage=st)
+        stage = max(per, key=per.get)
     ms, stage_ms = time_steps(plan, caller(plan), args.steps, args.warmup, stage=stage)
     other = "fp64" if args.precision == "mixed" else "mixed"
     ms_other, _ = time_steps(plans[other], caller(plans[other]), max(10, args.steps // 4),

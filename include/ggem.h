@@ -149,6 +149,61 @@ int ggem_plan_time_stage(ggem_plan_t plan, int stage, int max_calls);
  * their number. */
 int ggem_plan_stage_time(ggem_plan_t plan, double* total_ms, int* calls);
 
+/* Work units of the last evaluation, counted by the kernels themselves:
+ * counts[0] = target/source pairs within rc evaluated by the local sum (the
+ * wall nodes excluded), counts[1] = (source, grid node within rc) updates of
+ * the global density.  Waits for the plan's stream.  counts: host array of 2. */
+int ggem_plan_work(ggem_plan_t plan, unsigned long long* counts);
+
+/* ---- Fredholm equation of the single-layer density (Eq. qa) ------------
+ *
+ * At every element node x_b of a triangulated surface (flat triangles,
+ * density q linear on each):
+ *   q_j(x_b) + (kappa_b/4pi) n_k(x_b) sum int q_i(x) T_jik(x_b, x) dS(x) = b_j(x_b),
+ * kappa = (lambda - 1)/(lambda + 1).  The surface integral uses the three
+ * interior Gauss points of every triangle (barycentric (2/3,1/6,1/6) and
+ * permutations, weight area/3); each matrix-vector product is one GGEM double
+ * layer on the plan.  Solved by restarted GMRES (Sec. 3.5) with FP64 Krylov
+ * vectors and norms.  A solver owns its workspace (allocated at creation). */
+typedef struct ggem_solver_s* ggem_solver_t;
+
+typedef struct {
+  long long max_nodes;  /* node capacity (plan max_tgt must cover it)           */
+  long long max_tri;    /* triangle capacity (plan max_src must cover 3 x it)   */
+  int restart;          /* Krylov dimension m of GMRES(m), 1..200               */
+} ggem_solver_params;
+
+int ggem_solver_create(ggem_plan_t plan, const ggem_solver_params* params, ggem_solver_t* out);
+int ggem_solver_destroy(ggem_solver_t solver);
+
+/* y = (I + kappa/4pi D) x for nodal vectors x, y (n_nodes, 3) float64.
+ * nodes (n_nodes,3), normals (n_nodes,3) (the paper's area-averaged node
+ * normals, Sec. 3.4.2), kappa (n_nodes) or NULL to use kappa0, tri (n_tri,3)
+ * int32 node indices: all device arrays owned by the caller, read on the
+ * plan's stream.  Node positions may be unwrapped (x and z are wrapped by the
+ * evaluation); every triangle must be contiguous in space.  Triangle indices
+ * are checked on the device before any node is read (one stream
+ * synchronisation).  Errors: GGEM_E_ARG (null pointer, empty surface, node
+ * index outside [0, n_nodes)), GGEM_E_CAPACITY (n_nodes or n_tri above the
+ * solver's capacities), GGEM_E_DOMAIN (a node or Gauss point outside the
+ * slit), GGEM_E_DEVICE. */
+int ggem_fredholm_apply(ggem_solver_t solver, long long n_nodes, const double* nodes,
+                        const double* normals, const double* kappa, double kappa0,
+                        long long n_tri, const int* tri, const double* x, double* y);
+
+/* Solve (I + kappa/4pi D) q = b; q holds the initial guess on entry and the
+ * solution on exit.  Stops when the relative residual |b - A q|/|b| <= tol or
+ * after max_iter matrix-vector products in total (restarting every m).
+ * *iters: products used in the Krylov iterations; *rel_res: the true relative
+ * residual of the returned q (one extra product).  Non-convergence is not an
+ * error: compare *rel_res with tol.  Returns after the plan's stream has
+ * finished (every iteration reads its dot products on the host).  Errors as
+ * for ggem_fredholm_apply, plus GGEM_E_ARG for tol <= 0 or max_iter < 1. */
+int ggem_fredholm_solve(ggem_solver_t solver, long long n_nodes, const double* nodes,
+                        const double* normals, const double* kappa, double kappa0,
+                        long long n_tri, const int* tri, const double* b, double* q,
+                        double tol, int max_iter, int* iters, double* rel_res);
+
 /* Thread-local description of the last error on the calling thread. */
 const char* ggem_last_error(void);
 

@@ -18,3 +18,4 @@ from .ggem import (  # noqa: F401
     cheb_diff_matrix, helmholtz_tau, solve_modes, pressure_gauge,
     global_fields, interpolate, single_layer, double_layer,
 )
+from .fredholm import fredholm_apply, gauss_points, interpolate_to_gauss  # noqa: F401

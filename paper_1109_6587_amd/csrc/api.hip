@@ -13,10 +13,6 @@
 
 using namespace ggem;
 
-struct ggem_plan_s {
-  Plan p;
-};
-
 static thread_local std::string g_last_error;
 
 static int fail(int code, const char* fmt, ...) {
@@ -37,6 +33,11 @@ static int fail(int code, const char* fmt, ...) {
   } while (0)
 
 extern "C" const char* ggem_last_error(void) { return g_last_error.c_str(); }
+
+int ggem_set_error(int code, const char* msg) {
+  g_last_error = msg;
+  return code;
+}
 
 namespace {
 
@@ -74,7 +75,7 @@ void free_plan(Plan& p) {
                   p.tgt.y,     p.tgt.z,       p.tgt.s,       p.nconst,     p.sweep,
                   p.wall.keys, p.wall.counts, p.wall.offs,   p.wall.cell_start,
                   p.wall.item_start, p.wall.perm, p.wall.x,  p.wall.y,     p.wall.z,
-                  p.wall.s};
+                  p.wall.s,    p.work};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (p.flags_host) (void)hipHostFree(p.flags_host);
@@ -257,6 +258,7 @@ template <typename T>
 int evaluate(Plan& p, long long ns, const double* xs, const double* f, long long nt,
              const double* xt, const double* nrm, double* out, int parts, bool dl) {
   fill_u32<<<1, 64, 0, p.stream>>>(p.flags, 0u, 1);
+  fill_zero<unsigned long long><<<1, 64, 0, p.stream>>>(p.work, 2);
   HIP_TRY(hipGetLastError());
   {
     StageScope s(p, GGEM_STAGE_BIN);
@@ -424,7 +426,7 @@ extern "C" int ggem_plan_create(const ggem_params* prm, void* hip_stream, ggem_p
             dev_alloc(&p.nconst, 3 * Ny) &&
             dev_alloc(&p.sweep, (6 * Ny + 2) * (size_t)p.nmodes) &&
             dev_alloc(&p.gauge, (size_t)(q.max_src / 256 + 4)) && dev_alloc(&p.flags, 1) &&
-            dev_alloc(&p.item_count, 4) &&
+            dev_alloc(&p.item_count, 4) && dev_alloc(&p.work, 2) &&
             hipHostMalloc((void**)&p.flags_host, sizeof(unsigned), 0) == hipSuccess &&
             alloc_binned(p.src, q.max_src, g.ncells, elt) &&
             alloc_binned(p.tgt, q.max_tgt, g.ncells, elt) &&
@@ -497,6 +499,7 @@ extern "C" int ggem_spread_grid(ggem_plan_t plan, long long ns, const double* xs
   if (ns > p.p.max_src) return fail(GGEM_E_CAPACITY, "ns=%lld exceeds max_src", ns);
   if ((ns > 0 && (!xs || !f)) || !grid) return fail(GGEM_E_ARG, "null array");
   fill_u32<<<1, 64, 0, p.stream>>>(p.flags, 0u, 1);
+  fill_zero<unsigned long long><<<1, 64, 0, p.stream>>>(p.work, 2);
   HIP_TRY(launch_bin(p, p.src, ns, xs, f, nullptr, true));
   if (p.fp64) {
     HIP_TRY(launch_spread<double>(p, 0));
@@ -545,5 +548,15 @@ extern "C" int ggem_plan_stage_time(ggem_plan_t plan, double* total_ms, int* cal
   }
   *total_ms = sum;
   *calls = p.timed_calls;
+  return GGEM_OK;
+}
+
+extern "C" int ggem_plan_work(ggem_plan_t plan, unsigned long long* counts) {
+  if (int rc = check_plan(plan)) return rc;
+  if (!counts) return fail(GGEM_E_ARG, "null output");
+  Plan& p = plan->p;
+  HIP_TRY(hipMemcpyAsync(counts, p.work, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                         p.stream));
+  HIP_TRY(hipStreamSynchronize(p.stream));
   return GGEM_OK;
 }

@@ -1,0 +1,408 @@
+// Fredholm second-kind equation for the single-layer density (Eq. qa,
+// discretised as in Sec. 3.5): at every element node x_b
+//   q_j(x_b) + (kappa_b/4pi) n_k(x_b) sum_n int q_i(x) T_jik(x_b, x) dS(x) = b_j(x_b),
+// i.e. (I + kappa/4pi D) q = b, solved by restarted GMRES (Sec. 3.5) with
+// every matrix-vector product evaluated by the GGEM double layer.
+//
+// Surface integral: q is linear on each flat triangle (Sec. 3.3.1); the
+// integral over a triangle uses its three interior Gauss points (barycentric
+// (2/3,1/6,1/6) and permutations, weight area/3), so
+//   int q_i T_jik n_k dS ~= 8 pi v_j,  v = ggem_double_layer(Gauss points,
+//   strengths q(x_g) w_g; targets = nodes, target normals n(x_b)),
+// and the operator is y = q + 2 kappa v.  Nodes never coincide with Gauss
+// points, so no pair is singular.
+//
+// GMRES(m) with classical Gram-Schmidt applied twice; Krylov vectors, dot
+// products and norms in FP64 with fixed-order reductions; the small
+// Hessenberg problem (Givens rotations) on the host.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "ggem_internal.h"
+
+using namespace ggem;
+
+namespace {
+
+// Gauss points and weights of every triangle.  A triangle whose node index
+// lies outside [0, nnode) raises *bad and gets zero weight at the origin, so
+// nothing reads outside the node array.
+__global__ void gauss_setup(int ntri, int nnode, const int* __restrict__ tri,
+                            const double* __restrict__ xn, double* __restrict__ gpos,
+                            double* __restrict__ gw, int* __restrict__ bad) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntri) return;
+  const int a = tri[3 * t], b = tri[3 * t + 1], c = tri[3 * t + 2];
+  if ((unsigned)a >= (unsigned)nnode || (unsigned)b >= (unsigned)nnode ||
+      (unsigned)c >= (unsigned)nnode) {
+    atomicOr(bad, 1);
+    for (int g = 3 * t; g < 3 * t + 3; ++g) {
+      gpos[3 * (size_t)g] = gpos[3 * (size_t)g + 1] = gpos[3 * (size_t)g + 2] = 0.0;
+      gw[g] = 0.0;
+    }
+    return;
+  }
+  double A[3], B[3], Cc[3];
+  for (int d = 0; d < 3; ++d) {
+    A[d] = xn[3 * (size_t)a + d];
+    B[d] = xn[3 * (size_t)b + d];
+    Cc[d] = xn[3 * (size_t)c + d];
+  }
+  const double e1[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+  const double e2[3] = {Cc[0] - A[0], Cc[1] - A[1], Cc[2] - A[2]};
+  const double cx = e1[1] * e2[2] - e1[2] * e2[1];
+  const double cy = e1[2] * e2[0] - e1[0] * e2[2];
+  const double cz = e1[0] * e2[1] - e1[1] * e2[0];
+  const double area = 0.5 * sqrt(cx * cx + cy * cy + cz * cz);
+  const double hi = 2.0 / 3.0, lo = 1.0 / 6.0;
+  for (int gp = 0; gp < 3; ++gp) {
+    const double la = gp == 0 ? hi : lo, lb = gp == 1 ? hi : lo, lc = gp == 2 ? hi : lo;
+    const size_t g = 3 * (size_t)t + gp;
+    for (int d = 0; d < 3; ++d) gpos[3 * g + d] = la * A[d] + lb * B[d] + lc * Cc[d];
+    gw[g] = area / 3.0;
+  }
+}
+
+// Gauss-point strengths q(x_g) w_g from nodal q (linear interpolation).
+__global__ void gauss_strengths(int ntri, const int* __restrict__ tri, const double* __restrict__ q,
+                                const double* __restrict__ gw, double* __restrict__ gs) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntri) return;
+  const int a = tri[3 * t], b = tri[3 * t + 1], c = tri[3 * t + 2];
+  const double hi = 2.0 / 3.0, lo = 1.0 / 6.0;
+  for (int gp = 0; gp < 3; ++gp) {
+    const double la = gp == 0 ? hi : lo, lb = gp == 1 ? hi : lo, lc = gp == 2 ? hi : lo;
+    const size_t g = 3 * (size_t)t + gp;
+    for (int d = 0; d < 3; ++d)
+      gs[3 * g + d] = gw[g] * (la * q[3 * (size_t)a + d] + lb * q[3 * (size_t)b + d] +
+                               lc * q[3 * (size_t)c + d]);
+  }
+}
+
+// y = x + 2 kappa v (per node kappa, or a uniform value)
+__global__ void fredholm_combine(int n3, const double* __restrict__ x, const double* __restrict__ v,
+                                 const double* __restrict__ kappa, double kappa0,
+                                 double* __restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n3) return;
+  const double k = kappa ? kappa[i / 3] : kappa0;
+  y[i] = x[i] + 2.0 * k * v[i];
+}
+
+__global__ void fill_ints(int* __restrict__ p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+constexpr int kDotBlock = 256;
+constexpr int kDotBlocks = 256;
+
+// part[i][b] = sum over block b's range of V_i . w  (fixed order)
+__global__ void __launch_bounds__(kDotBlock) dots_partial(int n, const double* __restrict__ V,
+                                                          size_t ldv, const double* __restrict__ w,
+                                                          double* __restrict__ part) {
+  __shared__ double red[kDotBlock];
+  const int i = blockIdx.y;
+  const double* vi = V + (size_t)i * ldv;
+  double s = 0.0;
+  for (int j = blockIdx.x * kDotBlock + threadIdx.x; j < n; j += kDotBlocks * kDotBlock)
+    s = fma(vi[j], w[j], s);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = kDotBlock / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(size_t)i * kDotBlocks + blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(kDotBlock) dots_final(const double* __restrict__ part,
+                                                        double* __restrict__ out) {
+  __shared__ double red[kDotBlock];
+  const int i = blockIdx.x;
+  red[threadIdx.x] = part[(size_t)i * kDotBlocks + threadIdx.x];
+  __syncthreads();
+  for (int o = kDotBlock / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i] = red[0];
+}
+
+// w -= sum_i c_i V_i   (or, with add, x += sum_i c_i V_i)
+__global__ void multi_axpy(int n, int k, const double* __restrict__ V, size_t ldv,
+                           const double* __restrict__ c, double sign, double* __restrict__ w) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double s = 0.0;
+  for (int i = 0; i < k; ++i) s = fma(c[i], V[(size_t)i * ldv + j], s);
+  w[j] = fma(sign, s, w[j]);
+}
+
+__global__ void scale_copy(int n, double a, const double* __restrict__ x, double* __restrict__ y) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) y[j] = a * x[j];
+}
+
+__global__ void sub_into(int n, const double* __restrict__ b, const double* __restrict__ ax,
+                         double* __restrict__ r) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) r[j] = b[j] - ax[j];
+}
+
+}  // namespace
+
+struct ggem_solver_s {
+  ggem_plan_s* plan;
+  long long max_nodes, max_tri;
+  int restart;
+  double *gpos, *gw, *gs;  // Gauss points, weights, strengths
+  double *V, *w, *v, *r;   // Krylov basis (restart + 1 vectors), work vectors
+  double *part, *dots, *coef;
+  double* dots_host;
+  int *bad, *bad_host;  // triangle index check
+  // geometry of the current solve
+  int n_nodes, n_tri;
+  const double *nodes, *normals, *kappa;
+  double kappa0;
+  const int* tri;
+};
+
+static thread_local char g_solver_err[256];
+
+#define SOLVER_TRY(expr)                                                              \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      snprintf(g_solver_err, sizeof g_solver_err, "%s: %s", #expr, hipGetErrorString(e_)); \
+      ggem_set_error(GGEM_E_DEVICE, g_solver_err);                                    \
+      return GGEM_E_DEVICE;                                                           \
+    }                                                                                 \
+  } while (0)
+
+static void free_solver(ggem_solver_s* s) {
+  void* ptrs[] = {s->gpos, s->gw, s->gs, s->V,    s->w,   s->v,
+                  s->r,    s->part, s->dots, s->coef, s->bad};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  if (s->dots_host) (void)hipHostFree(s->dots_host);
+  if (s->bad_host) (void)hipHostFree(s->bad_host);
+}
+
+extern "C" int ggem_solver_create(ggem_plan_t plan, const ggem_solver_params* prm,
+                                  ggem_solver_t* out) {
+  if (!plan || !prm || !out) return ggem_set_error(GGEM_E_ARG, "null argument");
+  *out = nullptr;
+  if (prm->restart < 1 || prm->restart > 200)
+    return ggem_set_error(GGEM_E_ARG, "restart must be in 1..200");
+  if (prm->max_nodes < 1 || prm->max_tri < 1 || prm->max_nodes > (1LL << 28) ||
+      prm->max_tri > (1LL << 28))
+    return ggem_set_error(GGEM_E_ARG, "capacities out of range");
+  if (3 * prm->max_tri > plan->p.p.max_src || prm->max_nodes > plan->p.p.max_tgt)
+    return ggem_set_error(GGEM_E_CAPACITY,
+                          "plan capacity must cover 3 Gauss points per triangle and the nodes");
+  ggem_solver_s* s = new (std::nothrow) ggem_solver_s();
+  if (!s) return ggem_set_error(GGEM_E_NOMEM, "host allocation failed");
+  memset(s, 0, sizeof *s);
+  s->plan = plan;
+  s->max_nodes = prm->max_nodes;
+  s->max_tri = prm->max_tri;
+  s->restart = prm->restart;
+  const size_t n3 = 3 * (size_t)prm->max_nodes, ng = 3 * (size_t)prm->max_tri;
+  const size_t m1 = (size_t)prm->restart + 1;
+  bool ok = hipMalloc((void**)&s->gpos, 3 * ng * 8) == hipSuccess &&
+            hipMalloc((void**)&s->gw, ng * 8) == hipSuccess &&
+            hipMalloc((void**)&s->gs, 3 * ng * 8) == hipSuccess &&
+            hipMalloc((void**)&s->V, m1 * n3 * 8) == hipSuccess &&
+            hipMalloc((void**)&s->w, n3 * 8) == hipSuccess &&
+            hipMalloc((void**)&s->v, n3 * 8) == hipSuccess &&
+            hipMalloc((void**)&s->r, n3 * 8) == hipSuccess &&
+            hipMalloc((void**)&s->part, m1 * kDotBlocks * 8) == hipSuccess &&
+            hipMalloc((void**)&s->dots, m1 * 8) == hipSuccess &&
+            hipMalloc((void**)&s->coef, m1 * 8) == hipSuccess &&
+            hipMalloc((void**)&s->bad, sizeof(int)) == hipSuccess &&
+            hipHostMalloc((void**)&s->dots_host, m1 * 8, 0) == hipSuccess &&
+            hipHostMalloc((void**)&s->bad_host, sizeof(int), 0) == hipSuccess;
+  if (!ok) {
+    free_solver(s);
+    delete s;
+    return ggem_set_error(GGEM_E_NOMEM, "device allocation failed");
+  }
+  *out = s;
+  return GGEM_OK;
+}
+
+extern "C" int ggem_solver_destroy(ggem_solver_t s) {
+  if (!s) return ggem_set_error(GGEM_E_ARG, "null solver");
+  (void)hipStreamSynchronize(s->plan->p.stream);
+  free_solver(s);
+  delete s;
+  return GGEM_OK;
+}
+
+static int set_geometry(ggem_solver_s* s, long long n_nodes, const double* nodes,
+                        const double* normals, const double* kappa, double kappa0,
+                        long long n_tri, const int* tri) {
+  if (n_nodes < 1 || n_tri < 1) return ggem_set_error(GGEM_E_ARG, "empty surface");
+  if (n_nodes > s->max_nodes || n_tri > s->max_tri)
+    return ggem_set_error(GGEM_E_CAPACITY, "surface exceeds the solver capacity");
+  if (!nodes || !normals || !tri) return ggem_set_error(GGEM_E_ARG, "null surface array");
+  s->n_nodes = (int)n_nodes;
+  s->n_tri = (int)n_tri;
+  s->nodes = nodes;
+  s->normals = normals;
+  s->kappa = kappa;
+  s->kappa0 = kappa0;
+  s->tri = tri;
+  hipStream_t st = s->plan->p.stream;
+  fill_ints<<<1, 64, 0, st>>>(s->bad, 1, 0);
+  gauss_setup<<<(s->n_tri + 255) / 256, 256, 0, st>>>(s->n_tri, s->n_nodes, tri, nodes, s->gpos,
+                                                      s->gw, s->bad);
+  SOLVER_TRY(hipGetLastError());
+  SOLVER_TRY(hipMemcpyAsync(s->bad_host, s->bad, sizeof(int), hipMemcpyDeviceToHost, st));
+  SOLVER_TRY(hipStreamSynchronize(st));
+  if (*s->bad_host) return ggem_set_error(GGEM_E_ARG, "triangle node index out of range");
+  return GGEM_OK;
+}
+
+// y = (I + kappa/4pi D) x
+static int apply(ggem_solver_s* s, const double* x, double* y) {
+  hipStream_t st = s->plan->p.stream;
+  gauss_strengths<<<(s->n_tri + 255) / 256, 256, 0, st>>>(s->n_tri, s->tri, x, s->gw, s->gs);
+  SOLVER_TRY(hipGetLastError());
+  int rc = ggem_double_layer(s->plan, 3LL * s->n_tri, s->gpos, s->gs, s->n_nodes, s->nodes,
+                             s->normals, s->v, GGEM_PART_ALL);
+  if (rc) return rc;
+  const int n3 = 3 * s->n_nodes;
+  fredholm_combine<<<(n3 + 255) / 256, 256, 0, st>>>(n3, x, s->v, s->kappa, s->kappa0, y);
+  SOLVER_TRY(hipGetLastError());
+  return GGEM_OK;
+}
+
+// k dot products V_i . w, returned on the host
+static int dots(ggem_solver_s* s, const double* V, size_t ldv, int k, const double* w, int n,
+                double* host) {
+  hipStream_t st = s->plan->p.stream;
+  dots_partial<<<dim3(kDotBlocks, k), kDotBlock, 0, st>>>(n, V, ldv, w, s->part);
+  dots_final<<<k, kDotBlock, 0, st>>>(s->part, s->dots);
+  SOLVER_TRY(hipMemcpyAsync(s->dots_host, s->dots, k * 8, hipMemcpyDeviceToHost, st));
+  SOLVER_TRY(hipStreamSynchronize(st));
+  memcpy(host, s->dots_host, k * 8);
+  return GGEM_OK;
+}
+
+extern "C" int ggem_fredholm_apply(ggem_solver_t s, long long n_nodes, const double* nodes,
+                                   const double* normals, const double* kappa, double kappa0,
+                                   long long n_tri, const int* tri, const double* x, double* y) {
+  if (!s) return ggem_set_error(GGEM_E_ARG, "null solver");
+  if (!x || !y) return ggem_set_error(GGEM_E_ARG, "null vector");
+  if (int rc = set_geometry(s, n_nodes, nodes, normals, kappa, kappa0, n_tri, tri)) return rc;
+  return apply(s, x, y);
+}
+
+extern "C" int ggem_fredholm_solve(ggem_solver_t s, long long n_nodes, const double* nodes,
+                                   const double* normals, const double* kappa, double kappa0,
+                                   long long n_tri, const int* tri, const double* b, double* q,
+                                   double tol, int max_iter, int* iters, double* rel_res) {
+  if (!s) return ggem_set_error(GGEM_E_ARG, "null solver");
+  if (!b || !q) return ggem_set_error(GGEM_E_ARG, "null vector");
+  if (!(tol > 0) || max_iter < 1) return ggem_set_error(GGEM_E_ARG, "bad tolerance or max_iter");
+  if (int rc = set_geometry(s, n_nodes, nodes, normals, kappa, kappa0, n_tri, tri)) return rc;
+  hipStream_t st = s->plan->p.stream;
+  const int n = 3 * (int)n_nodes;
+  const int m = s->restart;
+  const size_t ldv = 3 * (size_t)s->max_nodes;
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  double bnorm2;
+  if (int rc = dots(s, b, 0, 1, b, n, &bnorm2)) return rc;
+  const double bnorm = sqrt(bnorm2);
+  if (bnorm == 0.0) {
+    scale_copy<<<nb, 256, 0, st>>>(n, 0.0, b, q);
+    if (iters) *iters = 0;
+    if (rel_res) *rel_res = 0.0;
+    SOLVER_TRY(hipStreamSynchronize(st));
+    return GGEM_OK;
+  }
+  std::vector<double> Hm((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), h(m + 1), h2(m + 1), y(m);
+  int total = 0;
+  double res = 0.0;
+  bool converged = false;
+  while (total < max_iter && !converged) {
+    // r = b - A q, V_0 = r / |r|
+    if (int rc = apply(s, q, s->w)) return rc;
+    sub_into<<<nb, 256, 0, st>>>(n, b, s->w, s->r);
+    double beta2;
+    if (int rc = dots(s, s->r, 0, 1, s->r, n, &beta2)) return rc;
+    const double beta = sqrt(beta2);
+    res = beta / bnorm;
+    if (res <= tol) {
+      converged = true;
+      break;
+    }
+    scale_copy<<<nb, 256, 0, st>>>(n, 1.0 / beta, s->r, s->V);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int j = 0;
+    for (; j < m && total < max_iter; ++j) {
+      ++total;
+      double* Vj = s->V + (size_t)j * ldv;
+      if (int rc = apply(s, Vj, s->w)) return rc;
+      // classical Gram-Schmidt, twice
+      if (int rc = dots(s, s->V, ldv, j + 1, s->w, n, h.data())) return rc;
+      SOLVER_TRY(hipMemcpyAsync(s->coef, h.data(), (j + 1) * 8, hipMemcpyHostToDevice, st));
+      multi_axpy<<<nb, 256, 0, st>>>(n, j + 1, s->V, ldv, s->coef, -1.0, s->w);
+      if (int rc = dots(s, s->V, ldv, j + 1, s->w, n, h2.data())) return rc;
+      SOLVER_TRY(hipMemcpyAsync(s->coef, h2.data(), (j + 1) * 8, hipMemcpyHostToDevice, st));
+      multi_axpy<<<nb, 256, 0, st>>>(n, j + 1, s->V, ldv, s->coef, -1.0, s->w);
+      for (int i = 0; i <= j; ++i) h[i] += h2[i];
+      double wn2;
+      if (int rc = dots(s, s->w, 0, 1, s->w, n, &wn2)) return rc;
+      h[j + 1] = sqrt(wn2);
+      if (h[j + 1] > 0.0)
+        scale_copy<<<nb, 256, 0, st>>>(n, 1.0 / h[j + 1], s->w, s->V + (size_t)(j + 1) * ldv);
+      // Givens rotations on the new Hessenberg column
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * h[i] + sn[i] * h[i + 1];
+        h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+        h[i] = t;
+      }
+      const double den = hypot(h[j], h[j + 1]);
+      cs[j] = den > 0 ? h[j] / den : 1.0;
+      sn[j] = den > 0 ? h[j + 1] / den : 0.0;
+      h[j] = den;
+      h[j + 1] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      for (int i = 0; i <= j; ++i) Hm[(size_t)i * m + j] = h[i];
+      res = fabs(g[j + 1]) / bnorm;
+      if (res <= tol) {
+        ++j;
+        converged = true;
+        break;
+      }
+    }
+    // q += V y with H y = g (upper triangular, j columns)
+    const int k = j;
+    for (int i = k - 1; i >= 0; --i) {
+      double t = g[i];
+      for (int l = i + 1; l < k; ++l) t -= Hm[(size_t)i * m + l] * y[l];
+      y[i] = t / Hm[(size_t)i * m + i];
+    }
+    if (k > 0) {
+      SOLVER_TRY(hipMemcpyAsync(s->coef, y.data(), k * 8, hipMemcpyHostToDevice, st));
+      multi_axpy<<<nb, 256, 0, st>>>(n, k, s->V, ldv, s->coef, 1.0, q);
+      SOLVER_TRY(hipGetLastError());
+    }
+  }
+  // true relative residual of the returned q
+  if (int rc = apply(s, q, s->w)) return rc;
+  sub_into<<<nb, 256, 0, st>>>(n, b, s->w, s->r);
+  double rr;
+  if (int rc = dots(s, s->r, 0, 1, s->r, n, &rr)) return rc;
+  if (iters) *iters = total;
+  if (rel_res) *rel_res = sqrt(rr) / bnorm;
+  return GGEM_OK;
+}

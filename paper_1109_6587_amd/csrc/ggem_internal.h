@@ -7,6 +7,12 @@
 
 namespace ggem {
 
+// Sum of a per-lane count over the wave, added to *ctr by lane 0.
+__device__ inline void wave_count_add(unsigned long long* ctr, unsigned v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd(ctr, (unsigned long long)v);
+}
+
 constexpr int kMaxCells = 16384;     // cell-list size (LDS histograms)
 constexpr int kMaxChunks = 512;      // counting-sort chunks per point set (at most)
 constexpr int kNearBlock = 64;       // targets per near-field work item
@@ -84,6 +90,7 @@ struct Plan {
   unsigned* flags;    // device domain flags
   unsigned* flags_host;  // pinned host copy
   int* item_count;    // scratch
+  unsigned long long* work;  // [0]: local pairs at the targets, [1]: spread updates (last call)
 
   // stage timing hook (host side)
   int timed_stage;    // -1: off
@@ -119,3 +126,11 @@ template <typename T>
 hipError_t launch_grid_to_f64(Plan& p, double* out);
 
 }  // namespace ggem
+
+// The plan handle of the C ABI.
+struct ggem_plan_s {
+  ggem::Plan p;
+};
+
+// Record a thread-local error message and return code.
+int ggem_set_error(int code, const char* msg);

@@ -122,6 +122,7 @@ struct NearArgs {
   const int* tperm;        // wall mode: sorted target -> wall node index
   int nplane;              // wall mode: nodes per wall plane (0 = ordinary targets)
   double scale;            // output factor
+  unsigned long long* work;  // pair counter (null: not counted)
 };
 
 __device__ inline int find_cell(const int* __restrict__ start, int ncells, int item) {
@@ -188,6 +189,7 @@ __global__ void __launch_bounds__(64 * kNearWaves) near_field(NearArgs a, Kc<T> 
   const T* sf = (const T*)a.sf;
   T ux = 0, uy = 0, uz = 0;
   T sfx = 0, sfy = 0, sfz = 0;  // self contributions
+  unsigned npairs = 0;
   const int nxo = g.ncx >= 3 ? 3 : g.ncx, nzo = g.ncz >= 3 ? 3 : g.ncz;
   // wall targets only see the wall cell layer (cells are at least r_c high)
   const int oy0 = a.nplane ? 1 : 0, noy = a.nplane ? 1 : 3;
@@ -267,6 +269,7 @@ __global__ void __launch_bounds__(64 * kNearWaves) near_field(NearArgs a, Kc<T> 
         }
       }
       // pass 2: kernel evaluations only for in-range pairs, in source order
+      npairs += __popcll(mask);
       while (mask) {
         const int j = __builtin_ctzll(mask);
         mask &= mask - 1;
@@ -290,6 +293,7 @@ __global__ void __launch_bounds__(64 * kNearWaves) near_field(NearArgs a, Kc<T> 
       }
     }
   }
+  if (a.work) wave_count_add(a.work, npairs);
   part[wave][0][lane] = ux + k.selfc * sfx;
   part[wave][1][lane] = uy + k.selfc * sfy;
   part[wave][2][lane] = uz + k.selfc * sfz;
@@ -384,6 +388,7 @@ static NearArgs near_args(Plan& p, const Binned& tg, void* out, size_t ostride) 
   a.tperm = tg.perm;
   a.nplane = 0;
   a.scale = 0.039788735772973833942;  // 1/(8 pi)
+  a.work = nullptr;
   return a;
 }
 
@@ -394,6 +399,7 @@ hipError_t launch_near_sl(Plan& p, int nt) {
   if (nt <= 0) return hipSuccess;
   NearArgs a = near_args(p, *p.tview, p.ul, (size_t)p.p.max_tgt);
   a.tcap = (size_t)p.p.max_tgt;
+  a.work = p.work;
   launch_near_kernel<T, false>(p, a, near_grid(p, nt));
   return hipGetLastError();
 }
@@ -404,6 +410,7 @@ hipError_t launch_near_dl(Plan& p, int nt) {
   NearArgs a = near_args(p, *p.tview, p.ul, (size_t)p.p.max_tgt);
   a.tn = p.tnrm;
   a.tcap = (size_t)p.p.max_tgt;
+  a.work = p.work;
   launch_near_kernel<T, true>(p, a, near_grid(p, nt));
   return hipGetLastError();
 }

@@ -40,6 +40,7 @@ struct SpreadArgs {
   const void* sf;
   size_t scap;
   void* out;           // (3, Ny, Nx, Nz) T
+  unsigned long long* work;  // update counter
 };
 
 // Tile of TJ (y) x TI (x) x TK (z) nodes, one node per thread.
@@ -97,6 +98,7 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
   const T a2 = (T)(a.alpha * a.alpha);
   const int lane = tid & 63, wave = tid >> 6;
   T fx = 0, fy = 0, fz = 0;
+  unsigned nupd = 0;
   for (int cy = cy0; cy <= cy1; ++cy)
     for (int cxu = cx0; cxu <= cx1; ++cxu) {
       const int cx = ((cxu % g.ncx) + g.ncx) % g.ncx;
@@ -165,6 +167,7 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
                 if (!(d2 <= a.rc2)) continue;
                 r2 = (T)d2;
               }
+              ++nupd;
               const T ar = a2 * r2;
               const T w = t_exp_s(-ar) * ((T)2.5 - ar);
               const Q f = lf[s];
@@ -176,6 +179,7 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
         }
       }
     }
+  wave_count_add(a.work, nupd);
   if (valid) {
     const T c = (T)(a.alpha * a.alpha * a.alpha * 0.17958712212516656);  // alpha^3 pi^{-3/2}
     T* out = (T*)a.out;
@@ -207,6 +211,7 @@ hipError_t launch_spread(Plan& p, int /*unused*/) {
   a.sf = p.src.s;
   a.scap = (size_t)p.p.max_src;
   a.out = p.phys;
+  a.work = p.work + 1;
   dim3 grid((p.p.Nz + TK - 1) / TK, (p.p.Nx + TI - 1) / TI, (p.p.Ny + TJ - 1) / TJ);
   // tile-relative staging needs one periodic image per (tile, source) pair
   const bool rel = sizeof(T) == 4 && TI * p.dx + p.rc < 0.5 * p.p.Lx && TK * p.dz + p.rc < 0.5 * p.p.Lz;

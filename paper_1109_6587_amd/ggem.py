@@ -29,7 +29,8 @@ E_DEVICE = -5
 EXPORTS = (
     "ggem_plan_create", "ggem_plan_destroy", "ggem_plan_set_stream", "ggem_plan_status",
     "ggem_single_layer", "ggem_double_layer", "ggem_spread_grid", "ggem_plan_time_stage",
-    "ggem_plan_stage_time", "ggem_last_error",
+    "ggem_plan_stage_time", "ggem_plan_work", "ggem_solver_create", "ggem_solver_destroy",
+    "ggem_fredholm_apply", "ggem_fredholm_solve", "ggem_last_error",
 )
 
 STAGES = ("bin", "near", "wall", "spread", "fft_fwd", "cheb_fwd", "tau", "cheb_inv",
@@ -40,6 +41,11 @@ class GGEMError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"ggem error {code}: {msg}")
         self.code = code
+
+
+class SolverParams(ctypes.Structure):
+    _fields_ = [("max_nodes", ctypes.c_longlong), ("max_tri", ctypes.c_longlong),
+                ("restart", ctypes.c_int)]
 
 
 class Params(ctypes.Structure):
@@ -74,6 +80,13 @@ def load_library(path: str = LIB_PATH):
     lib.ggem_plan_time_stage.argtypes = [vp, ip, ip]
     lib.ggem_plan_stage_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int)]
+    lib.ggem_plan_work.argtypes = [vp, ctypes.POINTER(ctypes.c_ulonglong)]
+    lib.ggem_solver_create.argtypes = [vp, ctypes.POINTER(SolverParams), ctypes.POINTER(vp)]
+    lib.ggem_solver_destroy.argtypes = [vp]
+    dd = ctypes.c_double
+    lib.ggem_fredholm_apply.argtypes = [vp, ll, dp, dp, dp, dd, ll, dp, dp, dp]
+    lib.ggem_fredholm_solve.argtypes = [vp, ll, dp, dp, dp, dd, ll, dp, dp, dp, dd, ip,
+                                        ctypes.POINTER(ip), ctypes.POINTER(dd)]
     lib.ggem_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name != "ggem_last_error":
@@ -158,6 +171,12 @@ class Plan:
         _check(_lib.ggem_plan_stage_time(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
 
+    def work(self):
+        """(local pairs, spread updates) counted by the kernels in the last call."""
+        c = (ctypes.c_ulonglong * 2)()
+        _check(_lib.ggem_plan_work(self._h, c))
+        return int(c[0]), int(c[1])
+
     def single_layer(self, xs, f, xt, parts=PART_ALL, out=None):
         import torch
         ns, nt = xs.shape[0], xt.shape[0]
@@ -188,3 +207,65 @@ class Plan:
         _check(_lib.ggem_spread_grid(self._h, ns, _dev_ptr(xs, "xs"), _dev_ptr(f, "f", ns),
                                      out.data_ptr()))
         return out
+
+
+class Surface:
+    """A triangulated surface on the device: nodes (n,3) f64, node normals
+    (n,3) f64, triangles (m,3) int32, kappa per node (n,) f64 or a scalar."""
+
+    def __init__(self, nodes, normals, tri, kappa):
+        import torch
+        self.nodes = nodes
+        self.normals = normals
+        if tri.dtype != torch.int32 or not tri.is_cuda or not tri.is_contiguous():
+            raise TypeError("tri must be a contiguous int32 device tensor")
+        self.tri = tri
+        if isinstance(kappa, (int, float)):
+            self.kappa, self.kappa0 = None, float(kappa)
+        else:
+            self.kappa, self.kappa0 = kappa, 0.0
+
+    def args(self):
+        n = self.nodes.shape[0]
+        kp = self.kappa.data_ptr() if self.kappa is not None else None
+        return (n, _dev_ptr(self.nodes, "nodes"), _dev_ptr(self.normals, "normals", n), kp,
+                self.kappa0, self.tri.shape[0], self.tri.data_ptr())
+
+
+class FredholmSolver:
+    """GMRES(m) for (I + kappa/4pi D) q = b on a plan (see include/ggem.h)."""
+
+    def __init__(self, plan, max_nodes, max_tri, restart=30):
+        self.plan = plan
+        self._h = ctypes.c_void_p()
+        prm = SolverParams(int(max_nodes), int(max_tri), int(restart))
+        _check(_lib.ggem_solver_create(plan._h, ctypes.byref(prm), ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            _check(_lib.ggem_solver_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            if self._h and _lib is not None:
+                _lib.ggem_solver_destroy(self._h)
+        except Exception:
+            pass
+
+    def apply(self, surf, x, out=None):
+        import torch
+        if out is None:
+            out = torch.empty_like(x)
+        _check(_lib.ggem_fredholm_apply(self._h, *surf.args(), _dev_ptr(x, "x"),
+                                        _dev_ptr(out, "out")))
+        return out
+
+    def solve(self, surf, b, q, tol=1e-6, max_iter=200):
+        """Solve in place into q (initial guess on entry); returns (iters, rel_res)."""
+        it = ctypes.c_int()
+        rr = ctypes.c_double()
+        _check(_lib.ggem_fredholm_solve(self._h, *surf.args(), _dev_ptr(b, "b"),
+                                        _dev_ptr(q, "q"), float(tol), int(max_iter),
+                                        ctypes.byref(it), ctypes.byref(rr)))
+        return it.value, rr.value

@@ -13,7 +13,8 @@ def pytest_configure(config):
     config.addinivalue_line("markers", "slow: oracle runs that take tens of seconds")
 
 
-@pytest.fixture(scope="session")
+@pytest.fixture
 def rng():
+    """A fresh seeded generator per test, so draws do not depend on test order."""
     import numpy as np
     return np.random.default_rng(12345)

@@ -34,10 +34,12 @@ def fd(fun, x, k, h):
 
 @pytest.mark.parametrize("alpha", [0.7, 2.0, 6.0])
 def test_rho_g_mass_and_second_moment(alpha):
-    m0 = integrate.quad(lambda r: 4 * math.pi * r * r * O.rho_g(r * r, alpha), 0, np.inf,
-                        epsabs=1e-14, epsrel=1e-13)[0]
-    m2 = integrate.quad(lambda r: 4 * math.pi * r ** 4 * O.rho_g(r * r, alpha), 0, np.inf,
-                        epsabs=1e-14, epsrel=1e-13)[0]
+    # the density is below 1e-60 of its peak beyond r = 12/alpha
+    top = 12.0 / alpha
+    m0 = integrate.quad(lambda r: 4 * math.pi * r * r * O.rho_g(r * r, alpha), 0, top,
+                        epsabs=1e-14, epsrel=1e-13, limit=200)[0]
+    m2 = integrate.quad(lambda r: 4 * math.pi * r ** 4 * O.rho_g(r * r, alpha), 0, top,
+                        epsabs=1e-12, epsrel=0.0, limit=200)[0]
     assert abs(m0 - 1.0) < 1e-12
     assert abs(m2) * alpha ** 2 < 1e-12
 

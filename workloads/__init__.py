@@ -11,4 +11,6 @@ from .inputs import (  # noqa: F401
     case_capsules_dl,
     case_batched,
     random_case,
+    node_normals,
+    case_small_surface,
 )

@@ -292,3 +292,38 @@ def random_case(seed: int, ns: int, nt: int, L: float, H: float, alpha: float,
         nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
     return SlitCase(f"random_{seed}", L, Lz, H, alpha, rc, Nx, Nz, Ny,
                     xs, f, xt, nrm, dict(seed=seed))
+
+
+def node_normals(V, F):
+    """Area-averaged node normals of a triangulation (the node normal of the
+    paper's double layer, Sec. 3.4.2): sum of the adjacent triangles' area
+    vectors, normalised."""
+    a, b, c = V[F[:, 0]], V[F[:, 1]], V[F[:, 2]]
+    cr = np.cross(b - a, c - a)          # 2 * area * outward normal
+    acc = np.zeros_like(V)
+    for k in range(3):
+        np.add.at(acc, F[:, k], cr)
+    return acc / np.linalg.norm(acc, axis=1, keepdims=True)
+
+
+def case_small_surface(seed: int = 5, ncap: int = 2, level: int = 2, L: float = 8.0,
+                       H: float = 2.0, alpha: float = 3.0, N: int = 48, Ny: int = 33):
+    """Small triangulated capsule surfaces for Fredholm tests.
+
+    Draw order: sphere centres (as in ``case_capsules_sl``, |y_c| <= H - 1.2,
+    centre distance >= 2.2), then a standard-normal right-hand side of shape
+    (n_nodes, 3).  Returns (SlitCase with the nodes as targets, triangles,
+    node normals, rhs).
+    """
+    rng = np.random.default_rng(seed)
+    V, F = icosphere(level)
+    cen = _place_spheres(rng, ncap, L, H - 1.2, 2.2)
+    nodes = (cen[:, None, :] + V[None]).reshape(-1, 3)
+    tri = (F[None] + (np.arange(ncap) * V.shape[0])[:, None, None]).reshape(-1, 3)
+    nrm = node_normals(nodes, tri)
+    # positions stay unwrapped so every triangle is contiguous; the evaluation
+    # wraps x and z itself
+    b = rng.standard_normal(size=nodes.shape)
+    c = SlitCase(f"surface_{ncap}x{V.shape[0]}", L, L, H, alpha, 4.0 / alpha, N, N, Ny,
+                 nodes, np.zeros_like(nodes), nodes.copy(), nrm, dict(seed=seed))
+    return c, tri.astype(np.int32), nrm, b
