@@ -192,10 +192,12 @@ int ggem_fredholm_apply(ggem_solver_t solver, long long n_nodes, const double* n
                         long long n_tri, const int* tri, const double* x, double* y);
 
 /* Solve (I + kappa/4pi D) q = b; q holds the initial guess on entry and the
- * solution on exit.  Stops when the relative residual |b - A q|/|b| <= tol or
- * after max_iter matrix-vector products in total (restarting every m).
- * *iters: products used in the Krylov iterations; *rel_res: the true relative
- * residual of the returned q (one extra product).  Non-convergence is not an
+ * solution on exit.  Each cycle of m Krylov steps starts from the true
+ * residual b - A q (one product); the solve stops when that true relative
+ * residual |b - A q|/|b| is <= tol, or once max_iter Krylov products have
+ * been spent.  A cycle ends early when the Arnoldi estimate reaches tol.
+ * *iters: Krylov products (the residual products not counted); *rel_res: the
+ * true relative residual of the returned q.  Non-convergence is not an
  * error: compare *rel_res with tol.  Returns after the plan's stream has
  * finished (every iteration reads its dot products on the host).  Errors as
  * for ggem_fredholm_apply, plus GGEM_E_ARG for tol <= 0 or max_iter < 1. */
@@ -203,6 +205,51 @@ int ggem_fredholm_solve(ggem_solver_t solver, long long n_nodes, const double* n
                         const double* normals, const double* kappa, double kappa0,
                         long long n_tri, const int* tri, const double* b, double* q,
                         double tol, int max_iter, int* iters, double* rel_res);
+
+/* ---- surface quantities of a drop suspension in simple shear ------------
+ *
+ * Helpers that keep a time-stepped suspension of drops (closed triangulated
+ * membranes with uniform tension) on the device; they run on the solver's
+ * plan stream and use its Gauss-point workspace.
+ *
+ * ggem_surface_geometry: per node, the area-averaged normal (Sec. 3.4.2),
+ * the node area A_p (one third of every incident triangle, Sec. 4) and the
+ * cotangent Laplace-Beltrami of the position
+ *   (Lap x)_p = 1/(2 A_p) sum_j (cot a_pj + cot b_pj)(x_j - x_p)
+ *             = -(1/A_p) d(surface area)/dx_p.
+ * node_tri_off (n_nodes + 1) and node_tri (node_tri_off[n_nodes]) list the
+ * triangles incident to each node (CSR, int32, device).  Outputs: normals
+ * (n_nodes,3), area (n_nodes), lap (n_nodes,3) float64, device.  Inconsistent
+ * incidence lists (a triangle out of range, or one that does not contain the
+ * node) give GGEM_E_ARG (checked on the device; one stream synchronisation).
+ * Degenerate (zero-area) triangles give non-finite outputs. */
+int ggem_surface_geometry(ggem_solver_t solver, long long n_nodes, const double* nodes,
+                          long long n_tri, const int* tri, const int* node_tri_off,
+                          const int* node_tri, double* normals, double* area, double* lap);
+
+/* Right-hand side of Eq. qa for drops of viscosity ratio lambda and tension
+ * 1/Ca in the simple shear u_inf = (shear_rate y, 0, 0) (mu = 1):
+ *   b = -(1/4pi) (dF/(lambda + 1) + kappa f_inf),  kappa = (lambda-1)/(lambda+1),
+ *   dF = -(1/Ca) Lap x  (virtual work of the tension energy, Sec. 4),
+ *   f_inf = sigma_inf . n = shear_rate (n_y, n_x, 0)  (App. B).
+ * normals, lap, b: (n_nodes,3) float64 device arrays.  Errors: GGEM_E_ARG
+ * (null, lambda <= 0, non-finite inv_ca or shear), GGEM_E_CAPACITY. */
+int ggem_drop_rhs(ggem_solver_t solver, long long n_nodes, const double* normals,
+                  const double* lap, double lambda, double inv_ca, double shear_rate, double* b);
+
+/* Velocity of Eq. bi_ua at the nodes: u = u_inf + sum int q_i G_ji dS, the
+ * integral over the three interior Gauss points of every triangle (q linear
+ * on each triangle), evaluated as 8 pi times one GGEM single layer on the
+ * solver's plan.  q, u: (n_nodes,3) float64 device arrays.  Errors as for
+ * ggem_fredholm_apply. */
+int ggem_surface_velocity(ggem_solver_t solver, long long n_nodes, const double* nodes,
+                          long long n_tri, const int* tri, const double* q, double shear_rate,
+                          double* u);
+
+/* out = x + dt u over n doubles (device; out may alias x), on the solver's
+ * plan stream: the explicit update of the node positions. */
+int ggem_advance(ggem_solver_t solver, long long n, const double* x, const double* u, double dt,
+                 double* out);
 
 /* Thread-local description of the last error on the calling thread. */
 const char* ggem_last_error(void);

@@ -19,3 +19,7 @@ from .ggem import (  # noqa: F401
     global_fields, interpolate, single_layer, double_layer,
 )
 from .fredholm import fredholm_apply, gauss_points, interpolate_to_gauss  # noqa: F401
+from .surface import (  # noqa: F401
+    node_normals, node_areas, laplace_beltrami_position, curvature, drop_rhs,
+    surface_velocity,
+)

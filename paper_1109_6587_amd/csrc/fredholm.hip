@@ -329,19 +329,16 @@ extern "C" int ggem_fredholm_solve(ggem_solver_t s, long long n_nodes, const dou
   std::vector<double> Hm((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), h(m + 1), h2(m + 1), y(m);
   int total = 0;
   double res = 0.0;
-  bool converged = false;
-  while (total < max_iter && !converged) {
-    // r = b - A q, V_0 = r / |r|
+  for (;;) {
+    // true residual r = b - A q; stop on it (the Arnoldi estimate can be
+    // optimistic when the products carry FP32 rounding)
     if (int rc = apply(s, q, s->w)) return rc;
     sub_into<<<nb, 256, 0, st>>>(n, b, s->w, s->r);
     double beta2;
     if (int rc = dots(s, s->r, 0, 1, s->r, n, &beta2)) return rc;
     const double beta = sqrt(beta2);
     res = beta / bnorm;
-    if (res <= tol) {
-      converged = true;
-      break;
-    }
+    if (res <= tol || total >= max_iter) break;
     scale_copy<<<nb, 256, 0, st>>>(n, 1.0 / beta, s->r, s->V);
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
@@ -370,17 +367,16 @@ extern "C" int ggem_fredholm_solve(ggem_solver_t s, long long n_nodes, const dou
         h[i] = t;
       }
       const double den = hypot(h[j], h[j + 1]);
-      cs[j] = den > 0 ? h[j] / den : 1.0;
-      sn[j] = den > 0 ? h[j + 1] / den : 0.0;
+      if (!(den > 0)) break;  // A V_j = 0 within the basis: keep the j columns so far
+      cs[j] = h[j] / den;
+      sn[j] = h[j + 1] / den;
       h[j] = den;
       h[j + 1] = 0.0;
       g[j + 1] = -sn[j] * g[j];
       g[j] = cs[j] * g[j];
       for (int i = 0; i <= j; ++i) Hm[(size_t)i * m + j] = h[i];
-      res = fabs(g[j + 1]) / bnorm;
-      if (res <= tol) {
+      if (fabs(g[j + 1]) / bnorm <= tol) {
         ++j;
-        converged = true;
         break;
       }
     }
@@ -397,12 +393,193 @@ extern "C" int ggem_fredholm_solve(ggem_solver_t s, long long n_nodes, const dou
       SOLVER_TRY(hipGetLastError());
     }
   }
-  // true relative residual of the returned q
-  if (int rc = apply(s, q, s->w)) return rc;
-  sub_into<<<nb, 256, 0, st>>>(n, b, s->w, s->r);
-  double rr;
-  if (int rc = dots(s, s->r, 0, 1, s->r, n, &rr)) return rc;
   if (iters) *iters = total;
-  if (rel_res) *rel_res = sqrt(rr) / bnorm;
+  if (rel_res) *rel_res = res;
+  return GGEM_OK;
+}
+
+// ---- surface quantities of a drop suspension ------------------------------
+
+namespace {
+
+// Per node: area-averaged normal (Sec. 3.4.2), node area (one third of each
+// incident triangle, Sec. 4) and the cotangent Laplace-Beltrami of the
+// position, (Lap x)_i = 1/(2 A_i) sum (cot a + cot b)(x_j - x_i), gathered
+// over the node's incident triangles (fixed order, no atomics).  A node
+// whose incidence list names a triangle out of range, or a triangle that
+// does not contain the node or has a corner out of range, raises *bad.
+__global__ void surface_geometry(int nnode, int ntri, const double* __restrict__ xn,
+                                 const int* __restrict__ tri, const int* __restrict__ off,
+                                 const int* __restrict__ adj, double* __restrict__ nrm,
+                                 double* __restrict__ area, double* __restrict__ lap,
+                                 int* __restrict__ bad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nnode) return;
+  const int b0 = off[i], b1 = off[i + 1];
+  if (b0 < 0 || b1 < b0 || b1 > 3 * ntri) {
+    atomicOr(bad, 1);
+    return;
+  }
+  const double xi0 = xn[3 * (size_t)i], xi1 = xn[3 * (size_t)i + 1], xi2 = xn[3 * (size_t)i + 2];
+  double an0 = 0, an1 = 0, an2 = 0, A = 0, l0 = 0, l1 = 0, l2 = 0;
+  for (int e = b0; e < b1; ++e) {
+    const int t = adj[e];
+    if ((unsigned)t >= (unsigned)ntri) {
+      atomicOr(bad, 1);
+      return;
+    }
+    const int a = tri[3 * t], b = tri[3 * t + 1], c = tri[3 * t + 2];
+    int j, k;
+    if (a == i) {
+      j = b;
+      k = c;
+    } else if (b == i) {
+      j = c;
+      k = a;
+    } else if (c == i) {
+      j = a;
+      k = b;
+    } else {
+      atomicOr(bad, 1);
+      return;
+    }
+    if ((unsigned)j >= (unsigned)nnode || (unsigned)k >= (unsigned)nnode) {
+      atomicOr(bad, 1);
+      return;
+    }
+    const double ej0 = xn[3 * (size_t)j] - xi0, ej1 = xn[3 * (size_t)j + 1] - xi1,
+                 ej2 = xn[3 * (size_t)j + 2] - xi2;
+    const double ek0 = xn[3 * (size_t)k] - xi0, ek1 = xn[3 * (size_t)k + 1] - xi1,
+                 ek2 = xn[3 * (size_t)k + 2] - xi2;
+    // twice the area vector (orientation of the triangle as given)
+    const double c0 = ej1 * ek2 - ej2 * ek1, c1 = ej2 * ek0 - ej0 * ek2, c2 = ej0 * ek1 - ej1 * ek0;
+    const double cn = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+    an0 += c0;
+    an1 += c1;
+    an2 += c2;
+    A += cn / 6.0;
+    // cot of the angle at k (faces edge i-j) and at j (faces edge i-k)
+    const double jk0 = ek0 - ej0, jk1 = ek1 - ej1, jk2 = ek2 - ej2;  // x_k - x_j
+    const double cot_k = ((-ek0) * (ej0 - ek0) + (-ek1) * (ej1 - ek1) + (-ek2) * (ej2 - ek2)) / cn;
+    const double cot_j = ((-ej0) * jk0 + (-ej1) * jk1 + (-ej2) * jk2) / cn;
+    l0 += cot_k * ej0 + cot_j * ek0;
+    l1 += cot_k * ej1 + cot_j * ek1;
+    l2 += cot_k * ej2 + cot_j * ek2;
+  }
+  const double inv = 1.0 / sqrt(an0 * an0 + an1 * an1 + an2 * an2);
+  nrm[3 * (size_t)i] = an0 * inv;
+  nrm[3 * (size_t)i + 1] = an1 * inv;
+  nrm[3 * (size_t)i + 2] = an2 * inv;
+  area[i] = A;
+  const double s = 1.0 / (2.0 * A);
+  lap[3 * (size_t)i] = l0 * s;
+  lap[3 * (size_t)i + 1] = l1 * s;
+  lap[3 * (size_t)i + 2] = l2 * s;
+}
+
+// b = -(1/4pi) (dF/(lambda+1) + kappa f_inf), dF = -(1/Ca) Lap x,
+// f_inf = shear (n_y, n_x, 0)
+__global__ void drop_rhs_kernel(int nnode, const double* __restrict__ nrm,
+                                const double* __restrict__ lap, double lam, double inv_ca,
+                                double shear, double* __restrict__ b) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nnode) return;
+  const double kappa = (lam - 1.0) / (lam + 1.0);
+  const double s = -1.0 / (4.0 * M_PI);
+  const double fi[3] = {shear * nrm[3 * (size_t)i + 1], shear * nrm[3 * (size_t)i], 0.0};
+  for (int d = 0; d < 3; ++d) {
+    const double df = -inv_ca * lap[3 * (size_t)i + d];
+    b[3 * (size_t)i + d] = s * (df / (lam + 1.0) + kappa * fi[d]);
+  }
+}
+
+// u = (shear y, 0, 0) + 8 pi u_sl
+__global__ void velocity_finish(int nnode, const double* __restrict__ xn, double shear,
+                                double* __restrict__ u) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nnode) return;
+  const double e = 8.0 * M_PI;
+  u[3 * (size_t)i] = fma(e, u[3 * (size_t)i], shear * xn[3 * (size_t)i + 1]);
+  u[3 * (size_t)i + 1] *= e;
+  u[3 * (size_t)i + 2] *= e;
+}
+
+__global__ void axpy_out(long long n, const double* __restrict__ x, const double* __restrict__ u,
+                         double dt, double* __restrict__ out) {
+  const long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (j < n) out[j] = fma(dt, u[j], x[j]);
+}
+
+}  // namespace
+
+static int read_flag(ggem_solver_s* s, const char* msg) {
+  hipStream_t st = s->plan->p.stream;
+  SOLVER_TRY(hipGetLastError());
+  SOLVER_TRY(hipMemcpyAsync(s->bad_host, s->bad, sizeof(int), hipMemcpyDeviceToHost, st));
+  SOLVER_TRY(hipStreamSynchronize(st));
+  if (*s->bad_host) return ggem_set_error(GGEM_E_ARG, msg);
+  return GGEM_OK;
+}
+
+extern "C" int ggem_surface_geometry(ggem_solver_t s, long long n_nodes, const double* nodes,
+                                     long long n_tri, const int* tri, const int* node_tri_off,
+                                     const int* node_tri, double* normals, double* area,
+                                     double* lap) {
+  if (!s) return ggem_set_error(GGEM_E_ARG, "null solver");
+  if (n_nodes < 1 || n_tri < 1) return ggem_set_error(GGEM_E_ARG, "empty surface");
+  if (n_nodes > s->max_nodes || n_tri > s->max_tri)
+    return ggem_set_error(GGEM_E_CAPACITY, "surface exceeds the solver capacity");
+  if (!nodes || !tri || !node_tri_off || !node_tri || !normals || !area || !lap)
+    return ggem_set_error(GGEM_E_ARG, "null array");
+  hipStream_t st = s->plan->p.stream;
+  const int n = (int)n_nodes;
+  fill_ints<<<1, 64, 0, st>>>(s->bad, 1, 0);
+  surface_geometry<<<(n + 255) / 256, 256, 0, st>>>(n, (int)n_tri, nodes, tri, node_tri_off,
+                                                    node_tri, normals, area, lap, s->bad);
+  return read_flag(s, "inconsistent triangle incidence lists");
+}
+
+extern "C" int ggem_drop_rhs(ggem_solver_t s, long long n_nodes, const double* normals,
+                             const double* lap, double lambda, double inv_ca, double shear_rate,
+                             double* b) {
+  if (!s) return ggem_set_error(GGEM_E_ARG, "null solver");
+  if (n_nodes < 1 || n_nodes > s->max_nodes)
+    return ggem_set_error(GGEM_E_CAPACITY, "node count outside 1..capacity");
+  if (!normals || !lap || !b) return ggem_set_error(GGEM_E_ARG, "null array");
+  if (!(lambda > 0) || !isfinite(inv_ca) || !isfinite(shear_rate))
+    return ggem_set_error(GGEM_E_ARG, "lambda must be positive, inv_ca and shear finite");
+  const int n = (int)n_nodes;
+  drop_rhs_kernel<<<(n + 255) / 256, 256, 0, s->plan->p.stream>>>(n, normals, lap, lambda, inv_ca,
+                                                                  shear_rate, b);
+  SOLVER_TRY(hipGetLastError());
+  return GGEM_OK;
+}
+
+extern "C" int ggem_surface_velocity(ggem_solver_t s, long long n_nodes, const double* nodes,
+                                     long long n_tri, const int* tri, const double* q,
+                                     double shear_rate, double* u) {
+  if (!s) return ggem_set_error(GGEM_E_ARG, "null solver");
+  if (!q || !u) return ggem_set_error(GGEM_E_ARG, "null vector");
+  if (!isfinite(shear_rate)) return ggem_set_error(GGEM_E_ARG, "shear rate must be finite");
+  // the normals are not used by the single layer; the node array stands in
+  if (int rc = set_geometry(s, n_nodes, nodes, nodes, nullptr, 0.0, n_tri, tri)) return rc;
+  hipStream_t st = s->plan->p.stream;
+  gauss_strengths<<<(s->n_tri + 255) / 256, 256, 0, st>>>(s->n_tri, s->tri, q, s->gw, s->gs);
+  SOLVER_TRY(hipGetLastError());
+  int rc = ggem_single_layer(s->plan, 3LL * s->n_tri, s->gpos, s->gs, s->n_nodes, s->nodes, u,
+                             GGEM_PART_ALL);
+  if (rc) return rc;
+  velocity_finish<<<(s->n_nodes + 255) / 256, 256, 0, st>>>(s->n_nodes, nodes, shear_rate, u);
+  SOLVER_TRY(hipGetLastError());
+  return GGEM_OK;
+}
+
+extern "C" int ggem_advance(ggem_solver_t s, long long n, const double* x, const double* u,
+                            double dt, double* out) {
+  if (!s) return ggem_set_error(GGEM_E_ARG, "null solver");
+  if (n < 0 || (n > 0 && (!x || !u || !out))) return ggem_set_error(GGEM_E_ARG, "bad arrays");
+  if (n == 0) return GGEM_OK;
+  axpy_out<<<(unsigned)((n + 255) / 256), 256, 0, s->plan->p.stream>>>(n, x, u, dt, out);
+  SOLVER_TRY(hipGetLastError());
   return GGEM_OK;
 }

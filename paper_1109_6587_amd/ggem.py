@@ -30,7 +30,8 @@ EXPORTS = (
     "ggem_plan_create", "ggem_plan_destroy", "ggem_plan_set_stream", "ggem_plan_status",
     "ggem_single_layer", "ggem_double_layer", "ggem_spread_grid", "ggem_plan_time_stage",
     "ggem_plan_stage_time", "ggem_plan_work", "ggem_solver_create", "ggem_solver_destroy",
-    "ggem_fredholm_apply", "ggem_fredholm_solve", "ggem_last_error",
+    "ggem_fredholm_apply", "ggem_fredholm_solve", "ggem_surface_geometry", "ggem_drop_rhs",
+    "ggem_surface_velocity", "ggem_advance", "ggem_last_error",
 )
 
 STAGES = ("bin", "near", "wall", "spread", "fft_fwd", "cheb_fwd", "tau", "cheb_inv",
@@ -87,6 +88,10 @@ def load_library(path: str = LIB_PATH):
     lib.ggem_fredholm_apply.argtypes = [vp, ll, dp, dp, dp, dd, ll, dp, dp, dp]
     lib.ggem_fredholm_solve.argtypes = [vp, ll, dp, dp, dp, dd, ll, dp, dp, dp, dd, ip,
                                         ctypes.POINTER(ip), ctypes.POINTER(dd)]
+    lib.ggem_surface_geometry.argtypes = [vp, ll, dp, ll, dp, dp, dp, dp, dp, dp]
+    lib.ggem_drop_rhs.argtypes = [vp, ll, dp, dp, dd, dd, dd, dp]
+    lib.ggem_surface_velocity.argtypes = [vp, ll, dp, ll, dp, dp, dd, dp]
+    lib.ggem_advance.argtypes = [vp, ll, dp, dp, dd, dp]
     lib.ggem_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name != "ggem_last_error":
@@ -223,6 +228,10 @@ class Surface:
         if isinstance(kappa, (int, float)):
             self.kappa, self.kappa0 = None, float(kappa)
         else:
+            if (not isinstance(kappa, torch.Tensor) or not kappa.is_cuda
+                    or kappa.dtype != torch.float64 or kappa.shape != (nodes.shape[0],)
+                    or not kappa.is_contiguous()):
+                raise TypeError("kappa must be a float or a contiguous (n,) float64 device tensor")
             self.kappa, self.kappa0 = kappa, 0.0
 
     def args(self):
@@ -269,3 +278,56 @@ class FredholmSolver:
                                         _dev_ptr(q, "q"), float(tol), int(max_iter),
                                         ctypes.byref(it), ctypes.byref(rr)))
         return it.value, rr.value
+
+    def geometry(self, nodes, tri, node_tri_off, node_tri):
+        """Node normals, areas and Lap x of a triangulation (ggem_surface_geometry)."""
+        import torch
+        n = nodes.shape[0]
+        _int_dev(tri, "tri", 2)
+        _int_dev(node_tri_off, "node_tri_off", 1, n + 1)
+        _int_dev(node_tri, "node_tri", 1)
+        nrm = torch.empty_like(nodes)
+        lap = torch.empty_like(nodes)
+        area = torch.empty((n,), dtype=torch.float64, device=nodes.device)
+        _check(_lib.ggem_surface_geometry(self._h, n, _dev_ptr(nodes, "nodes"), tri.shape[0],
+                                          tri.data_ptr(), node_tri_off.data_ptr(),
+                                          node_tri.data_ptr(), nrm.data_ptr(), area.data_ptr(),
+                                          lap.data_ptr()))
+        return nrm, area, lap
+
+    def drop_rhs(self, normals, lap, lam, inv_ca, shear, out=None):
+        import torch
+        n = normals.shape[0]
+        out = torch.empty_like(normals) if out is None else out
+        _check(_lib.ggem_drop_rhs(self._h, n, _dev_ptr(normals, "normals"), _dev_ptr(lap, "lap", n),
+                                  float(lam), float(inv_ca), float(shear), _dev_ptr(out, "out", n)))
+        return out
+
+    def velocity(self, nodes, tri, q, shear, out=None):
+        import torch
+        n = nodes.shape[0]
+        _int_dev(tri, "tri", 2)
+        out = torch.empty_like(nodes) if out is None else out
+        _check(_lib.ggem_surface_velocity(self._h, n, _dev_ptr(nodes, "nodes"), tri.shape[0],
+                                          tri.data_ptr(), _dev_ptr(q, "q", n), float(shear),
+                                          _dev_ptr(out, "out", n)))
+        return out
+
+    def advance(self, x, u, dt, out=None):
+        import torch
+        n = x.shape[0]
+        out = torch.empty_like(x) if out is None else out
+        _check(_lib.ggem_advance(self._h, 3 * n, _dev_ptr(x, "x"), _dev_ptr(u, "u", n), float(dt),
+                                 _dev_ptr(out, "out", n)))
+        return out
+
+
+def _int_dev(t, name, dim, n=None):
+    import torch
+    if (not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.int32
+            or t.dim() != dim or not t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous {dim}-d int32 device tensor")
+    if dim == 2 and t.shape[1] != 3:
+        raise ValueError(f"{name} must have 3 columns")
+    if n is not None and t.shape[0] != n:
+        raise ValueError(f"{name} must have {n} entries")

@@ -75,3 +75,98 @@ def test_fredholm_nonconvergence_reported(surf):
     q = torch.zeros((c.nt, 3), dtype=torch.float64, device=DEV)
     iters, rel = solver.solve(S, dev(b), q, tol=1e-16, max_iter=2)
     assert iters == 2 and rel > 1e-16
+
+
+# ---- surface quantities and the drop driver --------------------------------
+
+from paper_1109_6587_amd.drops import DropSuspension, incidence  # noqa: E402
+from workloads import case_shear_drops  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def drops():
+    c = case_shear_drops(4, level=2, ncap=3, N=32, Ny=33)
+    g = O.SlitGrid(c.Lx, c.Lz, c.H, c.alpha, c.rc, c.Nx, c.Nz, c.Ny)
+    return c, g
+
+
+def make_solver(c, precision="fp64"):
+    plan = G.Plan(c.Lx, c.Lz, c.H, c.alpha, c.Nx, c.Nz, c.Ny, rc=c.rc, precision=precision,
+                  max_src=3 * len(c.tri), max_tgt=len(c.nodes))
+    return plan, G.FredholmSolver(plan, len(c.nodes), len(c.tri), restart=10)
+
+
+def test_surface_geometry_and_rhs(drops):
+    c, g = drops
+    print("surface geometry", flush=True)
+    plan, s = make_solver(c)
+    off, adj = incidence(c.tri, len(c.nodes))
+    x = dev(c.nodes)
+    nrm, area, lap = s.geometry(x, dev(c.tri, torch.int32), dev(off, torch.int32),
+                                dev(adj, torch.int32))
+    rn = O.node_normals(c.nodes, c.tri)
+    ra = O.node_areas(c.nodes, c.tri)
+    rl = O.laplace_beltrami_position(c.nodes, c.tri)
+    assert np.abs(nrm.cpu().numpy() - rn).max() < 1e-13
+    assert np.abs(area.cpu().numpy() - ra).max() < 1e-13 * ra.max()
+    assert np.abs(lap.cpu().numpy() - rl).max() < 1e-12 * np.abs(rl).max()
+    b = s.drop_rhs(nrm, lap, c.lam, c.inv_ca, c.shear).cpu().numpy()
+    rb = O.drop_rhs(rn, rl, c.lam, c.inv_ca, c.shear)
+    assert np.abs(b - rb).max() < 1e-12 * np.abs(rb).max()
+
+
+def test_surface_geometry_rejects_bad_incidence(drops):
+    c, _ = drops
+    plan, s = make_solver(c)
+    off, adj = incidence(c.tri, len(c.nodes))
+    adj = adj.copy()
+    adj[5] = (adj[5] + 7) % len(c.tri)   # a triangle that does not hold the node
+    with pytest.raises(G.GGEMError):
+        s.geometry(dev(c.nodes), dev(c.tri, torch.int32), dev(off, torch.int32),
+                   dev(adj, torch.int32))
+    bad_tri = c.tri.copy()
+    bad_tri[3, 1] = len(c.nodes) + 5
+    S = G.Surface(dev(c.nodes), dev(O.node_normals(c.nodes, c.tri)), dev(bad_tri, torch.int32), 0.5)
+    with pytest.raises(G.GGEMError):
+        s.apply(S, dev(np.zeros_like(c.nodes)))
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_surface_velocity(drops, precision, tol):
+    c, g = drops
+    print(f"surface velocity {precision}", flush=True)
+    plan, s = make_solver(c, precision)
+    q = np.random.default_rng(3).standard_normal(c.nodes.shape)
+    u = s.velocity(dev(c.nodes), dev(c.tri, torch.int32), dev(q), c.shear).cpu().numpy()
+    ref = O.surface_velocity(g, c.nodes, c.tri, q, c.shear)
+    dist = ref.copy()
+    dist[:, 0] -= c.shear * c.nodes[:, 1]       # the disturbance alone
+    assert np.linalg.norm((u - ref)) / np.linalg.norm(dist) < tol
+    x2 = s.advance(dev(c.nodes), dev(ref), 0.25).cpu().numpy()
+    assert np.abs(x2 - (c.nodes + 0.25 * ref)).max() < 1e-14 * np.abs(c.nodes).max()
+
+
+def drop_volumes(x, tri, ncap, nv):
+    a, b, cc = x[tri[:, 0]], x[tri[:, 1]], x[tri[:, 2]]
+    vol = np.einsum("ij,ij->i", a, np.cross(b, cc)) / 6.0
+    return vol.reshape(ncap, -1).sum(axis=1)
+
+
+def test_drop_steps_conserve_volume(drops):
+    """Two midpoint steps: every solve reaches 1e-6 and the incompressible
+    flow keeps each drop's volume (to the discretisation error)."""
+    c, _ = drops
+    print("drop steps", flush=True)
+    sim = DropSuspension(c, precision="mixed", restart=10, tol=1e-6)
+    v0 = drop_volumes(c.nodes, c.tri, c.ncap, c.nv)
+    for _ in range(2):
+        sim.step()
+    x = sim.x.cpu().numpy()
+    v1 = drop_volumes(x, c.tri, c.ncap, c.nv)
+    assert all(r.rel_res <= 1e-6 for r in sim.records)
+    assert len(sim.records) == 4
+    assert np.abs(x - c.nodes).max() > 1e-2   # the shear did move the drops
+    # the oracle's flux of u through these meshes is about 1.1 % of the drop
+    # volume per unit time (point quadrature of the single layer); allow 5 %
+    t_total = 2 * c.dt
+    assert np.abs(v1 / v0 - 1).max() < 0.05 * t_total

@@ -13,4 +13,6 @@ from .inputs import (  # noqa: F401
     random_case,
     node_normals,
     case_small_surface,
+    DropCase,
+    case_shear_drops,
 )

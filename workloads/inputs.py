@@ -327,3 +327,70 @@ def case_small_surface(seed: int = 5, ncap: int = 2, level: int = 2, L: float = 
     c = SlitCase(f"surface_{ncap}x{V.shape[0]}", L, L, H, alpha, 4.0 / alpha, N, N, Ny,
                  nodes, np.zeros_like(nodes), nodes.copy(), nrm, dict(seed=seed))
     return c, tri.astype(np.int32), nrm, b
+
+
+def _real_sph_harm(l, m, theta, phi):
+    """Real spherical harmonic of degree l, order m (theta polar, phi azimuth)."""
+    from scipy.special import sph_harm_y
+    if m == 0:
+        return np.real(sph_harm_y(l, 0, theta, phi))
+    y = sph_harm_y(l, abs(m), theta, phi)
+    return math.sqrt(2.0) * (np.real(y) if m > 0 else np.imag(y))
+
+
+@dataclass
+class DropCase:
+    """Drops in simple shear between walls (the Fredholm workload)."""
+    name: str
+    Lx: float
+    Lz: float
+    H: float
+    alpha: float
+    rc: float
+    Nx: int
+    Nz: int
+    Ny: int
+    nodes: np.ndarray        # (ncap * nv, 3) unwrapped positions
+    tri: np.ndarray          # (ncap * nf, 3) int32, outward orientation
+    ncap: int
+    nv: int
+    lam: float               # viscosity ratio
+    inv_ca: float            # tension / (mu shear a)
+    shear: float
+    dt: float
+    steps: int
+    meta: dict
+
+
+def case_shear_drops(seed: int = 4, level: int = 3, ncap: int = 100, L: float = 16.0,
+                     H: float = 4.0, N: int = 64, Ny: int = 33) -> DropCase:
+    """100 drops of 642 nodes in a 16 x 8 x 16 slit in simple shear.
+
+    Draw order: the 100 occupied sites of a 6 x 3 x 6 lattice (cell centres in
+    x and z, y layers at -2.55, 0, 2.55) as ``rng.choice(108, 100,
+    replace=False)``; per site a jitter ``rng.uniform(-1, 1, 3) * (0.1, 0.05,
+    0.1)``; per drop the 24 coefficients c_lm ~ N(0, 1) of the real spherical
+    harmonics of degrees 1..4 (l-major, m = -l..l), the radial perturbation
+    sum c_lm Y_lm scaled so that its largest magnitude over the nodes is 0.1.
+    Viscosity ratio 5, Ca = 0.5, shear rate 1, dt = 0.01, 200 steps; alpha = 2.
+    """
+    rng = np.random.default_rng(seed)
+    V, F = icosphere(level)
+    sites = np.array([((i + 0.5) * L / 6, y, (k + 0.5) * L / 6)
+                      for i in range(6) for y in (-2.55, 0.0, 2.55) for k in range(6)])
+    pick = np.sort(rng.choice(len(sites), ncap, replace=False))
+    theta = np.arccos(np.clip(V[:, 1], -1, 1))      # polar angle about y
+    phi = np.arctan2(V[:, 0], V[:, 2])
+    Y = np.stack([_real_sph_harm(l, m, theta, phi) for l in range(1, 5) for m in range(-l, l + 1)],
+                 axis=1)
+    nodes = []
+    for s in pick:
+        cen = sites[s] + rng.uniform(-1, 1, 3) * np.array([0.1, 0.05, 0.1])
+        pert = Y @ rng.standard_normal(Y.shape[1])
+        pert *= 0.1 / np.abs(pert).max()
+        nodes.append(cen + V * (1.0 + pert)[:, None])
+    nodes = np.concatenate(nodes)
+    tri = (F[None] + (np.arange(ncap) * V.shape[0])[:, None, None]).reshape(-1, 3)
+    return DropCase(f"shear_drops_{ncap}x{V.shape[0]}", L, L, H, 2.0, 2.0, N, N, Ny, nodes,
+                    tri.astype(np.int32), ncap, V.shape[0], 5.0, 2.0, 1.0, 0.01, 200,
+                    dict(seed=seed, level=level))
