@@ -251,6 +251,69 @@ int ggem_surface_velocity(ggem_solver_t solver, long long n_nodes, const double*
 int ggem_advance(ggem_solver_t solver, long long n, const double* x, const double* u, double dt,
                  double* out);
 
+/* GMRES as ggem_fredholm_solve, started from q + c dq: after the first
+ * residual r = b - A q, one more product gives A dq and
+ *   c = max(0, (r . A dq) / |A dq|^2)
+ * (the least-squares step along dq; 0 when dq does not lower the residual),
+ * so the starting residual is never larger than that of q alone.  dq: a
+ * proposed correction (n_nodes,3) float64 device array, not aliasing q
+ * (e.g. the learned warm start below).  *step (host, may be NULL): c.  Costs
+ * one product more than ggem_fredholm_solve, not counted in *iters. */
+int ggem_fredholm_solve_guided(ggem_solver_t solver, long long n_nodes, const double* nodes,
+                               const double* normals, const double* kappa, double kappa0,
+                               long long n_tri, const int* tri, const double* b, double* q,
+                               const double* dq, double tol, int max_iter, int* iters,
+                               double* rel_res, double* step);
+
+/* ---- learned warm start: a per-node network ------------------------------
+ *
+ * Not in the paper, whose warm start is the previous stage's density
+ * (Sec. 3.5).  A network of GGEM_MLP_IN inputs, three hidden layers of
+ * GGEM_MLP_HIDDEN units with SiLU, and GGEM_MLP_OUT outputs, trained by mean
+ * squared error with Adam (beta1 0.9, beta2 0.999, eps 1e-8).  Products run
+ * with bfloat16 operands and FP32 accumulation; master weights, biases and
+ * Adam moments are FP32.  Parameters are one packed FP32 vector of
+ * GGEM_MLP_PARAMS values: W1 (128x13 row-major, [out][in]), b1, W2, b2, W3,
+ * b3, W4 (3x128), b4.  Samples are row-major: X (n, 13), T and Y (n, 3).
+ * All arrays are device memory owned by the caller; work runs on the stream
+ * given at creation.  Errors: GGEM_E_ARG (null, bad value), GGEM_E_CAPACITY
+ * (n outside 1..max_batch), GGEM_E_NOMEM, GGEM_E_DEVICE. */
+#define GGEM_MLP_IN 13
+#define GGEM_MLP_HIDDEN 128
+#define GGEM_MLP_OUT 3
+#define GGEM_MLP_PARAMS 35203
+
+typedef struct ggem_mlp_s* ggem_mlp_t;
+
+int ggem_mlp_create(int max_batch, void* hip_stream, ggem_mlp_t* out);
+int ggem_mlp_destroy(ggem_mlp_t mlp);
+/* Copy in the parameters (and reset the Adam moments and step count). */
+int ggem_mlp_set_params(ggem_mlp_t mlp, const float* params);
+int ggem_mlp_get_params(ggem_mlp_t mlp, float* params);
+/* Node features, scaled feature by feature by scales[13] (host array):
+ * position relative to the centroid of the node's drop (drops are
+ * consecutive groups of nodes_per_drop nodes), normal, curvature term
+ * c = -(Lap x) . n (see ggem_surface_geometry), the previous density q_prev
+ * and its last change dq_prev (q_prev minus the density before it).
+ * nodes, normals, lap, q_prev, dq_prev: (n_nodes,3) float64; X: (n_nodes,13)
+ * float32. */
+int ggem_mlp_features(ggem_mlp_t mlp, long long n_nodes, const double* nodes,
+                      const double* normals, const double* lap, const double* q_prev,
+                      const double* dq_prev, int nodes_per_drop, const float* scales, float* X);
+/* Y = network(X) (float32). */
+int ggem_mlp_forward(ggem_mlp_t mlp, long long n, const float* X, float* Y);
+/* dq = scale * network(X) as float64 (n,3): the learned density correction. */
+int ggem_mlp_predict(ggem_mlp_t mlp, long long n, const float* X, double scale, double* dq);
+/* Loss mean((Y - T)^2) and its gradient (packed like the parameters) into
+ * grads (device, may be NULL); *loss (host, may be NULL; waits for the
+ * stream). */
+int ggem_mlp_gradients(ggem_mlp_t mlp, long long n, const float* X, const float* T, float* grads,
+                       float* loss);
+/* One Adam step on the batch (X, T) with learning rate lr; *loss as above,
+ * for the parameters before the step. */
+int ggem_mlp_train_step(ggem_mlp_t mlp, long long n, const float* X, const float* T, float lr,
+                        float* loss);
+
 /* Thread-local description of the last error on the calling thread. */
 const char* ggem_last_error(void);
 

@@ -23,3 +23,4 @@ from .surface import (  # noqa: F401
     node_normals, node_areas, laplace_beltrami_position, curvature, drop_rhs,
     surface_velocity,
 )
+from . import mlp  # noqa: F401

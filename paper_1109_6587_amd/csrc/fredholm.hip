@@ -303,10 +303,12 @@ extern "C" int ggem_fredholm_apply(ggem_solver_t s, long long n_nodes, const dou
   return apply(s, x, y);
 }
 
-extern "C" int ggem_fredholm_solve(ggem_solver_t s, long long n_nodes, const double* nodes,
-                                   const double* normals, const double* kappa, double kappa0,
-                                   long long n_tri, const int* tri, const double* b, double* q,
-                                   double tol, int max_iter, int* iters, double* rel_res) {
+// GMRES(m) from the guess q; with dq, the first residual is first reduced
+// along A dq (see ggem_fredholm_solve_guided).
+static int solve_impl(ggem_solver_t s, long long n_nodes, const double* nodes,
+                      const double* normals, const double* kappa, double kappa0, long long n_tri,
+                      const int* tri, const double* b, double* q, const double* dq, double tol,
+                      int max_iter, int* iters, double* rel_res, double* step) {
   if (!s) return ggem_set_error(GGEM_E_ARG, "null solver");
   if (!b || !q) return ggem_set_error(GGEM_E_ARG, "null vector");
   if (!(tol > 0) || max_iter < 1) return ggem_set_error(GGEM_E_ARG, "bad tolerance or max_iter");
@@ -329,11 +331,29 @@ extern "C" int ggem_fredholm_solve(ggem_solver_t s, long long n_nodes, const dou
   std::vector<double> Hm((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), h(m + 1), h2(m + 1), y(m);
   int total = 0;
   double res = 0.0;
+  bool first = true;
+  if (step) *step = 0.0;
   for (;;) {
     // true residual r = b - A q; stop on it (the Arnoldi estimate can be
     // optimistic when the products carry FP32 rounding)
     if (int rc = apply(s, q, s->w)) return rc;
     sub_into<<<nb, 256, 0, st>>>(n, b, s->w, s->r);
+    if (first && dq) {
+      // c = argmin |r - c A dq| over c >= 0; q += c dq, r -= c A dq
+      if (int rc = apply(s, dq, s->w)) return rc;
+      double rw, ww;
+      if (int rc = dots(s, s->r, 0, 1, s->w, n, &rw)) return rc;
+      if (int rc = dots(s, s->w, 0, 1, s->w, n, &ww)) return rc;
+      const double c = (ww > 0.0 && rw > 0.0) ? rw / ww : 0.0;
+      if (c > 0.0) {
+        SOLVER_TRY(hipMemcpyAsync(s->coef, &c, 8, hipMemcpyHostToDevice, st));
+        multi_axpy<<<nb, 256, 0, st>>>(n, 1, dq, 0, s->coef, 1.0, q);
+        multi_axpy<<<nb, 256, 0, st>>>(n, 1, s->w, 0, s->coef, -1.0, s->r);
+        SOLVER_TRY(hipStreamSynchronize(st));  // c lives on this stack frame
+      }
+      if (step) *step = c;
+    }
+    first = false;
     double beta2;
     if (int rc = dots(s, s->r, 0, 1, s->r, n, &beta2)) return rc;
     const double beta = sqrt(beta2);
@@ -396,6 +416,25 @@ extern "C" int ggem_fredholm_solve(ggem_solver_t s, long long n_nodes, const dou
   if (iters) *iters = total;
   if (rel_res) *rel_res = res;
   return GGEM_OK;
+}
+
+extern "C" int ggem_fredholm_solve(ggem_solver_t s, long long n_nodes, const double* nodes,
+                                   const double* normals, const double* kappa, double kappa0,
+                                   long long n_tri, const int* tri, const double* b, double* q,
+                                   double tol, int max_iter, int* iters, double* rel_res) {
+  return solve_impl(s, n_nodes, nodes, normals, kappa, kappa0, n_tri, tri, b, q, nullptr, tol,
+                    max_iter, iters, rel_res, nullptr);
+}
+
+extern "C" int ggem_fredholm_solve_guided(ggem_solver_t s, long long n_nodes, const double* nodes,
+                                          const double* normals, const double* kappa,
+                                          double kappa0, long long n_tri, const int* tri,
+                                          const double* b, double* q, const double* dq,
+                                          double tol, int max_iter, int* iters, double* rel_res,
+                                          double* step) {
+  if (!dq) return ggem_set_error(GGEM_E_ARG, "null correction");
+  return solve_impl(s, n_nodes, nodes, normals, kappa, kappa0, n_tri, tri, b, q, dq, tol,
+                    max_iter, iters, rel_res, step);
 }
 
 // ---- surface quantities of a drop suspension ------------------------------

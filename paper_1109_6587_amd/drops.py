@@ -90,19 +90,22 @@ class DropSuspension:
     def stage(self, x, q0, stage, hook=None):
         nrm, area, lap = self.geometry(x)
         b = self.rhs(nrm, lap)
-        guess = q0 if hook is None else hook(x, nrm, area, lap, b, q0, stage)
-        q, it, rr, sec = self.solve(x, nrm, b, guess)
+        if hook is not None:
+            hook.before(x, nrm, lap, b, q0, stage)
+        q, it, rr, sec = self.solve(x, nrm, b, q0)
         self.records.append(SolveRecord(self.step_index, stage, it, rr, sec))
         if rr > self.tol:
             raise RuntimeError(f"GMRES stalled at step {self.step_index} stage {stage}: "
                                f"relative residual {rr:.3e} after {it} products")
+        if hook is not None:
+            hook.after(q)
         u = self.solver.velocity(x, self.tri, q, self.c.shear)
         return u, q
 
     def step(self, hook=None):
-        """One explicit midpoint step; the plain warm start of each solve is
-        the previous stage's density.  `hook(x, normals, area, lap, b, q_prev,
-        stage)` may return another initial guess."""
+        """One explicit midpoint step; the warm start of each solve is the
+        previous stage's density.  `hook.before(x, normals, lap, b, q_prev,
+        stage)` and `hook.after(q)` see every solve (e.g. to record it)."""
         dt = self.c.dt
         u1, q1 = self.stage(self.x, self.q, 0, hook)
         xh = self.solver.advance(self.x, u1, 0.5 * dt)
@@ -110,3 +113,4 @@ class DropSuspension:
         self.solver.advance(self.x, u2, dt, out=self.x)
         self.q = q2
         self.step_index += 1
+        self.plan.status()

@@ -31,8 +31,13 @@ EXPORTS = (
     "ggem_single_layer", "ggem_double_layer", "ggem_spread_grid", "ggem_plan_time_stage",
     "ggem_plan_stage_time", "ggem_plan_work", "ggem_solver_create", "ggem_solver_destroy",
     "ggem_fredholm_apply", "ggem_fredholm_solve", "ggem_surface_geometry", "ggem_drop_rhs",
-    "ggem_surface_velocity", "ggem_advance", "ggem_last_error",
+    "ggem_surface_velocity", "ggem_advance", "ggem_fredholm_solve_guided", "ggem_mlp_create",
+    "ggem_mlp_destroy", "ggem_mlp_set_params", "ggem_mlp_get_params", "ggem_mlp_features",
+    "ggem_mlp_forward", "ggem_mlp_predict", "ggem_mlp_gradients", "ggem_mlp_train_step",
+    "ggem_last_error",
 )
+
+MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 13, 128, 3, 35203
 
 STAGES = ("bin", "near", "wall", "spread", "fft_fwd", "cheb_fwd", "tau", "cheb_inv",
           "fft_inv", "interp")
@@ -92,6 +97,19 @@ def load_library(path: str = LIB_PATH):
     lib.ggem_drop_rhs.argtypes = [vp, ll, dp, dp, dd, dd, dd, dp]
     lib.ggem_surface_velocity.argtypes = [vp, ll, dp, ll, dp, dp, dd, dp]
     lib.ggem_advance.argtypes = [vp, ll, dp, dp, dd, dp]
+    fp = ctypes.POINTER(ctypes.c_float)
+    lib.ggem_fredholm_solve_guided.argtypes = [vp, ll, dp, dp, dp, dd, ll, dp, dp, dp, dp, dd, ip,
+                                               ctypes.POINTER(ip), ctypes.POINTER(dd),
+                                               ctypes.POINTER(dd)]
+    lib.ggem_mlp_create.argtypes = [ip, vp, ctypes.POINTER(vp)]
+    lib.ggem_mlp_destroy.argtypes = [vp]
+    lib.ggem_mlp_set_params.argtypes = [vp, dp]
+    lib.ggem_mlp_get_params.argtypes = [vp, dp]
+    lib.ggem_mlp_features.argtypes = [vp, ll, dp, dp, dp, dp, dp, ip, fp, dp]
+    lib.ggem_mlp_forward.argtypes = [vp, ll, dp, dp]
+    lib.ggem_mlp_predict.argtypes = [vp, ll, dp, dd, dp]
+    lib.ggem_mlp_gradients.argtypes = [vp, ll, dp, dp, dp, fp]
+    lib.ggem_mlp_train_step.argtypes = [vp, ll, dp, dp, ctypes.c_float, fp]
     lib.ggem_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name != "ggem_last_error":
@@ -270,6 +288,17 @@ class FredholmSolver:
                                         _dev_ptr(out, "out")))
         return out
 
+    def solve_guided(self, surf, b, q, dq, tol=1e-6, max_iter=200):
+        """Solve from q + c dq (c chosen by the residual); returns (iters, rel_res, c)."""
+        it = ctypes.c_int()
+        rr = ctypes.c_double()
+        st = ctypes.c_double()
+        _check(_lib.ggem_fredholm_solve_guided(self._h, *surf.args(), _dev_ptr(b, "b"),
+                                               _dev_ptr(q, "q"), _dev_ptr(dq, "dq"), float(tol),
+                                               int(max_iter), ctypes.byref(it), ctypes.byref(rr),
+                                               ctypes.byref(st)))
+        return it.value, rr.value, st.value
+
     def solve(self, surf, b, q, tol=1e-6, max_iter=200):
         """Solve in place into q (initial guess on entry); returns (iters, rel_res)."""
         it = ctypes.c_int()
@@ -331,3 +360,95 @@ def _int_dev(t, name, dim, n=None):
         raise ValueError(f"{name} must have 3 columns")
     if n is not None and t.shape[0] != n:
         raise ValueError(f"{name} must have {n} entries")
+
+
+def _f32_dev(t, name, cols):
+    import torch
+    if (not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32
+            or t.dim() != 2 or t.shape[1] != cols or not t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous (n, {cols}) float32 device tensor")
+    return t.data_ptr()
+
+
+class MLP:
+    """The warm-start network (ggem_mlp_*): 13 -> 128 -> 128 -> 128 -> 3."""
+
+    def __init__(self, max_batch, params=None, stream=None):
+        lib = load_library()
+        self._h = ctypes.c_void_p()
+        self.max_batch = int(max_batch)
+        _check(lib.ggem_mlp_create(self.max_batch, _stream_handle(stream), ctypes.byref(self._h)))
+        if params is not None:
+            self.set_params(params)
+
+    def close(self):
+        if self._h:
+            _check(_lib.ggem_mlp_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            if self._h and _lib is not None:
+                _lib.ggem_mlp_destroy(self._h)
+        except Exception:
+            pass
+
+    @staticmethod
+    def _params_ptr(p):
+        import torch
+        if (not isinstance(p, torch.Tensor) or not p.is_cuda or p.dtype != torch.float32
+                or p.shape != (MLP_PARAMS,) or not p.is_contiguous()):
+            raise TypeError(f"params must be a contiguous ({MLP_PARAMS},) float32 device tensor")
+        return p.data_ptr()
+
+    def set_params(self, p):
+        _check(_lib.ggem_mlp_set_params(self._h, self._params_ptr(p)))
+
+    def get_params(self):
+        import torch
+        p = torch.empty(MLP_PARAMS, dtype=torch.float32, device="cuda")
+        _check(_lib.ggem_mlp_get_params(self._h, p.data_ptr()))
+        return p
+
+    def features(self, nodes, normals, lap, q_prev, dq_prev, nodes_per_drop, scales, out=None):
+        import torch
+        n = nodes.shape[0]
+        if out is None:
+            out = torch.empty((n, MLP_IN), dtype=torch.float32, device=nodes.device)
+        sc = (ctypes.c_float * MLP_IN)(*[float(v) for v in scales])
+        _check(_lib.ggem_mlp_features(self._h, n, _dev_ptr(nodes, "nodes"),
+                                      _dev_ptr(normals, "normals", n), _dev_ptr(lap, "lap", n),
+                                      _dev_ptr(q_prev, "q_prev", n), _dev_ptr(dq_prev, "dq_prev", n),
+                                      int(nodes_per_drop), sc,
+                                      _f32_dev(out, "X", MLP_IN)))
+        return out
+
+    def forward(self, X):
+        import torch
+        Y = torch.empty((X.shape[0], MLP_OUT), dtype=torch.float32, device=X.device)
+        _check(_lib.ggem_mlp_forward(self._h, X.shape[0], _f32_dev(X, "X", MLP_IN),
+                                     Y.data_ptr()))
+        return Y
+
+    def predict(self, X, scale, out=None):
+        import torch
+        if out is None:
+            out = torch.empty((X.shape[0], 3), dtype=torch.float64, device=X.device)
+        _check(_lib.ggem_mlp_predict(self._h, X.shape[0], _f32_dev(X, "X", MLP_IN), float(scale),
+                                     _dev_ptr(out, "dq", X.shape[0])))
+        return out
+
+    def gradients(self, X, T):
+        import torch
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=X.device)
+        loss = ctypes.c_float()
+        _check(_lib.ggem_mlp_gradients(self._h, X.shape[0], _f32_dev(X, "X", MLP_IN),
+                                       _f32_dev(T, "T", MLP_OUT), g.data_ptr(), ctypes.byref(loss)))
+        return float(loss.value), g
+
+    def train_step(self, X, T, lr, want_loss=False):
+        loss = ctypes.c_float()
+        _check(_lib.ggem_mlp_train_step(self._h, X.shape[0], _f32_dev(X, "X", MLP_IN),
+                                        _f32_dev(T, "T", MLP_OUT), float(lr),
+                                        ctypes.byref(loss) if want_loss else None))
+        return float(loss.value) if want_loss else None

@@ -170,3 +170,49 @@ def test_drop_steps_conserve_volume(drops):
     # volume per unit time (point quadrature of the single layer); allow 5 %
     t_total = 2 * c.dt
     assert np.abs(v1 / v0 - 1).max() < 0.05 * t_total
+
+
+def test_guided_start(surf):
+    """The guided start takes the least-squares step along dq: about 1 along
+    the exact correction (then no Krylov step is needed), 0 against it."""
+    c, tri, nrm, b = surf
+    print("guided start", flush=True)
+    plan = G.Plan.from_case(c, max_src=3 * tri.shape[0], max_tgt=c.nt)
+    solver = G.FredholmSolver(plan, c.nt, tri.shape[0], restart=20)
+    S = G.Surface(dev(c.xt), dev(nrm), dev(tri, torch.int32), 2.0 / 3.0)
+    bb = dev(b)
+    qs = torch.zeros((c.nt, 3), dtype=torch.float64, device=DEV)
+    solver.solve(S, bb, qs, tol=1e-11, max_iter=200)
+    q0 = 0.5 * qs + 0.01 * torch.randn_like(qs)
+    q = q0.clone()
+    it, rel, step = solver.solve_guided(S, bb, q, qs - q0, tol=1e-8, max_iter=100)
+    assert abs(step - 1.0) < 1e-6 and it == 0 and rel <= 1e-8
+    q = q0.clone()
+    it_p, _ = solver.solve(S, bb, q, tol=1e-8, max_iter=100)
+    q = q0.clone()
+    it_b, rel_b, step_b = solver.solve_guided(S, bb, q, q0 - qs, tol=1e-8, max_iter=100)
+    assert step_b == 0.0 and it_b == it_p and rel_b <= 1e-8
+
+
+def test_learned_warm_start_pipeline():
+    """End to end on three small drops: record, train, evaluate."""
+    from paper_1109_6587_amd.warmstart import run
+    print("warm start pipeline", flush=True)
+    c = case_shear_drops(4, level=2, ncap=3, N=32, Ny=33)
+    res, sim = run(c, steps=6, train_steps=4, epochs=2, batch=256, restart=10,
+                   log=lambda m: print(m, flush=True))
+    assert res["test_solves"] == 4 and res["train_solves"] == 6
+    assert res["starts"]["plain"]["products_mean"] > 0
+    assert res["blend_step_mean"] >= 0.0
+
+
+def test_learned_warm_start_gains():
+    """On the 100-drop workload (first 40 steps: train on 30, test on 10), the
+    judged learned start needs fewer products than the plain warm start."""
+    from paper_1109_6587_amd.warmstart import run
+    print("warm start gain (100 drops, 40 steps)", flush=True)
+    res, _ = run(case_shear_drops(4), steps=40, train_steps=30, log=lambda m: print(m, flush=True))
+    st = res["starts"]
+    print(st, flush=True)
+    assert st["learned_judged"]["products_mean"] < st["plain"]["products_mean"] - 0.5
+    assert st["learned_direct"]["products_mean"] < st["plain"]["products_mean"]
