@@ -9,8 +9,9 @@ transforms, interpolation) on inputs resident in device memory.
 
 Prints one JSON line: throughput in Mpoints/s (points = targets) for the
 mixed-precision path, with its error against the FP64 path on the same GPU,
-the FP64 path's throughput, the dominant kernel's roofline and the CPU oracle
-timed on a bounded sample.
+the FP64 path's throughput, the dominant kernel's roofline, the Fredholm
+solve time to a relative residual of 1e-6 on 100 drops in shear (plain and
+learned warm starts) and the CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -43,10 +44,14 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
-    ap.add_argument("--workload", choices=["capsules_sl", "capsules_dl"], default="capsules_sl")
+    ap.add_argument("--workload", choices=["capsules_sl", "capsules_dl", "batched"],
+                    default="capsules_sl")
+    ap.add_argument("--branches", type=int, default=4, help="streams of the batched workload")
     ap.add_argument("--roofline-stage", default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-capsules", type=int, default=5)
+    ap.add_argument("--fredholm-steps", type=int, default=200,
+                    help="time steps of the drop run behind the Fredholm figures (0: skip)")
     return ap.parse_args()
 
 
@@ -98,12 +103,104 @@ def cpu_baseline(c, ncap):
     }
 
 
+def fredholm(steps):
+    """Seconds per Fredholm solve to 1e-6 on 100 drops in shear (64,200 nodes,
+    192,600 unknowns, 384,000 Gauss-point sources): the drop run, training of
+    the warm-start network on its first 3/4 and every start on the rest."""
+    from paper_1109_6587_amd.warmstart import run
+    from workloads import case_shear_drops
+    train = (3 * steps) // 4
+    res, _ = run(case_shear_drops(4), steps=steps, train_steps=train,
+                 log=lambda m: print(m, file=sys.stderr, flush=True))
+    st = res["starts"]
+    return {
+        "metric": "Fredholm solve s to 1e-6",
+        "value": round(st["learned_judged"]["seconds_mean"], 5),
+        "plain_warm_start_s": round(st["plain"]["seconds_mean"], 5),
+        "unit": "s",
+        "products": {k: v["products_mean"] for k, v in st.items()},
+        "seconds": {k: round(v["seconds_mean"], 5) for k, v in st.items()},
+        "speedup_learned_vs_plain": round(res["speedup_vs_plain"], 4),
+        "products_saved_per_solve": round(res["products_saved_per_solve"], 3),
+        "prediction_rel_err": round(res["prediction_rel_err_mean"], 4),
+        "workload": res["workload"], "unknowns": res["unknowns"], "sources": res["sources"],
+        "precision": res["precision"], "train_solves": res["train_solves"],
+        "test_solves": res["test_solves"], "simulation_s": res["simulation_s"],
+        "training_s": res["training_s"],
+    }
+
+
+def bench_batched(args):
+    """48 independent instances (1.5M points) as one captured graph per step."""
+    import numpy as np
+    import torch
+
+    import paper_1109_6587_amd as G
+    from workloads import case_batched
+
+    dev = torch.device("cuda:0")
+    cases = case_batched(3)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)  # noqa: E731
+    so = np.concatenate([[0], np.cumsum([c.ns for c in cases])])
+    to = np.concatenate([[0], np.cumsum([c.nt for c in cases])])
+    xs = t(np.concatenate([c.xs for c in cases]))
+    f = t(np.concatenate([c.f for c in cases]))
+    n = int(to[-1])
+    out = {p: torch.empty((n, 3), dtype=torch.float64, device=dev) for p in ("mixed", "fp64")}
+    batches = {p: G.Batch(cases, precision=p, n_branches=args.branches) for p in out}
+    for p, b in batches.items():
+        b.capture(so, xs, f, to, xs, out[p])
+        b.replay()
+        b.status()
+    err = float(torch.linalg.norm(out["mixed"] - out["fp64"]) / torch.linalg.norm(out["fp64"]))
+
+    def timed(b, steps):
+        for _ in range(args.warmup):
+            b.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            b.replay()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    prec = args.precision
+    other = "fp64" if prec == "mixed" else "mixed"
+    ms = timed(batches[prec], args.steps)
+    ms_other = timed(batches[other], max(10, args.steps // 4))
+    batches[prec].status()
+    # eager submission of the same batch, for the graph's launch saving
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        batches[prec].single_layer(so, xs, f, to, xs, out[prec])
+    torch.cuda.synchronize()
+    ms_eager = (time.perf_counter() - t0) * 1e3 / 10
+    line = {
+        "metric": "GGEM Mpoints/s (mixed vs FP64, rel err 1e-5); Fredholm solve s to 1e-6",
+        "value": round(n / (ms * 1e-3) / 1e6, 3), "unit": "Mpoints/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if prec == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": "batched_48", "instances": len(cases), "points": n,
+                   "precision": prec, "branches": args.branches, "submission": "hip graph"},
+        "err_vs_fp64": {"rel_l2": err},
+        f"{other}_ms_per_step": round(ms_other, 5),
+        "eager_ms_per_step": round(ms_eager, 5),
+        "roofline": None,
+    }
+    print(json.dumps(line))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "design is described but not built", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched":
+        bench_batched(args)
+        return
     import numpy as np
     import torch
 
@@ -186,6 +283,8 @@ def main():
         "work": {"near_pairs": near_pairs, "spread_updates": spread_pairs},
         "roofline": roof,
     }
+    if args.fredholm_steps > 0:
+        line["fredholm"] = fredholm(args.fredholm_steps)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(c, args.cpu_capsules)
     print(json.dumps(line))

@@ -155,6 +155,49 @@ int ggem_plan_stage_time(ggem_plan_t plan, double* total_ms, int* calls);
  * the global density.  Waits for the plan's stream.  counts: host array of 2. */
 int ggem_plan_work(ggem_plan_t plan, unsigned long long* counts);
 
+/* ---- batches of independent slit problems -------------------------------
+ *
+ * Not in the paper: many independent problems of uneven size (each with its
+ * own box, split parameter, grid and capacities) evaluated in one
+ * submission.  A batch owns one plan per instance and n_branches streams;
+ * instances are assigned to branches by longest-processing-time on an
+ * estimate of their work, and an evaluation forks into the branches and
+ * joins back, so instances run concurrently.  The enqueue can be captured
+ * once into a HIP graph and replayed with a single launch.  Per-instance
+ * sync_checks is forced off: domain errors are reported by
+ * ggem_batch_status.  Errors: GGEM_E_ARG, GGEM_E_CAPACITY (with the instance
+ * index in the message), GGEM_E_NOMEM, GGEM_E_DEVICE. */
+typedef struct ggem_batch_s* ggem_batch_t;
+
+int ggem_batch_create(int n_inst, const ggem_params* params, int n_branches, ggem_batch_t* out);
+int ggem_batch_destroy(ggem_batch_t batch);
+
+/* Single layer of every instance i: sources xs[src_off[i] .. src_off[i+1])
+ * with strengths f, targets xt[tgt_off[i] .. tgt_off[i+1]), velocities into
+ * u at the targets' rows (packed (N,3) float64 device arrays; src_off and
+ * tgt_off are HOST arrays of n_inst + 1 offsets starting at 0).  Ordered
+ * after prior work on hip_stream, and later work on hip_stream waits for it. */
+int ggem_batch_single_layer(ggem_batch_t batch, void* hip_stream, const long long* src_off,
+                            const double* xs, const double* f, const long long* tgt_off,
+                            const double* xt, double* u);
+
+/* Capture the same enqueue into the batch's graph (replacing any previous
+ * one) without running it.  Every replay reads and writes the device
+ * addresses given here: keep those buffers alive and in place. */
+int ggem_batch_capture_single_layer(ggem_batch_t batch, const long long* src_off,
+                                    const double* xs, const double* f, const long long* tgt_off,
+                                    const double* xt, double* u);
+
+/* Replay the captured graph on hip_stream. */
+int ggem_batch_graph_launch(ggem_batch_t batch, void* hip_stream);
+
+/* Wait for hip_stream and the batch, then report the first instance whose
+ * last evaluation saw a non-finite or out-of-slit point (GGEM_E_DOMAIN). */
+int ggem_batch_status(ggem_batch_t batch, void* hip_stream);
+
+/* Branch (stream index) an instance was assigned to, or a negative error. */
+int ggem_batch_branch(ggem_batch_t batch, int instance);
+
 /* ---- Fredholm equation of the single-layer density (Eq. qa) ------------
  *
  * At every element node x_b of a triangulated surface (flat triangles,

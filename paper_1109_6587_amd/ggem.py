@@ -34,7 +34,9 @@ EXPORTS = (
     "ggem_surface_velocity", "ggem_advance", "ggem_fredholm_solve_guided", "ggem_mlp_create",
     "ggem_mlp_destroy", "ggem_mlp_set_params", "ggem_mlp_get_params", "ggem_mlp_features",
     "ggem_mlp_forward", "ggem_mlp_predict", "ggem_mlp_gradients", "ggem_mlp_train_step",
-    "ggem_last_error",
+    "ggem_batch_create", "ggem_batch_destroy", "ggem_batch_single_layer",
+    "ggem_batch_capture_single_layer", "ggem_batch_graph_launch", "ggem_batch_status",
+    "ggem_batch_branch", "ggem_last_error",
 )
 
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 13, 128, 3, 35203
@@ -110,6 +112,14 @@ def load_library(path: str = LIB_PATH):
     lib.ggem_mlp_predict.argtypes = [vp, ll, dp, dd, dp]
     lib.ggem_mlp_gradients.argtypes = [vp, ll, dp, dp, dp, fp]
     lib.ggem_mlp_train_step.argtypes = [vp, ll, dp, dp, ctypes.c_float, fp]
+    lp = ctypes.POINTER(ctypes.c_longlong)
+    lib.ggem_batch_create.argtypes = [ip, ctypes.POINTER(Params), ip, ctypes.POINTER(vp)]
+    lib.ggem_batch_destroy.argtypes = [vp]
+    lib.ggem_batch_single_layer.argtypes = [vp, vp, lp, dp, dp, lp, dp, dp]
+    lib.ggem_batch_capture_single_layer.argtypes = [vp, lp, dp, dp, lp, dp, dp]
+    lib.ggem_batch_graph_launch.argtypes = [vp, vp]
+    lib.ggem_batch_status.argtypes = [vp, vp]
+    lib.ggem_batch_branch.argtypes = [vp, ip]
     lib.ggem_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name != "ggem_last_error":
@@ -452,3 +462,65 @@ class MLP:
                                         _f32_dev(T, "T", MLP_OUT), float(lr),
                                         ctypes.byref(loss) if want_loss else None))
         return float(loss.value) if want_loss else None
+
+
+class Batch:
+    """Independent slit problems evaluated together (ggem_batch_*).
+
+    ``cases``: objects with Lx, Lz, H, alpha, rc, Nx, Nz, Ny and ns/nt (for
+    the capacities), e.g. workloads.SlitCase."""
+
+    def __init__(self, cases, precision="mixed", n_branches=4):
+        lib = load_library()
+        prec = {"fp64": FP64, "mixed": MIXED}[precision]
+        arr = (Params * len(cases))()
+        for i, c in enumerate(cases):
+            arr[i] = Params(float(c.Lx), float(c.Lz), float(c.H), float(c.alpha), float(c.rc),
+                            int(c.Nx), int(c.Nz), int(c.Ny), prec, 0, max(int(c.ns), 1),
+                            max(int(c.nt), 1))
+        self.n = len(cases)
+        self._h = ctypes.c_void_p()
+        _check(lib.ggem_batch_create(self.n, arr, int(n_branches), ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            _check(_lib.ggem_batch_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            if self._h and _lib is not None:
+                _lib.ggem_batch_destroy(self._h)
+        except Exception:
+            pass
+
+    def _offs(self, off):
+        if len(off) != self.n + 1:
+            raise ValueError(f"offsets must have {self.n + 1} entries")
+        return (ctypes.c_longlong * (self.n + 1))(*[int(v) for v in off])
+
+    def _arrays(self, src_off, xs, f, tgt_off, xt, u):
+        ns, nt = int(src_off[-1]), int(tgt_off[-1])
+        return (self._offs(src_off), _dev_ptr(xs, "xs", ns), _dev_ptr(f, "f", ns),
+                self._offs(tgt_off), _dev_ptr(xt, "xt", nt), _dev_ptr(u, "u", nt))
+
+    def single_layer(self, src_off, xs, f, tgt_off, xt, u, stream=None):
+        so, a, b, to, c, d = self._arrays(src_off, xs, f, tgt_off, xt, u)
+        _check(_lib.ggem_batch_single_layer(self._h, _stream_handle(stream), so, a, b, to, c, d))
+        return u
+
+    def capture(self, src_off, xs, f, tgt_off, xt, u):
+        so, a, b, to, c, d = self._arrays(src_off, xs, f, tgt_off, xt, u)
+        _check(_lib.ggem_batch_capture_single_layer(self._h, so, a, b, to, c, d))
+
+    def replay(self, stream=None):
+        _check(_lib.ggem_batch_graph_launch(self._h, _stream_handle(stream)))
+
+    def status(self, stream=None):
+        _check(_lib.ggem_batch_status(self._h, _stream_handle(stream)))
+
+    def branch(self, i):
+        r = _lib.ggem_batch_branch(self._h, int(i))
+        if r < 0:
+            _check(r)
+        return r

@@ -1,0 +1,133 @@
+"""Batches of independent slit problems (ggem_batch_*).
+
+Each instance of a batch equals its solo evaluation bit for bit (same kernels,
+same inputs), the solo FP64 evaluation equals the oracle (1e-10), and every
+replay of the captured graph equals the eager batch, with other GPU work and
+host synchronisations between replays.  The 48-instance workload runs in the
+configuration the benchmark times: graph replays in mixed precision, checked
+against the FP64 batch (1e-5) and, on its smallest instance, the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import case_batched, random_case
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+import paper_1109_6587_amd as G  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def pack(cases):
+    so = np.concatenate([[0], np.cumsum([c.ns for c in cases])])
+    to = np.concatenate([[0], np.cumsum([c.nt for c in cases])])
+    xs = dev(np.concatenate([c.xs for c in cases]))
+    f = dev(np.concatenate([c.f for c in cases]))
+    xt = dev(np.concatenate([c.xt for c in cases]))
+    return so, xs, f, to, xt
+
+
+def small_cases():
+    return [
+        random_case(21, 40, 30, 4.0, 1.0, 4.0, 1.0, 32, 32, 17),
+        random_case(22, 200, 10, 6.0, 2.0, 3.0, 1.3, 48, 48, 33),
+        random_case(23, 1, 5, 5.0, 1.5, 4.0, 1.0, 40, 40, 25),
+        random_case(24, 90, 90, 8.0, 0.8, 5.0, 0.8, 64, 64, 21, Lz=6.0),
+        random_case(25, 300, 200, 5.0, 1.0, 4.0, 1.0, 36, 36, 33),
+    ]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_equals_solo_and_oracle(precision):
+    print(f"batch small {precision}", flush=True)
+    cases = small_cases()
+    so, xs, f, to, xt = pack(cases)
+    u = torch.full((int(to[-1]), 3), np.nan, dtype=torch.float64, device=DEV)
+    b = G.Batch(cases, precision=precision, n_branches=3)
+    b.single_layer(so, xs, f, to, xt, u)
+    b.status()
+    got = u.cpu().numpy()
+    for i, c in enumerate(cases):
+        plan = G.Plan.from_case(c, precision=precision)
+        solo = plan.single_layer(dev(c.xs), dev(c.f), dev(c.xt)).cpu().numpy()
+        assert np.array_equal(got[to[i]:to[i + 1]], solo), i
+        if precision == "fp64":
+            ref = O.single_layer(O.SlitGrid.from_case(c), c.xs, c.f, c.xt)
+            assert np.abs(solo - ref).max() <= 1e-10 * np.abs(ref).max(), i
+
+
+def test_graph_replays_match_eager():
+    print("batch graph replays", flush=True)
+    cases = small_cases()
+    so, xs, f, to, xt = pack(cases)
+    b = G.Batch(cases, precision="mixed", n_branches=4)
+    ref = torch.empty((int(to[-1]), 3), dtype=torch.float64, device=DEV)
+    b.single_layer(so, xs, f, to, xt, ref)
+    b.status()
+    u = torch.zeros_like(ref)
+    b.capture(so, xs, f, to, xt, u)
+    other = G.Plan.from_case(cases[0], precision="mixed")
+    for r in range(4):
+        u.fill_(np.nan)
+        b.replay()
+        b.status()
+        assert torch.equal(u, ref), r
+        other.single_layer(dev(cases[0].xs), dev(cases[0].f), dev(cases[0].xt))
+        torch.cuda.synchronize()
+
+
+def test_batch_errors():
+    cases = small_cases()[:2]
+    so, xs, f, to, xt = pack(cases)
+    b = G.Batch(cases, precision="fp64", n_branches=2)
+    u = torch.empty((int(to[-1]), 3), dtype=torch.float64, device=DEV)
+    with pytest.raises(G.GGEMError):
+        b.single_layer([0, 41, 240], xs, f, to, xt, u)   # 41 sources exceed instance 0
+    bad = xs.clone()
+    bad[3, 1] = 5.0                                            # |y| > H in instance 0
+    b.single_layer(so, bad, f, to, xt, u)
+    with pytest.raises(G.GGEMError) as e:
+        b.status()
+    assert "instance 0" in str(e.value)
+    b.single_layer(so, xs, f, to, xt, u)
+    b.status()
+
+
+@pytest.mark.timeout(400)
+def test_batched_workload_graph():
+    """48 instances (1.5M points): mixed graph replay vs the FP64 batch and,
+    on the smallest instance (about a minute of oracle time), the oracle."""
+    print("batched workload", flush=True)
+    cases = case_batched(3)
+    so, xs, f, to, xt = pack(cases)
+    n = int(to[-1])
+    b64 = G.Batch(cases, precision="fp64")
+    ref = torch.empty((n, 3), dtype=torch.float64, device=DEV)
+    b64.single_layer(so, xs, f, to, xt, ref)
+    b64.status()
+    bm = G.Batch(cases, precision="mixed")
+    u = torch.empty_like(ref)
+    bm.capture(so, xs, f, to, xt, u)
+    bm.replay()
+    bm.replay()
+    bm.status()
+    r, g = ref.cpu().numpy(), u.cpu().numpy()
+    for i in range(len(cases)):
+        a, e = r[to[i]:to[i + 1]], g[to[i]:to[i + 1]]
+        assert np.linalg.norm(e - a) <= 1e-5 * np.linalg.norm(a), i
+    del b64, bm
+    for i in np.argsort([c.ns for c in cases])[:1]:
+        c = cases[i]
+        print(f"oracle on instance {i} ({c.ns} points, grid {c.Nx}x{c.Nz}x{c.Ny})", flush=True)
+        o = O.single_layer(O.SlitGrid.from_case(c), c.xs, c.f, c.xt)
+        assert np.abs(r[to[i]:to[i + 1]] - o).max() <= 1e-10 * np.abs(o).max(), i
