@@ -46,7 +46,8 @@ def parse():
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--workload", choices=["capsules_sl", "capsules_dl", "batched"],
                     default="capsules_sl")
-    ap.add_argument("--branches", type=int, default=4, help="streams of the batched workload")
+    ap.add_argument("--branches", type=int, default=0,
+                    help="streams of the batched workload (0: autotuned, cached on disk)")
     ap.add_argument("--roofline-stage", default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-capsules", type=int, default=5)
@@ -147,7 +148,13 @@ def bench_batched(args):
     f = t(np.concatenate([c.f for c in cases]))
     n = int(to[-1])
     out = {p: torch.empty((n, 3), dtype=torch.float64, device=dev) for p in ("mixed", "fp64")}
-    batches = {p: G.Batch(cases, precision=p, n_branches=args.branches) for p in out}
+    branches, tuned_ms, cached = args.branches, None, None
+    if branches <= 0:
+        from paper_1109_6587_amd.autotune import tune_batch
+        branches, tuned_ms, cached = tune_batch(
+            cases, (so, xs, f, to, xs, out[args.precision]), precision=args.precision,
+            log=lambda m: print(m, file=sys.stderr, flush=True))
+    batches = {p: G.Batch(cases, precision=p, n_branches=branches) for p in out}
     for p, b in batches.items():
         b.capture(so, xs, f, to, xs, out[p])
         b.replay()
@@ -183,7 +190,8 @@ def bench_batched(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64" if prec == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": "batched_48", "instances": len(cases), "points": n,
-                   "precision": prec, "branches": args.branches, "submission": "hip graph"},
+                   "precision": prec, "branches": branches, "submission": "hip graph"},
+        "autotune": {"ms_by_branches": tuned_ms, "from_cache": cached},
         "err_vs_fp64": {"rel_l2": err},
         f"{other}_ms_per_step": round(ms_other, 5),
         "eager_ms_per_step": round(ms_eager, 5),

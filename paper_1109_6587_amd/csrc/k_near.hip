@@ -135,12 +135,12 @@ __device__ inline int find_cell(const int* __restrict__ start, int ncells, int i
   return lo;
 }
 
-constexpr int kNearWaves = 4;
-
-// Work item: up to 64 sorted targets of one cell (one per lane).  The four
+// Work item: up to 64 sorted targets of one cell (one per lane).  The W
 // waves of the block take disjoint subsets of the neighbour cells (cell k of
-// the list goes to wave k mod 4), stage each cell's sources through their own
-// LDS slice, and the four partial sums are added in wave order at the end.
+// the list goes to wave k mod W), stage each cell's sources through their own
+// LDS slice, and the W partial sums are added in wave order at the end.  W is
+// 4 for ordinary targets and 9 for the wall nodes (one neighbour cell of the
+// wall layer per wave: there are few wall work items, each with much work).
 //
 // Pass 1 tests every staged source against the lane's target and keeps a bit
 // mask of the pairs within r_c; pass 2 evaluates the kernel only for those.
@@ -149,12 +149,12 @@ constexpr int kNearWaves = 4;
 // FP32 relative to the cell corner and pass 2 forms the displacement in FP64
 // without a per-pair image search.  Otherwise every displacement is the FP64
 // minimum image and the cutoff is decided in FP64.
-template <typename T, bool DL, bool FAST>
-__global__ void __launch_bounds__(64 * kNearWaves) near_field(NearArgs a, Kc<T> k) {
-  __shared__ double lx[kNearWaves][64], ly[kNearWaves][64], lz[kNearWaves][64];
-  __shared__ float4 lr[kNearWaves][64];
-  __shared__ T lf[kNearWaves][3][64];
-  __shared__ T part[kNearWaves][3][64];
+template <typename T, bool DL, bool FAST, int W>
+__global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k) {
+  __shared__ double lx[W][64], ly[W][64], lz[W][64];
+  __shared__ float4 lr[W][64];
+  __shared__ T lf[W][3][64];
+  __shared__ T part[W][3][64];
   const CellGeom& g = a.g;
   const int item = blockIdx.x;
   const int nitems = a.item_start[g.ncells];
@@ -194,7 +194,7 @@ __global__ void __launch_bounds__(64 * kNearWaves) near_field(NearArgs a, Kc<T> 
   // wall targets only see the wall cell layer (cells are at least r_c high)
   const int oy0 = a.nplane ? 1 : 0, noy = a.nplane ? 1 : 3;
   const int ncand = noy * nxo * nzo;
-  for (int kc = wave; kc < ncand; kc += kNearWaves) {
+  for (int kc = wave; kc < ncand; kc += W) {
     const int oyi = kc / (nxo * nzo) + oy0 - 1;
     const int oxi = (kc / nzo) % nxo, ozi = kc % nzo;
     const int cy = iy + oyi;
@@ -302,7 +302,7 @@ __global__ void __launch_bounds__(64 * kNearWaves) near_field(NearArgs a, Kc<T> 
     T v[3];
     for (int d = 0; d < 3; ++d) {
       T acc = part[0][d][lane];
-      for (int w = 1; w < kNearWaves; ++w) acc += part[w][d][lane];
+      for (int w = 1; w < W; ++w) acc += part[w][d][lane];
       v[d] = (T)a.scale * acc;
     }
     T* out = (T*)a.out;
@@ -318,11 +318,18 @@ __global__ void __launch_bounds__(64 * kNearWaves) near_field(NearArgs a, Kc<T> 
   }
 }
 
+template <typename T, bool DL, int W>
+static void launch_near_w(Plan& p, const NearArgs& a, unsigned grid) {
+  const bool fast = sizeof(T) == 4 && p.cg.ncx >= 3 && p.cg.ncz >= 3;
+  if (fast) near_field<T, DL, true, W><<<grid, 64 * W, 0, p.stream>>>(a, make_kc<T>(p.p.alpha));
+  else near_field<T, DL, false, W><<<grid, 64 * W, 0, p.stream>>>(a, make_kc<T>(p.p.alpha));
+}
+
+// grid = an upper bound of the work items (targets/64 + cells)
 template <typename T, bool DL>
 static void launch_near_kernel(Plan& p, const NearArgs& a, unsigned grid) {
-  const bool fast = sizeof(T) == 4 && p.cg.ncx >= 3 && p.cg.ncz >= 3;
-  if (fast) near_field<T, DL, true><<<grid, 64 * kNearWaves, 0, p.stream>>>(a, make_kc<T>(p.p.alpha));
-  else near_field<T, DL, false><<<grid, 64 * kNearWaves, 0, p.stream>>>(a, make_kc<T>(p.p.alpha));
+  if (a.nplane) launch_near_w<T, DL, 9>(p, a, grid);
+  else launch_near_w<T, DL, 4>(p, a, grid);
 }
 
 // Pressure gauge of the double layer: the k = 0 pressure at y = -H equals

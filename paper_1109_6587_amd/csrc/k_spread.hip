@@ -60,6 +60,10 @@ struct V4<float> {
 // REL: sources staged relative to the tile corner in T (mixed mode: the
 // displacement is formed once per source in FP64, the pair test in FP32);
 // otherwise every pair displacement is formed in FP64 with the minimum image.
+//
+// Sources are visited row by row: for each (y, x) cell pair the cells of the
+// z range are contiguous in the sorted order (two segments where the range
+// wraps), so one staged batch spans several cells.
 template <typename T, bool REL>
 __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
   using Q = typename V4<T>::t;
@@ -94,6 +98,11 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
   if (cz1 - cz0 + 1 >= g.ncz) { cz0 = 0; cz1 = g.ncz - 1; }
   const int cy0 = max(0, (int)floor((by0 - a.rc - eps + g.H) * g.icy));
   const int cy1 = min(g.ncy - 1, (int)floor((by1 + a.rc + eps + g.H) * g.icy));
+  // z segments of a row (wrapped cell indices)
+  const int zl0 = ((cz0 % g.ncz) + g.ncz) % g.ncz;
+  const int zlen = cz1 - cz0 + 1;
+  const int nseg = zl0 + zlen > g.ncz ? 2 : 1;
+  const int seg_hi0 = nseg == 2 ? g.ncz - 1 : zl0 + zlen - 1, seg_hi1 = zl0 + zlen - 1 - g.ncz;
   const T* sf = (const T*)a.sf;
   const T a2 = (T)(a.alpha * a.alpha);
   const int lane = tid & 63, wave = tid >> 6;
@@ -102,10 +111,10 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
   for (int cy = cy0; cy <= cy1; ++cy)
     for (int cxu = cx0; cxu <= cx1; ++cxu) {
       const int cx = ((cxu % g.ncx) + g.ncx) % g.ncx;
-      for (int czu = cz0; czu <= cz1; ++czu) {
-        const int cz = ((czu % g.ncz) + g.ncz) % g.ncz;
-        const int nc = (cy * g.ncx + cx) * g.ncz + cz;
-        const int s0 = a.scell[nc], s1 = a.scell[nc + 1];
+      const int row = (cy * g.ncx + cx) * g.ncz;
+      for (int sg = 0; sg < nseg; ++sg) {
+        const int lo = sg == 0 ? zl0 : 0, hi = sg == 0 ? seg_hi0 : seg_hi1;
+        const int s0 = a.scell[row + lo], s1 = a.scell[row + hi + 1];
         for (int b = s0; b < s1; b += TB) {
           // stage sources that can reach the tile, compacted per wave
           const int si = b + tid;

@@ -131,3 +131,16 @@ def test_batched_workload_graph():
         print(f"oracle on instance {i} ({c.ns} points, grid {c.Nx}x{c.Nz}x{c.Ny})", flush=True)
         o = O.single_layer(O.SlitGrid.from_case(c), c.xs, c.f, c.xt)
         assert np.abs(r[to[i]:to[i + 1]] - o).max() <= 1e-10 * np.abs(o).max(), i
+
+
+def test_autotune_caches(tmp_path):
+    from paper_1109_6587_amd.autotune import tune_batch
+    print("autotune", flush=True)
+    cases = small_cases()
+    so, xs, f, to, xt = pack(cases)
+    u = torch.empty((int(to[-1]), 3), dtype=torch.float64, device=DEV)
+    path = str(tmp_path / "tune.json")
+    best, ms, cached = tune_batch(cases, (so, xs, f, to, xt, u), candidates=(1, 2), path=path)
+    assert not cached and best in (1, 2) and set(ms) == {"1", "2"}
+    best2, _, cached2 = tune_batch(cases, (so, xs, f, to, xt, u), candidates=(1, 2), path=path)
+    assert cached2 and best2 == best
