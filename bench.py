@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--roofline-stage", default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-capsules", type=int, default=5)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after the run, copy MIB MiB device to device three times (a "
+                         "plain copy of known size, to scale HBM counters)")
     ap.add_argument("--fredholm-steps", type=int, default=200,
                     help="time steps of the drop run behind the Fredholm figures (0: skip)")
     return ap.parse_args()
@@ -76,6 +79,24 @@ def time_steps(plan, call, steps, warmup, stage=None):
         stage_ms = tot / max(n, 1)
         plan.time_stage(-1, 1)
     return (t1 - t0) * 1e3 / steps, stage_ms
+
+
+def measured_traffic(stage, workload, precision):
+    """HBM bytes per launch of the stage's kernel from the committed counter
+    runs (profiles/traffic.json), or None when there are none for this
+    workload or the kernel's source has changed since they were taken."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic.json")) as fh:
+            ent = json.load(fh).get(stage)
+    except (OSError, ValueError):
+        return None
+    if not ent or ent.get("workload") != workload or ent.get("precision") != precision:
+        return None
+    with open(os.path.join(ROOT, ent["source"]), "rb") as fh:
+        if hashlib.sha256(fh.read()).hexdigest() != ent["sha256"]:
+            return None
+    return int(ent["bytes_per_launch"])
 
 
 def cpu_baseline(c, ncap):
@@ -208,7 +229,20 @@ def main():
         sys.exit(2)
     if args.workload == "batched":
         bench_batched(args)
-        return
+    else:
+        bench_single(args)
+    if args.calibrate_copy > 0:
+        import torch
+        n = args.calibrate_copy * (1 << 20)
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"calibration: copied {n} bytes three times", file=sys.stderr)
+
+
+def bench_single(args):
     import numpy as np
     import torch
 
@@ -265,7 +299,8 @@ def main():
     if flops is not None and stage_ms:
         ach = flops / (stage_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(ach / peak, 4), "traffic": None, "kernel": stage,
+                "frac": round(ach / peak, 4),
+                "traffic": measured_traffic(stage, c.name, args.precision), "kernel": stage,
                 "kernel_ms": round(stage_ms, 5), "work_units": near_pairs if stage == "near" else spread_pairs}
 
     line = {
