@@ -79,6 +79,10 @@ void free_plan(Plan& p) {
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (p.flags_host) (void)hipHostFree(p.flags_host);
+  if (p.side) (void)hipStreamDestroy(p.side);
+  hipEvent_t evs[] = {p.ev_fork, p.ev_wall, p.ev_near};
+  for (hipEvent_t e : evs)
+    if (e) (void)hipEventDestroy(e);
   if (p.timed_ev) {
     for (int i = 0; i < 2 * p.timed_max; ++i) (void)hipEventDestroy(p.timed_ev[i]);
     delete[] p.timed_ev;
@@ -277,22 +281,59 @@ int evaluate(Plan& p, long long ns, const double* xs, const double* f, long long
     }
     p.tnrm = p.tgt.s;
   }
-  if (parts & GGEM_PART_LOCAL) {
-    StageScope s(p, GGEM_STAGE_NEAR);
-    if (dl) HIP_TRY(launch_near_dl<T>(p, (int)nt));
-    else HIP_TRY(launch_near_sl<T>(p, (int)nt));
-  } else {
+  const bool glob = (parts & GGEM_PART_GLOBAL) != 0 && nt > 0;
+  const bool local = (parts & GGEM_PART_LOCAL) != 0;
+  if (!local) {
     int rc = zero_ul<T>(p, (int)nt);
     if (rc) return rc;
   }
-  const bool glob = (parts & GGEM_PART_GLOBAL) != 0;
-  if (glob && nt > 0) {
-    const int Ny = p.p.Ny;
-    {
-      StageScope s(p, GGEM_STAGE_WALL);
-      HIP_TRY(launch_wall<T>(p));
-      if (dl) HIP_TRY(launch_gauge(p));
+  // side stream: wall data (and gauge, wall-plane FFT), then the local sum at
+  // the targets; the main stream meanwhile spreads and transforms.  While the
+  // caller's stream is being captured into a graph, everything stays on it
+  // (in the same order), so a capture never forks into the plan's stream.
+  const hipStream_t main_stream = p.stream;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(main_stream, &cap));
+  const bool fork = cap == hipStreamCaptureStatusNone;
+  if (fork) {
+    HIP_TRY(hipEventRecord(p.ev_fork, main_stream));
+    HIP_TRY(hipStreamWaitEvent(p.side, p.ev_fork, 0));
+    p.stream = p.side;
+  }
+  int side_rc = GGEM_OK;
+  do {
+    if (glob) {
+      {
+        StageScope s(p, GGEM_STAGE_WALL);
+        if (launch_wall<T>(p) != hipSuccess || (dl && launch_gauge(p) != hipSuccess)) {
+          side_rc = fail(GGEM_E_DEVICE, "wall data launch failed");
+          break;
+        }
+      }
+      if (launch_fft_forward<T>(p, p.wall_phys, p.wall_spec, 6) != hipSuccess) {
+        side_rc = fail(GGEM_E_DEVICE, "wall FFT launch failed");
+        break;
+      }
     }
+    if (fork && hipEventRecord(p.ev_wall, p.side) != hipSuccess) {
+      side_rc = fail(GGEM_E_DEVICE, "event record failed");
+      break;
+    }
+    if (local) {
+      StageScope s(p, GGEM_STAGE_NEAR);
+      const hipError_t e = dl ? launch_near_dl<T>(p, (int)nt) : launch_near_sl<T>(p, (int)nt);
+      if (e != hipSuccess) {
+        side_rc = fail(GGEM_E_DEVICE, "local sum launch failed");
+        break;
+      }
+    }
+    if (fork && hipEventRecord(p.ev_near, p.side) != hipSuccess)
+      side_rc = fail(GGEM_E_DEVICE, "event record failed");
+  } while (false);
+  p.stream = main_stream;
+  if (side_rc) return side_rc;
+  if (glob) {
+    const int Ny = p.p.Ny;
     {
       StageScope s(p, GGEM_STAGE_SPREAD);
       HIP_TRY(launch_spread<T>(p, 0));
@@ -300,12 +341,12 @@ int evaluate(Plan& p, long long ns, const double* xs, const double* f, long long
     {
       StageScope s(p, GGEM_STAGE_FFT_FWD);
       HIP_TRY(launch_fft_forward<T>(p, p.phys, p.specA, 3 * Ny));
-      HIP_TRY(launch_fft_forward<T>(p, p.wall_phys, p.wall_spec, 6));
     }
     {
       StageScope s(p, GGEM_STAGE_CHEB_FWD);
       HIP_TRY(launch_cheb<T>(p, p.specA, p.specB, 3, true));
     }
+    if (fork) HIP_TRY(hipStreamWaitEvent(p.stream, p.ev_wall, 0));
     {
       StageScope s(p, GGEM_STAGE_TAU);
       HIP_TRY(launch_tau<T>(p, dl));
@@ -320,6 +361,7 @@ int evaluate(Plan& p, long long ns, const double* xs, const double* f, long long
       HIP_TRY(launch_fft_inverse<T>(p, p.specB, p.phys, nf * Ny));
     }
   }
+  if (fork) HIP_TRY(hipStreamWaitEvent(p.stream, p.ev_near, 0));
   {
     StageScope s(p, GGEM_STAGE_INTERP);
     HIP_TRY(launch_interp<T>(p, (int)nt, out, dl, glob));
@@ -430,7 +472,11 @@ extern "C" int ggem_plan_create(const ggem_params* prm, void* hip_stream, ggem_p
             hipHostMalloc((void**)&p.flags_host, sizeof(unsigned), 0) == hipSuccess &&
             alloc_binned(p.src, q.max_src, g.ncells, elt) &&
             alloc_binned(p.tgt, q.max_tgt, g.ncells, elt) &&
-            alloc_binned(p.wall, 2LL * q.Nx * q.Nz, g.ncells, elt);
+            alloc_binned(p.wall, 2LL * q.Nx * q.Nz, g.ncells, elt) &&
+            hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&p.ev_fork, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&p.ev_wall, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&p.ev_near, hipEventDisableTiming) == hipSuccess;
   if (!ok) {
     free_plan(p);
     delete h;
@@ -449,6 +495,7 @@ extern "C" int ggem_plan_create(const ggem_params* prm, void* hip_stream, ggem_p
 extern "C" int ggem_plan_destroy(ggem_plan_t plan) {
   if (!plan) return fail(GGEM_E_ARG, "null plan");
   (void)hipStreamSynchronize(plan->p.stream);
+  if (plan->p.side) (void)hipStreamSynchronize(plan->p.side);
   free_plan(plan->p);
   delete plan;
   return GGEM_OK;

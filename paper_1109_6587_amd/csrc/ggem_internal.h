@@ -52,6 +52,10 @@ struct Binned {
 struct Plan {
   ggem_params p;
   hipStream_t stream;
+  // the local sums (wall data, then the targets) run on `side`, concurrently
+  // with the spread and the transforms on `stream`
+  hipStream_t side;
+  hipEvent_t ev_fork, ev_wall, ev_near;
   int device;
   bool fp64;
   double rc, rc2;

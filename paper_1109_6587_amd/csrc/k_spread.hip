@@ -3,10 +3,7 @@
 //   rho_g(r) = alpha^3 pi^{-3/2} exp(-alpha^2 r^2) (5/2 - alpha^2 r^2)   (Eq. rho_l_g a).
 //
 // Each thread owns one grid node and sums over the sources in the cells that
-// can reach its tile, in sorted order: no atomics, bitwise reproducible.  A
-// workgroup covers a tile of 4 (y) x 8 (x) x 8 (z) nodes; sources of every
-// overlapping cell are staged through LDS, and sources whose distance to the
-// tile's bounding box exceeds r_c are compacted away before the pair loop.
+// can reach its tile, in sorted order: no atomics, bitwise reproducible.
 #include "ggem_internal.h"
 
 namespace ggem {
@@ -43,8 +40,9 @@ struct SpreadArgs {
   unsigned long long* work;  // update counter
 };
 
-// Tile of TJ (y) x TI (x) x TK (z) nodes, one node per thread.
-constexpr int TJ = 4, TI = 8, TK = 8, TB = TJ * TI * TK;
+// A block covers 8 (z) x 8 (x) x 4 (y) nodes as four independent wave tiles
+// of 4 x 4 x 4 nodes, one node per lane.
+constexpr int TZ = 8, TX = 8, TY = 4, TB = 256, WT = 4;
 
 template <typename T>
 struct V4;
@@ -57,30 +55,36 @@ struct V4<float> {
   using t = float4;
 };
 
+// Each wave owns its 4 x 4 x 4 node tile and works alone (no block
+// barriers): it walks the cell rows that can reach its tile (the z cells of a
+// (y, x) pair are contiguous in sorted order; two segments where the range
+// wraps), loads 64 sources at a time, keeps those within r_c of its tile's
+// box (compacted in sorted order into its own LDS slice) and every lane adds
+// the kept sources to its node.  Out-of-range terms add exactly zero, so the
+// loop is branch-free and unrolled.
+//
 // REL: sources staged relative to the tile corner in T (mixed mode: the
 // displacement is formed once per source in FP64, the pair test in FP32);
 // otherwise every pair displacement is formed in FP64 with the minimum image.
-//
-// Sources are visited row by row: for each (y, x) cell pair the cells of the
-// z range are contiguous in the sorted order (two segments where the range
-// wraps), so one staged batch spans several cells.
 template <typename T, bool REL>
 __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
   using Q = typename V4<T>::t;
-  __shared__ double lx[REL ? 1 : TB], ly[REL ? 1 : TB], lz[REL ? 1 : TB];
-  __shared__ Q lr[REL ? TB : 1];
-  __shared__ Q lf[TB];
-  __shared__ int wave_cnt[TB / 64];
+  __shared__ double lx[REL ? 1 : 4][64], ly[REL ? 1 : 4][64], lz[REL ? 1 : 4][64];
+  __shared__ Q lr[REL ? 4 : 1][64];
+  __shared__ Q lf[4][64];
   const CellGeom& g = a.g;
-  const int tid = threadIdx.x;
-  const int k = blockIdx.x * TK + (tid % TK);
-  const int i = blockIdx.y * TI + ((tid / TK) % TI);
-  const int j = blockIdx.z * TJ + tid / (TK * TI);
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int k_lo = blockIdx.x * TZ + (wave & 1) * WT;
+  const int i_lo = blockIdx.y * TX + (wave >> 1) * WT;
+  const int j_lo = blockIdx.z * TY;
+  const int k = k_lo + (lane & 3), i = i_lo + ((lane >> 2) & 3), j = j_lo + (lane >> 4);
   const bool valid = (k < a.Nz) && (i < a.Nx) && (j < a.Ny);
+  if (k_lo >= a.Nz || i_lo >= a.Nx) return;  // the whole wave is past the grid
   // tile bounds
-  const int i_lo = blockIdx.y * TI, i_hi = min(a.Nx - 1, i_lo + TI - 1);
-  const int k_lo = blockIdx.x * TK, k_hi = min(a.Nz - 1, k_lo + TK - 1);
-  const int j_lo = blockIdx.z * TJ, j_hi = min(a.Ny - 1, j_lo + TJ - 1);
+  const int i_hi = min(a.Nx - 1, i_lo + WT - 1);
+  const int k_hi = min(a.Nz - 1, k_lo + WT - 1);
+  const int j_hi = min(a.Ny - 1, j_lo + TY - 1);
   const double bx0 = i_lo * a.dx, bx1 = i_hi * a.dx;
   const double bz0 = k_lo * a.dz, bz1 = k_hi * a.dz;
   const double by1 = a.y[j_lo], by0 = a.y[j_hi];  // y decreases with j
@@ -105,7 +109,7 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
   const int seg_hi0 = nseg == 2 ? g.ncz - 1 : zl0 + zlen - 1, seg_hi1 = zl0 + zlen - 1 - g.ncz;
   const T* sf = (const T*)a.sf;
   const T a2 = (T)(a.alpha * a.alpha);
-  const int lane = tid & 63, wave = tid >> 6;
+  const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   T fx = 0, fy = 0, fz = 0;
   unsigned nupd = 0;
   for (int cy = cy0; cy <= cy1; ++cy)
@@ -115,9 +119,9 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
       for (int sg = 0; sg < nseg; ++sg) {
         const int lo = sg == 0 ? zl0 : 0, hi = sg == 0 ? seg_hi0 : seg_hi1;
         const int s0 = a.scell[row + lo], s1 = a.scell[row + hi + 1];
-        for (int b = s0; b < s1; b += TB) {
-          // stage sources that can reach the tile, compacted per wave
-          const int si = b + tid;
+        for (int b = s0; b < s1; b += 64) {
+          // the batch's sources within r_c of the tile's box, compacted
+          const int si = b + lane;
           bool keep = false;
           double qx = 0, qy = 0, qz = 0;
           if (si < s1) {
@@ -130,65 +134,87 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
             keep = dist2_s(gx, gy, gz) <= a.rc2 * (1.0 + 1e-12);
           }
           const unsigned long long m = __ballot(keep);
-          const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-          __syncthreads();
-          if (lane == 0) wave_cnt[wave] = __popcll(m);
-          __syncthreads();
-          int off = 0;
-          for (int w = 0; w < wave; ++w) off += wave_cnt[w];
-          int total = 0;
-          for (int w = 0; w < TB / 64; ++w) total += wave_cnt[w];
+          const int cnt = __popcll(m);
+          if (cnt == 0) continue;
+          const int cnt4 = (cnt + 3) & ~3;
+          __builtin_amdgcn_wave_barrier();
           if (keep) {
-            const int slot = off + __popcll(m & lt);
+            const int slot = __popcll(m & lt);
             if (REL) {
               Q r;
               r.x = (T)min_image_s(qx - bx0, g.Lx, g.invLx);
               r.y = (T)(qy - by0);
               r.z = (T)min_image_s(qz - bz0, g.Lz, g.invLz);
               r.w = (T)0;
-              lr[slot] = r;
+              lr[wave][slot] = r;
             } else {
-              lx[slot] = qx;
-              ly[slot] = qy;
-              lz[slot] = qz;
+              lx[wave][slot] = qx;
+              ly[wave][slot] = qy;
+              lz[wave][slot] = qz;
             }
             Q f;
             f.x = sf[si];
             f.y = sf[a.scap + si];
             f.z = sf[2 * a.scap + si];
             f.w = (T)0;
-            lf[slot] = f;
+            lf[wave][slot] = f;
           }
-          __syncthreads();
+          if (lane >= cnt && lane < cnt4) {
+            // padding up to a multiple of 4 (kept lanes write below cnt): a
+            // source far outside the slit
+            if (REL) {
+              Q r;
+              r.x = (T)0;
+              r.y = (T)1e30;
+              r.z = (T)0;
+              r.w = (T)0;
+              lr[wave][lane] = r;
+            } else {
+              lx[wave][lane] = 0.0;
+              ly[wave][lane] = 1e30;
+              lz[wave][lane] = 0.0;
+            }
+            Q f;
+            f.x = f.y = f.z = f.w = (T)0;
+            lf[wave][lane] = f;
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
           if (valid) {
-            for (int s = 0; s < total; ++s) {
-              T r2;
-              if (REL) {
-                const Q q = lr[s];
-                const T dx = nrx - q.x, dy = nry - q.y, dz = nrz - q.z;
-                r2 = dx * dx + dy * dy + dz * dz;
-                if (!(r2 <= rc2t)) continue;
-              } else {
-                const double dx = min_image_s(px - lx[s], g.Lx, g.invLx);
-                const double dy = py - ly[s];
-                const double dz = min_image_s(pz - lz[s], g.Lz, g.invLz);
-                const double d2 = dist2_s(dx, dy, dz);
-                if (!(d2 <= a.rc2)) continue;
-                r2 = (T)d2;
+            for (int e0 = 0; e0 < cnt4; e0 += 4) {
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u;
+                T r2;
+                bool in;
+                if (REL) {
+                  const Q q = lr[wave][e];
+                  const T dx = nrx - q.x, dy = nry - q.y, dz = nrz - q.z;
+                  r2 = dx * dx + dy * dy + dz * dz;
+                  in = r2 <= rc2t;
+                } else {
+                  const double dx = min_image_s(px - lx[wave][e], g.Lx, g.invLx);
+                  const double dy = py - ly[wave][e];
+                  const double dz = min_image_s(pz - lz[wave][e], g.Lz, g.invLz);
+                  const double d2 = dist2_s(dx, dy, dz);
+                  in = d2 <= a.rc2;
+                  r2 = (T)d2;
+                }
+                nupd += (unsigned)__popcll(__ballot(in));  // the wave's count, scalar
+                const T w = in ? t_exp_s(-a2 * r2) * fma(-a2, r2, (T)2.5) : (T)0;
+                const Q f = lf[wave][e];
+                fx += w * f.x;
+                fy += w * f.y;
+                fz += w * f.z;
               }
-              ++nupd;
-              const T ar = a2 * r2;
-              const T w = t_exp_s(-ar) * ((T)2.5 - ar);
-              const Q f = lf[s];
-              fx += w * f.x;
-              fy += w * f.y;
-              fz += w * f.z;
             }
           }
         }
       }
     }
-  wave_count_add(a.work, nupd);
+  // nupd is the wave's count in every lane (lanes of valid nodes only)
+  if (lane == 0 && nupd) atomicAdd(a.work, (unsigned long long)nupd);
   if (valid) {
     const T c = (T)(a.alpha * a.alpha * a.alpha * 0.17958712212516656);  // alpha^3 pi^{-3/2}
     T* out = (T*)a.out;
@@ -221,9 +247,9 @@ hipError_t launch_spread(Plan& p, int /*unused*/) {
   a.scap = (size_t)p.p.max_src;
   a.out = p.phys;
   a.work = p.work + 1;
-  dim3 grid((p.p.Nz + TK - 1) / TK, (p.p.Nx + TI - 1) / TI, (p.p.Ny + TJ - 1) / TJ);
+  dim3 grid((p.p.Nz + TZ - 1) / TZ, (p.p.Nx + TX - 1) / TX, (p.p.Ny + TY - 1) / TY);
   // tile-relative staging needs one periodic image per (tile, source) pair
-  const bool rel = sizeof(T) == 4 && TI * p.dx + p.rc < 0.5 * p.p.Lx && TK * p.dz + p.rc < 0.5 * p.p.Lz;
+  const bool rel = sizeof(T) == 4 && WT * p.dx + p.rc < 0.5 * p.p.Lx && WT * p.dz + p.rc < 0.5 * p.p.Lz;
   if (rel) spread_tile<T, true><<<grid, TB, 0, p.stream>>>(a);
   else spread_tile<T, false><<<grid, TB, 0, p.stream>>>(a);
   return hipGetLastError();
