@@ -186,6 +186,22 @@ __global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k) {
   }
   const float prx = (float)(px - ox), pry = (float)(py - oy), prz = (float)(pz - oz);
   const float rc2f = (float)a.rc2;
+  // bounding box of the item's targets (they share one cell, so no wrap)
+  double bx0 = active ? px : 1e300, bx1 = active ? px : -1e300;
+  double by0 = active ? py : 1e300, by1 = active ? py : -1e300;
+  double bz0 = active ? pz : 1e300, bz1 = active ? pz : -1e300;
+  for (int o = 32; o > 0; o >>= 1) {
+    bx0 = fmin(bx0, __shfl_xor(bx0, o));
+    bx1 = fmax(bx1, __shfl_xor(bx1, o));
+    by0 = fmin(by0, __shfl_xor(by0, o));
+    by1 = fmax(by1, __shfl_xor(by1, o));
+    bz0 = fmin(bz0, __shfl_xor(bz0, o));
+    bz1 = fmax(bz1, __shfl_xor(bz1, o));
+  }
+  const double bcx = 0.5 * (bx0 + bx1), bhx = 0.5 * (bx1 - bx0);
+  const double bcz = 0.5 * (bz0 + bz1), bhz = 0.5 * (bz1 - bz0);
+  const double keep_r2 = a.rc2 * (1.0 + 1e-6);
+  const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const T* sf = (const T*)a.sf;
   T ux = 0, uy = 0, uz = 0;
   T sfx = 0, sfy = 0, sfz = 0;  // self contributions
@@ -218,26 +234,44 @@ __global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k) {
     const int nc = (cy * g.ncx + cx) * g.ncz + cz;
     const int s0 = a.scell[nc], s1 = a.scell[nc + 1];
     for (int b = s0; b < s1; b += 64) {
+      // the batch's sources within r_c of the targets' box, compacted in order
+      // (the others are out of range of every target of the item)
       const int si = b + lane;
-      __builtin_amdgcn_wave_barrier();
+      bool keep = false;
+      double qx = 0, qy = 0, qz = 0;
       if (si < s1) {
-        double qx = a.sx[si], qy = a.sy[si], qz = a.sz[si];
+        qx = a.sx[si];
+        qy = a.sy[si];
+        qz = a.sz[si];
         if (FAST) {
           qx += shx;
           qz += shz;
-          lr[wave][lane] = make_float4((float)(qx - ox), (float)(qy - oy), (float)(qz - oz), 0.f);
         }
-        lx[wave][lane] = qx;
-        ly[wave][lane] = qy;
-        lz[wave][lane] = qz;
-        lf[wave][0][lane] = sf[si];
-        lf[wave][1][lane] = sf[a.scap + si];
-        lf[wave][2][lane] = sf[2 * a.scap + si];
+        double gx = fabs(FAST ? qx - bcx : min_image(qx - bcx, g.Lx, g.invLx)) - bhx;
+        double gz = fabs(FAST ? qz - bcz : min_image(qz - bcz, g.Lz, g.invLz)) - bhz;
+        const double gy = qy < by0 ? by0 - qy : (qy > by1 ? qy - by1 : 0.0);
+        gx = gx > 0.0 ? gx : 0.0;
+        gz = gz > 0.0 ? gz : 0.0;
+        keep = dist2(gx, gy, gz) <= keep_r2;
+      }
+      const unsigned long long km = __ballot(keep);
+      const int cnt = __popcll(km);
+      if (cnt == 0) continue;
+      __builtin_amdgcn_wave_barrier();
+      if (keep) {
+        const int slot = __popcll(km & lt);
+        if (FAST)
+          lr[wave][slot] = make_float4((float)(qx - ox), (float)(qy - oy), (float)(qz - oz), 0.f);
+        lx[wave][slot] = qx;
+        ly[wave][slot] = qy;
+        lz[wave][slot] = qz;
+        lf[wave][0][slot] = sf[si];
+        lf[wave][1][slot] = sf[a.scap + si];
+        lf[wave][2][slot] = sf[2 * a.scap + si];
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      const int cnt = min(64, s1 - b);
       // pass 1: this lane's in-range sources of the batch as a bit mask
       unsigned long long mask = 0;
       if (active) {
