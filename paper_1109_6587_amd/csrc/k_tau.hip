@@ -133,6 +133,7 @@ __device__ inline void hel_par(const Sweep& w, int par, double2* lds, double2 g,
   const int Nc = N + 1;
   // row right-hand sides s_i = h2 (c_{n-2} q1 r_{n-2} - q2 r_n + q3 r_{n+2}), in place
   double2 rprev = lds[0];
+#pragma unroll 8
   for (int i = 1; i <= M; ++i) {
     const int n = par + 2 * i;
     const double2 ri = (n <= N - 2) ? lds[i * 64] : z2(0, 0);
@@ -145,7 +146,7 @@ __device__ inline void hel_par(const Sweep& w, int par, double2* lds, double2 g,
   }
   // backward: alpha_i = (s_i - u_i alpha_{i+1}) / pivot_i
   double2 an = z2(0, 0);
-#pragma unroll 4
+#pragma unroll 8
   for (int i = M; i >= 1; --i) {
     const int n = par + 2 * i;
     const double u = (n + 2 <= N - 2) ? -w.h2l * w.nc[2 * Nc + n] : 0.0;
@@ -154,7 +155,7 @@ __device__ inline void hel_par(const Sweep& w, int par, double2* lds, double2 g,
   }
   // forward: P_i = alpha_i + beta_i P_{i-1}
   double2 P = z2(0, 0), SP = z2(0, 0);
-#pragma unroll 4
+#pragma unroll 8
   for (int i = 1; i <= M; ++i) {
     const int n = par + 2 * i;
     P = zfma(w.pre[w.NyS + (size_t)n * w.S], P, lds[i * 64]);
@@ -163,7 +164,7 @@ __device__ inline void hel_par(const Sweep& w, int par, double2* lds, double2 g,
   }
   const double2 x0 = zscale(1.0 / w.pre[3 * w.NyS + par * w.S], zsub(g, SP));
   dst(par, x0);
-#pragma unroll 4
+#pragma unroll 8
   for (int i = 1; i <= M; ++i) {
     const int n = par + 2 * i;
     dst(n, zfma(w.pre[2 * w.NyS + (size_t)n * w.S], x0, lds[i * 64]));
@@ -180,6 +181,7 @@ __device__ inline void fill_rhs_deriv(int N, int par, double2* lds, SRC a, RHS r
   double2 S = z2(0, 0);
   // contributions of p > mt + 1 of the opposite parity
   for (int p = N - ((N & 1) == par ? 1 : 0); p > mt + 1; p -= 2) S = zfma((double)p, a(p), S);
+#pragma unroll 8
   for (int m = mt; m >= par; m -= 2) {
     S = zfma((double)(m + 1), a(m + 1), S);
     const double2 D = zscale(m == 0 ? 1.0 : 2.0, S);
@@ -189,6 +191,7 @@ __device__ inline void fill_rhs_deriv(int N, int par, double2* lds, SRC a, RHS r
 
 template <class RHS>
 __device__ inline void fill_rhs(int N, int par, double2* lds, RHS rhs) {
+#pragma unroll 8
   for (int m = par; m <= N - 2; m += 2) lds[((m - par) / 2) * 64] = rhs(m);
 }
 
