@@ -49,14 +49,21 @@ struct InterpArgs {
   double* out;         // (nt, 3) in input order
 };
 
-template <typename T, bool STRESS, bool GLOBAL>
+// G lanes per target (G = 1, 4 or 16, more when there are few targets):
+// lane r of a target's group takes the stencil rows (y, x) = r, r + G, ...
+// of the 25 rows of 5 contiguous z nodes, and the group adds its partial
+// sums in a fixed tree order.  Weights and stencil indices are recomputed by
+// every lane of the group from the same FP64 position, so they are identical
+// across the group.
+template <typename T, bool STRESS, bool GLOBAL, int kGrp>
 __global__ void __launch_bounds__(256) interp_combine(InterpArgs a) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= a.nt) return;
-  const T* ul = (const T*)a.ul;
-  double r[3] = {(double)ul[t], (double)ul[a.tcap + t], (double)ul[2 * a.tcap + t]};
-  if (GLOBAL) {
-    constexpr int NC = STRESS ? 6 : 3;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = gid / kGrp, r = gid % kGrp;
+  const bool valid = t < a.nt;
+  constexpr int NC = STRESS ? 6 : 3;
+  double acc[NC];
+  for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+  if (GLOBAL && valid) {
     const double x = a.tx[t], y = a.ty[t], z = a.tz[t];
     const double fx = floor(x / a.dx + 0.5), fz = floor(z / a.dz + 0.5);
     double wx[5], wz[5], wy[5], ny[5];
@@ -68,44 +75,54 @@ __global__ void __launch_bounds__(256) interp_combine(InterpArgs a) {
     for (int q = 0; q < 5; ++q) ny[q] = a.y[j0 - 2 + q];
     lagrange5(y, ny, wy);
     const int i0 = (int)fx, k0 = (int)fz;
-    int ii[5], kk[5];
-    for (int q = 0; q < 5; ++q) {
-      ii[q] = ((i0 - 2 + q) % a.Nx + a.Nx) % a.Nx;
-      kk[q] = ((k0 - 2 + q) % a.Nz + a.Nz) % a.Nz;
-    }
+    int kk[5];
+    for (int q = 0; q < 5; ++q) kk[q] = ((k0 - 2 + q) % a.Nz + a.Nz) % a.Nz;
     const T* g = (const T*)a.grid;
     const size_t fs = (size_t)a.Ny * a.Nx * a.Nz;
-    double acc[NC];
-    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
-    for (int qa = 0; qa < 5; ++qa) {
-      const size_t jrow = (size_t)(j0 - 2 + qa) * a.Nx;
-      for (int qb = 0; qb < 5; ++qb) {
-        const size_t row = (jrow + ii[qb]) * a.Nz;
-        const double wab = wy[qa] * wx[qb];
-        for (int qc = 0; qc < 5; ++qc) {
-          const double w = wab * wz[qc];
-          const size_t idx = row + kk[qc];
-          for (int c = 0; c < NC; ++c) acc[c] += w * (double)g[c * fs + idx];
-        }
+    for (int row = r; row < 25; row += kGrp) {
+      const int qa = row / 5, qb = row % 5;
+      const int ii = ((i0 - 2 + qb) % a.Nx + a.Nx) % a.Nx;
+      const size_t base = ((size_t)(j0 - 2 + qa) * a.Nx + ii) * a.Nz;
+      const double wab = wy[qa] * wx[qb];
+      for (int qc = 0; qc < 5; ++qc) {
+        const double w = wab * wz[qc];
+        const size_t idx = base + kk[qc];
+        for (int c = 0; c < NC; ++c) acc[c] += w * (double)g[c * fs + idx];
       }
     }
+  }
+  // fixed-order reduction over the group (lanes r and r + o, o = 8, 4, 2, 1)
+  for (int o = kGrp / 2; o > 0; o >>= 1)
+    for (int c = 0; c < NC; ++c) acc[c] += __shfl_down(acc[c], o, kGrp);  // none when G = 1
+  if (!valid || r != 0) return;
+  const T* ul = (const T*)a.ul;
+  double res[3] = {(double)ul[t], (double)ul[a.tcap + t], (double)ul[2 * a.tcap + t]};
+  if (GLOBAL) {
     if (!STRESS) {
-      r[0] += acc[0];
-      r[1] += acc[1];
-      r[2] += acc[2];
+      res[0] += acc[0];
+      res[1] += acc[1];
+      res[2] += acc[2];
     } else {
       const T* tn = (const T*)a.tn;
       const double nx = tn[t], nyv = tn[a.tcap + t], nz = tn[2 * a.tcap + t];
       // acc: xx, yy, zz, xy, xz, yz
-      r[0] += acc[0] * nx + acc[3] * nyv + acc[4] * nz;
-      r[1] += acc[3] * nx + acc[1] * nyv + acc[5] * nz;
-      r[2] += acc[4] * nx + acc[5] * nyv + acc[2] * nz;
+      res[0] += acc[0] * nx + acc[3] * nyv + acc[4] * nz;
+      res[1] += acc[3] * nx + acc[1] * nyv + acc[5] * nz;
+      res[2] += acc[4] * nx + acc[5] * nyv + acc[2] * nz;
     }
   }
   const size_t o = 3 * (size_t)a.perm[t];
-  a.out[o] = r[0];
-  a.out[o + 1] = r[1];
-  a.out[o + 2] = r[2];
+  a.out[o] = res[0];
+  a.out[o + 1] = res[1];
+  a.out[o + 2] = res[2];
+}
+
+template <typename T, int G>
+static void launch_interp_g(Plan& p, const InterpArgs& a, int nt, bool stress, bool with_global) {
+  const unsigned nb = (unsigned)(((size_t)nt * G + 255) / 256);
+  if (!with_global) interp_combine<T, false, false, G><<<nb, 256, 0, p.stream>>>(a);
+  else if (stress) interp_combine<T, true, true, G><<<nb, 256, 0, p.stream>>>(a);
+  else interp_combine<T, false, true, G><<<nb, 256, 0, p.stream>>>(a);
 }
 
 template <typename T>
@@ -129,10 +146,9 @@ hipError_t launch_interp(Plan& p, int nt, double* out, bool stress, bool with_gl
   a.ul = p.ul;
   a.grid = p.phys;
   a.out = out;
-  const unsigned nb = (unsigned)((nt + 255) / 256);
-  if (!with_global) interp_combine<T, false, false><<<nb, 256, 0, p.stream>>>(a);
-  else if (stress) interp_combine<T, true, true><<<nb, 256, 0, p.stream>>>(a);
-  else interp_combine<T, false, true><<<nb, 256, 0, p.stream>>>(a);
+  if (nt < 65536) launch_interp_g<T, 16>(p, a, nt, stress, with_global);
+  else if (nt < 262144) launch_interp_g<T, 4>(p, a, nt, stress, with_global);
+  else launch_interp_g<T, 1>(p, a, nt, stress, with_global);
   return hipGetLastError();
 }
 
