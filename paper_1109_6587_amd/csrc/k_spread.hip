@@ -19,6 +19,8 @@ __device__ inline double dist2_s(double dx, double dy, double dz) {
 
 __device__ inline double t_exp_s(double v) { return exp(v); }
 __device__ inline float t_exp_s(float v) { return __builtin_amdgcn_exp2f(1.44269504088896341f * v); }
+__device__ inline double t_exp2_s(double v) { return exp2(v); }
+__device__ inline float t_exp2_s(float v) { return __builtin_amdgcn_exp2f(v); }
 
 // distance from v to the interval [lo, hi] along a periodic axis
 __device__ inline double box_gap_periodic(double v, double lo, double hi, double L, double invL) {
@@ -92,8 +94,11 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
   const double pz = valid ? k * a.dz : 0.0;
   const double py = valid ? a.y[j] : 0.0;
   // node relative to the tile corner
-  const T nrx = (T)(px - bx0), nry = (T)(py - by0), nrz = (T)(pz - bz0);
-  const T rc2t = (T)a.rc2;
+  // REL: coordinates scaled by alpha sqrt(log2 e), so the squared scaled
+  // distance u gives exp(-alpha^2 r^2) = 2^-u and alpha^2 r^2 = u ln 2
+  const double sc = REL ? a.alpha * 1.2011224087864498 : 1.0;  // sqrt(log2 e)
+  const T nrx = (T)((px - bx0) * sc), nry = (T)((py - by0) * sc), nrz = (T)((pz - bz0) * sc);
+  const T rc2t = (T)(a.rc2 * sc * sc);
   const double eps = 1e-9 * (g.Lx + g.Lz);
   // cell ranges (unwrapped in x, z; clamped in y)
   int cx0 = (int)floor((bx0 - a.rc - eps) * g.icx), cx1 = (int)floor((bx1 + a.rc + eps) * g.icx);
@@ -142,9 +147,9 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
             const int slot = __popcll(m & lt);
             if (REL) {
               Q r;
-              r.x = (T)min_image_s(qx - bx0, g.Lx, g.invLx);
-              r.y = (T)(qy - by0);
-              r.z = (T)min_image_s(qz - bz0, g.Lz, g.invLz);
+              r.x = (T)(min_image_s(qx - bx0, g.Lx, g.invLx) * sc);
+              r.y = (T)((qy - by0) * sc);
+              r.z = (T)(min_image_s(qz - bz0, g.Lz, g.invLz) * sc);
               r.w = (T)0;
               lr[wave][slot] = r;
             } else {
@@ -202,7 +207,11 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
                   r2 = (T)d2;
                 }
                 nupd += (unsigned)__popcll(__ballot(in));  // the wave's count, scalar
-                const T w = in ? t_exp_s(-a2 * r2) * fma(-a2, r2, (T)2.5) : (T)0;
+                T w;
+                if (REL)  // r2 is the scaled u
+                  w = in ? t_exp2_s(-r2) * fma((T)-0.69314718055994531, r2, (T)2.5) : (T)0;
+                else
+                  w = in ? t_exp_s(-a2 * r2) * fma(-a2, r2, (T)2.5) : (T)0;
                 const Q f = lf[wave][e];
                 fx += w * f.x;
                 fy += w * f.y;
