@@ -31,7 +31,12 @@
 //      double layer, the stress components that need no y-derivative)
 //   E  double layer: one thread per (mode, component) for the stress
 //      components with a y-derivative.
-// Vectors are stored [n][mode] so a wave's accesses are coalesced.
+// Vectors are stored [n][mode] so a wave's accesses are coalesced.  With few
+// modes per compute unit each thread's chain of dependent steps is the time,
+// so for Chebyshev order N <= 64 A, B and E keep a parity's column in
+// registers, recompute the sweep factors inline and issue their loads ahead
+// of the sweeps; larger orders use the LDS-column kernels with the plan-time
+// factor tables.
 #include "ggem_internal.h"
 
 namespace ggem {
@@ -195,6 +200,118 @@ __device__ inline void fill_rhs(int N, int par, double2* lds, RHS rhs) {
   for (int m = par; m <= N - 2; m += 2) lds[((m - par) / 2) * 64] = rhs(m);
 }
 
+// ---- register-resident sweeps for N <= MAXN -------------------------------
+// The same solves with the parity's column held in registers.  Every loop is
+// unrolled over the compile-time bound MAXN/2 with the parity a template
+// argument, so each row's Chebyshev constants are literals; the sweep
+// factors (1/pivot, multiplier, Q and its sum, as in sweep_factors) are
+// recomputed in the sweep rather than loaded, and the only global loads left
+// are the right-hand-side reads, which carry no control dependence (indices
+// beyond N are clamped and their terms masked) and so issue in bulk.
+// A wave-uniform int copied into a vector register.  Clamps and masks on the
+// Chebyshev order then use per-lane compares; on the scalar unit they would
+// all share the one condition bit, whose def-use chain pins every unrolled
+// iteration's address arithmetic, and with it its loads, behind the previous
+// iteration.
+__device__ __forceinline__ int lane_copy(int s) {
+  int v;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(s));
+  return v;
+}
+
+__device__ constexpr double cheb_c1(int n) { return 1.0 / (4.0 * n * (n - 1)); }
+__device__ constexpr double cheb_c2(int n) { return 1.0 / (2.0 * ((double)n * n - 1.0)); }
+__device__ constexpr double cheb_c3(int n) { return 1.0 / (4.0 * n * (n + 1)); }
+
+// r[i] holds r(PAR + 2i) for PAR + 2i <= N-2 and zero elsewhere (r[MAXN/2]
+// is always zero); dst(n, a_n) receives the solution for n <= N.
+template <int MAXN, int PAR, class DST>
+__device__ __forceinline__ void hel_reg(int N, double h2, double lam, const double2 (&r)[MAXN / 2 + 1],
+                                        double2 g, DST dst) {
+  constexpr int MM = MAXN / 2;
+  const int M = (N - PAR) / 2;
+  const double h2l = h2 * lam;
+  // row right-hand sides s_i; zero for i > M since r vanishes there
+  double2 s[MM + 1];
+#pragma unroll
+  for (int i = 1; i <= MM; ++i) {
+    const int n = PAR + 2 * i;
+    const double2 rn = i < MM ? r[i + 1] : z2(0, 0);
+    double2 t = zscale((n == 2 ? 2.0 : 1.0) * cheb_c1(n), r[i - 1]);
+    t = zfma(-cheb_c2(n), r[i], t);
+    t = zfma(cheb_c3(n), rn, t);
+    s[i] = zscale(h2, t);
+  }
+  // backward: pivots and multipliers b_i, alpha_i = (s_i - u_i alpha_{i+1}) / pivot_i
+  double mq[MM + 1];
+  double bn = 0.0;
+  double2 an = z2(0, 0);
+#pragma unroll
+  for (int i = MM; i >= 1; --i) {
+    const int n = PAR + 2 * i;
+    mq[i] = 0.0;
+    if (i <= M) {
+      const double lo = -h2l * (n == 2 ? 2.0 : 1.0) * cheb_c1(n);
+      const double d = 1.0 + ((n <= N - 2) ? h2l * cheb_c2(n) : 0.0);
+      const double u = (n + 2 <= N - 2) ? -h2l * cheb_c3(n) : 0.0;
+      const double iv = 1.0 / (d + u * bn);
+      bn = -lo * iv;
+      mq[i] = bn;
+      an = zscale(iv, zfma(-u, an, s[i]));
+      s[i] = an;
+    }
+  }
+  // forward: P_i = alpha_i + b_i P_{i-1}, Q_i = b_i Q_{i-1}
+  double2 P = z2(0, 0), SP = z2(0, 0);
+  double Q = 1.0, sq = 1.0;
+#pragma unroll
+  for (int i = 1; i <= MM; ++i) {
+    if (i <= M) {
+      P = zfma(mq[i], P, s[i]);
+      s[i] = P;
+      SP = zadd(SP, P);
+      Q *= mq[i];
+      mq[i] = Q;
+      sq += Q;
+    }
+  }
+  const double2 x0 = zscale(1.0 / sq, zsub(g, SP));
+  dst(PAR, x0);
+#pragma unroll
+  for (int i = 1; i <= MM; ++i)
+    if (i <= M) dst(PAR + 2 * i, zfma(mq[i], x0, s[i]));
+}
+
+// r[i] = rhs(m, D_m) for rows m = PAR + 2i <= N-2, where D_m is the
+// y-derivative coefficient of the vector `a` (c_m D_m = 2 sum over p > m,
+// p + m odd, of p a_p); a(p) and rhs(m, .) are called with indices <= N.
+template <int MAXN, int PAR, class SRC, class RHS>
+__device__ __forceinline__ void fill_reg_deriv(int N, double2 (&r)[MAXN / 2 + 1], SRC a, RHS rhs) {
+  constexpr int MM = MAXN / 2;
+  double2 S = z2(0, 0);
+#pragma unroll
+  for (int i = MM - 1; i >= 0; --i) {
+    const int m = PAR + 2 * i, p = m + 1;
+    const double2 ap = a(p < N ? p : N);
+    S = zfma(p <= N ? (double)p : 0.0, ap, S);
+    const double2 v = rhs(m < N ? m : N, zscale(m == 0 ? 1.0 : 2.0, S));
+    r[i] = m <= N - 2 ? v : z2(0, 0);
+  }
+  r[MM] = z2(0, 0);
+}
+
+template <int MAXN, int PAR, class RHS>
+__device__ __forceinline__ void fill_reg(int N, double2 (&r)[MAXN / 2 + 1], RHS rhs) {
+  constexpr int MM = MAXN / 2;
+#pragma unroll
+  for (int i = 0; i < MM; ++i) {
+    const int m = PAR + 2 * i;
+    const double2 v = rhs(m < N ? m : N);
+    r[i] = m <= N - 2 ? v : z2(0, 0);
+  }
+  r[MM] = z2(0, 0);
+}
+
 // ---- A: p_a, one thread per (mode, parity) ---------------------------------
 template <typename T>
 __global__ void __launch_bounds__(64) tau_pressure(TauArgs a) {
@@ -281,6 +398,119 @@ __global__ void __launch_bounds__(64) tau_velocity(TauArgs a) {
     hel_par(make_sweep(a, q, md.lam), par, lds, g,
             [&](int n, double2 v) { dst[(size_t)n * S] = v; });
   }
+}
+
+// ---- A and B with register-resident columns (N <= MAXN) -------------------
+template <typename T, int MAXN, int PAR>
+__device__ __forceinline__ void pressure_par(const TauArgs& a, const Mode& md, int q) {
+  using C = typename CT<T>::t;
+  const int N = lane_copy(a.N), Ny = N + 1;
+  const size_t S = (size_t)a.nmodes;
+  const C* in = (const C*)a.in;
+  auto F = [&](int c, int n) { return to_z(in[((size_t)c * Ny + n) * S + q]); };
+  double2* PA = a.scr + (size_t)kPA * Ny * S + q;
+  const double iH = 1.0 / a.H;
+  double2 r[MAXN / 2 + 1];
+  fill_reg_deriv<MAXN, PAR>(N, r, [&](int p) { return F(1, p); }, [&](int m, double2 dfy) {
+    return zadd(zadd(zi(md.kx, F(0, m)), zscale(iH, dfy)), zi(md.kz, F(2, m)));
+  });
+  hel_reg<MAXN, PAR>(N, a.H * a.H, md.lam, r, z2(0, 0),
+                     [&](int n, double2 v) { PA[(size_t)n * S] = v; });
+}
+
+// k = 0 (N <= 64): 2n p_n = c_{n-1} b_{n-1} - b_{n+1} with b = H F_y and
+// p(-H) = gauge, one lane per coefficient n = lane + 1; the wall condition's
+// alternating sum is a fixed-order wave reduction.
+template <typename T>
+__device__ __forceinline__ void pressure_zero(const TauArgs& a) {
+  using C = typename CT<T>::t;
+  const int N = a.N, Ny = N + 1;
+  const size_t S = (size_t)a.nmodes;
+  const C* Fy = (const C*)a.in + (size_t)Ny * S;
+  double2* PA = a.scr + (size_t)kPA * Ny * S;
+  const int n = threadIdx.x + 1;
+  double2 t = z2(0, 0);
+  if (n <= N) {
+    const double2 bm = zscale(a.H * (n == 1 ? 2.0 : 1.0), to_z(Fy[(size_t)(n - 1) * S]));
+    const double2 bp = (n + 1 <= N - 1) ? zscale(a.H, to_z(Fy[(size_t)(n + 1) * S])) : z2(0, 0);
+    const double2 pn = zscale(1.0 / (2.0 * n), zsub(bm, bp));
+    PA[(size_t)n * S] = pn;
+    t = (n & 1) ? zscale(-1.0, pn) : pn;
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    t.x += __shfl_xor(t.x, o);
+    t.y += __shfl_xor(t.y, o);
+  }
+  if (threadIdx.x == 0) PA[0] = zsub(z2(a.gauge[0], 0.0), t);
+}
+
+template <typename T, int MAXN>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) tau_pressure_r(TauArgs a) {
+  const int par = blockIdx.y;
+  if (blockIdx.x == gridDim.x - 1) {  // the extra block: mode 0
+    if (par == 0) pressure_zero<T>(a);
+    return;
+  }
+  const int q = blockIdx.x * 64 + threadIdx.x;
+  if (q == 0 || q >= a.nmodes) return;
+  const Mode md = mode_of(a, q);
+  if (md.nyquist) return;
+  if (par == 0) pressure_par<T, MAXN, 0>(a, md, q);
+  else pressure_par<T, MAXN, 1>(a, md, q);
+}
+
+template <typename T, int MAXN, int PAR, bool VCOMP>
+__device__ __forceinline__ void velocity_par(const TauArgs& a, const Mode& md, int q, int comp) {
+  using C = typename CT<T>::t;
+  const int N = lane_copy(a.N), Ny = N + 1;
+  const size_t S = (size_t)a.nmodes;
+  const C* in = (const C*)a.in;
+  const C* wall = (const C*)a.wall;
+  auto F = [&](int c, int n) { return to_z(in[((size_t)c * Ny + n) * S + q]); };
+  const double2* PA = a.scr + (size_t)kPA * Ny * S + q;
+  double2* dst = a.scr + (size_t)(kUA + comp) * Ny * S + q;
+  const double2 gm = to_z(wall[(size_t)comp * S + q]);
+  const double2 gp = to_z(wall[(size_t)(3 + comp) * S + q]);
+  const double2 g = PAR == 0 ? zscale(0.5, zadd(gp, gm)) : zscale(0.5, zsub(gp, gm));
+  const double iH = 1.0 / a.H, h2 = a.H * a.H;
+  const bool zero = q == 0;  // k = 0: no pressure coupling, v'' = 0
+  double2 r[MAXN / 2 + 1];
+  if (VCOMP) {
+    if (zero) fill_reg<MAXN, PAR>(N, r, [](int) { return z2(0, 0); });
+    else
+      fill_reg_deriv<MAXN, PAR>(N, r, [&](int p) { return PA[(size_t)p * S]; },
+                                [&](int m, double2 dp) { return zsub(zscale(iH, dp), F(1, m)); });
+    double2 dm = z2(0, 0), dpl = z2(0, 0);
+    hel_reg<MAXN, PAR>(N, h2, md.lam, r, g, [&](int n, double2 v) {
+      dst[(size_t)n * S] = v;
+      const double2 t = zscale((double)n * n, v);
+      dpl = zadd(dpl, t);
+      dm = (n & 1) ? zadd(dm, t) : zsub(dm, t);
+    });
+    double2* sl = a.scr + (size_t)kSlope * Ny * S + q;
+    sl[(size_t)(2 * PAR) * S] = dm;
+    sl[(size_t)(2 * PAR + 1) * S] = dpl;
+  } else {
+    const double k = comp == 0 ? md.kx : md.kz;
+    if (zero) fill_reg<MAXN, PAR>(N, r, [&](int m) { return zscale(-1.0, F(comp, m)); });
+    else
+      fill_reg<MAXN, PAR>(N, r, [&](int m) { return zsub(zi(k, PA[(size_t)m * S]), F(comp, m)); });
+    hel_reg<MAXN, PAR>(N, h2, md.lam, r, g, [&](int n, double2 v) { dst[(size_t)n * S] = v; });
+  }
+}
+
+// VCOMP: the v component alone (grid z = 1); otherwise u and w (grid z = 2).
+// Separate instantiations keep the two paths' register budgets apart.
+template <typename T, int MAXN, bool VCOMP>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) tau_velocity_r(TauArgs a) {
+  const int q = blockIdx.x * 64 + threadIdx.x;
+  const int par = blockIdx.y, comp = VCOMP ? 1 : 2 * (int)blockIdx.z;
+  if (q >= a.nmodes) return;
+  const Mode md = mode_of(a, q);
+  if (md.nyquist) return;
+  if (par == 0) velocity_par<T, MAXN, 0, VCOMP>(a, md, q, comp);
+  else velocity_par<T, MAXN, 1, VCOMP>(a, md, q, comp);
 }
 
 // ---- D: wall pressures and superposition, one thread per (mode, n) --------
@@ -378,6 +608,53 @@ __global__ void __launch_bounds__(64) tau_stress_dy(TauArgs a) {
     b2 = b1;
     b1 = b;
   }
+}
+
+// Branch-free over the unrolled rows: loads use clamped indices, and the
+// rows past N (iterated first, descending) store to row N, which its own
+// iteration overwrites last.
+// (restrict holds as parameters: the output never overlaps the scratch)
+template <typename T, int MAXN, int COMP>
+__device__ __forceinline__ void stress_dy_comp(const TauArgs& a, const Mode& md,
+                                               const double2* __restrict__ scr,
+                                               typename CT<T>::t* __restrict__ out) {
+  const int N = lane_copy(a.N), Ny = N + 1;
+  const size_t S = (size_t)a.nmodes;
+  constexpr int src = COMP == 0 ? kV : (COMP == 1 ? kU : kW);
+  auto A = [&](int slot, int n) { return scr[((size_t)slot * Ny + n) * S]; };
+  const double iH = 1.0 / a.H;
+  double2 b2 = z2(0, 0), b1 = z2(0, 0);
+#pragma unroll
+  for (int n = MAXN; n >= 0; --n) {
+    const int nn = n < N ? n : N;
+    const double2 an1 = A(src, n + 1 < N ? n + 1 : N);
+    double2 b = zfma(2.0 * (n + 1), an1, b2);
+    if (n == 0) b = zscale(0.5, b);
+    b = n < N ? b : z2(0, 0);
+    double2 val;
+    if (COMP == 0) val = zadd(zscale(-1.0, A(kP, nn)), zscale(2.0 * iH, b));
+    else if (COMP == 1) val = zadd(zscale(iH, b), zi(md.kx, A(kV, nn)));
+    else val = zadd(zi(md.kz, A(kV, nn)), zscale(iH, b));
+    out[(size_t)nn * S] = from_z<T>(val);
+    b2 = b1;
+    b1 = b;
+  }
+}
+
+template <typename T, int MAXN>
+__global__ void __launch_bounds__(64) tau_stress_dy_r(TauArgs a) {
+  const int q = blockIdx.x * 64 + threadIdx.x;
+  const int comp = blockIdx.y;  // 0: sigma_yy (v'), 1: sigma_xy (u'), 2: sigma_yz (w')
+  if (q >= a.nmodes) return;
+  const Mode md = mode_of(a, q);
+  if (md.nyquist) return;
+  using C = typename CT<T>::t;
+  const size_t NyS = (size_t)(a.N + 1) * a.nmodes;
+  const double2* scr = a.scr + q;
+  C* out = (C*)a.out + q;
+  if (comp == 0) stress_dy_comp<T, MAXN, 0>(a, md, scr, out + 1 * NyS);
+  else if (comp == 1) stress_dy_comp<T, MAXN, 1>(a, md, scr, out + 3 * NyS);
+  else stress_dy_comp<T, MAXN, 2>(a, md, scr, out + 5 * NyS);
 }
 
 // ---- plan time ------------------------------------------------------------
@@ -495,15 +772,38 @@ static TauArgs tau_args(Plan& p) {
 
 static size_t tau_lds_bytes(Plan& p) { return (size_t)((p.p.Ny - 1) / 2 + 2) * 64 * sizeof(double2); }
 
+// Chebyshev orders up to 64 keep each parity's column in registers; larger
+// orders stage it in LDS.
+template <typename T, int MAXN>
+static void launch_tau_reg(Plan& p, const TauArgs& a, unsigned nb, unsigned nc, bool stress) {
+  tau_pressure_r<T, MAXN><<<dim3(nb + 1, 2), 64, 0, p.stream>>>(a);
+  tau_velocity_r<T, MAXN, true><<<dim3(nb, 2, 1), 64, 0, p.stream>>>(a);
+  tau_velocity_r<T, MAXN, false><<<dim3(nb, 2, 2), 64, 0, p.stream>>>(a);
+  if (stress) {
+    tau_combine<T, true><<<nc, 256, 0, p.stream>>>(a);
+    tau_stress_dy_r<T, MAXN><<<dim3(nb, 3), 64, 0, p.stream>>>(a);
+  } else {
+    tau_combine<T, false><<<nc, 256, 0, p.stream>>>(a);
+  }
+}
+
 template <typename T>
 hipError_t launch_tau(Plan& p, bool stress) {
   TauArgs a = tau_args(p);
   const unsigned nb = (unsigned)((p.nmodes + 63) / 64);
+  const size_t tot = (size_t)p.p.Ny * p.nmodes;
+  const unsigned nc = (unsigned)((tot + 255) / 256);
+  if (a.N <= 32) {
+    launch_tau_reg<T, 32>(p, a, nb, nc, stress);
+    return hipGetLastError();
+  }
+  if (a.N <= 64) {
+    launch_tau_reg<T, 64>(p, a, nb, nc, stress);
+    return hipGetLastError();
+  }
   const size_t lds = tau_lds_bytes(p);
   tau_pressure<T><<<dim3(nb, 2), 64, lds, p.stream>>>(a);
   tau_velocity<T><<<dim3(nb, 2, 3), 64, lds, p.stream>>>(a);
-  const size_t tot = (size_t)p.p.Ny * p.nmodes;
-  const unsigned nc = (unsigned)((tot + 255) / 256);
   if (stress) {
     tau_combine<T, true><<<nc, 256, 0, p.stream>>>(a);
     tau_stress_dy<T><<<dim3(nb, 3), 64, 0, p.stream>>>(a);

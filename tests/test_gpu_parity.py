@@ -87,6 +87,8 @@ DL_CASES = [
     # seed, ns, nt, L, H, alpha, rc, Nx, Nz, Ny, Lz
     (11, 40, 70, 4.0, 1.0, 4.0, 1.5, 40, 32, 33, 3.5),
     (12, 150, 33, 6.0, 1.3, 3.0, 1.9, 48, 60, 25, None),
+    (14, 60, 45, 4.0, 1.5, 3.0, 1.3, 20, 16, 65, None),      # Chebyshev order 64
+    (15, 50, 30, 4.0, 1.5, 3.0, 1.3, 16, 16, 97, None),      # order above 64
 ]
 
 
@@ -110,6 +112,8 @@ SL_CASES = [
     (21, 1, 5, 4.0, 1.0, 4.0, 1.5, 32, 32, 17, None),       # one source
     (22, 300, 257, 5.0, 2.0, 2.5, 2.0, 40, 36, 33, 6.0),     # ragged, non-square box
     (23, 129, 3, 3.2, 0.7, 5.0, 1.2, 30, 50, 9, 3.0),       # radix 3/5 sizes, small Ny
+    (24, 200, 90, 5.0, 2.0, 2.5, 1.6, 24, 24, 65, None),     # Chebyshev order 64
+    (25, 80, 60, 4.0, 1.6, 3.0, 1.3, 16, 20, 97, None),      # order above 64
 ]
 
 
