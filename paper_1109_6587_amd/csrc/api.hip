@@ -75,7 +75,7 @@ void free_plan(Plan& p) {
                   p.tgt.y,     p.tgt.z,       p.tgt.s,       p.nconst,     p.sweep,
                   p.wall.keys, p.wall.counts, p.wall.offs,   p.wall.cell_start,
                   p.wall.item_start, p.wall.perm, p.wall.x,  p.wall.y,     p.wall.z,
-                  p.wall.s,    p.work};
+                  p.wall.s,    p.work,        p.wall_part};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (p.flags_host) (void)hipHostFree(p.flags_host);
@@ -216,7 +216,7 @@ int check_plan(ggem_plan_t plan) {
 
 template <typename T>
 int zero_ul(Plan& p, int nt) {
-  const size_t n = (size_t)3 * p.p.max_tgt;
+  const size_t n = (size_t)kNearSlices * 3 * p.p.max_tgt;
   if (nt > 0) fill_zero<T><<<(unsigned)((n + 255) / 256), 256, 0, p.stream>>>((T*)p.ul, n);
   HIP_TRY(hipGetLastError());
   return GGEM_OK;
@@ -458,11 +458,13 @@ extern "C" int ggem_plan_create(const ggem_params* prm, void* hip_stream, ggem_p
             hipMalloc(&p.twx, 2 * Nx * elt) == hipSuccess &&
             hipMalloc(&p.twz, 2 * Nz * elt) == hipSuccess &&
             dev_alloc(&p.infl, 4 * (size_t)p.nmodes) &&
-            hipMalloc(&p.ul, 3 * (size_t)(q.max_tgt > 0 ? q.max_tgt : 1) * elt) == hipSuccess &&
+            hipMalloc(&p.ul, kNearSlices * 3 * (size_t)(q.max_tgt > 0 ? q.max_tgt : 1) * elt) ==
+                hipSuccess &&
             hipMalloc(&p.phys, 6 * Ny * Nx * Nz * elt) == hipSuccess &&
             hipMalloc(&p.specA, 6 * Ny * p.nmodes * 2 * elt) == hipSuccess &&
             hipMalloc(&p.specB, 6 * Ny * p.nmodes * 2 * elt) == hipSuccess &&
             hipMalloc(&p.wall_phys, 6 * Nx * Nz * elt) == hipSuccess &&
+            hipMalloc(&p.wall_part, kWallSlices * 6 * Nx * Nz * elt) == hipSuccess &&
             hipMalloc(&p.wall_spec, 6 * (size_t)p.nmodes * 2 * elt) == hipSuccess &&
             dev_alloc(&p.tau_scr, 2 * 9 * Ny * (size_t)p.nmodes) &&
             dev_alloc(&p.nconst, 3 * Ny) &&

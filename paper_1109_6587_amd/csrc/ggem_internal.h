@@ -14,6 +14,8 @@ __device__ inline void wave_count_add(unsigned long long* ctr, unsigned v) {
 }
 
 constexpr int kMaxCells = 16384;     // cell-list size (LDS histograms)
+constexpr int kNearSlices = 3;       // blocks per near-field work item (partial sums)
+constexpr int kWallSlices = 3;       // blocks per wall-data work item (partial sums)
 constexpr int kMaxChunks = 512;      // counting-sort chunks per point set (at most)
 constexpr int kNearBlock = 64;       // targets per near-field work item
 constexpr int kMaxNy = 129;
@@ -83,11 +85,12 @@ struct Plan {
   Binned wall;        // wall nodes of y = -H and y = +H, binned once per plan
   Binned* tview;      // targets of the current call (tgt, or src when they coincide)
   void* tnrm;         // sorted target normals of the current call (3 x max_tgt, T)
-  void* ul;           // local result at sorted targets (3 x max_tgt, T)
+  void* ul;           // local result at sorted targets (kNearSlices x 3 x max_tgt, T)
   void* phys;         // physical grid fields (6 x Ny x Nx x Nz, T)
   void* specA;        // spectral fields (6 x Ny x Nx x Nzh, complex T)
   void* specB;
   void* wall_phys;    // wall velocities (2 x 3 x Nx x Nz, T)
+  void* wall_part;    // their partial sums (kWallSlices x 2 x 3 x Nx x Nz, T)
   void* wall_spec;    // (2 x 3 x Nx x Nzh, complex T)
   double* tau_scr;    // tau scratch (9 x Ny x nmodes, complex FP64)
   double* gauge;      // gauge partial sums and value

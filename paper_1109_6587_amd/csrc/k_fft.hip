@@ -160,81 +160,112 @@ __device__ inline void stockham_pass(const typename Cx<T>::t* __restrict__ src,
   }
 }
 
-// Forward R2C along z: one wave per line, 4 lines per block.
-template <typename T>
-__global__ void __launch_bounds__(256) fft_z_r2c(const T* __restrict__ in,
-                                                 typename Cx<T>::t* __restrict__ out, int nlines,
-                                                 int Nz, Radices rz,
-                                                 const typename Cx<T>::t* __restrict__ tw) {
-  using C = typename Cx<T>::t;
-  extern __shared__ unsigned char smem_raw[];
-  C* smem = (C*)smem_raw;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int line = blockIdx.x * 4 + wave;
-  C* b0 = smem + wave * 2 * Nz;
-  C* b1 = b0 + Nz;
-  const bool ok = line < nlines;
-  if (ok)
-    for (int n = lane; n < Nz; n += 64) {
-      C v;
-      v.x = in[(size_t)line * Nz + n];
-      v.y = (T)0;
-      b0[n] = v;
-    }
+// Wave-local LDS hand-off: the wave's own writes are visible to all its
+// lanes after this (the z transforms keep each line within one wave).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The block's copy of a twiddle table (n entries) in LDS: every pass then
+// reads its twiddles at LDS latency.
+template <typename C>
+__device__ inline void stage_twiddles(C* __restrict__ dst, const C* __restrict__ tw, int n) {
+  for (int t = threadIdx.x; t < n; t += blockDim.x) dst[t] = tw[t];
   __syncthreads();
+}
+
+// The LPW lines of a wave: the butterflies of all of them are shared out
+// over its 64 lanes, so short lines keep every lane busy.
+template <typename T, int SIGN>
+__device__ inline void wave_lines_fft(typename Cx<T>::t*& b0, typename Cx<T>::t*& b1, int N,
+                                      int lpw, const Radices& rad,
+                                      const typename Cx<T>::t* __restrict__ tw, int lane) {
+  using C = typename Cx<T>::t;
   int Ns = 1;
-  for (int s = 0; s < rz.n; ++s) {
-    if (ok) stockham_pass<T, -1>(b0, b1, Nz, rz.r[s], Ns, tw, lane, 64);
-    __syncthreads();
+  for (int s = 0; s < rad.n; ++s) {
+    const int R = rad.r[s], NR = N / R;
+    for (int w = lane; w < lpw * NR; w += 64) {
+      const int l = w / NR, j = w - l * NR;
+      stockham_pass<T, SIGN>(b0 + l * N, b1 + l * N, N, R, Ns, tw, j, NR);
+    }
+    wave_sync();
     C* t = b0;
     b0 = b1;
     b1 = t;
-    Ns *= rz.r[s];
+    Ns *= R;
   }
+}
+
+// Forward R2C along z: each wave owns LPW consecutive lines, 4 waves per
+// block; LDS: the twiddles, then per wave two buffers of LPW lines.
+template <typename T>
+__global__ void __launch_bounds__(256) fft_z_r2c(const T* __restrict__ in,
+                                                 typename Cx<T>::t* __restrict__ out, int nlines,
+                                                 int Nz, int lpw, Radices rz,
+                                                 const typename Cx<T>::t* __restrict__ tw) {
+  using C = typename Cx<T>::t;
+  extern __shared__ unsigned char smem_raw[];
+  C* twl = (C*)smem_raw;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int line0 = (blockIdx.x * 4 + wave) * lpw;
+  C* b0 = twl + Nz + wave * 2 * lpw * Nz;
+  C* b1 = b0 + lpw * Nz;
+  for (int e = lane; e < lpw * Nz; e += 64) {
+    const int l = e / Nz, n = e - l * Nz;
+    C v;
+    v.x = line0 + l < nlines ? in[(size_t)(line0 + l) * Nz + n] : (T)0;
+    v.y = (T)0;
+    b0[e] = v;
+  }
+  stage_twiddles(twl, tw, Nz);  // its barrier also publishes the lines
+  wave_lines_fft<T, -1>(b0, b1, Nz, lpw, rz, twl, lane);
   const int Nzh = Nz / 2 + 1;
-  if (ok)
-    for (int m = lane; m < Nzh; m += 64) out[(size_t)line * Nzh + m] = b0[m];
+  for (int e = lane; e < lpw * Nzh; e += 64) {
+    const int l = e / Nzh, m = e - l * Nzh;
+    if (line0 + l < nlines) out[(size_t)(line0 + l) * Nzh + m] = b0[l * Nz + m];
+  }
 }
 
 // Inverse C2R along z: rebuild the Hermitian line, inverse FFT, real part.
 template <typename T>
 __global__ void __launch_bounds__(256) fft_z_c2r(const typename Cx<T>::t* __restrict__ in,
-                                                 T* __restrict__ out, int nlines, int Nz,
+                                                 T* __restrict__ out, int nlines, int Nz, int lpw,
                                                  Radices rz,
                                                  const typename Cx<T>::t* __restrict__ tw) {
   using C = typename Cx<T>::t;
   extern __shared__ unsigned char smem_raw[];
-  C* smem = (C*)smem_raw;
+  C* twl = (C*)smem_raw;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int line = blockIdx.x * 4 + wave;
-  C* b0 = smem + wave * 2 * Nz;
-  C* b1 = b0 + Nz;
-  const bool ok = line < nlines;
+  const int line0 = (blockIdx.x * 4 + wave) * lpw;
+  C* b0 = twl + Nz + wave * 2 * lpw * Nz;
+  C* b1 = b0 + lpw * Nz;
   const int Nzh = Nz / 2 + 1;
-  if (ok)
-    for (int m = lane; m < Nzh; m += 64) {
-      C v = in[(size_t)line * Nzh + m];
-      b0[m] = v;
-      if (m > 0 && m < Nz / 2) {
-        v.y = -v.y;
-        b0[Nz - m] = v;
-      }
+  for (int e = lane; e < lpw * Nzh; e += 64) {
+    const int l = e / Nzh, m = e - l * Nzh;
+    C v;
+    v.x = (T)0;
+    v.y = (T)0;
+    if (line0 + l < nlines) v = in[(size_t)(line0 + l) * Nzh + m];
+    C* line = b0 + l * Nz;
+    line[m] = v;
+    if (m > 0 && m < Nz / 2) {
+      v.y = -v.y;
+      line[Nz - m] = v;
     }
-  __syncthreads();
-  int Ns = 1;
-  for (int s = 0; s < rz.n; ++s) {
-    if (ok) stockham_pass<T, 1>(b0, b1, Nz, rz.r[s], Ns, tw, lane, 64);
-    __syncthreads();
-    C* t = b0;
-    b0 = b1;
-    b1 = t;
-    Ns *= rz.r[s];
   }
-  if (ok)
-    for (int n = lane; n < Nz; n += 64) out[(size_t)line * Nz + n] = b0[n].x;
+  stage_twiddles(twl, tw, Nz);
+  wave_lines_fft<T, 1>(b0, b1, Nz, lpw, rz, twl, lane);
+  for (int e = lane; e < lpw * Nz; e += 64) {
+    const int l = e / Nz, n = e - l * Nz;
+    if (line0 + l < nlines) out[(size_t)(line0 + l) * Nz + n] = b0[e].x;
+  }
 }
 
-// C2C along x on [plane][l][m] data, in place: CB columns per block.
+// C2C along x on [plane][l][m] data, in place: CB columns per block, each
+// column at stride Nx + 1 in LDS so the transposing loads and stores of
+// consecutive columns fall in different banks.
 template <typename T, int SIGN>
 __global__ void __launch_bounds__(256) fft_x(typename Cx<T>::t* __restrict__ data, int Nx,
                                              int Nzh, int CB, Radices rx,
@@ -244,8 +275,10 @@ __global__ void __launch_bounds__(256) fft_x(typename Cx<T>::t* __restrict__ dat
   C* smem = (C*)smem_raw;
   const int plane = blockIdx.y;
   const int m0 = blockIdx.x * CB;
-  C* b0 = smem;
-  C* b1 = smem + CB * Nx;
+  const int NxP = Nx + 1;
+  C* twl = smem;
+  C* b0 = smem + Nx;
+  C* b1 = b0 + CB * NxP;
   C* base = data + (size_t)plane * Nx * Nzh;
   for (int idx = threadIdx.x; idx < CB * Nx; idx += 256) {
     const int i = idx / CB, c = idx - (idx / CB) * CB;
@@ -254,9 +287,9 @@ __global__ void __launch_bounds__(256) fft_x(typename Cx<T>::t* __restrict__ dat
     v.x = (T)0;
     v.y = (T)0;
     if (m < Nzh) v = base[(size_t)i * Nzh + m];
-    b0[c * Nx + i] = v;
+    b0[c * NxP + i] = v;
   }
-  __syncthreads();
+  stage_twiddles(twl, tw, Nx);
   int Ns = 1;
   for (int s = 0; s < rx.n; ++s) {
     const int R = rx.r[s];
@@ -264,7 +297,7 @@ __global__ void __launch_bounds__(256) fft_x(typename Cx<T>::t* __restrict__ dat
     // spread the CB lines' butterflies over the block
     for (int w = threadIdx.x; w < CB * NR; w += 256) {
       const int c = w / NR, j = w - (w / NR) * NR;
-      stockham_pass<T, SIGN>(b0 + c * Nx, b1 + c * Nx, Nx, R, Ns, tw, j, NR + 1);
+      stockham_pass<T, SIGN>(b0 + c * NxP, b1 + c * NxP, Nx, R, Ns, twl, j, NR + 1);
     }
     __syncthreads();
     C* t = b0;
@@ -275,7 +308,7 @@ __global__ void __launch_bounds__(256) fft_x(typename Cx<T>::t* __restrict__ dat
   for (int idx = threadIdx.x; idx < CB * Nx; idx += 256) {
     const int i = idx / CB, c = idx - (idx / CB) * CB;
     const int m = m0 + c;
-    if (m < Nzh) base[(size_t)i * Nzh + m] = b0[c * Nx + i];
+    if (m < Nzh) base[(size_t)i * Nzh + m] = b0[c * NxP + i];
   }
 }
 
@@ -287,11 +320,17 @@ static Radices radices(const int* r, int n) {
 }
 
 static int cols_per_block(int Nx, size_t elt) {
-  int cb = (int)(32768 / ((size_t)Nx * elt));  // ping-pong buffers of <= 64 KB
+  int cb = (int)(32768 / ((size_t)(Nx + 1) * elt));  // ping-pong buffers of <= 64 KB
   if (cb < 1) cb = 1;
   if (cb > 16) cb = 16;
   return cb;
 }
+
+// lines per wave of the z transforms (LDS of a block stays within 80 KB)
+static int lines_per_wave(int Nz, size_t celt) { return (Nz + 8 * 2 * Nz) * celt <= 81920 ? 2 : 1; }
+
+static size_t fft_z_lds(int Nz, int lpw, size_t celt) { return (size_t)(Nz + 8 * lpw * Nz) * celt; }
+static size_t fft_x_lds(int Nx, int CB, size_t celt) { return (size_t)(Nx + 2 * CB * (Nx + 1)) * celt; }
 
 template <typename T>
 hipError_t launch_fft_forward(Plan& p, void* phys, void* spec, int nplanes) {
@@ -299,12 +338,14 @@ hipError_t launch_fft_forward(Plan& p, void* phys, void* spec, int nplanes) {
   const int Nx = p.p.Nx, Nz = p.p.Nz, Nzh = p.Nzh;
   const int nlines = nplanes * Nx;
   Radices rz = radices(p.radz, p.nradz), rx = radices(p.radx, p.nradx);
-  fft_z_r2c<T><<<(nlines + 3) / 4, 256, 4 * 2 * Nz * sizeof(C), p.stream>>>(
-      (const T*)phys, (C*)spec, nlines, Nz, rz, (const C*)p.twz);
+  const int lpw = lines_per_wave(Nz, sizeof(C));
+  const int lpb = 4 * lpw;
+  fft_z_r2c<T><<<(nlines + lpb - 1) / lpb, 256, fft_z_lds(Nz, lpw, sizeof(C)), p.stream>>>(
+      (const T*)phys, (C*)spec, nlines, Nz, lpw, rz, (const C*)p.twz);
   const int CB = cols_per_block(Nx, sizeof(C));
   dim3 g((Nzh + CB - 1) / CB, nplanes);
-  fft_x<T, -1><<<g, 256, 2 * CB * Nx * sizeof(C), p.stream>>>((C*)spec, Nx, Nzh, CB, rx,
-                                                              (const C*)p.twx);
+  fft_x<T, -1><<<g, 256, fft_x_lds(Nx, CB, sizeof(C)), p.stream>>>((C*)spec, Nx, Nzh, CB, rx,
+                                                                   (const C*)p.twx);
   return hipGetLastError();
 }
 
@@ -316,10 +357,12 @@ hipError_t launch_fft_inverse(Plan& p, void* spec, void* phys, int nplanes) {
   Radices rz = radices(p.radz, p.nradz), rx = radices(p.radx, p.nradx);
   const int CB = cols_per_block(Nx, sizeof(C));
   dim3 g((Nzh + CB - 1) / CB, nplanes);
-  fft_x<T, 1><<<g, 256, 2 * CB * Nx * sizeof(C), p.stream>>>((C*)spec, Nx, Nzh, CB, rx,
-                                                             (const C*)p.twx);
-  fft_z_c2r<T><<<(nlines + 3) / 4, 256, 4 * 2 * Nz * sizeof(C), p.stream>>>(
-      (const C*)spec, (T*)phys, nlines, Nz, rz, (const C*)p.twz);
+  fft_x<T, 1><<<g, 256, fft_x_lds(Nx, CB, sizeof(C)), p.stream>>>((C*)spec, Nx, Nzh, CB, rx,
+                                                                  (const C*)p.twx);
+  const int lpw = lines_per_wave(Nz, sizeof(C));
+  const int lpb = 4 * lpw;
+  fft_z_c2r<T><<<(nlines + lpb - 1) / lpb, 256, fft_z_lds(Nz, lpw, sizeof(C)), p.stream>>>(
+      (const C*)spec, (T*)phys, nlines, Nz, lpw, rz, (const C*)p.twz);
   return hipGetLastError();
 }
 

@@ -44,7 +44,7 @@ struct InterpArgs {
   const double *tx, *ty, *tz;
   const void* tn;      // sorted normals (T, SoA) for the double layer
   size_t tcap;
-  const void* ul;      // local part at sorted targets (T, SoA)
+  const void* ul;      // local part at sorted targets (kNearSlices x 3 components, T, SoA)
   const void* grid;    // [ncomp][Ny][Nx][Nz] T
   double* out;         // (nt, 3) in input order
 };
@@ -95,8 +95,14 @@ __global__ void __launch_bounds__(256) interp_combine(InterpArgs a) {
   for (int o = kGrp / 2; o > 0; o >>= 1)
     for (int c = 0; c < NC; ++c) acc[c] += __shfl_down(acc[c], o, kGrp);  // none when G = 1
   if (!valid || r != 0) return;
+  // local part: the near-field slices' partial sums, added in slice order
   const T* ul = (const T*)a.ul;
-  double res[3] = {(double)ul[t], (double)ul[a.tcap + t], (double)ul[2 * a.tcap + t]};
+  double res[3];
+  for (int c = 0; c < 3; ++c) {
+    double v = 0.0;
+    for (int s = 0; s < kNearSlices; ++s) v += (double)ul[(size_t)(3 * s + c) * a.tcap + t];
+    res[c] = v;
+  }
   if (GLOBAL) {
     if (!STRESS) {
       res[0] += acc[0];

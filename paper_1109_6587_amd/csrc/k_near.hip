@@ -121,6 +121,8 @@ struct NearArgs {
   size_t ostride;
   const int* tperm;        // wall mode: sorted target -> wall node index
   int nplane;              // wall mode: nodes per wall plane (0 = ordinary targets)
+  int nslice;              // blocks per work item, each over its share of the neighbour cells
+  size_t sstride;          // elements between the slices' partial outputs
   double scale;            // output factor
   unsigned long long* work;  // pair counter (null: not counted)
 };
@@ -135,12 +137,14 @@ __device__ inline int find_cell(const int* __restrict__ start, int ncells, int i
   return lo;
 }
 
-// Work item: up to 64 sorted targets of one cell (one per lane).  The W
-// waves of the block take disjoint subsets of the neighbour cells (cell k of
-// the list goes to wave k mod W), stage each cell's sources through their own
-// LDS slice, and the W partial sums are added in wave order at the end.  W is
-// 4 for ordinary targets and 9 for the wall nodes (one neighbour cell of the
-// wall layer per wave: there are few wall work items, each with much work).
+// Work item: up to 64 sorted targets of one cell (one per lane).  Its
+// neighbour cells are split into nslice consecutive runs, one block per
+// (item, run), each writing its own partial sums (added in run order by the
+// consumer), so a crowded neighbourhood is shared by several blocks and the
+// dispatcher balances the load.  Within a block the run's source batches
+// (64 sources of one cell) are numbered in cell order and batch u goes to
+// wave u mod W; each wave stages its batches through its own LDS slice, and
+// the W partial sums are added in wave order at the end.
 //
 // Pass 1 tests every staged source against the lane's target and keeps a bit
 // mask of the pairs within r_c; pass 2 evaluates the kernel only for those.
@@ -210,30 +214,53 @@ __global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k) {
   // wall targets only see the wall cell layer (cells are at least r_c high)
   const int oy0 = a.nplane ? 1 : 0, noy = a.nplane ? 1 : 3;
   const int ncand = noy * nxo * nzo;
-  for (int kc = wave; kc < ncand; kc += W) {
+  const int slice = blockIdx.y;
+  const int kc0 = slice * ncand / a.nslice, nk = (slice + 1) * ncand / a.nslice - kc0;
+  // lane l < nk describes neighbour cell kc0 + l: source range, periodic
+  // shift and number of batches
+  int cs0 = 0, cs1 = 0, nbat = 0;
+  double cshx = 0.0, cshz = 0.0;
+  if (lane < nk) {
+    const int kc = kc0 + lane;
     const int oyi = kc / (nxo * nzo) + oy0 - 1;
     const int oxi = (kc / nzo) % nxo, ozi = kc % nzo;
     const int cy = iy + oyi;
-    if (cy < 0 || cy >= g.ncy) continue;
-    int cx, cz;
-    double shx = 0.0, shz = 0.0;
-    if (g.ncx >= 3) {
-      const int u = ix + oxi - 1;
-      cx = u < 0 ? u + g.ncx : (u >= g.ncx ? u - g.ncx : u);
-      shx = u < 0 ? -g.Lx : (u >= g.ncx ? g.Lx : 0.0);
-    } else {
-      cx = oxi;
+    if (cy >= 0 && cy < g.ncy) {
+      int cx, cz;
+      if (g.ncx >= 3) {
+        const int u = ix + oxi - 1;
+        cx = u < 0 ? u + g.ncx : (u >= g.ncx ? u - g.ncx : u);
+        cshx = u < 0 ? -g.Lx : (u >= g.ncx ? g.Lx : 0.0);
+      } else {
+        cx = oxi;
+      }
+      if (g.ncz >= 3) {
+        const int u = iz + ozi - 1;
+        cz = u < 0 ? u + g.ncz : (u >= g.ncz ? u - g.ncz : u);
+        cshz = u < 0 ? -g.Lz : (u >= g.ncz ? g.Lz : 0.0);
+      } else {
+        cz = ozi;
+      }
+      const int nc = (cy * g.ncx + cx) * g.ncz + cz;
+      cs0 = a.scell[nc];
+      cs1 = a.scell[nc + 1];
+      nbat = (cs1 - cs0 + 63) >> 6;
     }
-    if (g.ncz >= 3) {
-      const int u = iz + ozi - 1;
-      cz = u < 0 ? u + g.ncz : (u >= g.ncz ? u - g.ncz : u);
-      shz = u < 0 ? -g.Lz : (u >= g.ncz ? g.Lz : 0.0);
-    } else {
-      cz = ozi;
-    }
-    const int nc = (cy * g.ncx + cx) * g.ncz + cz;
-    const int s0 = a.scell[nc], s1 = a.scell[nc + 1];
-    for (int b = s0; b < s1; b += 64) {
+  }
+  int bend = nbat;  // inclusive prefix of the batch counts over the cells
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(bend, o);
+    if (lane >= o) bend += v;
+  }
+  const int nunits = __shfl(bend, 63);
+  int cc = 0;  // the cell of the wave's current batch (advances monotonically)
+  for (int u = wave; u < nunits; u += W) {
+    while (u >= __shfl(bend, cc)) ++cc;
+    const int first = __shfl(bend, cc) - __shfl(nbat, cc);
+    const int s1 = __shfl(cs1, cc);
+    const double shx = __shfl(cshx, cc), shz = __shfl(cshz, cc);
+    {
+      const int b = __shfl(cs0, cc) + (u - first) * 64;
       // the batch's sources within r_c of the targets' box, compacted in order
       // (the others are out of range of every target of the item)
       const int si = b + lane;
@@ -339,7 +366,7 @@ __global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k) {
       for (int w = 1; w < W; ++w) acc += part[w][d][lane];
       v[d] = (T)a.scale * acc;
     }
-    T* out = (T*)a.out;
+    T* out = (T*)a.out + (size_t)slice * a.sstride;
     size_t o = (size_t)t;
     if (a.nplane) {
       const int r = a.tperm[t];
@@ -355,15 +382,15 @@ __global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k) {
 template <typename T, bool DL, int W>
 static void launch_near_w(Plan& p, const NearArgs& a, unsigned grid) {
   const bool fast = sizeof(T) == 4 && p.cg.ncx >= 3 && p.cg.ncz >= 3;
-  if (fast) near_field<T, DL, true, W><<<grid, 64 * W, 0, p.stream>>>(a, make_kc<T>(p.p.alpha));
-  else near_field<T, DL, false, W><<<grid, 64 * W, 0, p.stream>>>(a, make_kc<T>(p.p.alpha));
+  const dim3 g(grid, (unsigned)a.nslice);
+  if (fast) near_field<T, DL, true, W><<<g, 64 * W, 0, p.stream>>>(a, make_kc<T>(p.p.alpha));
+  else near_field<T, DL, false, W><<<g, 64 * W, 0, p.stream>>>(a, make_kc<T>(p.p.alpha));
 }
 
 // grid = an upper bound of the work items (targets/64 + cells)
 template <typename T, bool DL>
 static void launch_near_kernel(Plan& p, const NearArgs& a, unsigned grid) {
-  if (a.nplane) launch_near_w<T, DL, 9>(p, a, grid);
-  else launch_near_w<T, DL, 4>(p, a, grid);
+  launch_near_w<T, DL, 4>(p, a, grid);
 }
 
 // Pressure gauge of the double layer: the k = 0 pressure at y = -H equals
@@ -428,6 +455,8 @@ static NearArgs near_args(Plan& p, const Binned& tg, void* out, size_t ostride) 
   a.ostride = ostride;
   a.tperm = tg.perm;
   a.nplane = 0;
+  a.nslice = kNearSlices;
+  a.sstride = 3 * ostride;
   a.scale = 0.039788735772973833942;  // 1/(8 pi)
   a.work = nullptr;
   return a;
@@ -462,12 +491,27 @@ hipError_t launch_near_dl(Plan& p, int nt) {
 // the wall planes are transformed in x, z only, while the grid fields get the
 // 1/(Nx Nz) of the forward DFT through the Chebyshev forward matrix.
 template <typename T>
+__global__ void __launch_bounds__(256) sum_slices(const T* __restrict__ part, T* __restrict__ out,
+                                                  size_t n) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  T v = part[i];
+  for (int s = 1; s < kWallSlices; ++s) v += part[(size_t)s * n + i];
+  out[i] = v;
+}
+
+template <typename T>
 hipError_t launch_wall(Plan& p) {
   const int nplane = p.p.Nx * p.p.Nz;
-  NearArgs a = near_args(p, p.wall, p.wall_phys, (size_t)nplane);
+  NearArgs a = near_args(p, p.wall, p.wall_part, (size_t)nplane);
   a.nplane = nplane;
+  a.nslice = kWallSlices;
+  a.sstride = 6 * (size_t)nplane;
   a.scale = -0.039788735772973833942 / ((double)p.p.Nx * (double)p.p.Nz);
   launch_near_kernel<T, false>(p, a, near_grid(p, 2 * nplane));
+  const size_t n = 6 * (size_t)nplane;
+  sum_slices<T><<<(unsigned)((n + 255) / 256), 256, 0, p.stream>>>((const T*)p.wall_part,
+                                                                   (T*)p.wall_phys, n);
   return hipGetLastError();
 }
 
