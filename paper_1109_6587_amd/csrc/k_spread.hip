@@ -188,13 +188,21 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
           if (valid) {
             for (int e0 = 0; e0 < cnt4; e0 += 4) {
+              // the group's four positions and strengths are read before any
+              // is used, so one LDS latency covers four candidates
+              Q qg[4], fg[4];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                if (REL) qg[u] = lr[wave][e0 + u];
+                fg[u] = lf[wave][e0 + u];
+              }
 #pragma unroll
               for (int u = 0; u < 4; ++u) {
                 const int e = e0 + u;
                 T r2;
                 bool in;
                 if (REL) {
-                  const Q q = lr[wave][e];
+                  const Q q = qg[u];
                   const T dx = nrx - q.x, dy = nry - q.y, dz = nrz - q.z;
                   r2 = dx * dx + dy * dy + dz * dz;
                   in = r2 <= rc2t;
@@ -212,7 +220,7 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
                   w = in ? t_exp2_s(-r2) * fma((T)-0.69314718055994531, r2, (T)2.5) : (T)0;
                 else
                   w = in ? t_exp_s(-a2 * r2) * fma(-a2, r2, (T)2.5) : (T)0;
-                const Q f = lf[wave][e];
+                const Q f = fg[u];
                 fx += w * f.x;
                 fy += w * f.y;
                 fz += w * f.z;

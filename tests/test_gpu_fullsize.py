@@ -1,0 +1,114 @@
+"""Parity at the full benchmark sizes, on sampled targets.
+
+The oracle cannot evaluate these workloads inside a test, so its values at a
+seeded sample of 256 targets were written once by tests/golden/
+make_fullsize.py (oracle only).  The HIP path runs the whole workload in the
+benchmark's launch configuration (targets passed as the source array) and
+the sampled rows are compared: FP64 to 1e-10 relative max-norm, mixed to
+1e-5 relative 2-norm, over the sample; the local and global parts are also
+compared separately in FP64.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from workloads import case_capsules_dl, case_capsules_sl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+import paper_1109_6587_amd as G  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+DEV = torch.device("cuda:0")
+TOL64 = 1e-10
+TOLMIX = 1e-5
+
+
+def load(name):
+    path = os.path.join(GOLDEN, f"{name}_sampled.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not written (tests/golden/make_fullsize.py)")
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=DEV)
+
+
+def rel_max(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def run(c, precision, parts=G.PART_ALL):
+    plan = G.Plan.from_case(c, precision=precision)
+    xs, f = dev(c.xs), dev(c.f)
+    if c.normals is None:
+        out = plan.single_layer(xs, f, xs, parts=parts)
+    else:
+        out = plan.double_layer(xs, f, xs, dev(c.normals), parts=parts)
+    return out.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def capsules_sl():
+    c = case_capsules_sl()
+    ref = load(c.name)
+    assert ref["seed"] == c.meta["seed"] and ref["grid"] == [c.Nx, c.Nz, c.Ny]
+    return c, ref
+
+
+@pytest.mark.timeout(300)
+def test_capsules_sl_fp64(capsules_sl):
+    c, ref = capsules_sl
+    sel = np.asarray(ref["targets"])
+    print(f"case {c.name} fp64, {sel.size} sampled targets", flush=True)
+    for key, parts in (("total", G.PART_ALL), ("local", G.PART_LOCAL), ("global", G.PART_GLOBAL)):
+        u = run(c, "fp64", parts)[sel]
+        assert rel_max(u, np.asarray(ref[key])) < TOL64, key
+
+
+@pytest.mark.timeout(300)
+def test_capsules_sl_mixed(capsules_sl):
+    c, ref = capsules_sl
+    sel = np.asarray(ref["targets"])
+    print(f"case {c.name} mixed, {sel.size} sampled targets", flush=True)
+    u = run(c, "mixed")[sel]
+    assert rel_l2(u, np.asarray(ref["total"])) < TOLMIX
+
+
+@pytest.fixture(scope="module")
+def capsules_dl():
+    c = case_capsules_dl()
+    ref = load(c.name)
+    assert ref["seed"] == c.meta["seed"] and ref["grid"] == [c.Nx, c.Nz, c.Ny]
+    return c, ref
+
+
+@pytest.mark.timeout(300)
+def test_capsules_dl_fp64(capsules_dl):
+    c, ref = capsules_dl
+    sel = np.asarray(ref["targets"])
+    print(f"case {c.name} fp64, {sel.size} sampled targets", flush=True)
+    for key, parts in (("total", G.PART_ALL), ("local", G.PART_LOCAL), ("global", G.PART_GLOBAL)):
+        v = run(c, "fp64", parts)[sel]
+        assert rel_max(v, np.asarray(ref[key])) < TOL64, key
+
+
+@pytest.mark.timeout(300)
+def test_capsules_dl_mixed(capsules_dl):
+    c, ref = capsules_dl
+    sel = np.asarray(ref["targets"])
+    print(f"case {c.name} mixed, {sel.size} sampled targets", flush=True)
+    v = run(c, "mixed")[sel]
+    assert rel_l2(v, np.asarray(ref["total"])) < TOLMIX
