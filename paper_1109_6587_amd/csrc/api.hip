@@ -43,12 +43,12 @@ namespace {
 
 bool factor_radices(int n, int* r, int* nr) {
   int k = 0;
-  while (n % 4 == 0 && n > 4) {
-    r[k++] = 4;
-    n /= 4;
+  while (n % 8 == 0 && n > 8) {
+    r[k++] = 8;
+    n /= 8;
   }
-  const int ps[4] = {4, 2, 3, 5};
-  for (int i = 0; i < 4; ++i)
+  const int ps[5] = {8, 4, 2, 3, 5};
+  for (int i = 0; i < 5; ++i)
     while (n % ps[i] == 0) {
       if (k >= 12) return false;
       r[k++] = ps[i];

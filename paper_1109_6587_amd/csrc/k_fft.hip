@@ -5,10 +5,12 @@
 //   forward:  real z-lines -> complex (R2C), then complex x-columns (C2C)
 //   inverse:  complex x-columns (C2C), then Hermitian z-lines -> real (C2R)
 //
-// Each 1-D transform is a mixed-radix (2, 3, 4, 5) Stockham autosort FFT in
-// LDS with twiddles from a table computed once per plan in FP64.  The
-// 1/(Nx Nz) normalisation of the forward transform is folded into the
-// Chebyshev forward matrix.
+// Each 1-D transform is a mixed-radix (2, 3, 4, 5, 8) Stockham autosort FFT
+// in LDS with twiddles from a table computed once per plan in FP64 and staged
+// in LDS.  The z transforms carry two real lines per complex line (one as the
+// real part, one as the imaginary part) and separate the two spectra by their
+// Hermitian symmetry.  The 1/(Nx Nz) normalisation of the forward transform
+// is folded into the Chebyshev forward matrix.
 #include "ggem_internal.h"
 
 namespace ggem {
@@ -46,10 +48,16 @@ __device__ inline C csub(C a, C b) {
   return r;
 }
 
+// The passes of one transform length N: radix R, the product Ns of the
+// earlier radices, the twiddle stride N / (Ns R), and multipliers for the
+// index divisions by Ns and by N / R: q = (x m) >> 20 equals x / d exactly
+// for m = ceil(2^20 / d) whenever x d < 2^20 (here x < 2N, d <= N <= 512).
 struct Radices {
   int n;
-  int r[12];
+  int r[12], ns[12], tstep[12], mns[12], mnr[12];
 };
+
+__device__ inline int fdiv(int x, int m) { return (int)(((unsigned)x * (unsigned)m) >> 20); }
 
 // In-register DFT of length R (2..5), sign -1 forward, +1 inverse.
 template <typename T, int SIGN, int R>
@@ -85,6 +93,28 @@ __device__ inline void small_dft(typename Cx<T>::t* v) {
     v[0] = y0;
     v[1] = y1;
     v[2] = y2;
+  } else if constexpr (R == 8) {
+    // two 4-point DFTs (even, odd samples) joined by the twiddles w8^k
+    C e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+    small_dft<T, SIGN, 4>(e);
+    small_dft<T, SIGN, 4>(o);
+    const T h = (T)0.70710678118654752440;
+    C t[4];
+    t[0] = o[0];
+    // w8^1 = h (1 + SIGN i)
+    t[1].x = h * (o[1].x - (T)SIGN * o[1].y);
+    t[1].y = h * (o[1].y + (T)SIGN * o[1].x);
+    // w8^2 = SIGN i
+    t[2].x = -(T)SIGN * o[2].y;
+    t[2].y = (T)SIGN * o[2].x;
+    // w8^3 = h (-1 + SIGN i)
+    t[3].x = h * (-o[3].x - (T)SIGN * o[3].y);
+    t[3].y = h * (-o[3].y + (T)SIGN * o[3].x);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[k] = cadd(e[k], t[k]);
+      v[k + 4] = csub(e[k], t[k]);
+    }
   } else {  // R == 5
     const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;
     const T s1 = (T)SIGN * (T)0.95105651629515357212, s2 = (T)SIGN * (T)0.58778525229247312917;
@@ -114,12 +144,11 @@ __device__ inline void small_dft(typename Cx<T>::t* v) {
 // (tw: exp(-2 pi i t/N), conjugated for the inverse).
 template <typename T, int SIGN, int R>
 __device__ inline void stockham_bfly(const typename Cx<T>::t* __restrict__ src,
-                                     typename Cx<T>::t* __restrict__ dst, int N, int Ns, int j,
-                                     const typename Cx<T>::t* __restrict__ tw) {
+                                     typename Cx<T>::t* __restrict__ dst, int NR, int Ns, int tstep,
+                                     int mns, int j, const typename Cx<T>::t* __restrict__ tw) {
   using C = typename Cx<T>::t;
-  const int NR = N / R;
-  const int k = j % Ns;
-  const int tstep = N / (Ns * R);
+  const int q = fdiv(j, mns);
+  const int k = j - q * Ns;
   C v[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -132,31 +161,24 @@ __device__ inline void stockham_bfly(const typename Cx<T>::t* __restrict__ src,
     v[r] = a;
   }
   small_dft<T, SIGN, R>(v);
-  const int base = (j / Ns) * Ns * R + k;
+  const int base = q * Ns * R + k;
 #pragma unroll
   for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[r];
 }
 
-// Stockham pass: workers j run from `start` with step `stride`.
+// Butterfly j (< N/R) of pass s of a line.
 template <typename T, int SIGN>
 __device__ inline void stockham_pass(const typename Cx<T>::t* __restrict__ src,
-                                     typename Cx<T>::t* __restrict__ dst, int N, int R, int Ns,
-                                     const typename Cx<T>::t* __restrict__ tw, int start,
-                                     int stride) {
-  const int NR = N / R;
+                                     typename Cx<T>::t* __restrict__ dst, int N,
+                                     const Radices& rad, int s,
+                                     const typename Cx<T>::t* __restrict__ tw, int j) {
+  const int R = rad.r[s], NR = N / R, Ns = rad.ns[s], ts = rad.tstep[s], m = rad.mns[s];
   switch (R) {
-    case 2:
-      for (int j = start; j < NR; j += stride) stockham_bfly<T, SIGN, 2>(src, dst, N, Ns, j, tw);
-      break;
-    case 3:
-      for (int j = start; j < NR; j += stride) stockham_bfly<T, SIGN, 3>(src, dst, N, Ns, j, tw);
-      break;
-    case 4:
-      for (int j = start; j < NR; j += stride) stockham_bfly<T, SIGN, 4>(src, dst, N, Ns, j, tw);
-      break;
-    default:
-      for (int j = start; j < NR; j += stride) stockham_bfly<T, SIGN, 5>(src, dst, N, Ns, j, tw);
-      break;
+    case 2: stockham_bfly<T, SIGN, 2>(src, dst, NR, Ns, ts, m, j, tw); break;
+    case 3: stockham_bfly<T, SIGN, 3>(src, dst, NR, Ns, ts, m, j, tw); break;
+    case 4: stockham_bfly<T, SIGN, 4>(src, dst, NR, Ns, ts, m, j, tw); break;
+    case 8: stockham_bfly<T, SIGN, 8>(src, dst, NR, Ns, ts, m, j, tw); break;
+    default: stockham_bfly<T, SIGN, 5>(src, dst, NR, Ns, ts, m, j, tw); break;
   }
 }
 
@@ -183,23 +205,23 @@ __device__ inline void wave_lines_fft(typename Cx<T>::t*& b0, typename Cx<T>::t*
                                       int lpw, const Radices& rad,
                                       const typename Cx<T>::t* __restrict__ tw, int lane) {
   using C = typename Cx<T>::t;
-  int Ns = 1;
   for (int s = 0; s < rad.n; ++s) {
-    const int R = rad.r[s], NR = N / R;
+    const int NR = N / rad.r[s];
     for (int w = lane; w < lpw * NR; w += 64) {
-      const int l = w / NR, j = w - l * NR;
-      stockham_pass<T, SIGN>(b0 + l * N, b1 + l * N, N, R, Ns, tw, j, NR);
+      const int l = fdiv(w, rad.mnr[s]), j = w - l * NR;
+      stockham_pass<T, SIGN>(b0 + l * N, b1 + l * N, N, rad, s, tw, j);
     }
     wave_sync();
     C* t = b0;
     b0 = b1;
     b1 = t;
-    Ns *= R;
   }
 }
 
-// Forward R2C along z: each wave owns LPW consecutive lines, 4 waves per
-// block; LDS: the twiddles, then per wave two buffers of LPW lines.
+// Forward R2C along z: each wave owns LPW complex lines, each carrying two
+// consecutive real lines a (real part) and b (imaginary part), 4 waves per
+// block; LDS: the twiddles, then per wave two buffers of LPW lines.  With
+// Z = FFT(a + i b): A_m = (Z_m + conj Z_{N-m}) / 2, B_m = (Z_m - conj Z_{N-m}) / 2i.
 template <typename T>
 __global__ void __launch_bounds__(256) fft_z_r2c(const T* __restrict__ in,
                                                  typename Cx<T>::t* __restrict__ out, int nlines,
@@ -209,26 +231,41 @@ __global__ void __launch_bounds__(256) fft_z_r2c(const T* __restrict__ in,
   extern __shared__ unsigned char smem_raw[];
   C* twl = (C*)smem_raw;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int line0 = (blockIdx.x * 4 + wave) * lpw;
+  const int line0 = (blockIdx.x * 4 + wave) * lpw * 2;  // first real line
   C* b0 = twl + Nz + wave * 2 * lpw * Nz;
   C* b1 = b0 + lpw * Nz;
-  for (int e = lane; e < lpw * Nz; e += 64) {
-    const int l = e / Nz, n = e - l * Nz;
-    C v;
-    v.x = line0 + l < nlines ? in[(size_t)(line0 + l) * Nz + n] : (T)0;
-    v.y = (T)0;
-    b0[e] = v;
+  for (int l = 0; l < lpw; ++l) {
+    const int ra = line0 + 2 * l, rb = ra + 1;
+    for (int n = lane; n < Nz; n += 64) {
+      C v;
+      v.x = ra < nlines ? in[(size_t)ra * Nz + n] : (T)0;
+      v.y = rb < nlines ? in[(size_t)rb * Nz + n] : (T)0;
+      b0[l * Nz + n] = v;
+    }
   }
   stage_twiddles(twl, tw, Nz);  // its barrier also publishes the lines
   wave_lines_fft<T, -1>(b0, b1, Nz, lpw, rz, twl, lane);
   const int Nzh = Nz / 2 + 1;
-  for (int e = lane; e < lpw * Nzh; e += 64) {
-    const int l = e / Nzh, m = e - l * Nzh;
-    if (line0 + l < nlines) out[(size_t)(line0 + l) * Nzh + m] = b0[l * Nz + m];
+  for (int l = 0; l < lpw; ++l) {
+    const int ra = line0 + 2 * l, rb = ra + 1;
+    const C* z = b0 + l * Nz;
+    for (int m = lane; m < Nzh; m += 64) {
+      const C P = z[m], Qn = z[m == 0 ? 0 : Nz - m];
+      // Q = conj(Z_{N-m})
+      C A, B;
+      A.x = (T)0.5 * (P.x + Qn.x);
+      A.y = (T)0.5 * (P.y - Qn.y);
+      B.x = (T)0.5 * (P.y + Qn.y);
+      B.y = (T)0.5 * (Qn.x - P.x);
+      if (ra < nlines) out[(size_t)ra * Nzh + m] = A;
+      if (rb < nlines) out[(size_t)rb * Nzh + m] = B;
+    }
   }
 }
 
-// Inverse C2R along z: rebuild the Hermitian line, inverse FFT, real part.
+// Inverse C2R along z: two Hermitian lines A, B packed as Z = A + i B (the
+// imaginary parts at m = 0 and m = N/2 dropped, as a real line's own C2R
+// would), inverse FFT, real part -> line a, imaginary part -> line b.
 template <typename T>
 __global__ void __launch_bounds__(256) fft_z_c2r(const typename Cx<T>::t* __restrict__ in,
                                                  T* __restrict__ out, int nlines, int Nz, int lpw,
@@ -238,28 +275,38 @@ __global__ void __launch_bounds__(256) fft_z_c2r(const typename Cx<T>::t* __rest
   extern __shared__ unsigned char smem_raw[];
   C* twl = (C*)smem_raw;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int line0 = (blockIdx.x * 4 + wave) * lpw;
+  const int line0 = (blockIdx.x * 4 + wave) * lpw * 2;
   C* b0 = twl + Nz + wave * 2 * lpw * Nz;
   C* b1 = b0 + lpw * Nz;
   const int Nzh = Nz / 2 + 1;
-  for (int e = lane; e < lpw * Nzh; e += 64) {
-    const int l = e / Nzh, m = e - l * Nzh;
-    C v;
-    v.x = (T)0;
-    v.y = (T)0;
-    if (line0 + l < nlines) v = in[(size_t)(line0 + l) * Nzh + m];
-    C* line = b0 + l * Nz;
-    line[m] = v;
-    if (m > 0 && m < Nz / 2) {
-      v.y = -v.y;
-      line[Nz - m] = v;
+  for (int l = 0; l < lpw; ++l) {
+    const int ra = line0 + 2 * l, rb = ra + 1;
+    for (int m = lane; m < Nz; m += 64) {
+      const int mm = m < Nzh ? m : Nz - m;
+      C A, B;
+      A.x = A.y = B.x = B.y = (T)0;
+      if (ra < nlines) A = in[(size_t)ra * Nzh + mm];
+      if (rb < nlines) B = in[(size_t)rb * Nzh + mm];
+      if (m == 0 || 2 * m == Nz) A.y = B.y = (T)0;
+      if (m >= Nzh) {
+        A.y = -A.y;
+        B.y = -B.y;
+      }
+      C z;
+      z.x = A.x - B.y;
+      z.y = A.y + B.x;
+      b0[l * Nz + m] = z;
     }
   }
   stage_twiddles(twl, tw, Nz);
   wave_lines_fft<T, 1>(b0, b1, Nz, lpw, rz, twl, lane);
-  for (int e = lane; e < lpw * Nz; e += 64) {
-    const int l = e / Nz, n = e - l * Nz;
-    if (line0 + l < nlines) out[(size_t)(line0 + l) * Nz + n] = b0[e].x;
+  for (int l = 0; l < lpw; ++l) {
+    const int ra = line0 + 2 * l, rb = ra + 1;
+    for (int n = lane; n < Nz; n += 64) {
+      const C z = b0[l * Nz + n];
+      if (ra < nlines) out[(size_t)ra * Nz + n] = z.x;
+      if (rb < nlines) out[(size_t)rb * Nz + n] = z.y;
+    }
   }
 }
 
@@ -290,20 +337,17 @@ __global__ void __launch_bounds__(256) fft_x(typename Cx<T>::t* __restrict__ dat
     b0[c * NxP + i] = v;
   }
   stage_twiddles(twl, tw, Nx);
-  int Ns = 1;
   for (int s = 0; s < rx.n; ++s) {
-    const int R = rx.r[s];
-    const int NR = Nx / R;
+    const int NR = Nx / rx.r[s];
     // spread the CB lines' butterflies over the block
     for (int w = threadIdx.x; w < CB * NR; w += 256) {
-      const int c = w / NR, j = w - (w / NR) * NR;
-      stockham_pass<T, SIGN>(b0 + c * NxP, b1 + c * NxP, Nx, R, Ns, twl, j, NR + 1);
+      const int c = fdiv(w, rx.mnr[s]), j = w - c * NR;
+      stockham_pass<T, SIGN>(b0 + c * NxP, b1 + c * NxP, Nx, rx, s, twl, j);
     }
     __syncthreads();
     C* t = b0;
     b0 = b1;
     b1 = t;
-    Ns *= R;
   }
   for (int idx = threadIdx.x; idx < CB * Nx; idx += 256) {
     const int i = idx / CB, c = idx - (idx / CB) * CB;
@@ -312,17 +356,32 @@ __global__ void __launch_bounds__(256) fft_x(typename Cx<T>::t* __restrict__ dat
   }
 }
 
-static Radices radices(const int* r, int n) {
+static int div_mult(int d) { return (int)(((1u << 20) + (unsigned)d - 1) / (unsigned)d); }
+
+static Radices radices(const int* r, int n, int N) {
   Radices R;
   R.n = n;
-  for (int i = 0; i < 12; ++i) R.r[i] = i < n ? r[i] : 1;
+  int ns = 1;
+  for (int i = 0; i < 12; ++i) {
+    R.r[i] = i < n ? r[i] : 1;
+    R.ns[i] = ns;
+    R.tstep[i] = N / (ns * R.r[i]);
+    R.mns[i] = div_mult(ns);
+    R.mnr[i] = div_mult(N / R.r[i]);
+    if (i < n) ns *= r[i];
+  }
   return R;
 }
 
-static int cols_per_block(int Nx, size_t elt) {
-  int cb = (int)(32768 / ((size_t)(Nx + 1) * elt));  // ping-pong buffers of <= 64 KB
+// columns per block of the x transform: ping-pong buffers of <= 64 KB, and
+// the butterfly index CB N/R below 2048 (exact multiply-shift division)
+static int cols_per_block(int Nx, size_t elt, const Radices& rx) {
+  int cb = (int)(32768 / ((size_t)(Nx + 1) * elt));
   if (cb < 1) cb = 1;
   if (cb > 16) cb = 16;
+  int nrmax = 1;
+  for (int s = 0; s < rx.n; ++s) nrmax = Nx / rx.r[s] > nrmax ? Nx / rx.r[s] : nrmax;
+  while (cb > 1 && cb * nrmax >= 2048) --cb;
   return cb;
 }
 
@@ -337,12 +396,12 @@ hipError_t launch_fft_forward(Plan& p, void* phys, void* spec, int nplanes) {
   using C = typename Cx<T>::t;
   const int Nx = p.p.Nx, Nz = p.p.Nz, Nzh = p.Nzh;
   const int nlines = nplanes * Nx;
-  Radices rz = radices(p.radz, p.nradz), rx = radices(p.radx, p.nradx);
+  Radices rz = radices(p.radz, p.nradz, Nz), rx = radices(p.radx, p.nradx, Nx);
   const int lpw = lines_per_wave(Nz, sizeof(C));
-  const int lpb = 4 * lpw;
+  const int lpb = 8 * lpw;  // real lines per block
   fft_z_r2c<T><<<(nlines + lpb - 1) / lpb, 256, fft_z_lds(Nz, lpw, sizeof(C)), p.stream>>>(
       (const T*)phys, (C*)spec, nlines, Nz, lpw, rz, (const C*)p.twz);
-  const int CB = cols_per_block(Nx, sizeof(C));
+  const int CB = cols_per_block(Nx, sizeof(C), rx);
   dim3 g((Nzh + CB - 1) / CB, nplanes);
   fft_x<T, -1><<<g, 256, fft_x_lds(Nx, CB, sizeof(C)), p.stream>>>((C*)spec, Nx, Nzh, CB, rx,
                                                                    (const C*)p.twx);
@@ -354,13 +413,13 @@ hipError_t launch_fft_inverse(Plan& p, void* spec, void* phys, int nplanes) {
   using C = typename Cx<T>::t;
   const int Nx = p.p.Nx, Nz = p.p.Nz, Nzh = p.Nzh;
   const int nlines = nplanes * Nx;
-  Radices rz = radices(p.radz, p.nradz), rx = radices(p.radx, p.nradx);
-  const int CB = cols_per_block(Nx, sizeof(C));
+  Radices rz = radices(p.radz, p.nradz, Nz), rx = radices(p.radx, p.nradx, Nx);
+  const int CB = cols_per_block(Nx, sizeof(C), rx);
   dim3 g((Nzh + CB - 1) / CB, nplanes);
   fft_x<T, 1><<<g, 256, fft_x_lds(Nx, CB, sizeof(C)), p.stream>>>((C*)spec, Nx, Nzh, CB, rx,
                                                                   (const C*)p.twx);
   const int lpw = lines_per_wave(Nz, sizeof(C));
-  const int lpb = 4 * lpw;
+  const int lpb = 8 * lpw;  // real lines per block
   fft_z_c2r<T><<<(nlines + lpb - 1) / lpb, 256, fft_z_lds(Nz, lpw, sizeof(C)), p.stream>>>(
       (const C*)spec, (T*)phys, nlines, Nz, lpw, rz, (const C*)p.twz);
   return hipGetLastError();
