@@ -115,9 +115,13 @@ double cospi_frac(long m, int N) {
   return cos(M_PI * (double)m / (double)N);
 }
 
-__global__ void fill_u32(unsigned* p, unsigned v, size_t n) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
+// the input-check flags and the two work counters, cleared before a call
+__global__ void reset_counters(unsigned* flags, unsigned long long* work) {
+  if (threadIdx.x == 0) {
+    *flags = 0u;
+    work[0] = 0ull;
+    work[1] = 0ull;
+  }
 }
 
 // normals of coinciding targets, in the sources' sorted order
@@ -261,8 +265,7 @@ void destroy_timer(Plan& p) {
 template <typename T>
 int evaluate(Plan& p, long long ns, const double* xs, const double* f, long long nt,
              const double* xt, const double* nrm, double* out, int parts, bool dl) {
-  fill_u32<<<1, 64, 0, p.stream>>>(p.flags, 0u, 1);
-  fill_zero<unsigned long long><<<1, 64, 0, p.stream>>>(p.work, 2);
+  reset_counters<<<1, 64, 0, p.stream>>>(p.flags, p.work);
   HIP_TRY(hipGetLastError());
   {
     StageScope s(p, GGEM_STAGE_BIN);
@@ -547,8 +550,7 @@ extern "C" int ggem_spread_grid(ggem_plan_t plan, long long ns, const double* xs
   if (ns < 0) return fail(GGEM_E_ARG, "negative point count");
   if (ns > p.p.max_src) return fail(GGEM_E_CAPACITY, "ns=%lld exceeds max_src", ns);
   if ((ns > 0 && (!xs || !f)) || !grid) return fail(GGEM_E_ARG, "null array");
-  fill_u32<<<1, 64, 0, p.stream>>>(p.flags, 0u, 1);
-  fill_zero<unsigned long long><<<1, 64, 0, p.stream>>>(p.work, 2);
+  reset_counters<<<1, 64, 0, p.stream>>>(p.flags, p.work);
   HIP_TRY(launch_bin(p, p.src, ns, xs, f, nullptr, true));
   if (p.fp64) {
     HIP_TRY(launch_spread<double>(p, 0));

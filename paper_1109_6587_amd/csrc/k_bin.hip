@@ -2,8 +2,8 @@
 // neighbours within r_c are found through a cell-linked list; here the list is
 // a sorted order plus per-cell ranges, so later kernels read contiguous runs).
 //
-//   bin_keys     wrap x,z into [0,L), check the slab, cell key per point
-//   bin_count    per-chunk histogram in LDS             -> counts[chunk][cell]
+//   bin_keys     per chunk: wrap x,z into [0,L), check the slab, cell key per
+//                point, and the chunk's histogram in LDS -> counts[chunk][cell]
 //   bin_cellscan per-cell running sum over chunks       -> offs[chunk][cell]
 //   bin_scan     exclusive scan over cells              -> cell_start, item_start
 //   bin_scatter  one wave per chunk, stable ranks by wave match -> sorted SoA
@@ -31,32 +31,32 @@ __device__ inline int cell_key(const CellGeom& g, double x, double y, double z) 
   return (iy * g.ncx + ix) * g.ncz + iz;
 }
 
-__global__ void bin_keys(int n, const double* __restrict__ x, CellGeom g, int is_source,
-                         int* __restrict__ keys, unsigned* __restrict__ flags) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double px = x[3 * (size_t)i], py = x[3 * (size_t)i + 1], pz = x[3 * (size_t)i + 2];
-  unsigned f = 0;
-  if (!(isfinite(px) && isfinite(py) && isfinite(pz))) {
-    f |= kFlagNonFinite;
-    px = py = pz = 0.0;
-  }
-  if (is_source ? !(fabs(py) < g.H) : !(fabs(py) <= g.H)) f |= kFlagOutside;
-  px = wrap_periodic(px, g.Lx);
-  pz = wrap_periodic(pz, g.Lz);
-  keys[i] = cell_key(g, px, py, pz);
-  if (f) atomicOr(flags, f);
-}
-
-__global__ void bin_count(int n, int chunk_size, int nchunks, int ncells,
-                          const int* __restrict__ keys, int* __restrict__ counts) {
+// One block per chunk: the chunk's keys and its histogram (counts are
+// integers, so the LDS atomics give the same result in any order).
+__global__ void bin_keys(int n, int chunk_size, int ncells, const double* __restrict__ x,
+                         CellGeom g, int is_source, int* __restrict__ keys,
+                         int* __restrict__ counts, unsigned* __restrict__ flags) {
   extern __shared__ int hist[];
-  int chunk = blockIdx.x;
+  const int chunk = blockIdx.x;
   for (int c = threadIdx.x; c < ncells; c += blockDim.x) hist[c] = 0;
   __syncthreads();
-  int i0 = chunk * chunk_size;
-  int i1 = min(n, i0 + chunk_size);
-  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) atomicAdd(&hist[keys[i]], 1);
+  const int i0 = chunk * chunk_size;
+  const int i1 = min(n, i0 + chunk_size);
+  unsigned f = 0;
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    double px = x[3 * (size_t)i], py = x[3 * (size_t)i + 1], pz = x[3 * (size_t)i + 2];
+    if (!(isfinite(px) && isfinite(py) && isfinite(pz))) {
+      f |= kFlagNonFinite;
+      px = py = pz = 0.0;
+    }
+    if (is_source ? !(fabs(py) < g.H) : !(fabs(py) <= g.H)) f |= kFlagOutside;
+    px = wrap_periodic(px, g.Lx);
+    pz = wrap_periodic(pz, g.Lz);
+    const int key = cell_key(g, px, py, pz);
+    keys[i] = key;
+    atomicAdd(&hist[key], 1);
+  }
+  if (f) atomicOr(flags, f);
   __syncthreads();
   for (int c = threadIdx.x; c < ncells; c += blockDim.x) counts[(size_t)chunk * ncells + c] = hist[c];
 }
@@ -189,10 +189,9 @@ static hipError_t bin_impl(Plan& p, Binned& b, long long n, const double* x, con
   b.chunk = (int)(per < 256 ? 256 : ((per + 63) / 64) * 64);
   b.nchunks = (int)((n + b.chunk - 1) / b.chunk);
   if (n > 0) {
-    bin_keys<<<(unsigned)((n + 255) / 256), 256, 0, st>>>((int)n, x, g, is_source ? 1 : 0, b.keys,
-                                                          p.flags);
-    bin_count<<<b.nchunks, 256, g.ncells * sizeof(int), st>>>((int)n, b.chunk, b.nchunks, g.ncells,
-                                                               b.keys, b.counts);
+    bin_keys<<<b.nchunks, 256, g.ncells * sizeof(int), st>>>((int)n, b.chunk, g.ncells, x, g,
+                                                              is_source ? 1 : 0, b.keys, b.counts,
+                                                              p.flags);
     bin_cellscan<<<(g.ncells + 255) / 256, 256, 0, st>>>(b.nchunks, g.ncells, b.counts, b.offs,
                                                          b.cell_start);
   } else {

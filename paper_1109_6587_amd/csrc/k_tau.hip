@@ -500,17 +500,23 @@ __device__ __forceinline__ void velocity_par(const TauArgs& a, const Mode& md, i
   }
 }
 
-// VCOMP: the v component alone (grid z = 1); otherwise u and w (grid z = 2).
-// Separate instantiations keep the two paths' register budgets apart.
-template <typename T, int MAXN, bool VCOMP>
+// Grid z = 3: slice 0 is the v component (the wall slopes), slices 1 and 2
+// are u and w.
+template <typename T, int MAXN>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) tau_velocity_r(TauArgs a) {
   const int q = blockIdx.x * 64 + threadIdx.x;
-  const int par = blockIdx.y, comp = VCOMP ? 1 : 2 * (int)blockIdx.z;
+  const int par = blockIdx.y, z = blockIdx.z;
   if (q >= a.nmodes) return;
   const Mode md = mode_of(a, q);
   if (md.nyquist) return;
-  if (par == 0) velocity_par<T, MAXN, 0, VCOMP>(a, md, q, comp);
-  else velocity_par<T, MAXN, 1, VCOMP>(a, md, q, comp);
+  if (z == 0) {
+    if (par == 0) velocity_par<T, MAXN, 0, true>(a, md, q, 1);
+    else velocity_par<T, MAXN, 1, true>(a, md, q, 1);
+  } else {
+    const int comp = 2 * (z - 1);
+    if (par == 0) velocity_par<T, MAXN, 0, false>(a, md, q, comp);
+    else velocity_par<T, MAXN, 1, false>(a, md, q, comp);
+  }
 }
 
 // ---- D: wall pressures and superposition, one thread per (mode, n) --------
@@ -777,8 +783,7 @@ static size_t tau_lds_bytes(Plan& p) { return (size_t)((p.p.Ny - 1) / 2 + 2) * 6
 template <typename T, int MAXN>
 static void launch_tau_reg(Plan& p, const TauArgs& a, unsigned nb, unsigned nc, bool stress) {
   tau_pressure_r<T, MAXN><<<dim3(nb + 1, 2), 64, 0, p.stream>>>(a);
-  tau_velocity_r<T, MAXN, true><<<dim3(nb, 2, 1), 64, 0, p.stream>>>(a);
-  tau_velocity_r<T, MAXN, false><<<dim3(nb, 2, 2), 64, 0, p.stream>>>(a);
+  tau_velocity_r<T, MAXN><<<dim3(nb, 2, 3), 64, 0, p.stream>>>(a);
   if (stress) {
     tau_combine<T, true><<<nc, 256, 0, p.stream>>>(a);
     tau_stress_dy_r<T, MAXN><<<dim3(nb, 3), 64, 0, p.stream>>>(a);
