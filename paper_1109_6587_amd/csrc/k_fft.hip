@@ -55,9 +55,14 @@ __device__ inline C csub(C a, C b) {
 struct Radices {
   int n;
   int r[12], ns[12], tstep[12], mns[12], mnr[12];
+  unsigned long long mnr32[12];  // ceil(2^32 / (N/R)): exact for x < 2^17
 };
 
 __device__ inline int fdiv(int x, int m) { return (int)(((unsigned)x * (unsigned)m) >> 20); }
+// x / d for 0 <= x < 2^17, d <= 1024, with m = ceil(2^32 / d)
+__device__ inline int udiv32(int x, unsigned long long m) {
+  return (int)(((unsigned long long)(unsigned)x * m) >> 32);
+}
 
 // In-register DFT of length R (2..5), sign -1 forward, +1 inverse.
 template <typename T, int SIGN, int R>
@@ -356,6 +361,177 @@ __global__ void __launch_bounds__(256) fft_x(typename Cx<T>::t* __restrict__ dat
   }
 }
 
+// Whole-plane transforms (planes whose two Nx x (Nz/2 + 1) complex buffers
+// fit in LDS): one block of 1024 threads per plane does the z transforms and
+// the x transforms with one read and one write of the plane.  Forward: the
+// real rows 2l and 2l+1 form complex line l (real, imaginary part), the z
+// FFTs run on the Nx/2 lines, the two spectra of each line are separated
+// into the columns m = 0..Nz/2 (stored as lines of length Nx, stride Nx + 1),
+// then the x FFTs run on those columns.  Inverse: the reverse order, with
+// the two Hermitian rows recombined into one complex line before the z FFT.
+struct Plane2 {
+  int Nx, Nz, Nzh;
+  unsigned long long mNz, mNzh;  // ceil(2^32 / Nz), ceil(2^32 / Nzh)
+};
+
+template <typename T>
+__global__ void __launch_bounds__(1024) fft2_fwd(const T* __restrict__ in,
+                                                 typename Cx<T>::t* __restrict__ out, Plane2 pl,
+                                                 Radices rx, Radices rz,
+                                                 const typename Cx<T>::t* __restrict__ twx,
+                                                 const typename Cx<T>::t* __restrict__ twz) {
+  using C = typename Cx<T>::t;
+  extern __shared__ unsigned char smem_raw[];
+  const int Nx = pl.Nx, Nz = pl.Nz, Nzh = pl.Nzh, NxP = Nx + 1, nl = Nx / 2;
+  C* twxl = (C*)smem_raw;
+  C* twzl = twxl + Nx;
+  C* b0 = twzl + Nz;
+  C* b1 = b0 + (size_t)Nzh * NxP;
+  const int tid = threadIdx.x;
+  const T* src = in + (size_t)blockIdx.x * Nx * Nz;
+  for (int e = tid; e < Nx * Nz; e += 1024) {
+    const int x = udiv32(e, pl.mNz), z = e - x * Nz;
+    T* line = (T*)(b0 + (x >> 1) * Nz + z);
+    line[x & 1] = src[e];
+  }
+  for (int t = tid; t < Nx; t += 1024) twxl[t] = twx[t];
+  for (int t = tid; t < Nz; t += 1024) twzl[t] = twz[t];
+  __syncthreads();
+  for (int s = 0; s < rz.n; ++s) {
+    const int NR = Nz / rz.r[s];
+    for (int w = tid; w < nl * NR; w += 1024) {
+      const int l = udiv32(w, rz.mnr32[s]), j = w - l * NR;
+      stockham_pass<T, -1>(b0 + l * Nz, b1 + l * Nz, Nz, rz, s, twzl, j);
+    }
+    __syncthreads();
+    C* t = b0;
+    b0 = b1;
+    b1 = t;
+  }
+  // separate the two rows of each line: A_m = (Z_m + conj Z_{N-m}) / 2,
+  // B_m = (Z_m - conj Z_{N-m}) / 2i, into column m (stride NxP)
+  for (int e = tid; e < nl * Nzh; e += 1024) {
+    const int l = udiv32(e, pl.mNzh), m = e - l * Nzh;
+    const C P = b0[l * Nz + m], Qn = b0[l * Nz + (m == 0 ? 0 : Nz - m)];
+    C A, B;
+    A.x = (T)0.5 * (P.x + Qn.x);
+    A.y = (T)0.5 * (P.y - Qn.y);
+    B.x = (T)0.5 * (P.y + Qn.y);
+    B.y = (T)0.5 * (Qn.x - P.x);
+    b1[m * NxP + 2 * l] = A;
+    b1[m * NxP + 2 * l + 1] = B;
+  }
+  __syncthreads();
+  {
+    C* t = b0;
+    b0 = b1;
+    b1 = t;
+  }
+  for (int s = 0; s < rx.n; ++s) {
+    const int NR = Nx / rx.r[s];
+    for (int w = tid; w < Nzh * NR; w += 1024) {
+      const int c = udiv32(w, rx.mnr32[s]), j = w - c * NR;
+      stockham_pass<T, -1>(b0 + c * NxP, b1 + c * NxP, Nx, rx, s, twxl, j);
+    }
+    __syncthreads();
+    C* t = b0;
+    b0 = b1;
+    b1 = t;
+  }
+  C* dst = out + (size_t)blockIdx.x * Nx * Nzh;
+  for (int e = tid; e < Nx * Nzh; e += 1024) {
+    const int l = udiv32(e, pl.mNzh), m = e - l * Nzh;
+    dst[e] = b0[m * NxP + l];
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024) fft2_inv(const typename Cx<T>::t* __restrict__ in,
+                                                 T* __restrict__ out, Plane2 pl, Radices rx,
+                                                 Radices rz,
+                                                 const typename Cx<T>::t* __restrict__ twx,
+                                                 const typename Cx<T>::t* __restrict__ twz) {
+  using C = typename Cx<T>::t;
+  extern __shared__ unsigned char smem_raw[];
+  const int Nx = pl.Nx, Nz = pl.Nz, Nzh = pl.Nzh, NxP = Nx + 1, nl = Nx / 2;
+  C* twxl = (C*)smem_raw;
+  C* twzl = twxl + Nx;
+  C* b0 = twzl + Nz;
+  C* b1 = b0 + (size_t)Nzh * NxP;
+  const int tid = threadIdx.x;
+  const C* src = in + (size_t)blockIdx.x * Nx * Nzh;
+  for (int e = tid; e < Nx * Nzh; e += 1024) {
+    const int l = udiv32(e, pl.mNzh), m = e - l * Nzh;
+    b0[m * NxP + l] = src[e];
+  }
+  for (int t = tid; t < Nx; t += 1024) twxl[t] = twx[t];
+  for (int t = tid; t < Nz; t += 1024) twzl[t] = twz[t];
+  __syncthreads();
+  for (int s = 0; s < rx.n; ++s) {
+    const int NR = Nx / rx.r[s];
+    for (int w = tid; w < Nzh * NR; w += 1024) {
+      const int c = udiv32(w, rx.mnr32[s]), j = w - c * NR;
+      stockham_pass<T, 1>(b0 + c * NxP, b1 + c * NxP, Nx, rx, s, twxl, j);
+    }
+    __syncthreads();
+    C* t = b0;
+    b0 = b1;
+    b1 = t;
+  }
+  // rows 2l, 2l+1 as one complex line Z = A + i B over the full length,
+  // A and B completed by Hermitian symmetry (imaginary parts dropped at
+  // m = 0 and m = N/2)
+  for (int e = tid; e < nl * Nz; e += 1024) {
+    const int l = udiv32(e, pl.mNz), m = e - l * Nz;
+    const int mm = m < Nzh ? m : Nz - m;
+    C A = b0[mm * NxP + 2 * l], B = b0[mm * NxP + 2 * l + 1];
+    if (m == 0 || 2 * m == Nz) A.y = B.y = (T)0;
+    if (m >= Nzh) {
+      A.y = -A.y;
+      B.y = -B.y;
+    }
+    C z;
+    z.x = A.x - B.y;
+    z.y = A.y + B.x;
+    b1[l * Nz + m] = z;
+  }
+  __syncthreads();
+  {
+    C* t = b0;
+    b0 = b1;
+    b1 = t;
+  }
+  for (int s = 0; s < rz.n; ++s) {
+    const int NR = Nz / rz.r[s];
+    for (int w = tid; w < nl * NR; w += 1024) {
+      const int l = udiv32(w, rz.mnr32[s]), j = w - l * NR;
+      stockham_pass<T, 1>(b0 + l * Nz, b1 + l * Nz, Nz, rz, s, twzl, j);
+    }
+    __syncthreads();
+    C* t = b0;
+    b0 = b1;
+    b1 = t;
+  }
+  T* dst = out + (size_t)blockIdx.x * Nx * Nz;
+  for (int e = tid; e < Nx * Nz; e += 1024) {
+    const int x = udiv32(e, pl.mNz), z = e - x * Nz;
+    const T* line = (const T*)(b0 + (x >> 1) * Nz + z);
+    dst[e] = line[x & 1];
+  }
+}
+
+static unsigned long long div_mult32(int d) {
+  return (((unsigned long long)1 << 32) + (unsigned long long)d - 1) / (unsigned long long)d;
+}
+
+static size_t fft2_lds(int Nx, int Nz, size_t celt) {
+  return ((size_t)Nx + Nz + 2 * (size_t)(Nz / 2 + 1) * (Nx + 1)) * celt;
+}
+constexpr size_t kFft2Lds = 150 * 1024;
+// one block per plane pays a chain of passes per block: worth it only with
+// enough planes to fill the device (the six wall planes use the line kernels)
+constexpr int kFft2MinPlanes = 64;
+
 static int div_mult(int d) { return (int)(((1u << 20) + (unsigned)d - 1) / (unsigned)d); }
 
 static Radices radices(const int* r, int n, int N) {
@@ -368,6 +544,7 @@ static Radices radices(const int* r, int n, int N) {
     R.tstep[i] = N / (ns * R.r[i]);
     R.mns[i] = div_mult(ns);
     R.mnr[i] = div_mult(N / R.r[i]);
+    R.mnr32[i] = div_mult32(N / R.r[i]);
     if (i < n) ns *= r[i];
   }
   return R;
@@ -397,6 +574,12 @@ hipError_t launch_fft_forward(Plan& p, void* phys, void* spec, int nplanes) {
   const int Nx = p.p.Nx, Nz = p.p.Nz, Nzh = p.Nzh;
   const int nlines = nplanes * Nx;
   Radices rz = radices(p.radz, p.nradz, Nz), rx = radices(p.radx, p.nradx, Nx);
+  if (nplanes >= kFft2MinPlanes && fft2_lds(Nx, Nz, sizeof(C)) <= kFft2Lds) {
+    const Plane2 pl{Nx, Nz, Nzh, div_mult32(Nz), div_mult32(Nzh)};
+    fft2_fwd<T><<<nplanes, 1024, fft2_lds(Nx, Nz, sizeof(C)), p.stream>>>(
+        (const T*)phys, (C*)spec, pl, rx, rz, (const C*)p.twx, (const C*)p.twz);
+    return hipGetLastError();
+  }
   const int lpw = lines_per_wave(Nz, sizeof(C));
   const int lpb = 8 * lpw;  // real lines per block
   fft_z_r2c<T><<<(nlines + lpb - 1) / lpb, 256, fft_z_lds(Nz, lpw, sizeof(C)), p.stream>>>(
@@ -414,6 +597,12 @@ hipError_t launch_fft_inverse(Plan& p, void* spec, void* phys, int nplanes) {
   const int Nx = p.p.Nx, Nz = p.p.Nz, Nzh = p.Nzh;
   const int nlines = nplanes * Nx;
   Radices rz = radices(p.radz, p.nradz, Nz), rx = radices(p.radx, p.nradx, Nx);
+  if (nplanes >= kFft2MinPlanes && fft2_lds(Nx, Nz, sizeof(C)) <= kFft2Lds) {
+    const Plane2 pl{Nx, Nz, Nzh, div_mult32(Nz), div_mult32(Nzh)};
+    fft2_inv<T><<<nplanes, 1024, fft2_lds(Nx, Nz, sizeof(C)), p.stream>>>(
+        (const C*)spec, (T*)phys, pl, rx, rz, (const C*)p.twx, (const C*)p.twz);
+    return hipGetLastError();
+  }
   const int CB = cols_per_block(Nx, sizeof(C), rx);
   dim3 g((Nzh + CB - 1) / CB, nplanes);
   fft_x<T, 1><<<g, 256, fft_x_lds(Nx, CB, sizeof(C)), p.stream>>>((C*)spec, Nx, Nzh, CB, rx,
