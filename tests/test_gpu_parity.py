@@ -114,6 +114,7 @@ SL_CASES = [
     (23, 129, 3, 3.2, 0.7, 5.0, 1.2, 30, 50, 9, 3.0),       # radix 3/5 sizes, small Ny
     (24, 200, 90, 5.0, 2.0, 2.5, 1.6, 24, 24, 65, None),     # Chebyshev order 64
     (25, 80, 60, 4.0, 1.6, 3.0, 1.3, 16, 20, 97, None),      # order above 64
+    (26, 40, 30, 4.0, 1.5, 3.0, 1.3, 16, 16, 129, None),     # largest order
 ]
 
 
