@@ -70,6 +70,7 @@ void free_plan(Plan& p) {
                   p.specA,     p.specB,       p.wall_phys,   p.wall_spec,  p.tau_scr,
                   p.gauge,     p.flags,       p.item_count,  p.src.keys,   p.src.counts,
                   p.src.offs,  p.src.cell_start, p.src.item_start, p.src.perm, p.src.x,
+                  p.src.sub_start, p.tgt.sub_start, p.wall.sub_start,
                   p.src.y,     p.src.z,       p.src.s,       p.tgt.keys,   p.tgt.counts,
                   p.tgt.offs,  p.tgt.cell_start, p.tgt.item_start, p.tgt.perm, p.tgt.x,
                   p.tgt.y,     p.tgt.z,       p.tgt.s,       p.nconst,     p.sweep,
@@ -90,10 +91,12 @@ void free_plan(Plan& p) {
   }
 }
 
-bool alloc_binned(Binned& b, long long cap, int ncells, size_t elt) {
+bool alloc_binned(Binned& b, long long cap, const CellGeom& g, size_t elt) {
   const long long nch = kMaxChunks + 1;
-  return dev_alloc(&b.keys, (size_t)cap) && dev_alloc(&b.counts, (size_t)ncells * (nch + 1)) &&
-         dev_alloc(&b.offs, (size_t)ncells * (nch + 1)) && dev_alloc(&b.cell_start, ncells + 1) &&
+  const int ncells = g.ncells, nb = g.nbuckets;
+  return dev_alloc(&b.keys, (size_t)cap) && dev_alloc(&b.counts, (size_t)nb * (nch + 1)) &&
+         dev_alloc(&b.offs, (size_t)nb * (nch + 1)) && dev_alloc(&b.sub_start, nb + 1) &&
+         dev_alloc(&b.cell_start, ncells + 1) &&
          dev_alloc(&b.item_start, ncells + 1) && dev_alloc(&b.perm, (size_t)cap) &&
          dev_alloc(&b.x, (size_t)cap) && dev_alloc(&b.y, (size_t)cap) &&
          dev_alloc(&b.z, (size_t)cap) &&
@@ -443,6 +446,9 @@ extern "C" int ggem_plan_create(const ggem_params* prm, void* hip_stream, ggem_p
     cs *= 1.25;
   }
   g.ncells = g.ncx * g.ncy * g.ncz;
+  g.nzs = kMaxZSub;
+  while (g.nzs > 1 && (long)g.ncells * g.nzs > kMaxCells) g.nzs >>= 1;
+  g.nbuckets = g.ncells * g.nzs;
   g.Lx = q.Lx;
   g.Lz = q.Lz;
   g.H = q.H;
@@ -475,9 +481,9 @@ extern "C" int ggem_plan_create(const ggem_params* prm, void* hip_stream, ggem_p
             dev_alloc(&p.gauge, (size_t)(q.max_src / 256 + 4)) && dev_alloc(&p.flags, 1) &&
             dev_alloc(&p.item_count, 4) && dev_alloc(&p.work, 2) &&
             hipHostMalloc((void**)&p.flags_host, sizeof(unsigned), 0) == hipSuccess &&
-            alloc_binned(p.src, q.max_src, g.ncells, elt) &&
-            alloc_binned(p.tgt, q.max_tgt, g.ncells, elt) &&
-            alloc_binned(p.wall, 2LL * q.Nx * q.Nz, g.ncells, elt) &&
+            alloc_binned(p.src, q.max_src, g, elt) &&
+            alloc_binned(p.tgt, q.max_tgt, g, elt) &&
+            alloc_binned(p.wall, 2LL * q.Nx * q.Nz, g, elt) &&
             hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking) == hipSuccess &&
             hipEventCreateWithFlags(&p.ev_fork, hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&p.ev_wall, hipEventDisableTiming) == hipSuccess &&

@@ -13,7 +13,8 @@ __device__ inline void wave_count_add(unsigned long long* ctr, unsigned v) {
   if ((threadIdx.x & 63) == 0 && v) atomicAdd(ctr, (unsigned long long)v);
 }
 
-constexpr int kMaxCells = 16384;     // cell-list size (LDS histograms)
+constexpr int kMaxCells = 16384;     // counting-sort buckets (LDS histograms)
+constexpr int kMaxZSub = 8;          // z sub-slabs per cell (spread candidate windows)
 constexpr int kNearSlices = 3;       // blocks per near-field work item (partial sums)
 constexpr int kWallSlices = 3;       // blocks per wall-data work item (partial sums)
 constexpr int kMaxChunks = 512;      // counting-sort chunks per point set (at most)
@@ -25,12 +26,17 @@ constexpr int kMaxFFT = 512;
 enum : unsigned { kFlagNonFinite = 1u, kFlagOutside = 2u };
 
 // Geometry of the cell list: cells of size >= rc in x, y (over [-H, H]) and z.
+// Each cell is cut into nzs slabs along z; points are sorted by (cell, slab),
+// so a cell is still one contiguous run and a run of cells along z is sorted
+// by slab, which lets the spread read only the slabs within r_c of its tile.
 struct CellGeom {
   double Lx, Lz, H;
   double invLx, invLz;
   double icx, icy, icz;   // inverse cell sizes
   int ncx, ncy, ncz;
   int ncells;
+  int nzs;                // z slabs per cell (power of two)
+  int nbuckets;           // ncells * nzs
 };
 
 // A binned point set: sorted positions (wrapped) and cell ranges.
@@ -38,10 +44,11 @@ struct Binned {
   int n;
   int chunk;         // points per counting-sort chunk
   int nchunks;
-  int* keys;         // cell key per original point
-  int* counts;       // [cell][chunk]
-  int* offs;         // [cell][chunk] exclusive offsets inside the cell
-  int* cell_start;   // ncells + 1
+  int* keys;         // bucket (cell * nzs + slab) per original point
+  int* counts;       // [chunk][bucket]
+  int* offs;         // [chunk][bucket] exclusive offsets inside the bucket
+  int* sub_start;    // nbuckets + 1
+  int* cell_start;   // ncells + 1 (cell c starts at sub_start[c * nzs])
   int* item_start;   // ncells + 1: near-field work items per cell (prefix)
   int* perm;         // sorted position -> original index
   double* x;         // sorted wrapped positions (SoA)

@@ -1,14 +1,17 @@
 // Cell-list binning by a deterministic, stable counting sort (Sec. 3.2.1:
 // neighbours within r_c are found through a cell-linked list; here the list is
 // a sorted order plus per-cell ranges, so later kernels read contiguous runs).
+// The sort key is (cell, z slab): each cell is cut into nzs slabs along z, so
+// a cell stays one contiguous run and a row of cells along z is sorted by slab.
 //
-//   bin_keys     per chunk: wrap x,z into [0,L), check the slab, cell key per
-//                point, and the chunk's histogram in LDS -> counts[chunk][cell]
-//   bin_cellscan per-cell running sum over chunks       -> offs[chunk][cell]
-//   bin_scan     exclusive scan over cells              -> cell_start, item_start
+//   bin_keys     per chunk: wrap x,z into [0,L), check the slab, bucket key per
+//                point, and the chunk's histogram in LDS -> counts[chunk][bucket]
+//   bin_cellscan per-bucket running sum over chunks     -> offs[chunk][bucket]
+//   bin_scan     exclusive scan over buckets            -> sub_start, cell_start,
+//                                                          item_start
 //   bin_scatter  one wave per chunk, stable ranks by wave match -> sorted SoA
 //
-// Points keep their input order inside a cell, so every later sum over a
+// Points keep their input order inside a bucket, so every later sum over a
 // cell's points has a fixed order and results are bitwise reproducible.
 #include "ggem_internal.h"
 
@@ -23,22 +26,26 @@ __device__ inline double wrap_periodic(double v, double L) {
 
 __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// Cell key of a (wrapped, finite) position; y is clamped into the slab.
-__device__ inline int cell_key(const CellGeom& g, double x, double y, double z) {
+// Bucket (cell * nzs + z slab) of a (wrapped, finite) position; y is clamped
+// into the slit.  z * icz * nzs is exact (nzs is a power of two), so the slab
+// floor(z * icz * nzs) always lies inside the cell floor(z * icz).
+__device__ inline int bucket_key(const CellGeom& g, double x, double y, double z) {
   int ix = clampi((int)floor(x * g.icx), 0, g.ncx - 1);
   int iy = clampi((int)floor((y + g.H) * g.icy), 0, g.ncy - 1);
-  int iz = clampi((int)floor(z * g.icz), 0, g.ncz - 1);
-  return (iy * g.ncx + ix) * g.ncz + iz;
+  const double tz = z * g.icz;
+  int iz = clampi((int)floor(tz), 0, g.ncz - 1);
+  int sz = clampi((int)floor(tz * g.nzs) - iz * g.nzs, 0, g.nzs - 1);
+  return ((iy * g.ncx + ix) * g.ncz + iz) * g.nzs + sz;
 }
 
 // One block per chunk: the chunk's keys and its histogram (counts are
 // integers, so the LDS atomics give the same result in any order).
-__global__ void bin_keys(int n, int chunk_size, int ncells, const double* __restrict__ x,
+__global__ void bin_keys(int n, int chunk_size, int nb, const double* __restrict__ x,
                          CellGeom g, int is_source, int* __restrict__ keys,
                          int* __restrict__ counts, unsigned* __restrict__ flags) {
   extern __shared__ int hist[];
   const int chunk = blockIdx.x;
-  for (int c = threadIdx.x; c < ncells; c += blockDim.x) hist[c] = 0;
+  for (int c = threadIdx.x; c < nb; c += blockDim.x) hist[c] = 0;
   __syncthreads();
   const int i0 = chunk * chunk_size;
   const int i1 = min(n, i0 + chunk_size);
@@ -52,34 +59,42 @@ __global__ void bin_keys(int n, int chunk_size, int ncells, const double* __rest
     if (is_source ? !(fabs(py) < g.H) : !(fabs(py) <= g.H)) f |= kFlagOutside;
     px = wrap_periodic(px, g.Lx);
     pz = wrap_periodic(pz, g.Lz);
-    const int key = cell_key(g, px, py, pz);
+    const int key = bucket_key(g, px, py, pz);
     keys[i] = key;
     atomicAdd(&hist[key], 1);
   }
   if (f) atomicOr(flags, f);
   __syncthreads();
-  for (int c = threadIdx.x; c < ncells; c += blockDim.x) counts[(size_t)chunk * ncells + c] = hist[c];
+  for (int c = threadIdx.x; c < nb; c += blockDim.x) counts[(size_t)chunk * nb + c] = hist[c];
 }
 
-// counts and offsets are chunk-major ([chunk][cell]): a thread per cell walks
-// the chunks with coalesced, independent loads.
-__global__ void bin_cellscan(int nchunks, int ncells, const int* __restrict__ counts,
+// counts and offsets are chunk-major ([chunk][bucket]): a thread per bucket
+// walks the chunks with coalesced, independent loads.
+__global__ void bin_cellscan(int nchunks, int nb, const int* __restrict__ counts,
                              int* __restrict__ offs, int* __restrict__ totals) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncells) return;
+  if (c >= nb) return;
   int s = 0;
 #pragma unroll 8
   for (int k = 0; k < nchunks; ++k) {
-    const int v = counts[(size_t)k * ncells + c];
-    offs[(size_t)k * ncells + c] = s;
+    const int v = counts[(size_t)k * nb + c];
+    offs[(size_t)k * nb + c] = s;
     s += v;
   }
   totals[c] = s;
 }
 
-// Single block: exclusive scans of per-cell totals (in cell_start) and of
-// per-cell near-field work items ceil(total / kNearBlock).
-__global__ void __launch_bounds__(1024) bin_scan(int ncells, int* __restrict__ cell_start,
+__device__ inline int cell_total(const int* __restrict__ sub, int c, int nzs) {
+  int v = 0;
+  for (int q = 0; q < nzs; ++q) v += sub[c * nzs + q];
+  return v;
+}
+
+// Single block: exclusive scans of the per-bucket totals (held in sub_start
+// on entry), of the per-cell totals (cell_start) and of the per-cell
+// near-field work items ceil(total / kNearBlock) (item_start).
+__global__ void __launch_bounds__(1024) bin_scan(int ncells, int nzs, int* __restrict__ sub_start,
+                                                 int* __restrict__ cell_start,
                                                  int* __restrict__ item_start) {
   __shared__ int sa[1024], sb[1024];
   const int per = (ncells + 1023) / 1024;
@@ -87,7 +102,7 @@ __global__ void __launch_bounds__(1024) bin_scan(int ncells, int* __restrict__ c
   int c0 = t * per, c1 = min(ncells, c0 + per);
   int la = 0, lb = 0;
   for (int c = c0; c < c1; ++c) {
-    int v = cell_start[c];
+    int v = cell_total(sub_start, c, nzs);
     la += v;
     lb += (v + kNearBlock - 1) / kNearBlock;
   }
@@ -105,25 +120,31 @@ __global__ void __launch_bounds__(1024) bin_scan(int ncells, int* __restrict__ c
   }
   int ra = sa[t] - la, rb = sb[t] - lb;
   for (int c = c0; c < c1; ++c) {
-    int v = cell_start[c];
     cell_start[c] = ra;
     item_start[c] = rb;
+    int v = 0;
+    for (int q = 0; q < nzs; ++q) {
+      const int w = sub_start[c * nzs + q];
+      sub_start[c * nzs + q] = ra + v;
+      v += w;
+    }
     ra += v;
     rb += (v + kNearBlock - 1) / kNearBlock;
   }
   if (t == 1023) {
     cell_start[ncells] = sa[1023];
+    sub_start[ncells * nzs] = sa[1023];
     item_start[ncells] = sb[1023];
   }
 }
 
 template <typename T>
-__global__ void __launch_bounds__(64) bin_scatter(int n, int chunk_size, int nchunks, int ncells,
+__global__ void __launch_bounds__(64) bin_scatter(int n, int chunk_size, int nchunks, int nb,
                                                   CellGeom g,
                                                   const int* __restrict__ keys,
                                                   const double* __restrict__ x,
                                                   const double* __restrict__ s,
-                                                  const int* __restrict__ cell_start,
+                                                  const int* __restrict__ sub_start,
                                                   const int* __restrict__ offs,
                                                   int* __restrict__ perm, double* __restrict__ sx,
                                                   double* __restrict__ sy, double* __restrict__ sz,
@@ -131,7 +152,7 @@ __global__ void __launch_bounds__(64) bin_scatter(int n, int chunk_size, int nch
   extern __shared__ int cnt[];
   const int lane = threadIdx.x;
   const int chunk = blockIdx.x;
-  for (int c = lane; c < ncells; c += 64) cnt[c] = 0;
+  for (int c = lane; c < nb; c += 64) cnt[c] = 0;
   __syncthreads();
   const int i0 = chunk * chunk_size;
   const int i1 = min(n, i0 + chunk_size);
@@ -157,7 +178,7 @@ __global__ void __launch_bounds__(64) bin_scatter(int n, int chunk_size, int nch
       active &= ~m;
     }
     if (valid) {
-      int pos = cell_start[key] + offs[(size_t)chunk * ncells + key] + before + rank;
+      int pos = sub_start[key] + offs[(size_t)chunk * nb + key] + before + rank;
       double px = x[3 * (size_t)i], py = x[3 * (size_t)i + 1], pz = x[3 * (size_t)i + 2];
       if (!(isfinite(px) && isfinite(py) && isfinite(pz))) px = py = pz = 0.0;
       py = fmin(fmax(py, -g.H), g.H);
@@ -188,24 +209,24 @@ static hipError_t bin_impl(Plan& p, Binned& b, long long n, const double* x, con
   const long long per = (n + kMaxChunks - 1) / kMaxChunks;
   b.chunk = (int)(per < 256 ? 256 : ((per + 63) / 64) * 64);
   b.nchunks = (int)((n + b.chunk - 1) / b.chunk);
+  const int nb = g.nbuckets;
   if (n > 0) {
-    bin_keys<<<b.nchunks, 256, g.ncells * sizeof(int), st>>>((int)n, b.chunk, g.ncells, x, g,
-                                                              is_source ? 1 : 0, b.keys, b.counts,
-                                                              p.flags);
-    bin_cellscan<<<(g.ncells + 255) / 256, 256, 0, st>>>(b.nchunks, g.ncells, b.counts, b.offs,
-                                                         b.cell_start);
+    bin_keys<<<b.nchunks, 256, nb * sizeof(int), st>>>((int)n, b.chunk, nb, x, g,
+                                                        is_source ? 1 : 0, b.keys, b.counts,
+                                                        p.flags);
+    bin_cellscan<<<(nb + 255) / 256, 256, 0, st>>>(b.nchunks, nb, b.counts, b.offs, b.sub_start);
   } else {
-    zero_ints<<<(g.ncells + 1 + 255) / 256, 256, 0, st>>>(b.cell_start, g.ncells + 1);
+    zero_ints<<<(nb + 1 + 255) / 256, 256, 0, st>>>(b.sub_start, nb + 1);
   }
-  bin_scan<<<1, 1024, 0, st>>>(g.ncells, b.cell_start, b.item_start);
+  bin_scan<<<1, 1024, 0, st>>>(g.ncells, g.nzs, b.sub_start, b.cell_start, b.item_start);
   if (n > 0) {
     if (p.fp64)
-      bin_scatter<double><<<b.nchunks, 64, g.ncells * sizeof(int), st>>>(
-          (int)n, b.chunk, b.nchunks, g.ncells, g, b.keys, x, s, b.cell_start, b.offs, b.perm,
+      bin_scatter<double><<<b.nchunks, 64, nb * sizeof(int), st>>>(
+          (int)n, b.chunk, b.nchunks, nb, g, b.keys, x, s, b.sub_start, b.offs, b.perm,
           b.x, b.y, b.z, (double*)b.s, cap);
     else
-      bin_scatter<float><<<b.nchunks, 64, g.ncells * sizeof(int), st>>>(
-          (int)n, b.chunk, b.nchunks, g.ncells, g, b.keys, x, s, b.cell_start, b.offs, b.perm,
+      bin_scatter<float><<<b.nchunks, 64, nb * sizeof(int), st>>>(
+          (int)n, b.chunk, b.nchunks, nb, g, b.keys, x, s, b.sub_start, b.offs, b.perm,
           b.x, b.y, b.z, (float*)b.s, cap);
   }
   return hipGetLastError();

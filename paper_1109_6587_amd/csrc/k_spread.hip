@@ -34,7 +34,7 @@ struct SpreadArgs {
   int Nx, Nz, Ny;
   double dx, dz, rc, rc2, alpha;
   const double* y;     // Gauss-Lobatto nodes
-  const int* scell;
+  const int* scell;    // source bucket starts (cell, z slab)
   const double *sx, *sy, *sz;
   const void* sf;
   size_t scap;
@@ -42,9 +42,11 @@ struct SpreadArgs {
   unsigned long long* work;  // update counter
 };
 
-// A block covers 8 (z) x 8 (x) x 4 (y) nodes as four independent wave tiles
-// of 4 x 4 x 4 nodes, one node per lane.
-constexpr int TZ = 8, TX = 8, TY = 4, TB = 256, WT = 4;
+// A block covers 16 (z) x 8 (x) x 4 (y) nodes as four independent wave tiles
+// of 8 x 4 x 4 nodes; each lane owns two nodes, k and k + 4 along z, so every
+// staged source serves two nodes per LDS read and the x, y part of the
+// distance is shared by them.
+constexpr int TZ = 16, TX = 8, TY = 4, TB = 256, WT = 4, WZ = 8;
 
 template <typename T>
 struct V4;
@@ -57,13 +59,12 @@ struct V4<float> {
   using t = float4;
 };
 
-// Each wave owns its 4 x 4 x 4 node tile and works alone (no block
-// barriers): it walks the cell rows that can reach its tile (the z cells of a
-// (y, x) pair are contiguous in sorted order; two segments where the range
-// wraps), loads 64 sources at a time, keeps those within r_c of its tile's
-// box (compacted in sorted order into its own LDS slice) and every lane adds
-// the kept sources to its node.  Out-of-range terms add exactly zero, so the
-// loop is branch-free and unrolled.
+// Each wave owns its 8 x 4 x 4 node tile and works alone (no block
+// barriers): it walks the cell rows that can reach its tile, loads 64 sources
+// at a time, keeps those within r_c of its tile's box (compacted in sorted
+// order into its own LDS slice) and every lane adds the kept sources to its
+// two nodes.  Out-of-range terms add exactly zero, so the loop is branch-free
+// and unrolled.
 //
 // REL: sources staged relative to the tile corner in T (mixed mode: the
 // displacement is formed once per source in FP64, the pair test in FP32);
@@ -77,52 +78,74 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
   const CellGeom& g = a.g;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int k_lo = blockIdx.x * TZ + (wave & 1) * WT;
+  const int k_lo = blockIdx.x * TZ + (wave & 1) * WZ;
   const int i_lo = blockIdx.y * TX + (wave >> 1) * WT;
   const int j_lo = blockIdx.z * TY;
   const int k = k_lo + (lane & 3), i = i_lo + ((lane >> 2) & 3), j = j_lo + (lane >> 4);
+  const int k1 = k + 4;  // the lane's second node
   const bool valid = (k < a.Nz) && (i < a.Nx) && (j < a.Ny);
+  const bool valid1 = valid && k1 < a.Nz;
   if (k_lo >= a.Nz || i_lo >= a.Nx) return;  // the whole wave is past the grid
   // tile bounds
   const int i_hi = min(a.Nx - 1, i_lo + WT - 1);
-  const int k_hi = min(a.Nz - 1, k_lo + WT - 1);
+  const int k_hi = min(a.Nz - 1, k_lo + WZ - 1);
   const int j_hi = min(a.Ny - 1, j_lo + TY - 1);
   const double bx0 = i_lo * a.dx, bx1 = i_hi * a.dx;
   const double bz0 = k_lo * a.dz, bz1 = k_hi * a.dz;
   const double by1 = a.y[j_lo], by0 = a.y[j_hi];  // y decreases with j
   const double px = valid ? i * a.dx : 0.0;
   const double pz = valid ? k * a.dz : 0.0;
+  const double pz1 = valid1 ? k1 * a.dz : 0.0;
   const double py = valid ? a.y[j] : 0.0;
   // node relative to the tile corner
   // REL: coordinates scaled by alpha sqrt(log2 e), so the squared scaled
-  // distance u gives exp(-alpha^2 r^2) = 2^-u and alpha^2 r^2 = u ln 2
+  // distance u gives exp(-alpha^2 r^2) = 2^-u and alpha^2 r^2 = u ln 2.
+  // A second node past the grid sits far away, so its terms are all zero.
   const double sc = REL ? a.alpha * 1.2011224087864498 : 1.0;  // sqrt(log2 e)
   const T nrx = (T)((px - bx0) * sc), nry = (T)((py - by0) * sc), nrz = (T)((pz - bz0) * sc);
+  const T nrz1 = valid1 ? (T)((pz1 - bz0) * sc) : (T)1e30;
   const T rc2t = (T)(a.rc2 * sc * sc);
   const double eps = 1e-9 * (g.Lx + g.Lz);
-  // cell ranges (unwrapped in x, z; clamped in y)
+  // cell ranges (unwrapped in x; clamped in y)
   int cx0 = (int)floor((bx0 - a.rc - eps) * g.icx), cx1 = (int)floor((bx1 + a.rc + eps) * g.icx);
-  int cz0 = (int)floor((bz0 - a.rc - eps) * g.icz), cz1 = (int)floor((bz1 + a.rc + eps) * g.icz);
   if (cx1 - cx0 + 1 >= g.ncx) { cx0 = 0; cx1 = g.ncx - 1; }
-  if (cz1 - cz0 + 1 >= g.ncz) { cz0 = 0; cz1 = g.ncz - 1; }
   const int cy0 = max(0, (int)floor((by0 - a.rc - eps + g.H) * g.icy));
   const int cy1 = min(g.ncy - 1, (int)floor((by1 + a.rc + eps + g.H) * g.icy));
-  // z segments of a row (wrapped cell indices)
-  const int zl0 = ((cz0 % g.ncz) + g.ncz) % g.ncz;
-  const int zlen = cz1 - cz0 + 1;
-  const int nseg = zl0 + zlen > g.ncz ? 2 : 1;
-  const int seg_hi0 = nseg == 2 ? g.ncz - 1 : zl0 + zlen - 1, seg_hi1 = zl0 + zlen - 1 - g.ncz;
+  // Rows of cells along z, culled by the gap between the row's (x, y) cell
+  // box and the tile; in each row only the z slabs within the remaining
+  // reach sqrt(r_c^2 - gap^2) of the tile are read (two runs where the window
+  // wraps).  Every window is conservative: the per-source test below decides.
+  const double rc2m = a.rc2 * (1.0 + 1e-12);
+  const double szs = g.icz * g.nzs;  // slabs per unit z
+  const int nzf = g.ncz * g.nzs;     // slabs per row
+  const double hbx = 0.5 * (bx1 - bx0), cbx = 0.5 * (bx0 + bx1);
   const T* sf = (const T*)a.sf;
   const T a2 = (T)(a.alpha * a.alpha);
   const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  T fx = 0, fy = 0, fz = 0;
+  T fx = 0, fy = 0, fz = 0, gx1 = 0, gy1 = 0, gz1 = 0;
   unsigned nupd = 0;
-  for (int cy = cy0; cy <= cy1; ++cy)
+  for (int cy = cy0; cy <= cy1; ++cy) {
+    const double ylo = cy / g.icy - g.H, yhi = (cy + 1) / g.icy - g.H;
+    const double gyc = fmax(0.0, fmax(ylo - by1, by0 - yhi) - eps);
     for (int cxu = cx0; cxu <= cx1; ++cxu) {
       const int cx = ((cxu % g.ncx) + g.ncx) % g.ncx;
-      const int row = (cy * g.ncx + cx) * g.ncz;
+      const double xlo = cx / g.icx, xhi = (cx + 1) / g.icx;
+      const double gxc = fmax(
+          0.0, fabs(min_image_s(0.5 * (xlo + xhi) - cbx, g.Lx, g.invLx)) - 0.5 * (xhi - xlo) - hbx - eps);
+      const double h2 = rc2m - (gxc * gxc + gyc * gyc);
+      if (h2 < 0.0) continue;
+      const double hz = sqrt(h2) + eps;
+      int fa = (int)floor((bz0 - hz) * szs), fb = (int)floor((bz1 + hz) * szs);
+      if (fb - fa + 1 >= nzf) {
+        fa = 0;
+        fb = nzf - 1;
+      }
+      const int fl0 = ((fa % nzf) + nzf) % nzf, flen = fb - fa + 1;
+      const int nseg = fl0 + flen > nzf ? 2 : 1;
+      const int row = (cy * g.ncx + cx) * nzf;
       for (int sg = 0; sg < nseg; ++sg) {
-        const int lo = sg == 0 ? zl0 : 0, hi = sg == 0 ? seg_hi0 : seg_hi1;
+        const int lo = sg == 0 ? fl0 : 0;
+        const int hi = sg == 0 ? (nseg == 2 ? nzf - 1 : fl0 + flen - 1) : fl0 + flen - 1 - nzf;
         const int s0 = a.scell[row + lo], s1 = a.scell[row + hi + 1];
         for (int b = s0; b < s1; b += 64) {
           // the batch's sources within r_c of the tile's box, compacted
@@ -199,37 +222,53 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
 #pragma unroll
               for (int u = 0; u < 4; ++u) {
                 const int e = e0 + u;
-                T r2;
-                bool in;
+                T r2, r21;
+                bool in, in1;
                 if (REL) {
                   const Q q = qg[u];
-                  const T dx = nrx - q.x, dy = nry - q.y, dz = nrz - q.z;
-                  r2 = dx * dx + dy * dy + dz * dz;
+                  const T dx = nrx - q.x, dy = nry - q.y;
+                  const T dz = nrz - q.z, dz1 = nrz1 - q.z;
+                  const T dxy = dx * dx + dy * dy;
+                  r2 = dxy + dz * dz;
+                  r21 = dxy + dz1 * dz1;
                   in = r2 <= rc2t;
+                  in1 = r21 <= rc2t;
                 } else {
                   const double dx = min_image_s(px - lx[wave][e], g.Lx, g.invLx);
                   const double dy = py - ly[wave][e];
                   const double dz = min_image_s(pz - lz[wave][e], g.Lz, g.invLz);
+                  const double dz1 = min_image_s(pz1 - lz[wave][e], g.Lz, g.invLz);
                   const double d2 = dist2_s(dx, dy, dz);
+                  const double d21 = dist2_s(dx, dy, dz1);
                   in = d2 <= a.rc2;
+                  in1 = valid1 && d21 <= a.rc2;
                   r2 = (T)d2;
+                  r21 = (T)d21;
                 }
-                nupd += (unsigned)__popcll(__ballot(in));  // the wave's count, scalar
-                T w;
-                if (REL)  // r2 is the scaled u
+                // the wave's counts, scalar
+                nupd += (unsigned)__popcll(__ballot(in)) + (unsigned)__popcll(__ballot(in1));
+                T w, w1;
+                if (REL) {  // r2 is the scaled u
                   w = in ? t_exp2_s(-r2) * fma((T)-0.69314718055994531, r2, (T)2.5) : (T)0;
-                else
+                  w1 = in1 ? t_exp2_s(-r21) * fma((T)-0.69314718055994531, r21, (T)2.5) : (T)0;
+                } else {
                   w = in ? t_exp_s(-a2 * r2) * fma(-a2, r2, (T)2.5) : (T)0;
+                  w1 = in1 ? t_exp_s(-a2 * r21) * fma(-a2, r21, (T)2.5) : (T)0;
+                }
                 const Q f = fg[u];
                 fx += w * f.x;
                 fy += w * f.y;
                 fz += w * f.z;
+                gx1 += w1 * f.x;
+                gy1 += w1 * f.y;
+                gz1 += w1 * f.z;
               }
             }
           }
         }
       }
     }
+  }
   // nupd is the wave's count in every lane (lanes of valid nodes only)
   if (lane == 0 && nupd) atomicAdd(a.work, (unsigned long long)nupd);
   if (valid) {
@@ -240,6 +279,11 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
     out[idx] = c * fx;
     out[plane + idx] = c * fy;
     out[2 * plane + idx] = c * fz;
+    if (valid1) {
+      out[idx + 4] = c * gx1;
+      out[plane + idx + 4] = c * gy1;
+      out[2 * plane + idx + 4] = c * gz1;
+    }
   }
 }
 
@@ -256,7 +300,7 @@ hipError_t launch_spread(Plan& p, int /*unused*/) {
   a.rc2 = p.rc2;
   a.alpha = p.p.alpha;
   a.y = p.y;
-  a.scell = p.src.cell_start;
+  a.scell = p.src.sub_start;
   a.sx = p.src.x;
   a.sy = p.src.y;
   a.sz = p.src.z;
@@ -266,7 +310,7 @@ hipError_t launch_spread(Plan& p, int /*unused*/) {
   a.work = p.work + 1;
   dim3 grid((p.p.Nz + TZ - 1) / TZ, (p.p.Nx + TX - 1) / TX, (p.p.Ny + TY - 1) / TY);
   // tile-relative staging needs one periodic image per (tile, source) pair
-  const bool rel = sizeof(T) == 4 && WT * p.dx + p.rc < 0.5 * p.p.Lx && WT * p.dz + p.rc < 0.5 * p.p.Lz;
+  const bool rel = sizeof(T) == 4 && WT * p.dx + p.rc < 0.5 * p.p.Lx && WZ * p.dz + p.rc < 0.5 * p.p.Lz;
   if (rel) spread_tile<T, true><<<grid, TB, 0, p.stream>>>(a);
   else spread_tile<T, false><<<grid, TB, 0, p.stream>>>(a);
   return hipGetLastError();
