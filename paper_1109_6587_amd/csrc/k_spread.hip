@@ -42,11 +42,13 @@ struct SpreadArgs {
   unsigned long long* work;  // update counter
 };
 
-// A block covers 16 (z) x 8 (x) x 4 (y) nodes as four independent wave tiles
-// of 8 x 4 x 4 nodes; each lane owns two nodes, k and k + 4 along z, so every
-// staged source serves two nodes per LDS read and the x, y part of the
-// distance is shared by them.
-constexpr int TZ = 16, TX = 8, TY = 4, TB = 256, WT = 4, WZ = 8;
+// A block owns one tile of 8 (z) x 4 (x) x 4 (y) nodes; each lane owns two
+// nodes, k and k + 4 along z, so every staged source serves two nodes per LDS
+// read and the x, y part of the distance is shared by them.  The tile's
+// source batches are dealt to the block's four waves in turn, so a heavy
+// tile (mid-slab, many sources in reach) is shared by four waves instead of
+// setting the kernel's length alone.
+constexpr int TZ = 8, TX = 4, TY = 4, TB = 256, WT = 4, WZ = 8, NW = TB / 64;
 
 template <typename T>
 struct V4;
@@ -59,12 +61,13 @@ struct V4<float> {
   using t = float4;
 };
 
-// Each wave owns its 8 x 4 x 4 node tile and works alone (no block
-// barriers): it walks the cell rows that can reach its tile, loads 64 sources
-// at a time, keeps those within r_c of its tile's box (compacted in sorted
+// Every wave walks the cell rows that can reach the tile and numbers the
+// 64-source batches in sorted order; wave w takes batches w, w + 4, ...  It
+// keeps the batch's sources within r_c of the tile's box (compacted in sorted
 // order into its own LDS slice) and every lane adds the kept sources to its
 // two nodes.  Out-of-range terms add exactly zero, so the loop is branch-free
-// and unrolled.
+// and unrolled.  The four partial sums are added in wave order at the end
+// (one block barrier), so the result does not depend on timing.
 //
 // REL: sources staged relative to the tile corner in T (mixed mode: the
 // displacement is formed once per source in FP64, the pair test in FP32);
@@ -75,17 +78,18 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
   __shared__ double lx[REL ? 1 : 4][64], ly[REL ? 1 : 4][64], lz[REL ? 1 : 4][64];
   __shared__ Q lr[REL ? 4 : 1][64];
   __shared__ Q lf[4][64];
+  __shared__ T red[NW - 1][6][64];
+  __shared__ unsigned cnt_w[NW];
   const CellGeom& g = a.g;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int k_lo = blockIdx.x * TZ + (wave & 1) * WZ;
-  const int i_lo = blockIdx.y * TX + (wave >> 1) * WT;
+  const int k_lo = blockIdx.x * TZ;
+  const int i_lo = blockIdx.y * TX;
   const int j_lo = blockIdx.z * TY;
   const int k = k_lo + (lane & 3), i = i_lo + ((lane >> 2) & 3), j = j_lo + (lane >> 4);
   const int k1 = k + 4;  // the lane's second node
   const bool valid = (k < a.Nz) && (i < a.Nx) && (j < a.Ny);
   const bool valid1 = valid && k1 < a.Nz;
-  if (k_lo >= a.Nz || i_lo >= a.Nx) return;  // the whole wave is past the grid
   // tile bounds
   const int i_hi = min(a.Nx - 1, i_lo + WT - 1);
   const int k_hi = min(a.Nz - 1, k_lo + WZ - 1);
@@ -124,6 +128,7 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
   const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   T fx = 0, fy = 0, fz = 0, gx1 = 0, gy1 = 0, gz1 = 0;
   unsigned nupd = 0;
+  int bc = 0;  // batches numbered in walk order (uniform)
   for (int cy = cy0; cy <= cy1; ++cy) {
     const double ylo = cy / g.icy - g.H, yhi = (cy + 1) / g.icy - g.H;
     const double gyc = fmax(0.0, fmax(ylo - by1, by0 - yhi) - eps);
@@ -148,6 +153,7 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
         const int hi = sg == 0 ? (nseg == 2 ? nzf - 1 : fl0 + flen - 1) : fl0 + flen - 1 - nzf;
         const int s0 = a.scell[row + lo], s1 = a.scell[row + hi + 1];
         for (int b = s0; b < s1; b += 64) {
+          if (bc++ % NW != wave) continue;
           // the batch's sources within r_c of the tile's box, compacted
           const int si = b + lane;
           bool keep = false;
@@ -269,8 +275,34 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
       }
     }
   }
+  // partial sums of waves 1..3 through LDS, added by wave 0 in wave order;
   // nupd is the wave's count in every lane (lanes of valid nodes only)
-  if (lane == 0 && nupd) atomicAdd(a.work, (unsigned long long)nupd);
+  if (wave > 0) {
+    T* r = &red[wave - 1][0][0];
+    r[0 * 64 + lane] = fx;
+    r[1 * 64 + lane] = fy;
+    r[2 * 64 + lane] = fz;
+    r[3 * 64 + lane] = gx1;
+    r[4 * 64 + lane] = gy1;
+    r[5 * 64 + lane] = gz1;
+  }
+  if (lane == 0) cnt_w[wave] = nupd;
+  __syncthreads();
+  if (wave != 0) return;
+#pragma unroll
+  for (int w = 0; w < NW - 1; ++w) {
+    fx += red[w][0][lane];
+    fy += red[w][1][lane];
+    fz += red[w][2][lane];
+    gx1 += red[w][3][lane];
+    gy1 += red[w][4][lane];
+    gz1 += red[w][5][lane];
+  }
+  if (lane == 0) {
+    unsigned long long tot = 0;
+    for (int w = 0; w < NW; ++w) tot += cnt_w[w];
+    if (tot) atomicAdd(a.work, tot);
+  }
   if (valid) {
     const T c = (T)(a.alpha * a.alpha * a.alpha * 0.17958712212516656);  // alpha^3 pi^{-3/2}
     T* out = (T*)a.out;
