@@ -71,6 +71,7 @@ void free_plan(Plan& p) {
                   p.gauge,     p.flags,       p.item_count,  p.src.keys,   p.src.counts,
                   p.src.offs,  p.src.cell_start, p.src.item_start, p.src.perm, p.src.x,
                   p.src.sub_start, p.tgt.sub_start, p.wall.sub_start,
+                  p.src.cflags, p.tgt.cflags, p.wall.cflags,
                   p.src.y,     p.src.z,       p.src.s,       p.tgt.keys,   p.tgt.counts,
                   p.tgt.offs,  p.tgt.cell_start, p.tgt.item_start, p.tgt.perm, p.tgt.x,
                   p.tgt.y,     p.tgt.z,       p.tgt.s,       p.nconst,     p.sweep,
@@ -96,7 +97,7 @@ bool alloc_binned(Binned& b, long long cap, const CellGeom& g, size_t elt) {
   const int ncells = g.ncells, nb = g.nbuckets;
   return dev_alloc(&b.keys, (size_t)cap) && dev_alloc(&b.counts, (size_t)nb * (nch + 1)) &&
          dev_alloc(&b.offs, (size_t)nb * (nch + 1)) && dev_alloc(&b.sub_start, nb + 1) &&
-         dev_alloc(&b.cell_start, ncells + 1) &&
+         dev_alloc(&b.cell_start, ncells + 1) && dev_alloc(&b.cflags, kMaxChunks + 1) &&
          dev_alloc(&b.item_start, ncells + 1) && dev_alloc(&b.perm, (size_t)cap) &&
          dev_alloc(&b.x, (size_t)cap) && dev_alloc(&b.y, (size_t)cap) &&
          dev_alloc(&b.z, (size_t)cap) &&
@@ -116,15 +117,6 @@ std::vector<T> padded(const std::vector<double>& a, int Ny, int MP, int KP) {
 double cospi_frac(long m, int N) {
   m %= 2L * N;
   return cos(M_PI * (double)m / (double)N);
-}
-
-// the input-check flags and the two work counters, cleared before a call
-__global__ void reset_counters(unsigned* flags, unsigned long long* work) {
-  if (threadIdx.x == 0) {
-    *flags = 0u;
-    work[0] = 0ull;
-    work[1] = 0ull;
-  }
 }
 
 // normals of coinciding targets, in the sources' sorted order
@@ -207,7 +199,7 @@ int plan_constants(Plan& p) {
     double* dpos = nullptr;
     HIP_TRY(hipMalloc((void**)&dpos, wpos.size() * sizeof(double)));
     hipError_t e = hipMemcpy(dpos, wpos.data(), wpos.size() * sizeof(double), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = launch_bin(p, p.wall, (long long)nw, dpos, nullptr, nullptr, false);
+    if (e == hipSuccess) e = launch_bin(p, p.wall, (long long)nw, dpos, nullptr, nullptr, false, true);
     if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
     (void)hipFree(dpos);
     HIP_TRY(e);
@@ -229,9 +221,11 @@ int zero_ul(Plan& p, int nt) {
   return GGEM_OK;
 }
 
+// With sync_checks the call waits and reports the domain flags; otherwise it
+// returns at once and ggem_plan_status reads them later.
 int finish(Plan& p) {
-  HIP_TRY(hipMemcpyAsync(p.flags_host, p.flags, sizeof(unsigned), hipMemcpyDeviceToHost, p.stream));
   if (!p.p.sync_checks) return GGEM_OK;
+  HIP_TRY(hipMemcpyAsync(p.flags_host, p.flags, sizeof(unsigned), hipMemcpyDeviceToHost, p.stream));
   HIP_TRY(hipStreamSynchronize(p.stream));
   const unsigned f = *p.flags_host;
   if (f & kFlagNonFinite) return fail(GGEM_E_DOMAIN, "non-finite input position");
@@ -268,11 +262,9 @@ void destroy_timer(Plan& p) {
 template <typename T>
 int evaluate(Plan& p, long long ns, const double* xs, const double* f, long long nt,
              const double* xt, const double* nrm, double* out, int parts, bool dl) {
-  reset_counters<<<1, 64, 0, p.stream>>>(p.flags, p.work);
-  HIP_TRY(hipGetLastError());
   {
     StageScope s(p, GGEM_STAGE_BIN);
-    HIP_TRY(launch_bin(p, p.src, ns, xs, f, nullptr, true));
+    HIP_TRY(launch_bin(p, p.src, ns, xs, f, nullptr, true, true));
     if (xt == xs && nt == ns) {
       // targets coincide with the sources: reuse their binning
       p.tview = &p.src;
@@ -282,7 +274,7 @@ int evaluate(Plan& p, long long ns, const double* xs, const double* f, long long
         HIP_TRY(hipGetLastError());
       }
     } else {
-      HIP_TRY(launch_bin(p, p.tgt, nt, xt, dl ? nrm : nullptr, nullptr, false));
+      HIP_TRY(launch_bin(p, p.tgt, nt, xt, dl ? nrm : nullptr, nullptr, false, false));
       p.tview = &p.tgt;
     }
     p.tnrm = p.tgt.s;
@@ -521,6 +513,7 @@ extern "C" int ggem_plan_set_stream(ggem_plan_t plan, void* hip_stream) {
 extern "C" int ggem_plan_status(ggem_plan_t plan) {
   if (int rc = check_plan(plan)) return rc;
   Plan& p = plan->p;
+  HIP_TRY(hipMemcpyAsync(p.flags_host, p.flags, sizeof(unsigned), hipMemcpyDeviceToHost, p.stream));
   HIP_TRY(hipStreamSynchronize(p.stream));
   const unsigned f = *p.flags_host;
   if (f & kFlagNonFinite) return fail(GGEM_E_DOMAIN, "non-finite input position");
@@ -556,8 +549,7 @@ extern "C" int ggem_spread_grid(ggem_plan_t plan, long long ns, const double* xs
   if (ns < 0) return fail(GGEM_E_ARG, "negative point count");
   if (ns > p.p.max_src) return fail(GGEM_E_CAPACITY, "ns=%lld exceeds max_src", ns);
   if ((ns > 0 && (!xs || !f)) || !grid) return fail(GGEM_E_ARG, "null array");
-  reset_counters<<<1, 64, 0, p.stream>>>(p.flags, p.work);
-  HIP_TRY(launch_bin(p, p.src, ns, xs, f, nullptr, true));
+  HIP_TRY(launch_bin(p, p.src, ns, xs, f, nullptr, true, true));
   if (p.fp64) {
     HIP_TRY(launch_spread<double>(p, 0));
     HIP_TRY(launch_grid_to_f64<double>(p, grid));

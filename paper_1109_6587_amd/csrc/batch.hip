@@ -244,7 +244,9 @@ extern "C" int ggem_batch_status(ggem_batch_t b, void* hip_stream) {
   BATCH_TRY(hipStreamSynchronize((hipStream_t)hip_stream));
   BATCH_TRY(hipStreamSynchronize(b->origin));
   for (int i = 0; i < b->n; ++i) {
-    const unsigned fl = *b->plans[i]->p.flags_host;
+    Plan& p = b->plans[i]->p;
+    BATCH_TRY(hipMemcpy(p.flags_host, p.flags, sizeof(unsigned), hipMemcpyDeviceToHost));
+    const unsigned fl = *p.flags_host;
     if (fl & (kFlagNonFinite | kFlagOutside)) {
       char msg[160];
       snprintf(msg, sizeof msg, "instance %d: %s", i,

@@ -48,6 +48,7 @@ struct Binned {
   int* counts;       // [chunk][bucket]
   int* offs;         // [chunk][bucket] exclusive offsets inside the bucket
   int* sub_start;    // nbuckets + 1
+  unsigned* cflags;  // per-chunk domain flags (kMaxChunks)
   int* cell_start;   // ncells + 1 (cell c starts at sub_start[c * nzs])
   int* item_start;   // ncells + 1: near-field work items per cell (prefix)
   int* perm;         // sorted position -> original index
@@ -114,8 +115,10 @@ struct Plan {
 };
 
 // ---- kernel launchers (each enqueues on p.stream) -------------------------
+// first: this binning opens an evaluation, so its scan also resets the
+// pair counters and overwrites the domain flags (later ones OR into them).
 hipError_t launch_bin(Plan& p, Binned& b, long long n, const double* x, const double* s,
-                      const double* s2, bool is_source);
+                      const double* s2, bool is_source, bool first);
 template <typename T>
 hipError_t launch_near_sl(Plan& p, int nt);
 template <typename T>

@@ -42,10 +42,12 @@ __device__ inline int bucket_key(const CellGeom& g, double x, double y, double z
 // integers, so the LDS atomics give the same result in any order).
 __global__ void bin_keys(int n, int chunk_size, int nb, const double* __restrict__ x,
                          CellGeom g, int is_source, int* __restrict__ keys,
-                         int* __restrict__ counts, unsigned* __restrict__ flags) {
+                         int* __restrict__ counts, unsigned* __restrict__ cflags) {
   extern __shared__ int hist[];
+  __shared__ unsigned bflags;
   const int chunk = blockIdx.x;
   for (int c = threadIdx.x; c < nb; c += blockDim.x) hist[c] = 0;
+  if (threadIdx.x == 0) bflags = 0u;
   __syncthreads();
   const int i0 = chunk * chunk_size;
   const int i1 = min(n, i0 + chunk_size);
@@ -63,9 +65,10 @@ __global__ void bin_keys(int n, int chunk_size, int nb, const double* __restrict
     keys[i] = key;
     atomicAdd(&hist[key], 1);
   }
-  if (f) atomicOr(flags, f);
+  if (f) atomicOr(&bflags, f);
   __syncthreads();
   for (int c = threadIdx.x; c < nb; c += blockDim.x) counts[(size_t)chunk * nb + c] = hist[c];
+  if (threadIdx.x == 0) cflags[chunk] = bflags;
 }
 
 // counts and offsets are chunk-major ([chunk][bucket]): a thread per bucket
@@ -92,11 +95,25 @@ __device__ inline int cell_total(const int* __restrict__ sub, int c, int nzs) {
 
 // Single block: exclusive scans of the per-bucket totals (held in sub_start
 // on entry), of the per-cell totals (cell_start) and of the per-cell
-// near-field work items ceil(total / kNearBlock) (item_start).
+// near-field work items ceil(total / kNearBlock) (item_start).  It also
+// folds the chunks' domain flags into *flags: the first binning of an
+// evaluation overwrites them and clears the pair counters (no kernel of the
+// evaluation has touched either yet), later binnings OR into them.
 __global__ void __launch_bounds__(1024) bin_scan(int ncells, int nzs, int* __restrict__ sub_start,
                                                  int* __restrict__ cell_start,
-                                                 int* __restrict__ item_start) {
+                                                 int* __restrict__ item_start, int nchunks,
+                                                 const unsigned* __restrict__ cflags,
+                                                 unsigned* __restrict__ flags,
+                                                 unsigned long long* __restrict__ work,
+                                                 int first) {
   __shared__ int sa[1024], sb[1024];
+  __shared__ unsigned fl;
+  if (threadIdx.x == 0) fl = 0u;
+  __syncthreads();
+  if ((int)threadIdx.x < nchunks) {
+    const unsigned v = cflags[threadIdx.x];
+    if (v) atomicOr(&fl, v);
+  }
   const int per = (ncells + 1023) / 1024;
   int t = threadIdx.x;
   int c0 = t * per, c1 = min(ncells, c0 + per);
@@ -135,6 +152,15 @@ __global__ void __launch_bounds__(1024) bin_scan(int ncells, int nzs, int* __res
     cell_start[ncells] = sa[1023];
     sub_start[ncells * nzs] = sa[1023];
     item_start[ncells] = sb[1023];
+  }
+  if (t == 0) {
+    if (first) {
+      *flags = fl;
+      work[0] = 0ull;
+      work[1] = 0ull;
+    } else if (fl) {
+      *flags |= fl;
+    }
   }
 }
 
@@ -201,7 +227,7 @@ __global__ void zero_ints(int* p, int n) {
 }
 
 static hipError_t bin_impl(Plan& p, Binned& b, long long n, const double* x, const double* s,
-                           bool is_source, size_t cap) {
+                           bool is_source, size_t cap, bool first) {
   hipStream_t st = p.stream;
   const CellGeom& g = p.cg;
   b.n = (int)n;
@@ -213,12 +239,13 @@ static hipError_t bin_impl(Plan& p, Binned& b, long long n, const double* x, con
   if (n > 0) {
     bin_keys<<<b.nchunks, 256, nb * sizeof(int), st>>>((int)n, b.chunk, nb, x, g,
                                                         is_source ? 1 : 0, b.keys, b.counts,
-                                                        p.flags);
+                                                        b.cflags);
     bin_cellscan<<<(nb + 255) / 256, 256, 0, st>>>(b.nchunks, nb, b.counts, b.offs, b.sub_start);
   } else {
     zero_ints<<<(nb + 1 + 255) / 256, 256, 0, st>>>(b.sub_start, nb + 1);
   }
-  bin_scan<<<1, 1024, 0, st>>>(g.ncells, g.nzs, b.sub_start, b.cell_start, b.item_start);
+  bin_scan<<<1, 1024, 0, st>>>(g.ncells, g.nzs, b.sub_start, b.cell_start, b.item_start,
+                               n > 0 ? b.nchunks : 0, b.cflags, p.flags, p.work, first ? 1 : 0);
   if (n > 0) {
     if (p.fp64)
       bin_scatter<double><<<b.nchunks, 64, nb * sizeof(int), st>>>(
@@ -233,10 +260,10 @@ static hipError_t bin_impl(Plan& p, Binned& b, long long n, const double* x, con
 }
 
 hipError_t launch_bin(Plan& p, Binned& b, long long n, const double* x, const double* s,
-                      const double* /*s2*/, bool is_source) {
+                      const double* /*s2*/, bool is_source, bool first) {
   size_t cap = is_source ? (size_t)p.p.max_src : (size_t)p.p.max_tgt;
   if (&b == &p.wall) cap = 2 * (size_t)p.p.Nx * p.p.Nz;
-  return bin_impl(p, b, n, x, s, is_source, cap);
+  return bin_impl(p, b, n, x, s, is_source, cap, first);
 }
 
 }  // namespace ggem
