@@ -50,6 +50,10 @@ def parse():
                     help="streams of the batched workload (0: autotuned, cached on disk)")
     ap.add_argument("--roofline-stage", default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serialized", action="store_true",
+                    help="time one evaluation captured into a HIP graph on a single stream "
+                         "(no second stream: every kernel runs alone) and replayed; for "
+                         "per-kernel profiles, not the headline figure")
     ap.add_argument("--cpu-capsules", type=int, default=5)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB MiB device to device three times (a "
@@ -276,6 +280,8 @@ def bench_single(args):
     err_max = float((out - ref).abs().max() / ref.abs().max())
 
     plan = plans[args.precision]
+    if args.serialized:
+        return bench_serialized(args, c, plan, caller(plan), err_l2, err_max)
     caller(plan)()
     near_pairs, spread_pairs = plan.work()
     stage = args.roofline_stage
@@ -334,6 +340,36 @@ def bench_single(args):
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(c, args.cpu_capsules)
     print(json.dumps(line))
+
+
+def bench_serialized(args, c, plan, call, err_l2, err_max):
+    import torch
+    s = torch.cuda.Stream()
+    plan.set_stream(s)
+    with torch.cuda.stream(s):
+        call()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        call()
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.replay()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / args.steps * 1e3
+    plan.status()
+    print(json.dumps({
+        "metric": "GGEM Mpoints/s, one evaluation per graph replay on a single stream",
+        "value": round(c.nt / (ms * 1e-3) / 1e6, 3), "unit": "Mpoints/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if args.precision == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": c.name, "points": c.nt, "grid": [c.Nx, c.Nz, c.Ny],
+                   "precision": args.precision, "mode": "serialized graph"},
+        "err_vs_fp64": {"rel_l2": err_l2, "rel_max": err_max}}))
 
 
 if __name__ == "__main__":
