@@ -72,6 +72,7 @@ void free_plan(Plan& p) {
                   p.src.offs,  p.src.cell_start, p.src.item_start, p.src.perm, p.src.x,
                   p.src.sub_start, p.tgt.sub_start, p.wall.sub_start,
                   p.src.cflags, p.tgt.cflags, p.wall.cflags,
+                  p.src.item_cell, p.tgt.item_cell, p.wall.item_cell,
                   p.src.y,     p.src.z,       p.src.s,       p.tgt.keys,   p.tgt.counts,
                   p.tgt.offs,  p.tgt.cell_start, p.tgt.item_start, p.tgt.perm, p.tgt.x,
                   p.tgt.y,     p.tgt.z,       p.tgt.s,       p.nconst,     p.sweep,
@@ -98,7 +99,9 @@ bool alloc_binned(Binned& b, long long cap, const CellGeom& g, size_t elt) {
   return dev_alloc(&b.keys, (size_t)cap) && dev_alloc(&b.counts, (size_t)nb * (nch + 1)) &&
          dev_alloc(&b.offs, (size_t)nb * (nch + 1)) && dev_alloc(&b.sub_start, nb + 1) &&
          dev_alloc(&b.cell_start, ncells + 1) && dev_alloc(&b.cflags, kMaxChunks + 1) &&
-         dev_alloc(&b.item_start, ncells + 1) && dev_alloc(&b.perm, (size_t)cap) &&
+         dev_alloc(&b.item_start, ncells + 1) &&
+         dev_alloc(&b.item_cell, (size_t)(cap / kNearBlock) + ncells + 1) &&
+         dev_alloc(&b.perm, (size_t)cap) &&
          dev_alloc(&b.x, (size_t)cap) && dev_alloc(&b.y, (size_t)cap) &&
          dev_alloc(&b.z, (size_t)cap) &&
          hipMalloc(&b.s, (size_t)(3 * (cap > 0 ? cap : 1)) * elt) == hipSuccess;

@@ -51,6 +51,7 @@ struct Binned {
   unsigned* cflags;  // per-chunk domain flags (kMaxChunks)
   int* cell_start;   // ncells + 1 (cell c starts at sub_start[c * nzs])
   int* item_start;   // ncells + 1: near-field work items per cell (prefix)
+  int* item_cell;    // cell of each near-field work item (cap / kNearBlock + ncells)
   int* perm;         // sorted position -> original index
   double* x;         // sorted wrapped positions (SoA)
   double* y;

@@ -95,13 +95,15 @@ __device__ inline int cell_total(const int* __restrict__ sub, int c, int nzs) {
 
 // Single block: exclusive scans of the per-bucket totals (held in sub_start
 // on entry), of the per-cell totals (cell_start) and of the per-cell
-// near-field work items ceil(total / kNearBlock) (item_start).  It also
+// near-field work items ceil(total / kNearBlock) (item_start, and the cell of
+// every item in item_cell).  It also
 // folds the chunks' domain flags into *flags: the first binning of an
 // evaluation overwrites them and clears the pair counters (no kernel of the
 // evaluation has touched either yet), later binnings OR into them.
 __global__ void __launch_bounds__(1024) bin_scan(int ncells, int nzs, int* __restrict__ sub_start,
                                                  int* __restrict__ cell_start,
-                                                 int* __restrict__ item_start, int nchunks,
+                                                 int* __restrict__ item_start,
+                                                 int* __restrict__ item_cell, int nchunks,
                                                  const unsigned* __restrict__ cflags,
                                                  unsigned* __restrict__ flags,
                                                  unsigned long long* __restrict__ work,
@@ -145,8 +147,10 @@ __global__ void __launch_bounds__(1024) bin_scan(int ncells, int nzs, int* __res
       sub_start[c * nzs + q] = ra + v;
       v += w;
     }
+    const int ni = (v + kNearBlock - 1) / kNearBlock;
+    for (int it = 0; it < ni; ++it) item_cell[rb + it] = c;
     ra += v;
-    rb += (v + kNearBlock - 1) / kNearBlock;
+    rb += ni;
   }
   if (t == 1023) {
     cell_start[ncells] = sa[1023];
@@ -244,7 +248,7 @@ static hipError_t bin_impl(Plan& p, Binned& b, long long n, const double* x, con
   } else {
     zero_ints<<<(nb + 1 + 255) / 256, 256, 0, st>>>(b.sub_start, nb + 1);
   }
-  bin_scan<<<1, 1024, 0, st>>>(g.ncells, g.nzs, b.sub_start, b.cell_start, b.item_start,
+  bin_scan<<<1, 1024, 0, st>>>(g.ncells, g.nzs, b.sub_start, b.cell_start, b.item_start, b.item_cell,
                                n > 0 ? b.nchunks : 0, b.cflags, p.flags, p.work, first ? 1 : 0);
   if (n > 0) {
     if (p.fp64)

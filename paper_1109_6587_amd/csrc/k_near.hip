@@ -109,6 +109,7 @@ struct NearArgs {
   CellGeom g;
   double rc2;
   const int* item_start;   // target items per cell (prefix)
+  const int* item_cell;    // cell of each target item
   const int* tcell;        // target cell_start
   const double *tx, *ty, *tz;
   const void* tn;          // sorted target normals (T, SoA) for the double layer
@@ -126,16 +127,6 @@ struct NearArgs {
   double scale;            // output factor
   unsigned long long* work;  // pair counter (null: not counted)
 };
-
-__device__ inline int find_cell(const int* __restrict__ start, int ncells, int item) {
-  int lo = 0, hi = ncells - 1;
-  while (lo < hi) {  // largest c with start[c] <= item
-    int mid = (lo + hi + 1) >> 1;
-    if (start[mid] <= item) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
 
 // Work item: up to 64 sorted targets of one cell (one per lane).  Its
 // neighbour cells are split into nslice consecutive runs, one block per
@@ -165,7 +156,7 @@ __global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k) {
   if (item >= nitems) return;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int c = find_cell(a.item_start, g.ncells, item);
+  const int c = a.item_cell[item];
   const int t0 = a.tcell[c] + (item - a.item_start[c]) * 64;
   const int t1 = min(a.tcell[c + 1], t0 + 64);
   const int t = t0 + lane;
@@ -439,6 +430,7 @@ static NearArgs near_args(Plan& p, const Binned& tg, void* out, size_t ostride) 
   a.g = p.cg;
   a.rc2 = p.rc2;
   a.item_start = tg.item_start;
+  a.item_cell = tg.item_cell;
   a.tcell = tg.cell_start;
   a.tx = tg.x;
   a.ty = tg.y;
