@@ -276,6 +276,8 @@ __global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k) {
       const int cnt = __popcll(km);
       if (cnt == 0) continue;
       __builtin_amdgcn_wave_barrier();
+      if (FAST && lane >= cnt && lane < ((cnt + 3) & ~3))
+        lr[wave][lane] = make_float4(1e30f, 1e30f, 1e30f, 0.f);  // padding: out of range
       if (keep) {
         const int slot = __popcll(km & lt);
         if (FAST)
@@ -292,16 +294,45 @@ __global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       // pass 1: this lane's in-range sources of the batch as a bit mask
       unsigned long long mask = 0;
-      if (active) {
-        for (int j = 0; j < cnt; ++j) {
-          bool in, self;
-          if (FAST) {
+      if (FAST) {
+        // four staged sources per LDS round trip (the batch is padded to a
+        // multiple of four with far-away points); the mask is built without
+        // branches, and coincident points (r = 0) take a separate pass
+        unsigned mlo = 0u, mhi = 0u;
+        bool any_self = false;
+        for (int j0 = 0; j0 < cnt; j0 += 4) {
+          float4 qg[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) qg[u] = lr[wave][j0 + u];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int j = j0 + u;
+            const float dx = prx - qg[u].x, dy = pry - qg[u].y, dz = prz - qg[u].z;
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            const bool in = r2 <= rc2f;
+            const unsigned bit = (in && r2 != 0.f) ? (1u << (j & 31)) : 0u;
+            if (j < 32) mlo |= bit;
+            else mhi |= bit;
+            any_self |= in && r2 == 0.f;
+          }
+        }
+        mask = active ? (((unsigned long long)mhi << 32) | mlo) : 0ull;
+        if (!DL && __ballot(active && any_self)) {
+          for (int j = 0; j < cnt; ++j) {
             const float4 q = lr[wave][j];
             const float dx = prx - q.x, dy = pry - q.y, dz = prz - q.z;
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            in = r2 <= rc2f;
-            self = r2 == 0.f;
-          } else {
+            if (active && r2 == 0.f) {
+              sfx += lf[wave][0][j];
+              sfy += lf[wave][1][j];
+              sfz += lf[wave][2][j];
+            }
+          }
+        }
+      } else if (active) {
+        for (int j = 0; j < cnt; ++j) {
+          bool in, self;
+          {
             const double dx = min_image(px - lx[wave][j], g.Lx, g.invLx);
             const double dy = py - ly[wave][j];
             const double dz = min_image(pz - lz[wave][j], g.Lz, g.invLz);
