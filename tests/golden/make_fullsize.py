@@ -7,8 +7,8 @@ script evaluates it once at a fixed, seeded sample of targets and stores
 the values as JSON beside itself.  It calls only the oracle and the input
 generators.
 
-    python tests/golden/make_fullsize.py sl    # ~2 minutes on 8 cores
-    python tests/golden/make_fullsize.py dl    # about an hour
+    python tests/golden/make_fullsize.py sl      # ~2 minutes on 8 cores
+    python tests/golden/make_fullsize.py dl 8    # wall data on 8 processes
 
 Each file records the workload, the sample indices and, per target, the
 local part, the global part and their sum (single layer: velocity, Eq. u_g a;
@@ -17,6 +17,7 @@ double layer: traction n_k sigma_jk, Eq. wdbl).
 from __future__ import annotations
 
 import json
+import multiprocessing as mp
 import os
 import sys
 import time
@@ -37,11 +38,51 @@ def sample(nt):
     return np.sort(np.random.default_rng(SAMPLE_SEED).choice(nt, NSAMPLE, replace=False))
 
 
-def main(which):
+_W = {}
+
+
+def _wall_chunk(rng):
+    a, b = rng
+    return O.local_velocity(_W["g"], _W["xs"], _W["f"], _W["pts"][a:b])
+
+
+def parallel_wall_data(g, xs, f, workers):
+    """The oracle's wall data with its local sum split over wall-node chunks.
+
+    Every wall node's sum is formed by oracle.local_velocity over all sources
+    in the same order whatever the chunk, so the values are bitwise those of
+    oracle.wall_data; only the work is spread over processes.
+    """
+    X, Z = np.meshgrid(g.x, g.z, indexing="ij")
+    pts = np.concatenate([np.stack([X.ravel(), np.full(X.size, yw), Z.ravel()], axis=1)
+                          for yw in (-g.H, g.H)])
+    _W.update(g=g, xs=xs, f=f, pts=pts)
+    step = 512
+    chunks = [(a, min(a + step, len(pts))) for a in range(0, len(pts), step)]
+    with mp.get_context("fork").Pool(workers) as pool:
+        ul = np.concatenate(pool.map(_wall_chunk, chunks))
+    n = X.size
+    return -ul[:n].T.reshape(3, g.Nx, g.Nz), -ul[n:].T.reshape(3, g.Nx, g.Nz)
+
+
+def main(which, workers=1):
     c = case_capsules_sl() if which == "sl" else case_capsules_dl()
     g = O.SlitGrid.from_case(c)
     sel = sample(c.xt.shape[0])
     t0 = time.time()
+    if workers > 1:
+        # the global part calls oracle.ggem.wall_data(g, xs, f) with the wrapped
+        # sources; hand it the same values computed in parallel
+        xs_w = g.wrap(c.xs)
+        f64 = np.asarray(c.f, dtype=np.float64)
+        walls = parallel_wall_data(g, xs_w, f64, workers)
+        print(f"wall data done {time.time() - t0:.0f} s", flush=True)
+
+        def wall_data(g_, xs_, f_):
+            assert g_ is g and np.array_equal(xs_, xs_w) and np.array_equal(f_, f64)
+            return walls
+
+        O.ggem.wall_data = wall_data
     if which == "sl":
         loc = O.single_layer(g, c.xs, c.f, c.xt[sel], parts=O.LOCAL)
         print(f"local done {time.time() - t0:.0f} s", flush=True)
@@ -69,4 +110,4 @@ def main(which):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1] if len(sys.argv) > 1 else "sl")
+    main(sys.argv[1] if len(sys.argv) > 1 else "sl", int(sys.argv[2]) if len(sys.argv) > 2 else 1)
