@@ -36,6 +36,9 @@ __device__ inline void lagrange5(double t, const double* nd, double* w) {
   }
 }
 
+// v in [-n, 2n) mapped into [0, n)
+__device__ inline int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
 struct InterpArgs {
   int nt, Nx, Nz, Ny;
   double dx, dz, H;
@@ -75,13 +78,14 @@ __global__ void __launch_bounds__(256) interp_combine(InterpArgs a) {
     for (int q = 0; q < 5; ++q) ny[q] = a.y[j0 - 2 + q];
     lagrange5(y, ny, wy);
     const int i0 = (int)fx, k0 = (int)fz;
+    // k0 - 2 + q lies in [-2, Nz + 2] (z in [0, Lz)) and Nz >= 8: one wrap
     int kk[5];
-    for (int q = 0; q < 5; ++q) kk[q] = ((k0 - 2 + q) % a.Nz + a.Nz) % a.Nz;
+    for (int q = 0; q < 5; ++q) kk[q] = wrap1(k0 - 2 + q, a.Nz);
     const T* g = (const T*)a.grid;
     const size_t fs = (size_t)a.Ny * a.Nx * a.Nz;
     for (int row = r; row < 25; row += kGrp) {
       const int qa = row / 5, qb = row % 5;
-      const int ii = ((i0 - 2 + qb) % a.Nx + a.Nx) % a.Nx;
+      const int ii = wrap1(i0 - 2 + qb, a.Nx);
       const size_t base = ((size_t)(j0 - 2 + qa) * a.Nx + ii) * a.Nz;
       const double wab = wy[qa] * wx[qb];
       for (int qc = 0; qc < 5; ++qc) {
