@@ -574,7 +574,9 @@ extern "C" int ggem_plan_time_stage(ggem_plan_t plan, int stage, int max_calls) 
   p.timed_ev = new (std::nothrow) hipEvent_t[2 * (size_t)max_calls];
   if (!p.timed_ev) return fail(GGEM_E_NOMEM, "host allocation failed");
   for (int i = 0; i < 2 * max_calls; ++i) {
-    hipError_t e = hipEventCreate(&p.timed_ev[i]);
+    // timing-only events: no system-scope fence, so recording them around a
+    // stage adds no cache write-back between its kernels
+    hipError_t e = hipEventCreateWithFlags(&p.timed_ev[i], hipEventDisableSystemFence);
     if (e != hipSuccess) {
       p.timed_max = i / 2;
       destroy_timer(p);
