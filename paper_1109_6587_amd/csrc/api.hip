@@ -480,9 +480,11 @@ extern "C" int ggem_plan_create(const ggem_params* prm, void* hip_stream, ggem_p
             alloc_binned(p.tgt, q.max_tgt, g, elt) &&
             alloc_binned(p.wall, 2LL * q.Nx * q.Nz, g, elt) &&
             hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking) == hipSuccess &&
-            hipEventCreateWithFlags(&p.ev_fork, hipEventDisableTiming) == hipSuccess &&
-            hipEventCreateWithFlags(&p.ev_wall, hipEventDisableTiming) == hipSuccess &&
-            hipEventCreateWithFlags(&p.ev_near, hipEventDisableTiming) == hipSuccess;
+            // fork/join events order two streams of this device only: no
+            // system-scope fence (device-scope ordering is kept)
+            hipEventCreateWithFlags(&p.ev_fork, hipEventDisableTiming | hipEventDisableSystemFence) == hipSuccess &&
+            hipEventCreateWithFlags(&p.ev_wall, hipEventDisableTiming | hipEventDisableSystemFence) == hipSuccess &&
+            hipEventCreateWithFlags(&p.ev_near, hipEventDisableTiming | hipEventDisableSystemFence) == hipSuccess;
   if (!ok) {
     free_plan(p);
     delete h;
