@@ -9,7 +9,7 @@
 //   bin_cellscan per-bucket running sum over chunks     -> offs[chunk][bucket]
 //   bin_scan     exclusive scan over buckets            -> sub_start, cell_start,
 //                                                          item_start
-//   bin_scatter  one wave per chunk, stable ranks by wave match -> sorted SoA
+//   bin_scatter  one wave per chunk, stable ranks by bitwise key match -> sorted SoA
 //
 // Points keep their input order inside a bucket, so every later sum over a
 // cell's points has a fixed order and results are bitwise reproducible.
@@ -170,6 +170,7 @@ __global__ void __launch_bounds__(1024) bin_scan(int ncells, int nzs, int* __res
 
 template <typename T>
 __global__ void __launch_bounds__(64) bin_scatter(int n, int chunk_size, int nchunks, int nb,
+                                                  int kbits,
                                                   CellGeom g,
                                                   const int* __restrict__ keys,
                                                   const double* __restrict__ x,
@@ -190,23 +191,21 @@ __global__ void __launch_bounds__(64) bin_scatter(int n, int chunk_size, int nch
   for (int base = i0; base < i1; base += 64) {
     int i = base + lane;
     bool valid = i < i1;
-    int key = valid ? keys[i] : -1;
-    unsigned long long active = __ballot(valid);
-    int rank = 0, before = 0;
-    while (active) {
-      int leader = __ffsll((long long)active) - 1;
-      int lk = __shfl(key, leader);
-      unsigned long long m = __ballot(key == lk) & active;
-      int cur = cnt[lk];
-      if (key == lk) {
-        rank = __popcll(m & lt);
-        before = cur;
-      }
-      __builtin_amdgcn_wave_barrier();
-      if (lane == leader) cnt[lk] = cur + __popcll(m);
-      __builtin_amdgcn_wave_barrier();
-      active &= ~m;
+    int key = valid ? keys[i] : 0;
+    // the lanes holding the same key, found bit by bit (one ballot per key bit)
+    unsigned long long m = __ballot(valid);
+    for (int b = 0; b < kbits; ++b) {
+      const bool bit = (key >> b) & 1;
+      const unsigned long long bm = __ballot(bit);
+      m &= bit ? bm : ~bm;
     }
+    // rank among the earlier lanes of the key; the key's lowest lane advances
+    // the chunk's running count for the later groups
+    const int rank = __popcll(m & lt);
+    const int before = valid ? cnt[key] : 0;
+    __builtin_amdgcn_wave_barrier();
+    if (valid && rank == 0) cnt[key] = before + __popcll(m);
+    __builtin_amdgcn_wave_barrier();
     if (valid) {
       int pos = sub_start[key] + offs[(size_t)chunk * nb + key] + before + rank;
       double px = x[3 * (size_t)i], py = x[3 * (size_t)i + 1], pz = x[3 * (size_t)i + 2];
@@ -240,6 +239,8 @@ static hipError_t bin_impl(Plan& p, Binned& b, long long n, const double* x, con
   b.chunk = (int)(per < 256 ? 256 : ((per + 63) / 64) * 64);
   b.nchunks = (int)((n + b.chunk - 1) / b.chunk);
   const int nb = g.nbuckets;
+  int kbits = 1;  // bits of the largest bucket key
+  while ((1 << kbits) < nb) ++kbits;
   if (n > 0) {
     bin_keys<<<b.nchunks, 256, nb * sizeof(int), st>>>((int)n, b.chunk, nb, x, g,
                                                         is_source ? 1 : 0, b.keys, b.counts,
@@ -253,11 +254,11 @@ static hipError_t bin_impl(Plan& p, Binned& b, long long n, const double* x, con
   if (n > 0) {
     if (p.fp64)
       bin_scatter<double><<<b.nchunks, 64, nb * sizeof(int), st>>>(
-          (int)n, b.chunk, b.nchunks, nb, g, b.keys, x, s, b.sub_start, b.offs, b.perm,
+          (int)n, b.chunk, b.nchunks, nb, kbits, g, b.keys, x, s, b.sub_start, b.offs, b.perm,
           b.x, b.y, b.z, (double*)b.s, cap);
     else
       bin_scatter<float><<<b.nchunks, 64, nb * sizeof(int), st>>>(
-          (int)n, b.chunk, b.nchunks, nb, g, b.keys, x, s, b.sub_start, b.offs, b.perm,
+          (int)n, b.chunk, b.nchunks, nb, kbits, g, b.keys, x, s, b.sub_start, b.offs, b.perm,
           b.x, b.y, b.z, (float*)b.s, cap);
   }
   return hipGetLastError();
