@@ -71,20 +71,34 @@ __global__ void bin_keys(int n, int chunk_size, int nb, const double* __restrict
   if (threadIdx.x == 0) cflags[chunk] = bflags;
 }
 
-// counts and offsets are chunk-major ([chunk][bucket]): a thread per bucket
-// walks the chunks with coalesced, independent loads.
-__global__ void bin_cellscan(int nchunks, int nb, const int* __restrict__ counts,
-                             int* __restrict__ offs, int* __restrict__ totals) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nb) return;
+// counts and offsets are chunk-major ([chunk][bucket]).  A block takes 32
+// buckets; its 8 thread rows split the chunks into 8 consecutive runs, sum
+// their run, and write the offsets from the sum of the earlier runs (integer
+// sums: the same result as one thread walking all chunks).
+constexpr int kScanSeg = 8;
+__global__ void __launch_bounds__(32 * kScanSeg) bin_cellscan(int nchunks, int nb,
+                                                              const int* __restrict__ counts,
+                                                              int* __restrict__ offs,
+                                                              int* __restrict__ totals) {
+  __shared__ int part[kScanSeg][32];
+  const int bl = threadIdx.x & 31, seg = threadIdx.x >> 5;
+  const int c = blockIdx.x * 32 + bl;
+  const int per = (nchunks + kScanSeg - 1) / kScanSeg;
+  const int k0 = min(nchunks, seg * per), k1 = min(nchunks, k0 + per);
   int s = 0;
-#pragma unroll 8
-  for (int k = 0; k < nchunks; ++k) {
+  if (c < nb)
+    for (int k = k0; k < k1; ++k) s += counts[(size_t)k * nb + c];
+  part[seg][bl] = s;
+  __syncthreads();
+  int run = 0;
+  for (int q = 0; q < seg; ++q) run += part[q][bl];
+  if (c >= nb) return;
+  if (seg == kScanSeg - 1) totals[c] = run + s;
+  for (int k = k0; k < k1; ++k) {
     const int v = counts[(size_t)k * nb + c];
-    offs[(size_t)k * nb + c] = s;
-    s += v;
+    offs[(size_t)k * nb + c] = run;
+    run += v;
   }
-  totals[c] = s;
 }
 
 __device__ inline int cell_total(const int* __restrict__ sub, int c, int nzs) {
@@ -108,7 +122,7 @@ __global__ void __launch_bounds__(1024) bin_scan(int ncells, int nzs, int* __res
                                                  unsigned* __restrict__ flags,
                                                  unsigned long long* __restrict__ work,
                                                  int first) {
-  __shared__ int sa[1024], sb[1024];
+  __shared__ int sa[16], sb[16];
   __shared__ unsigned fl;
   if (threadIdx.x == 0) fl = 0u;
   __syncthreads();
@@ -125,19 +139,30 @@ __global__ void __launch_bounds__(1024) bin_scan(int ncells, int nzs, int* __res
     la += v;
     lb += (v + kNearBlock - 1) / kNearBlock;
   }
-  sa[t] = la;
-  sb[t] = lb;
-  __syncthreads();
-  // Hillis-Steele inclusive scan over 1024 partial sums
-  for (int o = 1; o < 1024; o <<= 1) {
-    int va = t >= o ? sa[t - o] : 0;
-    int vb = t >= o ? sb[t - o] : 0;
-    __syncthreads();
-    sa[t] += va;
-    sb[t] += vb;
-    __syncthreads();
+  // inclusive scan of the 1024 partial sums: within each wave by shuffles,
+  // then over the 16 wave totals
+  const int lane = t & 63, wv = t >> 6;
+  int ia = la, ib = lb;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int va = __shfl_up(ia, o), vb = __shfl_up(ib, o);
+    if (lane >= o) {
+      ia += va;
+      ib += vb;
+    }
   }
-  int ra = sa[t] - la, rb = sb[t] - lb;
+  if (lane == 63) {
+    sa[wv] = ia;
+    sb[wv] = ib;
+  }
+  __syncthreads();
+  int wa = 0, wb = 0;
+  for (int q = 0; q < wv; ++q) {
+    wa += sa[q];
+    wb += sb[q];
+  }
+  ia += wa;
+  ib += wb;
+  int ra = ia - la, rb = ib - lb;
   for (int c = c0; c < c1; ++c) {
     cell_start[c] = ra;
     item_start[c] = rb;
@@ -153,9 +178,9 @@ __global__ void __launch_bounds__(1024) bin_scan(int ncells, int nzs, int* __res
     rb += ni;
   }
   if (t == 1023) {
-    cell_start[ncells] = sa[1023];
-    sub_start[ncells * nzs] = sa[1023];
-    item_start[ncells] = sb[1023];
+    cell_start[ncells] = ia;
+    sub_start[ncells * nzs] = ia;
+    item_start[ncells] = ib;
   }
   if (t == 0) {
     if (first) {
@@ -245,7 +270,8 @@ static hipError_t bin_impl(Plan& p, Binned& b, long long n, const double* x, con
     bin_keys<<<b.nchunks, 256, nb * sizeof(int), st>>>((int)n, b.chunk, nb, x, g,
                                                         is_source ? 1 : 0, b.keys, b.counts,
                                                         b.cflags);
-    bin_cellscan<<<(nb + 255) / 256, 256, 0, st>>>(b.nchunks, nb, b.counts, b.offs, b.sub_start);
+    bin_cellscan<<<(nb + 31) / 32, 32 * kScanSeg, 0, st>>>(b.nchunks, nb, b.counts, b.offs,
+                                                          b.sub_start);
   } else {
     zero_ints<<<(nb + 1 + 255) / 256, 256, 0, st>>>(b.sub_start, nb + 1);
   }
