@@ -60,10 +60,30 @@ struct InterpArgs {
 // across the group.
 template <typename T, bool STRESS, bool GLOBAL, int kGrp>
 __global__ void __launch_bounds__(256) interp_combine(InterpArgs a) {
+  __shared__ double ly[kMaxNy];
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int t = gid / kGrp, r = gid % kGrp;
   const bool valid = t < a.nt;
   constexpr int NC = STRESS ? 6 : 3;
+  // the Gauss-Lobatto nodes once per block, so the stencil's y nodes come
+  // from LDS rather than a global load that waits for the stencil index
+  if (GLOBAL) {
+    for (int j = threadIdx.x; j < a.Ny; j += blockDim.x) ly[j] = a.y[j];
+    __syncthreads();
+  }
+  // the local part and the output slot, loaded before the gathers so that
+  // their latency overlaps them
+  const T* ul = (const T*)a.ul;
+  double res[3] = {0.0, 0.0, 0.0};
+  int slot = 0;
+  if (valid && r == 0) {
+    slot = a.perm[t];
+    for (int c = 0; c < 3; ++c) {
+      double v = 0.0;
+      for (int s = 0; s < kNearSlices; ++s) v += (double)ul[(size_t)(3 * s + c) * a.tcap + t];
+      res[c] = v;
+    }
+  }
   double acc[NC];
   for (int c = 0; c < NC; ++c) acc[c] = 0.0;
   if (GLOBAL && valid) {
@@ -75,7 +95,7 @@ __global__ void __launch_bounds__(256) interp_combine(InterpArgs a) {
     const int N = a.Ny - 1;
     int j0 = (int)rint(acos(y / a.H) * N / 3.141592653589793);
     j0 = j0 < 2 ? 2 : (j0 > a.Ny - 3 ? a.Ny - 3 : j0);
-    for (int q = 0; q < 5; ++q) ny[q] = a.y[j0 - 2 + q];
+    for (int q = 0; q < 5; ++q) ny[q] = ly[j0 - 2 + q];
     lagrange5(y, ny, wy);
     const int i0 = (int)fx, k0 = (int)fz;
     // k0 - 2 + q lies in [-2, Nz + 2] (z in [0, Lz)) and Nz >= 8: one wrap
@@ -99,14 +119,8 @@ __global__ void __launch_bounds__(256) interp_combine(InterpArgs a) {
   for (int o = kGrp / 2; o > 0; o >>= 1)
     for (int c = 0; c < NC; ++c) acc[c] += __shfl_down(acc[c], o, kGrp);  // none when G = 1
   if (!valid || r != 0) return;
-  // local part: the near-field slices' partial sums, added in slice order
-  const T* ul = (const T*)a.ul;
-  double res[3];
-  for (int c = 0; c < 3; ++c) {
-    double v = 0.0;
-    for (int s = 0; s < kNearSlices; ++s) v += (double)ul[(size_t)(3 * s + c) * a.tcap + t];
-    res[c] = v;
-  }
+  // res holds the local part: the near-field slices' partial sums, added in
+  // slice order
   if (GLOBAL) {
     if (!STRESS) {
       res[0] += acc[0];
@@ -121,7 +135,7 @@ __global__ void __launch_bounds__(256) interp_combine(InterpArgs a) {
       res[2] += acc[4] * nx + acc[5] * nyv + acc[2] * nz;
     }
   }
-  const size_t o = 3 * (size_t)a.perm[t];
+  const size_t o = 3 * (size_t)slot;
   a.out[o] = res[0];
   a.out[o + 1] = res[1];
   a.out[o + 2] = res[2];
