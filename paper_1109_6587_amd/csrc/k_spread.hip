@@ -49,6 +49,8 @@ struct SpreadArgs {
 // tile (mid-slab, many sources in reach) is shared by four waves instead of
 // setting the kernel's length alone.
 constexpr int TZ = 8, TX = 4, TY = 4, TB = 256, WT = 4, WZ = 8, NW = TB / 64;
+// single-half list capacity: at most 3 carried over plus one batch
+constexpr int kHalf = 68, kSlot = 64 + 2 * kHalf;
 
 template <typename T>
 struct V4;
@@ -60,6 +62,24 @@ template <>
 struct V4<float> {
   using t = float4;
 };
+
+// a staged source far outside the slit: every pair with it is out of range
+template <typename Q>
+__device__ inline Q far_q() {
+  Q r;
+  r.x = 0;
+  r.y = 1e30;
+  r.z = 0;
+  r.w = 0;
+  return r;
+}
+
+// the wave's LDS writes visible to all its lanes
+__device__ inline void lds_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // Every wave walks the cell rows that can reach the tile and numbers the
 // 64-source batches in sorted order; wave w takes batches w, w + 4, ...  It
@@ -76,8 +96,10 @@ template <typename T, bool REL>
 __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
   using Q = typename V4<T>::t;
   __shared__ double lx[REL ? 1 : 4][64], ly[REL ? 1 : 4][64], lz[REL ? 1 : 4][64];
-  __shared__ Q lr[REL ? 4 : 1][64];
-  __shared__ Q lf[4][64];
+  // REL: per wave the both-halves list [0, 64) and the low-only and
+  // high-only lists [64, 64 + kHalf) and [64 + kHalf, 64 + 2 kHalf)
+  __shared__ Q lr[REL ? 4 : 1][REL ? kSlot : 64];
+  __shared__ Q lf[4][REL ? kSlot : 64];
   __shared__ T red[NW - 1][6][64];
   __shared__ unsigned cnt_w[NW];
   const CellGeom& g = a.g;
@@ -129,6 +151,68 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
   T fx = 0, fy = 0, fz = 0, gx1 = 0, gy1 = 0, gz1 = 0;
   unsigned nupd = 0;
   int bc = 0;  // batches numbered in walk order (uniform)
+  // REL: the z halves of the tile and the single-half lists' lengths
+  const int k_mid = min(k_hi, k_lo + 3);
+  const bool has_hi = k_lo + 4 <= k_hi;
+  const double bzm0 = k_mid * a.dz, bzm1 = (k_lo + 4) * a.dz;
+  int cl = 0, ch = 0;
+  // A single-half list: its complete groups of four evaluated at the lane's
+  // node of that half (nz, one exponential per pair), the 0-3 left over moved
+  // to the list's front for the next batch; with flush the last group is
+  // padded with far-away sources and evaluated too.
+  auto half_pass = [&](int base, int& n, T nz, T& ax, T& ay, T& az, bool flush) {
+    const int ng = flush ? (n + 3) / 4 : n / 4;
+    if (ng == 0) return;
+    if (flush && (n & 3)) {
+      if (lane >= n && lane < 4 * ng) {
+        lr[wave][base + lane] = far_q<Q>();
+        Q f;
+        f.x = f.y = f.z = f.w = (T)0;
+        lf[wave][base + lane] = f;
+      }
+      lds_wave_sync();
+    }
+    if (valid) {
+      for (int e0 = 0; e0 < 4 * ng; e0 += 4) {
+        Q qg[4], fg[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          qg[u] = lr[wave][base + e0 + u];
+          fg[u] = lf[wave][base + e0 + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const T dx = nrx - qg[u].x, dy = nry - qg[u].y, dz = nz - qg[u].z;
+          const T r2 = dx * dx + dy * dy + dz * dz;
+          const bool in = r2 <= rc2t;
+          nupd += (unsigned)__popcll(__ballot(in));
+          const T w = in ? t_exp2_s(-r2) * fma((T)-0.69314718055994531, r2, (T)2.5) : (T)0;
+          ax += w * fg[u].x;
+          ay += w * fg[u].y;
+          az += w * fg[u].z;
+        }
+      }
+    }
+    if (flush) {
+      n = 0;
+      return;
+    }
+    const int rem = n - 4 * ng;
+    if (rem > 0) {
+      Q r, f;
+      if (lane < rem) {
+        r = lr[wave][base + 4 * ng + lane];
+        f = lf[wave][base + 4 * ng + lane];
+      }
+      lds_wave_sync();
+      if (lane < rem) {
+        lr[wave][base + lane] = r;
+        lf[wave][base + lane] = f;
+      }
+      lds_wave_sync();
+    }
+    n = rem;
+  };
   for (int cy = cy0; cy <= cy1; ++cy) {
     const double ylo = cy / g.icy - g.H, yhi = (cy + 1) / g.icy - g.H;
     const double gyc = fmax(0.0, fmax(ylo - by1, by0 - yhi) - eps);
@@ -154,26 +238,44 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
         const int s0 = a.scell[row + lo], s1 = a.scell[row + hi + 1];
         for (int b = s0; b < s1; b += 64) {
           if (bc++ % NW != wave) continue;
-          // the batch's sources within r_c of the tile's box, compacted
+          // the batch's sources within r_c of the tile's box, compacted; REL
+          // sorts them by the z half (nodes k_lo..k_lo+3, k_lo+4..k_lo+7)
+          // they can reach
           const int si = b + lane;
-          bool keep = false;
+          bool keep = false, inlo = false, inhi = false;
           double qx = 0, qy = 0, qz = 0;
           if (si < s1) {
             qx = a.sx[si];
             qy = a.sy[si];
             qz = a.sz[si];
             const double gx = box_gap_periodic(qx, bx0, bx1, g.Lx, g.invLx);
-            const double gz = box_gap_periodic(qz, bz0, bz1, g.Lz, g.invLz);
             const double gy = qy < by0 ? by0 - qy : (qy > by1 ? qy - by1 : 0.0);
-            keep = dist2_s(gx, gy, gz) <= a.rc2 * (1.0 + 1e-12);
+            if (REL) {
+              const double gzl = box_gap_periodic(qz, bz0, bzm0, g.Lz, g.invLz);
+              inlo = dist2_s(gx, gy, gzl) <= rc2m;
+              if (has_hi) {
+                const double gzh = box_gap_periodic(qz, bzm1, bz1, g.Lz, g.invLz);
+                inhi = dist2_s(gx, gy, gzh) <= rc2m;
+              }
+              keep = inlo || inhi;
+            } else {
+              const double gz = box_gap_periodic(qz, bz0, bz1, g.Lz, g.invLz);
+              keep = dist2_s(gx, gy, gz) <= rc2m;
+              inlo = inhi = keep;
+            }
           }
-          const unsigned long long m = __ballot(keep);
-          const int cnt = __popcll(m);
-          if (cnt == 0) continue;
-          const int cnt4 = (cnt + 3) & ~3;
+          const unsigned long long mb = __ballot(inlo && inhi);
+          const unsigned long long ml = REL ? __ballot(inlo && !inhi) : 0ull;
+          const unsigned long long mh = REL ? __ballot(inhi && !inlo) : 0ull;
+          const int nb = __popcll(mb), nl = __popcll(ml), nh = __popcll(mh);
+          if (nb + nl + nh == 0) continue;
+          const int nb4 = (nb + 3) & ~3;
           __builtin_amdgcn_wave_barrier();
           if (keep) {
-            const int slot = __popcll(m & lt);
+            int slot;
+            if (inlo && inhi) slot = __popcll(mb & lt);
+            else if (inlo) slot = 64 + cl + __popcll(ml & lt);
+            else slot = 64 + kHalf + ch + __popcll(mh & lt);
             if (REL) {
               Q r;
               r.x = (T)(min_image_s(qx - bx0, g.Lx, g.invLx) * sc);
@@ -193,16 +295,11 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
             f.w = (T)0;
             lf[wave][slot] = f;
           }
-          if (lane >= cnt && lane < cnt4) {
-            // padding up to a multiple of 4 (kept lanes write below cnt): a
+          if (lane >= nb && lane < nb4) {
+            // padding of the both-halves list up to a multiple of 4: a
             // source far outside the slit
             if (REL) {
-              Q r;
-              r.x = (T)0;
-              r.y = (T)1e30;
-              r.z = (T)0;
-              r.w = (T)0;
-              lr[wave][lane] = r;
+              lr[wave][lane] = far_q<Q>();
             } else {
               lx[wave][lane] = 0.0;
               ly[wave][lane] = 1e30;
@@ -212,11 +309,9 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
             f.x = f.y = f.z = f.w = (T)0;
             lf[wave][lane] = f;
           }
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          lds_wave_sync();
           if (valid) {
-            for (int e0 = 0; e0 < cnt4; e0 += 4) {
+            for (int e0 = 0; e0 < nb4; e0 += 4) {
               // the group's four positions and strengths are read before any
               // is used, so one LDS latency covers four candidates
               Q qg[4], fg[4];
@@ -271,9 +366,19 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
               }
             }
           }
+          if constexpr (REL) {
+            cl += nl;
+            ch += nh;
+            half_pass(64, cl, nrz, fx, fy, fz, false);
+            half_pass(64 + kHalf, ch, nrz1, gx1, gy1, gz1, false);
+          }
         }
       }
     }
+  }
+  if constexpr (REL) {
+    half_pass(64, cl, nrz, fx, fy, fz, true);
+    half_pass(64 + kHalf, ch, nrz1, gx1, gy1, gz1, true);
   }
   // partial sums of waves 1..3 through LDS, added by wave 0 in wave order;
   // nupd is the wave's count in every lane (lanes of valid nodes only)
