@@ -2,8 +2,8 @@
 //   F(node) = sum_s f_s rho_g(node - x_s),  |node - x_s| <= r_c (minimum image),
 //   rho_g(r) = alpha^3 pi^{-3/2} exp(-alpha^2 r^2) (5/2 - alpha^2 r^2)   (Eq. rho_l_g a).
 //
-// Each thread owns one grid node and sums over the sources in the cells that
-// can reach its tile, in sorted order: no atomics, bitwise reproducible.
+// Each lane owns two grid nodes and sums over the sources in the cells that
+// can reach its tile, in a fixed order: no atomics, bitwise reproducible.
 #include "ggem_internal.h"
 
 namespace ggem {
@@ -92,6 +92,10 @@ __device__ inline void lds_wave_sync() {
 // REL: sources staged relative to the tile corner in T (mixed mode: the
 // displacement is formed once per source in FP64, the pair test in FP32);
 // otherwise every pair displacement is formed in FP64 with the minimum image.
+// REL also sorts the kept sources by the z half of the tile they can reach:
+// those within r_c of both halves are added at both of a lane's nodes, the
+// others go to a per-half list that carries over between batches and is
+// added at the lane's node of that half in complete groups of four.
 template <typename T, bool REL>
 __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
   using Q = typename V4<T>::t;
