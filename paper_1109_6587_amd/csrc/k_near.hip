@@ -92,17 +92,18 @@ __device__ inline void stresslet_acc(T dx, T dy, T dz, T r2, T qx, T qy, T qz, T
   const T ir2 = ir * ir;
   T ec, ex;
   erfc_exp(k.alpha * r, k.a2 * r2, ec, ex);
-  const T ir4 = ir2 * ir2;
-  const T A = -(T)6 * ec * ir4 * ir - k.c12a * ex * ir4 - k.c8a3 * ex * ir2;
+  // A = -6 erfc/r^5 - c12 e/r^4 - c8 e/r^2, nested as -(1/r^2)((1/r^2)(6 erfc/r
+  // + c12 e) + c8 e); the B (q.n) d term is folded into the A term
+  const T A = -(ir2 * fma(ir2, fma((T)6 * ec, ir, k.c12a * ex), k.c8a3 * ex));
   const T B = k.c4a3 * ex;
   const T dq = dx * qx + dy * qy + dz * qz;
   const T dn = dx * nx + dy * ny + dz * nz;
   const T qn = qx * nx + qy * ny + qz * nz;
-  const T Ad = A * dq * dn;
-  const T Bqn = B * qn, Bdn = B * dn, Bdq = B * dq;
-  vx += Ad * dx + Bdn * qx + Bdq * nx + Bqn * dx;
-  vy += Ad * dy + Bdn * qy + Bdq * ny + Bqn * dy;
-  vz += Ad * dz + Bdn * qz + Bdq * nz + Bqn * dz;
+  const T Ad = fma(A * dq, dn, B * qn);
+  const T Bdn = B * dn, Bdq = B * dq;
+  vx += Ad * dx + Bdn * qx + Bdq * nx;
+  vy += Ad * dy + Bdn * qy + Bdq * ny;
+  vz += Ad * dz + Bdn * qz + Bdq * nz;
 }
 
 struct NearArgs {
