@@ -367,13 +367,16 @@ __global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k) {
           dy = py - ly[wave][j];
           dz = min_image(pz - lz[wave][j], g.Lz, g.invLz);
         }
-        const double r2 = dist2(dx, dy, dz);
+        // the displacement is formed in FP64; in FP32 mode its square is taken
+        // from the rounded components (the cutoff was decided in pass 1)
+        const T tdx = (T)dx, tdy = (T)dy, tdz = (T)dz;
+        const T r2 = sizeof(T) == 4 ? tdx * tdx + tdy * tdy + tdz * tdz : (T)dist2(dx, dy, dz);
         if (DL)
-          stresslet_acc<T>((T)dx, (T)dy, (T)dz, (T)r2, lf[wave][0][j], lf[wave][1][j],
-                           lf[wave][2][j], nx, ny, nz, k, ux, uy, uz);
+          stresslet_acc<T>(tdx, tdy, tdz, r2, lf[wave][0][j], lf[wave][1][j], lf[wave][2][j], nx,
+                           ny, nz, k, ux, uy, uz);
         else
-          stokeslet_acc<T>((T)dx, (T)dy, (T)dz, (T)r2, lf[wave][0][j], lf[wave][1][j],
-                           lf[wave][2][j], k, ux, uy, uz);
+          stokeslet_acc<T>(tdx, tdy, tdz, r2, lf[wave][0][j], lf[wave][1][j], lf[wave][2][j], k,
+                           ux, uy, uz);
       }
     }
   }
