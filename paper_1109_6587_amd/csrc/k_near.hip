@@ -106,6 +106,17 @@ __device__ inline void stresslet_acc(T dx, T dy, T dz, T r2, T qx, T qy, T qz, T
   vz += Ad * dz + Bdn * qz + Bdq * nz;
 }
 
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<float> {
+  using t = float4;
+};
+template <>
+struct Vec4<double> {
+  using t = double4;
+};
+
 struct NearArgs {
   CellGeom g;
   double rc2;
@@ -147,9 +158,11 @@ struct NearArgs {
 // minimum image and the cutoff is decided in FP64.
 template <typename T, bool DL, bool FAST, int W>
 __global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k) {
-  __shared__ double lx[W][64], ly[W][64], lz[W][64];
+  // staged sources: FP64 position (x, y, z, unused) and strength (x, y, z,
+  // unused), one vector read each
+  __shared__ double4 lp[W][64];
   __shared__ float4 lr[W][64];
-  __shared__ T lf[W][3][64];
+  __shared__ typename Vec4<T>::t lf[W][64];
   __shared__ T part[W][3][64];
   const CellGeom& g = a.g;
   const int item = blockIdx.x;
@@ -283,12 +296,13 @@ __global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k) {
         const int slot = __popcll(km & lt);
         if (FAST)
           lr[wave][slot] = make_float4((float)(qx - ox), (float)(qy - oy), (float)(qz - oz), 0.f);
-        lx[wave][slot] = qx;
-        ly[wave][slot] = qy;
-        lz[wave][slot] = qz;
-        lf[wave][0][slot] = sf[si];
-        lf[wave][1][slot] = sf[a.scap + si];
-        lf[wave][2][slot] = sf[2 * a.scap + si];
+        lp[wave][slot] = make_double4(qx, qy, qz, 0.0);
+        typename Vec4<T>::t fv;
+        fv.x = sf[si];
+        fv.y = sf[a.scap + si];
+        fv.z = sf[2 * a.scap + si];
+        fv.w = (T)0;
+        lf[wave][slot] = fv;
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
@@ -324,9 +338,9 @@ __global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k) {
             const float dx = prx - q.x, dy = pry - q.y, dz = prz - q.z;
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
             if (active && r2 == 0.f) {
-              sfx += lf[wave][0][j];
-              sfy += lf[wave][1][j];
-              sfz += lf[wave][2][j];
+              sfx += lf[wave][j].x;
+              sfy += lf[wave][j].y;
+              sfz += lf[wave][j].z;
             }
           }
         }
@@ -334,9 +348,10 @@ __global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k) {
         for (int j = 0; j < cnt; ++j) {
           bool in, self;
           {
-            const double dx = min_image(px - lx[wave][j], g.Lx, g.invLx);
-            const double dy = py - ly[wave][j];
-            const double dz = min_image(pz - lz[wave][j], g.Lz, g.invLz);
+            const double4 q = lp[wave][j];
+            const double dx = min_image(px - q.x, g.Lx, g.invLx);
+            const double dy = py - q.y;
+            const double dz = min_image(pz - q.z, g.Lz, g.invLz);
             const double r2 = dist2(dx, dy, dz);
             in = r2 <= a.rc2;
             self = r2 == 0.0;
@@ -345,9 +360,9 @@ __global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k) {
             if (!self) {
               mask |= 1ull << j;
             } else if (!DL) {
-              sfx += lf[wave][0][j];
-              sfy += lf[wave][1][j];
-              sfz += lf[wave][2][j];
+              sfx += lf[wave][j].x;
+              sfy += lf[wave][j].y;
+              sfz += lf[wave][j].z;
             }
           }
         }
@@ -357,26 +372,26 @@ __global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k) {
       while (mask) {
         const int j = __builtin_ctzll(mask);
         mask &= mask - 1;
+        const double4 q = lp[wave][j];
         double dx, dy, dz;
         if (FAST) {
-          dx = px - lx[wave][j];
-          dy = py - ly[wave][j];
-          dz = pz - lz[wave][j];
+          dx = px - q.x;
+          dy = py - q.y;
+          dz = pz - q.z;
         } else {
-          dx = min_image(px - lx[wave][j], g.Lx, g.invLx);
-          dy = py - ly[wave][j];
-          dz = min_image(pz - lz[wave][j], g.Lz, g.invLz);
+          dx = min_image(px - q.x, g.Lx, g.invLx);
+          dy = py - q.y;
+          dz = min_image(pz - q.z, g.Lz, g.invLz);
         }
+        const typename Vec4<T>::t fv = lf[wave][j];
         // the displacement is formed in FP64; in FP32 mode its square is taken
         // from the rounded components (the cutoff was decided in pass 1)
         const T tdx = (T)dx, tdy = (T)dy, tdz = (T)dz;
         const T r2 = sizeof(T) == 4 ? tdx * tdx + tdy * tdy + tdz * tdz : (T)dist2(dx, dy, dz);
         if (DL)
-          stresslet_acc<T>(tdx, tdy, tdz, r2, lf[wave][0][j], lf[wave][1][j], lf[wave][2][j], nx,
-                           ny, nz, k, ux, uy, uz);
+          stresslet_acc<T>(tdx, tdy, tdz, r2, fv.x, fv.y, fv.z, nx, ny, nz, k, ux, uy, uz);
         else
-          stokeslet_acc<T>(tdx, tdy, tdz, r2, lf[wave][0][j], lf[wave][1][j], lf[wave][2][j], k,
-                           ux, uy, uz);
+          stokeslet_acc<T>(tdx, tdy, tdz, r2, fv.x, fv.y, fv.z, k, ux, uy, uz);
       }
     }
   }
