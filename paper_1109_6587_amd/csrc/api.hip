@@ -296,6 +296,14 @@ int evaluate(Plan& p, long long ns, const double* xs, const double* f, long long
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   HIP_TRY(hipStreamIsCapturing(main_stream, &cap));
   const bool fork = cap == hipStreamCaptureStatusNone;
+  // Expected work of the local sum against the spread's, from the mean
+  // source density: pairs within r_c per target and node updates per node
+  // (weighted by their measured relative cost per pair).  A local sum well
+  // below the spread finishes before tau starts.
+  const double dens = (double)ns / (p.p.Lx * p.p.Lz * 2.0 * p.p.H);
+  const double near_cost = (dl ? 8.0 : 5.0) * (double)nt * dens;
+  const double spread_cost = (double)p.p.Nx * p.p.Nz * p.p.Ny * dens;
+  const bool one_join = local && near_cost < 0.5 * spread_cost;
   if (fork) {
     HIP_TRY(hipEventRecord(p.ev_fork, main_stream));
     HIP_TRY(hipStreamWaitEvent(p.side, p.ev_fork, 0));
@@ -347,7 +355,10 @@ int evaluate(Plan& p, long long ns, const double* xs, const double* f, long long
       StageScope s(p, GGEM_STAGE_CHEB_FWD);
       HIP_TRY(launch_cheb<T>(p, p.specA, p.specB, 3, true));
     }
-    if (fork) HIP_TRY(hipStreamWaitEvent(p.stream, p.ev_wall, 0));
+    // tau needs the wall data; when the local sum is expected to be done by
+    // then too, one wait for it (it follows the wall data on the second
+    // stream) also serves the interpolation
+    if (fork) HIP_TRY(hipStreamWaitEvent(p.stream, one_join ? p.ev_near : p.ev_wall, 0));
     {
       StageScope s(p, GGEM_STAGE_TAU);
       HIP_TRY(launch_tau<T>(p, dl));
@@ -362,7 +373,7 @@ int evaluate(Plan& p, long long ns, const double* xs, const double* f, long long
       HIP_TRY(launch_fft_inverse<T>(p, p.specB, p.phys, nf * Ny));
     }
   }
-  if (fork) HIP_TRY(hipStreamWaitEvent(p.stream, p.ev_near, 0));
+  if (fork && !(glob && one_join)) HIP_TRY(hipStreamWaitEvent(p.stream, p.ev_near, 0));
   {
     StageScope s(p, GGEM_STAGE_INTERP);
     HIP_TRY(launch_interp<T>(p, (int)nt, out, dl, glob));
