@@ -1,25 +1,33 @@
 """Throughput of the GGEM slit evaluation on one MI355X.
 
-Workload (default): single layer on 50 capsule meshes (unit spheres, 642 nodes
-each, 32,100 nodal point forces, force-free per capsule) in a 20 x 10 x 20
-slit (walls at y = +-5), alpha = 2, r_c = 2, grid 128 x 128 Fourier x 65
-Chebyshev; targets = sources.  A step is one full evaluation (binning, local
-sum, wall data, spread, forward FFT + Chebyshev, tau solves, inverse
-transforms, interpolation) on inputs resident in device memory.
+Headline workload: the double layer (stresslet, traction n . sigma at the
+targets) on 400 capsule meshes -- unit spheres of 1,280 triangles with three
+interior Gauss points each, 1,536,000 point force-dipole strengths q times
+the Gauss weight, targets = sources with the triangles' outward normals --
+in a 40 x 12 x 40 slit (walls at y = +-6), alpha = 2, r_c = 2, grid
+256 x 256 Fourier x 65 Chebyshev.  A step is one full evaluation (binning,
+local sum, wall data and pressure gauge, spread, forward FFT + Chebyshev,
+tau solves, stress assembly, inverse transforms, interpolation) on inputs
+resident in device memory; the value is targets per second in mixed
+precision.
 
-Prints one JSON line: throughput in Mpoints/s (points = targets) for the
-mixed-precision path, with its error against the FP64 path on the same GPU,
-the FP64 path's throughput, the dominant kernel's roofline, the Fredholm
-solve time to a relative residual of 1e-6 on 100 drops in shear (plain and
-learned warm starts) and the CPU oracle timed on a bounded sample.
+The JSON line also carries: the FP64 path's throughput on the same GPU and
+the mixed path's error against it; the error of each path against FP64
+oracle values stored for 256 sampled targets (total, local and global
+parts); the dominant kernel's roofline (the local sum) with the spread's
+beside it; the CPU oracle timed on a bounded sample; and extra workloads --
+64 forces + 1,000 probes (microseconds per call), the 50-capsule single
+layer, the 48-instance batch replayed as one HIP graph, and the Fredholm
+solve time to a relative residual of 1e-6 on 100 drops in shear with and
+without the learned warm start.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import resource
+import statistics
 import sys
 import time
 
@@ -37,33 +45,47 @@ FLOP_NEAR_SL = 50.0
 FLOP_NEAR_DL = 65.0
 FLOP_SPREAD = 12.0
 
+METRIC = "GGEM Mpoints/s (mixed vs FP64, rel err 1e-5); Fredholm solve s to 1e-6"
+EXTRAS = ("small", "capsules_sl", "batched", "fredholm")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
-    ap.add_argument("--workload", choices=["capsules_sl", "capsules_dl", "batched"],
-                    default="capsules_sl")
+    ap.add_argument("--workload", choices=["capsules_dl", "capsules_sl", "batched"],
+                    default="capsules_dl")
+    ap.add_argument("--extras", default=",".join(EXTRAS),
+                    help="comma-separated extra workloads in the line: "
+                         f"{', '.join(EXTRAS)}, or 'none'")
     ap.add_argument("--branches", type=int, default=0,
                     help="streams of the batched workload (0: autotuned, cached on disk)")
     ap.add_argument("--roofline-stage", default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true",
+                    help="skip the FP64 comparison path (profiling runs)")
     ap.add_argument("--serialized", action="store_true",
                     help="time one evaluation captured into a HIP graph on a single stream "
                          "(no second stream: every kernel runs alone) and replayed; for "
                          "per-kernel profiles, not the headline figure")
-    ap.add_argument("--cpu-capsules", type=int, default=5)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB MiB device to device three times (a "
                          "plain copy of known size, to scale HBM counters)")
     ap.add_argument("--fredholm-steps", type=int, default=200,
-                    help="time steps of the drop run behind the Fredholm figures (0: skip)")
+                    help="time steps of the drop run behind the Fredholm figures")
     return ap.parse_args()
 
 
 def time_steps(plan, call, steps, warmup, stage=None):
+    """Mean ms per call over `steps` calls after `warmup`, and the mean
+    duration of `stage` from HIP events the library records around that
+    stage's launches on the stream it runs on."""
     import torch
     for _ in range(warmup):
         call()
@@ -92,10 +114,10 @@ def measured_traffic(stage, workload, precision):
     import hashlib
     try:
         with open(os.path.join(ROOT, "profiles", "traffic.json")) as fh:
-            ent = json.load(fh).get(stage)
+            ent = json.load(fh).get(f"{workload}:{stage}")
     except (OSError, ValueError):
         return None
-    if not ent or ent.get("workload") != workload or ent.get("precision") != precision:
+    if not ent or ent.get("precision") != precision:
         return None
     with open(os.path.join(ROOT, ent["source"]), "rb") as fh:
         if hashlib.sha256(fh.read()).hexdigest() != ent["sha256"]:
@@ -103,60 +125,266 @@ def measured_traffic(stage, workload, precision):
     return int(ent["bytes_per_launch"])
 
 
-def cpu_baseline(c, ncap):
-    """FP64 oracle on the first `ncap` capsules (same box and grid)."""
+def rel_l2(a, b):
+    import numpy as np
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def rel_max(a, b):
+    import numpy as np
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def golden(c):
+    """FP64 oracle values at 256 sampled targets (tests/golden), or None."""
+    path = os.path.join(ROOT, "tests", "golden", f"{c.name}_sampled.json")
+    try:
+        with open(path) as fh:
+            ref = json.load(fh)
+    except OSError:
+        return None
+    if ref.get("seed") != c.meta.get("seed") or ref.get("grid") != [c.Nx, c.Nz, c.Ny]:
+        return None
+    return ref
+
+
+def cpu_baseline(c, budget_targets=16, spread_sources=1000, interp_frac=0.01):
+    """The FP64 NumPy oracle timed stage by stage on a bounded sample of the
+    workload and extrapolated linearly to the whole of it: the local sum on
+    `budget_targets` seeded targets (brute force over all sources), the wall
+    data on as many wall nodes, the spread on `spread_sources` seeded
+    sources; the grid stages (forward transforms, per-mode solves, stress or
+    velocity assembly, inverse transforms) in full; the interpolation on a
+    seeded `interp_frac` of the targets."""
+    import numpy as np
+
     import oracle as O
-    nv = c.meta.get("nv") or c.meta.get("ng")
-    n = ncap * nv
+    from oracle import ggem as OG
     g = O.SlitGrid.from_case(c)
+    dl = c.normals is not None
+    rng = np.random.default_rng(17)
+    xs, xt = g.wrap(c.xs), g.wrap(c.xt)
+    q = np.asarray(c.f, dtype=np.float64)
+    times = {}
     r0 = resource.getrusage(resource.RUSAGE_SELF)
-    t0 = time.perf_counter()
-    if c.normals is None:
-        O.single_layer(g, c.xs[:n], c.f[:n], c.xt[:n])
+    w0 = time.perf_counter()
+
+    def clock(name, fn, scale):
+        t0 = time.perf_counter()
+        out = fn()
+        times[name] = (time.perf_counter() - t0) * scale
+        return out
+
+    sel = np.sort(rng.choice(c.nt, size=min(budget_targets, c.nt), replace=False))
+    if dl:
+        clock("local", lambda: OG.local_traction(g, xs, q, xt[sel], c.normals[sel]),
+              c.nt / sel.size)
     else:
-        O.double_layer(g, c.xs[:n], c.f[:n], c.xt[:n], c.normals[:n])
-    wall = time.perf_counter() - t0
+        clock("local", lambda: OG.local_velocity(g, xs, q, xt[sel]), c.nt / sel.size)
+    nwall = 2 * g.Nx * g.Nz
+    wsel = rng.choice(nwall, size=min(budget_targets, nwall), replace=False)
+    X, Z = np.meshgrid(g.x, g.z, indexing="ij")
+    wpts = np.concatenate([np.stack([X.ravel(), np.full(X.size, yw), Z.ravel()], axis=1)
+                           for yw in (-g.H, g.H)])
+    clock("wall", lambda: OG.local_velocity(g, xs, q, wpts[wsel]), nwall / wsel.size)
+    if dl:
+        clock("gauge", lambda: OG.pressure_gauge(g, xs, q), 1.0)
+    ssel = np.sort(rng.choice(c.ns, size=min(spread_sources, c.ns), replace=False))
+    F = clock("spread", lambda: OG.spread(g, xs[ssel], q[ssel]), c.ns / ssel.size)
+    Cf, Ci = OG.cheb_forward_matrix(g.Ny), OG.cheb_inverse_matrix(g.Ny)
+    D = OG.cheb_diff_matrix(g.Ny)
+    zw = np.zeros((3, g.Nx, g.Nz))
+
+    def forward():
+        return (OG._apply_y(Cf, OG.dft_xz(g, F)), OG.dft_xz(g, zw), OG.dft_xz(g, zw))
+
+    Fh, gm, gp = clock("fft_cheb_fwd", forward, 1.0)
+    u, v, w, p = clock("tau", lambda: OG.solve_modes(g, Fh, gm, gp, 0.0), 1.0)
+
+    def inverse():
+        if not dl:
+            return np.stack([OG.idft_xz(g, OG._apply_y(Ci, a)) for a in (u, v, w)])
+        ikx = 1j * g.kx[None, :, None]
+        ikz = 1j * g.kz[None, None, :]
+        dy = lambda a: OG._apply_y(D, a) / g.H  # noqa: E731
+        sig = (-p + 2.0 * ikx * u, -p + 2.0 * dy(v), -p + 2.0 * ikz * w,
+               dy(u) + ikx * v, ikz * u + ikx * w, ikz * v + dy(w))
+        return np.stack([OG.idft_xz(g, OG._apply_y(Ci, a)) for a in sig])
+
+    fields = clock("cheb_fft_inv", inverse, 1.0)
+    isel = np.sort(rng.choice(c.nt, size=max(1, int(interp_frac * c.nt)), replace=False))
+    clock("interp", lambda: OG.interpolate(g, fields, xt[isel]), c.nt / isel.size)
+    wall_s = time.perf_counter() - w0
     r1 = resource.getrusage(resource.RUSAGE_SELF)
-    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    cpu_s = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    total = sum(times.values())
     return {
-        "value": n / wall / 1e6,
+        "value": c.nt / total / 1e6,
         "unit": "Mpoints/s",
-        "cores": max(1, int(round(cpu / wall))),
+        "cores": max(1, int(round(cpu_s / wall_s))),
         "kind": "oracle",
-        "sample": f"{ncap} of {c.meta['ncap']} capsules ({n} points as sources and targets) on "
-                  f"the full {c.Nx}x{c.Nz}x{c.Ny} grid, FP64 NumPy oracle, wall {wall:.1f} s, "
-                  f"cpu {cpu:.1f} s",
+        "extrapolated": True,
+        "seconds_per_evaluation": round(total, 2),
+        "stage_seconds": {k: round(v, 3) for k, v in times.items()},
+        "sample": (f"FP64 NumPy oracle, stage by stage, extrapolated linearly to the whole "
+                   f"workload ({c.nt} targets, {c.ns} sources): local sum on {sel.size} seeded "
+                   f"targets and wall data on {wsel.size} of {nwall} wall nodes (brute force "
+                   f"over all sources), spread on {ssel.size} seeded sources, grid stages on the "
+                   f"full {c.Nx}x{c.Nz}x{c.Ny} grid, interpolation on {isel.size} targets; "
+                   f"wall {wall_s:.1f} s, cpu {cpu_s:.1f} s"),
     }
 
 
-def fredholm(steps):
-    """Seconds per Fredholm solve to 1e-6 on 100 drops in shear (64,200 nodes,
-    192,600 unknowns, 384,000 Gauss-point sources): the drop run, training of
-    the warm-start network on its first 3/4 and every start on the rest."""
-    from paper_1109_6587_amd.warmstart import run
-    from workloads import case_shear_drops
-    train = (3 * steps) // 4
-    res, _ = run(case_shear_drops(4), steps=steps, train_steps=train,
-                 log=lambda m: print(m, file=sys.stderr, flush=True))
-    st = res["starts"]
-    return {
-        "metric": "Fredholm solve s to 1e-6",
-        "value": round(st["learned_judged"]["seconds_mean"], 5),
-        "plain_warm_start_s": round(st["plain"]["seconds_mean"], 5),
-        "unit": "s",
-        "products": {k: v["products_mean"] for k, v in st.items()},
-        "seconds": {k: round(v["seconds_mean"], 5) for k, v in st.items()},
-        "speedup_learned_vs_plain": round(res["speedup_vs_plain"], 4),
-        "products_saved_per_solve": round(res["products_saved_per_solve"], 3),
-        "prediction_rel_err": round(res["prediction_rel_err_mean"], 4),
-        "workload": res["workload"], "unknowns": res["unknowns"], "sources": res["sources"],
-        "precision": res["precision"], "train_solves": res["train_solves"],
-        "test_solves": res["test_solves"], "simulation_s": res["simulation_s"],
-        "training_s": res["training_s"],
-    }
+def roofline_entry(stage, stage_ms, work_units, flop, peak, traffic):
+    ach = work_units * flop / (stage_ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(ach / peak, 4), "traffic": traffic, "kernel": stage,
+            "kernel_ms": round(stage_ms, 5), "work_units": int(work_units),
+            "flop_per_unit": flop}
 
 
-def bench_batched(args):
+def measure_case(c, args, precision, with_other=True, golden_parts=True):
+    """Mixed (or FP64) evaluation of one case: throughput, the roofline of
+    the local sum and of the spread, errors against the other precision and
+    against the stored oracle sample."""
+    import numpy as np
+    import torch
+
+    import paper_1109_6587_amd as G
+
+    dev = torch.device("cuda:0")
+    dl = c.normals is not None
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)  # noqa: E731
+    xs, f = t(c.xs), t(c.f)
+    # the capsule workloads evaluate at their own sources: passing the same
+    # array lets the library reuse the source binning for the targets
+    xt = xs if np.array_equal(c.xt, c.xs) else t(c.xt)
+    nrm = t(c.normals) if dl else None
+    out = torch.empty((c.nt, 3), dtype=torch.float64, device=dev)
+    other = "fp64" if precision == "mixed" else "mixed"
+    precs = (precision, other) if with_other else (precision,)
+    plans = {p: G.Plan.from_case(c, precision=p, sync_checks=False) for p in precs}
+
+    def caller(plan, parts=G.PART_ALL):
+        if dl:
+            return lambda: plan.double_layer(xs, f, xt, nrm, parts=parts, out=out)
+        return lambda: plan.single_layer(xs, f, xt, parts=parts, out=out)
+
+    res = {}
+    ref = golden(c)
+    outs = {}
+    for p in precs:
+        caller(plans[p])()
+        plans[p].status()
+        outs[p] = out.cpu().numpy()
+    if ref is not None:
+        sel = np.asarray(ref["targets"])
+        err = {}
+        for p in precs:
+            e = {"total": {"rel_l2": rel_l2(outs[p][sel], np.asarray(ref["total"])),
+                           "rel_max": rel_max(outs[p][sel], np.asarray(ref["total"]))}}
+            if golden_parts:
+                for key, parts in (("local", G.PART_LOCAL), ("global", G.PART_GLOBAL)):
+                    caller(plans[p], parts)()
+                    plans[p].status()
+                    o = out.cpu().numpy()[sel]
+                    e[key] = {"rel_l2": rel_l2(o, np.asarray(ref[key])),
+                              "rel_max": rel_max(o, np.asarray(ref[key]))}
+            err[p] = e
+        res["err_vs_oracle"] = {"targets": int(sel.size), "sample_seed": ref.get("sample_seed"),
+                                **err}
+    if with_other:
+        a, b = outs[precision], outs[other]
+        refv = outs["fp64"]
+        res["err_vs_fp64"] = {"rel_l2": float(np.linalg.norm(a - b) / np.linalg.norm(refv)),
+                              "rel_max": float(np.abs(a - b).max() / np.abs(refv).max())}
+
+    plan = plans[precision]
+    call = caller(plan)
+    call()
+    near_units, spread_units = plan.work()
+    stage = args.roofline_stage
+    if stage == "auto":
+        # the dominant of the two pair kernels, timed before the measured region
+        per = {}
+        for st in ("near", "spread"):
+            _, per[st] = time_steps(plan, call, 5, 1, stage=st)
+        stage = max(per, key=per.get)
+    side = "spread" if stage == "near" else "near"
+    ms, stage_ms = time_steps(plan, call, args.steps, args.warmup, stage=stage)
+    _, side_ms = time_steps(plan, call, max(5, args.steps // 2), 2, stage=side)
+    peak = PEAK_FP32_TFLOPS if precision == "mixed" else PEAK_FP64_TFLOPS
+    flop_near = FLOP_NEAR_DL if dl else FLOP_NEAR_SL
+    rl = {}
+    for st, sms in ((stage, stage_ms), (side, side_ms)):
+        units, flop = (near_units, flop_near) if st == "near" else (spread_units, FLOP_SPREAD)
+        rl[st] = roofline_entry(st, sms, units, flop, peak, measured_traffic(st, c.name, precision))
+    res.update(ms=ms, mpts=c.nt / (ms * 1e-3) / 1e6, stage=stage, roofline=rl[stage],
+               roofline_other=rl[side], work={"near_pairs": near_units,
+                                              "spread_updates": spread_units})
+    if with_other:
+        ms_o, _ = time_steps(plans[other], caller(plans[other]), max(5, args.steps // 2), 2)
+        res[f"{other}_ms_per_step"] = round(ms_o, 5)
+        res[f"{other}_mpoints_per_s"] = round(c.nt / (ms_o * 1e-3) / 1e6, 3)
+        fp64_ms = ms_o if other == "fp64" else ms
+        mixed_ms = ms if other == "fp64" else ms_o
+        res["speedup_mixed_vs_fp64"] = round(fp64_ms / mixed_ms, 3)
+    for p in plans.values():
+        p.close()
+    return res
+
+
+def extra_small(args):
+    """64 forces + 1,000 probes: microseconds per call (latency-bound)."""
+    import numpy as np
+    import torch
+
+    import paper_1109_6587_amd as G
+    from workloads import case_small_sl
+
+    c = case_small_sl(0)
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)  # noqa: E731
+    xs, f, xt = t(c.xs), t(c.f), t(c.xt)
+    out = torch.empty((c.nt, 3), dtype=torch.float64, device=dev)
+    res = {"workload": c.name, "targets": c.nt, "sources": c.ns, "grid": [c.Nx, c.Nz, c.Ny]}
+    ref = None
+    for p in ("fp64", "mixed"):
+        plan = G.Plan.from_case(c, precision=p, sync_checks=False)
+        call = lambda: plan.single_layer(xs, f, xt, out=out)  # noqa: E731
+        ms, _ = time_steps(plan, call, 200, 20)
+        lat = []
+        for _ in range(50):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            call()
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - t0) * 1e6)
+        o = out.cpu().numpy()
+        if p == "fp64":
+            ref = o
+        res[p] = {"us_per_call_back_to_back": round(ms * 1e3, 2),
+                  "us_per_call_synchronised_median": round(statistics.median(lat), 2)}
+        if p == "mixed":
+            res[p]["rel_l2_vs_fp64"] = rel_l2(o, ref)
+        plan.close()
+    return res
+
+
+def extra_capsules_sl(args):
+    from workloads import case_capsules_sl
+    c = case_capsules_sl(1)
+    r = measure_case(c, args, "mixed", with_other=True, golden_parts=False)
+    return {"workload": c.name, "points": c.nt, "grid": [c.Nx, c.Nz, c.Ny],
+            "mpoints_per_s": round(r["mpts"], 3), "ms_per_step": round(r["ms"], 5),
+            "fp64_mpoints_per_s": r.get("fp64_mpoints_per_s"),
+            "speedup_mixed_vs_fp64": r.get("speedup_mixed_vs_fp64"),
+            "err_vs_fp64": r.get("err_vs_fp64"), "err_vs_oracle": r.get("err_vs_oracle"),
+            "roofline": r["roofline"], "roofline_other": r["roofline_other"],
+            "work": r["work"]}
+
+
+def batched(args, steps):
     """48 independent instances (1.5M points) as one captured graph per step."""
     import numpy as np
     import torch
@@ -177,8 +405,7 @@ def bench_batched(args):
     if branches <= 0:
         from paper_1109_6587_amd.autotune import tune_batch
         branches, tuned_ms, cached = tune_batch(
-            cases, (so, xs, f, to, xs, out[args.precision]), precision=args.precision,
-            log=lambda m: print(m, file=sys.stderr, flush=True))
+            cases, (so, xs, f, to, xs, out[args.precision]), precision=args.precision, log=log)
     batches = {p: G.Batch(cases, precision=p, n_branches=branches) for p in out}
     for p, b in batches.items():
         b.capture(so, xs, f, to, xs, out[p])
@@ -186,164 +413,110 @@ def bench_batched(args):
         b.status()
     err = float(torch.linalg.norm(out["mixed"] - out["fp64"]) / torch.linalg.norm(out["fp64"]))
 
-    def timed(b, steps):
+    def timed(b, k):
         for _ in range(args.warmup):
             b.replay()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
+        for _ in range(k):
             b.replay()
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) * 1e3 / steps
+        return (time.perf_counter() - t0) * 1e3 / k
 
     prec = args.precision
     other = "fp64" if prec == "mixed" else "mixed"
-    ms = timed(batches[prec], args.steps)
-    ms_other = timed(batches[other], max(10, args.steps // 4))
+    ms = timed(batches[prec], steps)
+    ms_other = timed(batches[other], max(5, steps // 2))
     batches[prec].status()
-    # eager submission of the same batch, for the graph's launch saving
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(10):
+    for _ in range(5):
         batches[prec].single_layer(so, xs, f, to, xs, out[prec])
     torch.cuda.synchronize()
-    ms_eager = (time.perf_counter() - t0) * 1e3 / 10
-    line = {
-        "metric": "GGEM Mpoints/s (mixed vs FP64, rel err 1e-5); Fredholm solve s to 1e-6",
-        "value": round(n / (ms * 1e-3) / 1e6, 3), "unit": "Mpoints/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64" if prec == "mixed" else "f64", "data": "synthetic",
-        "config": {"workload": "batched_48", "instances": len(cases), "points": n,
-                   "precision": prec, "branches": branches, "submission": "hip graph"},
-        "autotune": {"ms_by_branches": tuned_ms, "from_cache": cached},
-        "err_vs_fp64": {"rel_l2": err},
-        f"{other}_ms_per_step": round(ms_other, 5),
-        "eager_ms_per_step": round(ms_eager, 5),
-        "roofline": None,
+    ms_eager = (time.perf_counter() - t0) * 1e3 / 5
+    for b in batches.values():
+        b.close()
+    return {"workload": "batched_48", "instances": len(cases), "points": n, "precision": prec,
+            "branches": branches, "submission": "hip graph",
+            "mpoints_per_s": round(n / (ms * 1e-3) / 1e6, 3), "ms_per_step": round(ms, 5),
+            f"{other}_ms_per_step": round(ms_other, 5), "eager_ms_per_step": round(ms_eager, 5),
+            "err_vs_fp64": {"rel_l2": err},
+            "autotune": {"ms_by_branches": tuned_ms, "from_cache": cached}}
+
+
+def fredholm(steps):
+    """Seconds per Fredholm solve to 1e-6 on 100 drops in shear (64,200 nodes,
+    192,600 unknowns, 384,000 Gauss-point sources): the drop run, training of
+    the warm-start network on its first 3/4 and every start on the rest."""
+    from paper_1109_6587_amd.warmstart import run
+    from workloads import case_shear_drops
+    train = (3 * steps) // 4
+    res, _ = run(case_shear_drops(4), steps=steps, train_steps=train, log=log)
+    st = res["starts"]
+    return {
+        "metric": "Fredholm solve s to 1e-6",
+        "value": round(st["learned_judged"]["seconds_mean"], 5),
+        "plain_warm_start_s": round(st["plain"]["seconds_mean"], 5),
+        "unit": "s",
+        "products": {k: v["products_mean"] for k, v in st.items()},
+        "seconds": {k: round(v["seconds_mean"], 5) for k, v in st.items()},
+        "speedup_learned_vs_plain": round(res["speedup_vs_plain"], 4),
+        "products_saved_per_solve": round(res["products_saved_per_solve"], 3),
+        "prediction_rel_err": round(res["prediction_rel_err_mean"], 4),
+        "workload": res["workload"], "unknowns": res["unknowns"], "sources": res["sources"],
+        "precision": res["precision"], "train_solves": res["train_solves"],
+        "test_solves": res["test_solves"], "simulation_s": res["simulation_s"],
+        "training_s": res["training_s"],
     }
-    print(json.dumps(line))
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "design is described but not built", file=sys.stderr)
-        sys.exit(2)
-    if args.workload == "batched":
-        bench_batched(args)
-    else:
-        bench_single(args)
-    if args.calibrate_copy > 0:
-        import torch
-        n = args.calibrate_copy * (1 << 20)
-        src = torch.ones(n, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(f"calibration: copied {n} bytes three times", file=sys.stderr)
+def base_line(args, value, ms, dtype, config):
+    return {
+        "metric": METRIC, "value": round(value, 3), "unit": "Mpoints/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+        "data": "synthetic", "config": config,
+    }
 
 
 def bench_single(args):
+    from workloads import case_capsules_dl, case_capsules_sl
+
+    c = case_capsules_sl(1) if args.workload == "capsules_sl" else case_capsules_dl(2)
+    dl = c.normals is not None
+    log(f"workload {c.name}: {c.nt} targets, grid {c.Nx}x{c.Nz}x{c.Ny}, {args.precision}")
+    if args.serialized:
+        return bench_serialized(args, c)
+    r = measure_case(c, args, args.precision, with_other=not args.no_fp64)
+    config = {"workload": c.name, "points": c.nt, "sources": c.ns,
+              "grid": [c.Nx, c.Nz, c.Ny], "alpha": c.alpha, "rc": c.rc,
+              "box": [c.Lx, 2 * c.H, c.Lz], "precision": args.precision,
+              "layer": "double" if dl else "single"}
+    line = base_line(args, r["mpts"], r["ms"], "f32+f64" if args.precision == "mixed" else "f64",
+                     config)
+    for k in ("err_vs_oracle", "err_vs_fp64", "fp64_ms_per_step", "fp64_mpoints_per_s",
+              "mixed_ms_per_step", "mixed_mpoints_per_s", "speedup_mixed_vs_fp64", "work",
+              "roofline_other"):
+        if k in r:
+            line[k] = r[k]
+    line["roofline"] = r["roofline"]
+    return c, line
+
+
+def bench_serialized(args, c):
     import numpy as np
     import torch
 
     import paper_1109_6587_amd as G
-    from workloads import case_capsules_dl, case_capsules_sl
-
     dev = torch.device("cuda:0")
-    c = case_capsules_sl(1) if args.workload == "capsules_sl" else case_capsules_dl(2)
     dl = c.normals is not None
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)  # noqa: E731
     xs, f = t(c.xs), t(c.f)
-    # the capsule workloads evaluate at their own sources: passing the same
-    # array lets the library reuse the source binning for the targets
-    xt = xs if np.array_equal(c.xt, c.xs) else t(c.xt)
     nrm = t(c.normals) if dl else None
     out = torch.empty((c.nt, 3), dtype=torch.float64, device=dev)
-
-    plans = {p: G.Plan.from_case(c, precision=p, sync_checks=False) for p in ("mixed", "fp64")}
-
-    def caller(plan):
-        if dl:
-            return lambda: plan.double_layer(xs, f, xt, nrm, out=out)
-        return lambda: plan.single_layer(xs, f, xt, out=out)
-
-    # accuracy of the mixed path against the FP64 path (same inputs)
-    caller(plans["fp64"])()
-    ref = out.clone()
-    caller(plans["mixed"])()
-    torch.cuda.synchronize()
-    err_l2 = float(torch.linalg.norm(out - ref) / torch.linalg.norm(ref))
-    err_max = float((out - ref).abs().max() / ref.abs().max())
-
-    plan = plans[args.precision]
-    if args.serialized:
-        return bench_serialized(args, c, plan, caller(plan), err_l2, err_max)
-    caller(plan)()
-    near_pairs, spread_pairs = plan.work()
-    stage = args.roofline_stage
-    if stage == "auto":
-        # the dominant of the two pair kernels, timed before the measured region
-        per = {}
-        for st in ("near", "spread"):
-            _, per[st] = time_steps(plan, caller(plan), 10, 2, stage=st)
-        stage = max(per, key=per.get)
-    ms, stage_ms = time_steps(plan, caller(plan), args.steps, args.warmup, stage=stage)
-    other = "fp64" if args.precision == "mixed" else "mixed"
-    ms_other, _ = time_steps(plans[other], caller(plans[other]), max(10, args.steps // 4),
-                             args.warmup)
-    value = c.nt / (ms * 1e-3) / 1e6
-
-    if stage == "near":
-        flops = near_pairs * (FLOP_NEAR_DL if dl else FLOP_NEAR_SL)
-    elif stage == "spread":
-        flops = spread_pairs * FLOP_SPREAD
-    else:
-        flops = None
-    peak = PEAK_FP32_TFLOPS if args.precision == "mixed" else PEAK_FP64_TFLOPS
-    roof = None
-    if flops is not None and stage_ms:
-        ach = flops / (stage_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(ach / peak, 4),
-                "traffic": measured_traffic(stage, c.name, args.precision), "kernel": stage,
-                "kernel_ms": round(stage_ms, 5), "work_units": near_pairs if stage == "near" else spread_pairs}
-
-    line = {
-        "metric": "GGEM Mpoints/s (mixed vs FP64, rel err 1e-5); Fredholm solve s to 1e-6",
-        "value": round(value, 3),
-        "unit": "Mpoints/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms, 5),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64" if args.precision == "mixed" else "f64",
-        "data": "synthetic",
-        "config": {"workload": c.name, "points": c.nt, "sources": c.ns,
-                   "grid": [c.Nx, c.Nz, c.Ny], "alpha": c.alpha, "rc": c.rc,
-                   "box": [c.Lx, 2 * c.H, c.Lz], "precision": args.precision,
-                   "layer": "double" if dl else "single"},
-        "err_vs_fp64": {"rel_l2": err_l2, "rel_max": err_max},
-        f"{other}_mpoints_per_s": round(c.nt / (ms_other * 1e-3) / 1e6, 3),
-        f"{other}_ms_per_step": round(ms_other, 5),
-        "work": {"near_pairs": near_pairs, "spread_updates": spread_pairs},
-        "roofline": roof,
-    }
-    if args.fredholm_steps > 0:
-        line["fredholm"] = fredholm(args.fredholm_steps)
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(c, args.cpu_capsules)
-    print(json.dumps(line))
-
-
-def bench_serialized(args, c, plan, call, err_l2, err_max):
-    import torch
+    plan = G.Plan.from_case(c, precision=args.precision, sync_checks=False)
+    call = ((lambda: plan.double_layer(xs, f, xs, nrm, out=out)) if dl
+            else (lambda: plan.single_layer(xs, f, xs, out=out)))
     s = torch.cuda.Stream()
     plan.set_stream(s)
     with torch.cuda.stream(s):
@@ -361,15 +534,64 @@ def bench_serialized(args, c, plan, call, err_l2, err_max):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) / args.steps * 1e3
     plan.status()
-    print(json.dumps({
-        "metric": "GGEM Mpoints/s, one evaluation per graph replay on a single stream",
-        "value": round(c.nt / (ms * 1e-3) / 1e6, 3), "unit": "Mpoints/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64" if args.precision == "mixed" else "f64", "data": "synthetic",
-        "config": {"workload": c.name, "points": c.nt, "grid": [c.Nx, c.Nz, c.Ny],
-                   "precision": args.precision, "mode": "serialized graph"},
-        "err_vs_fp64": {"rel_l2": err_l2, "rel_max": err_max}}))
+    line = base_line(args, c.nt / (ms * 1e-3) / 1e6, ms,
+                     "f32+f64" if args.precision == "mixed" else "f64",
+                     {"workload": c.name, "points": c.nt, "grid": [c.Nx, c.Nz, c.Ny],
+                      "precision": args.precision, "mode": "serialized graph"})
+    line["metric"] = "GGEM Mpoints/s, one evaluation per graph replay on a single stream"
+    line["roofline"] = None
+    return c, line
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "design is described but not built", file=sys.stderr)
+        sys.exit(2)
+    extras = [] if args.extras in ("", "none") else args.extras.split(",")
+    for e in extras:
+        if e not in EXTRAS:
+            print(f"unknown extra workload {e!r}", file=sys.stderr)
+            sys.exit(2)
+    if args.workload == "batched":
+        r = batched(args, args.steps)
+        line = base_line(args, r["mpoints_per_s"], r["ms_per_step"],
+                         "f32+f64" if args.precision == "mixed" else "f64",
+                         {"workload": "batched_48", "instances": r["instances"],
+                          "points": r["points"], "precision": args.precision,
+                          "branches": r["branches"], "submission": "hip graph"})
+        line.update({k: v for k, v in r.items() if k not in line and k != "config"})
+        line["roofline"] = None
+        print(json.dumps(line), flush=True)
+        return
+    c, line = bench_single(args)
+    if not args.serialized:
+        if "small" in extras:
+            log("extra: small_sl_64")
+            line["small_sl_64"] = extra_small(args)
+        if "capsules_sl" in extras:
+            log("extra: capsules_sl_50x642")
+            line["capsules_sl_50x642"] = extra_capsules_sl(args)
+        if "batched" in extras:
+            log("extra: batched_48")
+            line["batched_48"] = batched(args, args.steps)
+        if "fredholm" in extras:
+            log("extra: fredholm")
+            line["fredholm"] = fredholm(args.fredholm_steps)
+        if not args.no_cpu_baseline:
+            log("cpu baseline (oracle)")
+            line["cpu_baseline"] = cpu_baseline(c)
+    print(json.dumps(line), flush=True)
+    if args.calibrate_copy > 0:
+        import torch
+        n = args.calibrate_copy * (1 << 20)
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration: copied {n} bytes three times")
 
 
 if __name__ == "__main__":
