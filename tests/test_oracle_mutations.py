@@ -1,0 +1,143 @@
+"""Mutation check of the oracle's pins (CPU).
+
+Each case plants one plausible mistake in a copy of an oracle module (a
+sign, a dropped term, a transposed operand, a wrong index, a missing 1/H, a
+wrong scale factor), swaps the copy in for the oracle, and runs the pins of
+tests/test_oracle_*.py against it: at least one must fail.  The unmutated oracle passes the same
+checks (control), so a failure is the mutation's doing.
+"""
+import types
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle.fredholm
+import oracle.ggem
+import oracle.surface
+import test_oracle_invariants as INV
+import test_oracle_kernels as KER
+import test_oracle_physics as PHY
+import test_oracle_spectral as SPE
+
+pytestmark = pytest.mark.slow
+
+MUTATIONS = {
+    "Fredholm operator scale (kappa instead of 2 kappa)": ("fredholm",
+        "return x + 2.0 * k * v",
+        "return x + k * v"),
+    "surface velocity scale (4 pi instead of 8 pi)": ("surface",
+        "u = 8.0 * np.pi * single_layer(",
+        "u = 4.0 * np.pi * single_layer("),
+    "pressure equation sign": ("ggem",
+        "divF = ikx * fx + (fy @ D.T) / H + ikz * fz",
+        "divF = -(ikx * fx + (fy @ D.T) / H + ikz * fz)"),
+    "dropped pressure gauge": ("ggem",
+        "gauge = pressure_gauge(g, xs, f) if stress else 0.0",
+        "gauge = 0.0"),
+    "dropped self term": ("ggem",
+        "self_coef = -(4.0 * g.alpha / SQRT_PI) * INV_8PI",
+        "self_coef = 0.0"),
+    "transposed Chebyshev operand": ("ggem",
+        'return np.einsum("nj,...jab->...nab", M, a)',
+        'return np.einsum("jn,...jab->...nab", M, a)'),
+    "wrong wavenumber in sigma_xy": ("ggem",
+        "dy(u) + ikx * v,",
+        "dy(u) + ikz * v,"),
+    "dropped Gaussian term of G^l": ("ggem",
+        "- (2.0 * alpha / SQRT_PI) * (I - dd / r2[..., None, None]) * ex[..., None, None])",
+        "- 0.0 * (I - dd / r2[..., None, None]) * ex[..., None, None])"),
+    "wall data sign": ("ggem",
+        "out.append(-ul.T.reshape(3, g.Nx, g.Nz))",
+        "out.append(ul.T.reshape(3, g.Nx, g.Nz))"),
+    "k = 0 pressure without 1/H": ("ggem",
+        "A[:N] = D[:N] / H",
+        "A[:N] = D[:N]"),
+    "stresslet B term sign": ("ggem",
+        "+ 4.0 * alpha ** 3 / SQRT_PI * (dI - 2.0 * ddd / e(r2)) * e(ex))",
+        "- 4.0 * alpha ** 3 / SQRT_PI * (dI - 2.0 * ddd / e(r2)) * e(ex))"),
+    "index of the Lagrange stencil in y": ("ggem",
+        "wy = _lagrange(xt[:, 1], g.y[jj])",
+        "wy = _lagrange(xt[:, 1], g.y[jj[:, ::-1]])"),
+}
+
+
+def mutant(module, old, new):
+    with open(getattr(oracle, module).__file__) as fh:
+        src = fh.read()
+    assert src.count(old) == 1, old
+    src = src.replace(old, new).replace("from .", "from oracle.")
+    mod = types.ModuleType(f"oracle_{module}_mutant")
+    exec(compile(src, f"oracle_{module}_mutant", "exec"), mod.__dict__)
+    return mod
+
+
+def install(monkeypatch, mod):
+    """Point the oracle package (and the modules that import from it) at `mod`."""
+    for name, val in vars(mod).items():
+        if name.startswith("__") or not callable(val) and not isinstance(val, (int, float)):
+            continue
+        for target in (oracle.ggem, oracle, oracle.fredholm, oracle.surface):
+            if hasattr(target, name):
+                monkeypatch.setattr(target, name, val)
+
+
+def alpha_independence():
+    """SL with self pairs and DL at mesh nodes, alpha 4 vs 5 (r_c = 6/alpha)."""
+    rng = np.random.default_rng(5)
+    L, H, N, Ny = 3.2, 1.2, 48, 65
+    g0 = oracle.SlitGrid(L, L, H, 4.0, 1.5, N, N, Ny)
+    xs = np.stack([rng.uniform(0, L, 4), rng.uniform(-0.8, 0.8, 4), rng.uniform(0, L, 4)], 1)
+    xs[:2] = [[g0.x[9], g0.y[30], g0.z[40]], [g0.x[40], g0.y[20], g0.z[3]]]
+    f = rng.standard_normal((4, 3))
+    j, i, k = rng.integers(0, Ny, 20), rng.integers(0, N, 20), rng.integers(0, N, 20)
+    xt = np.vstack([np.stack([g0.x[i], g0.y[j], g0.z[k]], 1), xs[:2]])
+    nrm = rng.standard_normal(xt.shape)
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    res = []
+    for a in (4.0, 5.0):
+        g = oracle.SlitGrid(L, L, H, a, 6.0 / a, N, N, Ny)
+        res.append((oracle.single_layer(g, xs, f, xt), oracle.double_layer(g, xs, f, xt, nrm)))
+    for q in range(2):
+        a, b = res[0][q], res[1][q]
+        assert np.abs(a - b).max() < 1e-8 * np.abs(a).max()
+
+
+def interpolation_of_polynomials():
+    SPE.test_interpolation_reproduces_polynomials(np.random.default_rng(7))
+
+
+# cheapest first: a mutant stops at the first pin that fails
+CHECKS = [
+    ("G^l is Stokes flow", lambda: KER.test_local_pair_is_stokes_flow(0)),
+    ("T^l is the Newtonian stress", lambda: KER.test_stresslet_is_newtonian_stress(3)),
+    ("manufactured Stokes mode", lambda: SPE.test_stokes_mode_manufactured((3, 1), np.random.default_rng(1))),
+    ("manufactured zero mode", lambda: SPE.test_stokes_zero_mode_manufactured(np.random.default_rng(2))),
+    ("Lagrange interpolation", interpolation_of_polynomials),
+    ("no-slip", lambda: INV.test_no_slip_at_walls(np.random.default_rng(12345))),
+    ("alpha independence", alpha_independence),
+    ("wall force balance", PHY.test_wall_force_balance),
+    ("Fredholm operator on q = n", PHY.test_fredholm_uniform_normal_density),
+    ("surface velocity of a uniform density", PHY.test_surface_velocity_uniform_density_translates_sphere),
+]
+
+
+def first_failure():
+    for name, check in CHECKS:
+        try:
+            check()
+        except AssertionError:
+            return name
+    return None
+
+
+def test_control_passes_every_check():
+    assert first_failure() is None
+
+
+@pytest.mark.parametrize("mutation", sorted(MUTATIONS))
+def test_mutation_is_caught(mutation, monkeypatch):
+    install(monkeypatch, mutant(*MUTATIONS[mutation]))
+    caught = first_failure()
+    print(f"{mutation}: caught by {caught}")
+    assert caught is not None, f"no pin fails for: {mutation}"
