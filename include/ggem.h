@@ -115,6 +115,26 @@ int ggem_double_layer(ggem_plan_t plan, long long ns, const double* xs, const do
                       long long nt, const double* xt, const double* nrm, double* v,
                       int parts);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc: serving loops, harnesses that forbid allocation): the single
+ * layer of ggem_single_layer (parts = ALL) without a plan object.  The
+ * workspace is a static device array of 64 MiB per GPU, held by the library
+ * until the process ends; params describe the problem as for
+ * ggem_plan_create (max_src/max_tgt give the capacities the workspace is laid
+ * out for).  The first call on a device, and every call whose params differ
+ * from the previous call's on that device, recomputes the plan constants into
+ * the array (host work and synchronous copies; no allocation); calls with
+ * the same params only enqueue the evaluation on hip_stream, on that one
+ * stream (no second stream).  All calls on one GPU share its array, which
+ * keeps the last call's contents: calls that overlap on one GPU (from two
+ * threads, or on two streams whose work overlaps) race and give wrong
+ * results.  Errors: as ggem_single_layer, plus GGEM_E_CAPACITY when the
+ * workspace for these params exceeds the 64 MiB array (e.g. a 64x64x33 grid
+ * with 2^17 sources and targets fits; a 128x128x65 grid does not). */
+int ggem_single_layer_noalloc(const ggem_params* params, void* hip_stream, long long ns,
+                              const double* xs, const double* f, long long nt, const double* xt,
+                              double* u);
+
 /* Diagnostic: the global force density of Sec. 3.2.2 on the grid,
  *   F(node) = sum_s f_s rho_g(node - x_s)   over |node - x_s| <= rc,
  * written as float64 (3, Ny, Nx, Nz) with y_j = H cos(pi j/(Ny-1)),

@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -58,30 +59,96 @@ bool factor_radices(int n, int* r, int* nr) {
   return n == 1;
 }
 
-template <typename T>
-bool dev_alloc(T** ptr, size_t count) {
-  if (count == 0) count = 1;
-  return hipMalloc((void**)ptr, count * sizeof(T)) == hipSuccess;
+// Sub-allocation of a plan's device workspace from one block: every buffer
+// starts on a 256-byte boundary.  With base == nullptr only the size is
+// computed (the pointers stay null).
+struct Carver {
+  char* base;
+  size_t off;
+  void* take_bytes(size_t bytes) {
+    off = (off + 255) & ~(size_t)255;
+    void* r = base ? (void*)(base + off) : nullptr;
+    off += bytes ? bytes : 1;
+    return r;
+  }
+  template <typename T>
+  T* take(size_t n) {
+    return (T*)take_bytes((n ? n : 1) * sizeof(T));
+  }
+};
+
+// The same for the host arrays the plan constants are computed in.
+struct HostStage {
+  char* base;
+  size_t off, cap;
+  template <typename T>
+  T* take(size_t n) {
+    off = (off + 63) & ~(size_t)63;
+    T* r = (base && off + n * sizeof(T) <= cap) ? (T*)(base + off) : nullptr;
+    off += (n ? n : 1) * sizeof(T);
+    return r;
+  }
+};
+
+void carve_binned(Carver& c, Binned& b, long long cap, const CellGeom& g, size_t elt) {
+  const size_t nch = kMaxChunks + 1;
+  const size_t nb = (size_t)g.nbuckets, ncells = (size_t)g.ncells;
+  const size_t n = (size_t)(cap > 0 ? cap : 1);
+  b.keys = c.take<int>(n);
+  b.counts = c.take<int>(nb * (nch + 1));
+  b.offs = c.take<int>(nb * (nch + 1));
+  b.sub_start = c.take<int>(nb + 1);
+  b.cell_start = c.take<int>(ncells + 1);
+  b.cflags = c.take<unsigned>(kMaxChunks + 1);
+  b.item_start = c.take<int>(ncells + 1);
+  b.item_cell = c.take<int>(n / kNearBlock + ncells + 1);
+  b.perm = c.take<int>(n);
+  b.x = c.take<double>(n);
+  b.y = c.take<double>(n);
+  b.z = c.take<double>(n);
+  b.s = c.take_bytes(3 * n * elt);
+}
+
+// Every device buffer of a plan, in one layout shared by ggem_plan_create
+// (one hipMalloc) and ggem_single_layer_noalloc (the static scratch array).
+void layout_plan(Plan& p, Carver& c) {
+  const ggem_params& q = p.p;
+  const size_t elt = p.fp64 ? 8 : 4;
+  const size_t Ny = q.Ny, Nx = q.Nx, Nz = q.Nz, nm = (size_t)p.nmodes;
+  const size_t MP = ((q.Ny + 15) / 16) * 16, KP = ((q.Ny + 3) / 4) * 4;
+  const size_t mt = (size_t)(q.max_tgt > 0 ? q.max_tgt : 1);
+  p.y = c.take<double>(Ny);
+  p.cf64 = c.take<double>(MP * KP);
+  p.ci64 = c.take<double>(MP * KP);
+  p.cf32 = c.take<float>(MP * KP);
+  p.ci32 = c.take<float>(MP * KP);
+  p.twx = c.take_bytes(2 * Nx * elt);
+  p.twz = c.take_bytes(2 * Nz * elt);
+  p.infl = c.take<double>(4 * nm);
+  p.nconst = c.take<double>(3 * Ny);
+  p.sweep = c.take<double>((6 * Ny + 2) * nm);
+  p.ul = c.take_bytes(kNearSlices * 3 * mt * elt);
+  p.phys = c.take_bytes(6 * Ny * Nx * Nz * elt);
+  p.specA = c.take_bytes(6 * Ny * nm * 2 * elt);
+  p.specB = c.take_bytes(6 * Ny * nm * 2 * elt);
+  p.wall_phys = c.take_bytes(6 * Nx * Nz * elt);
+  p.wall_part = c.take_bytes(kWallSlices * 6 * Nx * Nz * elt);
+  p.wall_spec = c.take_bytes(6 * nm * 2 * elt);
+  p.tau_scr = c.take<double>(2 * 9 * Ny * nm);
+  p.gauge = c.take<double>((size_t)(q.max_src / 256 + 4));
+  p.flags = c.take<unsigned>(1);
+  p.work = c.take<unsigned long long>(2);
+  p.wall_pos = c.take<double>(3 * 2 * Nx * Nz);
+  carve_binned(c, p.src, q.max_src, p.cg, elt);
+  carve_binned(c, p.tgt, q.max_tgt, p.cg, elt);
+  carve_binned(c, p.wall, 2LL * q.Nx * q.Nz, p.cg, elt);
 }
 
 void free_plan(Plan& p) {
-  void* ptrs[] = {p.y,         p.cf64,        p.ci64,        p.cf32,       p.ci32,
-                  p.twx,       p.twz,         p.infl,        p.ul,         p.phys,
-                  p.specA,     p.specB,       p.wall_phys,   p.wall_spec,  p.tau_scr,
-                  p.gauge,     p.flags,       p.item_count,  p.src.keys,   p.src.counts,
-                  p.src.offs,  p.src.cell_start, p.src.item_start, p.src.perm, p.src.x,
-                  p.src.sub_start, p.tgt.sub_start, p.wall.sub_start,
-                  p.src.cflags, p.tgt.cflags, p.wall.cflags,
-                  p.src.item_cell, p.tgt.item_cell, p.wall.item_cell,
-                  p.src.y,     p.src.z,       p.src.s,       p.tgt.keys,   p.tgt.counts,
-                  p.tgt.offs,  p.tgt.cell_start, p.tgt.item_start, p.tgt.perm, p.tgt.x,
-                  p.tgt.y,     p.tgt.z,       p.tgt.s,       p.nconst,     p.sweep,
-                  p.wall.keys, p.wall.counts, p.wall.offs,   p.wall.cell_start,
-                  p.wall.item_start, p.wall.perm, p.wall.x,  p.wall.y,     p.wall.z,
-                  p.wall.s,    p.work,        p.wall_part};
-  for (void* q : ptrs)
-    if (q) (void)hipFree(q);
-  if (p.flags_host) (void)hipHostFree(p.flags_host);
+  if (p.block && p.owns_block) (void)hipFree(p.block);
+  p.block = nullptr;
+  if (p.flags_host && p.owns_flags_host) (void)hipHostFree(p.flags_host);
+  p.flags_host = nullptr;
   if (p.side) (void)hipStreamDestroy(p.side);
   hipEvent_t evs[] = {p.ev_fork, p.ev_wall, p.ev_near};
   for (hipEvent_t e : evs)
@@ -91,29 +158,6 @@ void free_plan(Plan& p) {
     delete[] p.timed_ev;
     p.timed_ev = nullptr;
   }
-}
-
-bool alloc_binned(Binned& b, long long cap, const CellGeom& g, size_t elt) {
-  const long long nch = kMaxChunks + 1;
-  const int ncells = g.ncells, nb = g.nbuckets;
-  return dev_alloc(&b.keys, (size_t)cap) && dev_alloc(&b.counts, (size_t)nb * (nch + 1)) &&
-         dev_alloc(&b.offs, (size_t)nb * (nch + 1)) && dev_alloc(&b.sub_start, nb + 1) &&
-         dev_alloc(&b.cell_start, ncells + 1) && dev_alloc(&b.cflags, kMaxChunks + 1) &&
-         dev_alloc(&b.item_start, ncells + 1) &&
-         dev_alloc(&b.item_cell, (size_t)(cap / kNearBlock) + ncells + 1) &&
-         dev_alloc(&b.perm, (size_t)cap) &&
-         dev_alloc(&b.x, (size_t)cap) && dev_alloc(&b.y, (size_t)cap) &&
-         dev_alloc(&b.z, (size_t)cap) &&
-         hipMalloc(&b.s, (size_t)(3 * (cap > 0 ? cap : 1)) * elt) == hipSuccess;
-}
-
-// padded (MP x KP) copy of an (Ny x Ny) matrix
-template <typename T>
-std::vector<T> padded(const std::vector<double>& a, int Ny, int MP, int KP) {
-  std::vector<T> o((size_t)MP * KP, (T)0);
-  for (int r = 0; r < Ny; ++r)
-    for (int c = 0; c < Ny; ++c) o[(size_t)r * KP + c] = (T)a[(size_t)r * Ny + c];
-  return o;
 }
 
 // cos(pi * m / N) with the argument reduced exactly (m integer)
@@ -140,31 +184,48 @@ __global__ void fill_zero(T* p, size_t n) {
   if (i < n) p[i] = (T)0;
 }
 
-int plan_constants(Plan& p) {
+// Host arrays of the plan constants, carved from `hs` (a sizing pass with
+// hs.base == nullptr gives the bytes needed; GGEM_E_CAPACITY when they do
+// not fit).  Then copies them to the device, derives the per-mode tau
+// factors and influence matrices, and bins the wall nodes, all on p.stream.
+int plan_constants(Plan& p, HostStage& hs) {
   const int Ny = p.p.Ny, N = Ny - 1, Nx = p.p.Nx, Nz = p.p.Nz;
-  std::vector<double> y(Ny);
+  const int MP = ((Ny + 15) / 16) * 16, KP = ((Ny + 3) / 4) * 4;
+  const size_t nw = 2 * (size_t)Nx * Nz;
+  double* y = hs.take<double>(Ny);
+  double* cf64 = hs.take<double>((size_t)MP * KP);
+  double* ci64 = hs.take<double>((size_t)MP * KP);
+  float* cf32 = hs.take<float>((size_t)MP * KP);
+  float* ci32 = hs.take<float>((size_t)MP * KP);
+  double* tw = hs.take<double>(2 * (size_t)(Nx > Nz ? Nx : Nz));
+  float* tf = hs.take<float>(2 * (size_t)(Nx > Nz ? Nx : Nz));
+  double* nc = hs.take<double>(3 * (size_t)Ny);
+  double* wpos = hs.take<double>(3 * nw);
+  if (!hs.base) return GGEM_OK;  // sizing pass
+  if (hs.off > hs.cap || !wpos) return fail(GGEM_E_CAPACITY, "host staging of the plan constants too small");
   for (int j = 0; j < Ny; ++j) y[j] = p.p.H * cospi_frac(j, N);
-  HIP_TRY(hipMemcpy(p.y, y.data(), Ny * sizeof(double), hipMemcpyHostToDevice));
-  std::vector<double> cf((size_t)Ny * Ny), ci((size_t)Ny * Ny);
+  HIP_TRY(hipMemcpy(p.y, y, Ny * sizeof(double), hipMemcpyHostToDevice));
   const double norm = 1.0 / ((double)Nx * (double)Nz);
+  for (size_t i = 0; i < (size_t)MP * KP; ++i) cf64[i] = ci64[i] = 0.0;
   for (int n = 0; n < Ny; ++n)
     for (int j = 0; j < Ny; ++j) {
       const double cbn = (n == 0 || n == N) ? 2.0 : 1.0;
       const double cbj = (j == 0 || j == N) ? 2.0 : 1.0;
       const double c = cospi_frac((long)n * j, N);
-      cf[(size_t)n * Ny + j] = 2.0 / (N * cbn * cbj) * c * norm;
-      ci[(size_t)j * Ny + n] = c;
+      // padded (MP x KP) row-major copies of the (Ny x Ny) matrices
+      cf64[(size_t)n * KP + j] = 2.0 / (N * cbn * cbj) * c * norm;
+      ci64[(size_t)j * KP + n] = c;
     }
-  const int MP = ((Ny + 15) / 16) * 16, KP = ((Ny + 3) / 4) * 4;
-  auto cf64 = padded<double>(cf, Ny, MP, KP), ci64 = padded<double>(ci, Ny, MP, KP);
-  auto cf32 = padded<float>(cf, Ny, MP, KP), ci32 = padded<float>(ci, Ny, MP, KP);
-  HIP_TRY(hipMemcpy(p.cf64, cf64.data(), cf64.size() * 8, hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(p.ci64, ci64.data(), ci64.size() * 8, hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(p.cf32, cf32.data(), cf32.size() * 4, hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(p.ci32, ci32.data(), ci32.size() * 4, hipMemcpyHostToDevice));
+  for (size_t i = 0; i < (size_t)MP * KP; ++i) {
+    cf32[i] = (float)cf64[i];
+    ci32[i] = (float)ci64[i];
+  }
+  HIP_TRY(hipMemcpy(p.cf64, cf64, (size_t)MP * KP * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p.ci64, ci64, (size_t)MP * KP * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p.cf32, cf32, (size_t)MP * KP * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p.ci32, ci32, (size_t)MP * KP * 4, hipMemcpyHostToDevice));
   for (int ax = 0; ax < 2; ++ax) {
     const int n = ax == 0 ? Nx : Nz;
-    std::vector<double> tw(2 * (size_t)n);
     for (int t = 0; t < n; ++t) {
       // exp(-2 pi i t/n) = cos(pi 2t/n) - i sin(pi 2t/n)
       const long m = (2L * t) % (2L * n);
@@ -173,40 +234,31 @@ int plan_constants(Plan& p) {
     }
     void* dst = ax == 0 ? p.twx : p.twz;
     if (p.fp64) {
-      HIP_TRY(hipMemcpy(dst, tw.data(), tw.size() * 8, hipMemcpyHostToDevice));
+      HIP_TRY(hipMemcpy(dst, tw, 2 * (size_t)n * 8, hipMemcpyHostToDevice));
     } else {
-      std::vector<float> tf(tw.begin(), tw.end());
-      HIP_TRY(hipMemcpy(dst, tf.data(), tf.size() * 4, hipMemcpyHostToDevice));
+      for (int i = 0; i < 2 * n; ++i) tf[i] = (float)tw[i];
+      HIP_TRY(hipMemcpy(dst, tf, 2 * (size_t)n * 4, hipMemcpyHostToDevice));
     }
   }
-  std::vector<double> nc(3 * (size_t)Ny, 0.0);
+  for (int i = 0; i < 3 * Ny; ++i) nc[i] = 0.0;
   for (int n = 2; n < Ny; ++n) {
     nc[n] = 1.0 / (4.0 * n * (n - 1));
     nc[Ny + n] = 1.0 / (2.0 * ((double)n * n - 1.0));
     nc[2 * Ny + n] = 1.0 / (4.0 * n * (n + 1));
   }
-  HIP_TRY(hipMemcpy(p.nconst, nc.data(), nc.size() * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p.nconst, nc, 3 * (size_t)Ny * 8, hipMemcpyHostToDevice));
   HIP_TRY(launch_influence(p));
-  {
-    // wall nodes (x_i, -H, z_k) then (x_i, +H, z_k), binned once
-    const size_t nw = 2 * (size_t)Nx * Nz;
-    std::vector<double> wpos(3 * nw);
-    for (int w = 0; w < 2; ++w)
-      for (int i = 0; i < Nx; ++i)
-        for (int k = 0; k < Nz; ++k) {
-          const size_t r = (size_t)w * Nx * Nz + (size_t)i * Nz + k;
-          wpos[3 * r] = i * p.dx;
-          wpos[3 * r + 1] = w ? p.p.H : -p.p.H;
-          wpos[3 * r + 2] = k * p.dz;
-        }
-    double* dpos = nullptr;
-    HIP_TRY(hipMalloc((void**)&dpos, wpos.size() * sizeof(double)));
-    hipError_t e = hipMemcpy(dpos, wpos.data(), wpos.size() * sizeof(double), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = launch_bin(p, p.wall, (long long)nw, dpos, nullptr, nullptr, false, true);
-    if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
-    (void)hipFree(dpos);
-    HIP_TRY(e);
-  }
+  // wall nodes (x_i, -H, z_k) then (x_i, +H, z_k), binned once
+  for (int w = 0; w < 2; ++w)
+    for (int i = 0; i < Nx; ++i)
+      for (int k = 0; k < Nz; ++k) {
+        const size_t r = (size_t)w * Nx * Nz + (size_t)i * Nz + k;
+        wpos[3 * r] = i * p.dx;
+        wpos[3 * r + 1] = w ? p.p.H : -p.p.H;
+        wpos[3 * r + 2] = k * p.dz;
+      }
+  HIP_TRY(hipMemcpy(p.wall_pos, wpos, 3 * nw * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(launch_bin(p, p.wall, (long long)nw, p.wall_pos, nullptr, nullptr, false, true));
   HIP_TRY(hipStreamSynchronize(p.stream));
   return GGEM_OK;
 }
@@ -290,12 +342,13 @@ int evaluate(Plan& p, long long ns, const double* xs, const double* f, long long
   }
   // side stream: wall data (and gauge, wall-plane FFT), then the local sum at
   // the targets; the main stream meanwhile spreads and transforms.  While the
-  // caller's stream is being captured into a graph, everything stays on it
-  // (in the same order), so a capture never forks into the plan's stream.
+  // caller's stream is being captured into a graph, or when the plan has no
+  // second stream (the allocation-free entry), everything stays on the
+  // caller's stream in the same order.
   const hipStream_t main_stream = p.stream;
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   HIP_TRY(hipStreamIsCapturing(main_stream, &cap));
-  const bool fork = cap == hipStreamCaptureStatusNone;
+  const bool fork = cap == hipStreamCaptureStatusNone && p.side != nullptr;
   // Expected work of the local sum against the spread's, from the mean
   // source density: pairs within r_c per target and node updates per node
   // (weighted by their measured relative cost per pair).  A local sum well
@@ -392,11 +445,8 @@ int check_eval(Plan& p, long long ns, const double* xs, const double* f, long lo
   return GGEM_OK;
 }
 
-}  // namespace
-
-extern "C" int ggem_plan_create(const ggem_params* prm, void* hip_stream, ggem_plan_t* out) {
-  if (!prm || !out) return fail(GGEM_E_ARG, "null argument");
-  *out = nullptr;
+// Validate the parameters and fill in a plan's geometry (no device work).
+int init_plan(Plan& p, const ggem_params* prm, hipStream_t stream) {
   ggem_params q = *prm;
   if (!(q.Lx > 0 && q.Lz > 0 && isfinite(q.Lx) && isfinite(q.Lz)))
     return fail(GGEM_E_ARG, "Lx, Lz must be positive");
@@ -417,12 +467,9 @@ extern "C" int ggem_plan_create(const ggem_params* prm, void* hip_stream, ggem_p
   if (q.max_src < 0 || q.max_tgt < 0 || q.max_src > (1LL << 30) || q.max_tgt > (1LL << 30))
     return fail(GGEM_E_ARG, "capacities must be in 0..2^30");
 
-  ggem_plan_s* h = new (std::nothrow) ggem_plan_s();
-  if (!h) return fail(GGEM_E_NOMEM, "host allocation failed");
-  Plan& p = h->p;
   memset(&p, 0, sizeof(Plan));
   p.p = q;
-  p.stream = (hipStream_t)hip_stream;
+  p.stream = stream;
   (void)hipGetDevice(&p.device);
   p.fp64 = q.precision == GGEM_FP64;
   p.timed_stage = -1;
@@ -464,44 +511,48 @@ extern "C" int ggem_plan_create(const ggem_params* prm, void* hip_stream, ggem_p
   g.icz = g.ncz / q.Lz;
   g.icy = g.ncy / (2.0 * q.H);
 
-  const size_t elt = p.fp64 ? 8 : 4;
-  const size_t Ny = q.Ny, Nx = q.Nx, Nz = q.Nz;
-  const int MP = ((q.Ny + 15) / 16) * 16, KP = ((q.Ny + 3) / 4) * 4;
-  bool ok = dev_alloc(&p.y, Ny) && dev_alloc(&p.cf64, (size_t)MP * KP) &&
-            dev_alloc(&p.ci64, (size_t)MP * KP) && dev_alloc(&p.cf32, (size_t)MP * KP) &&
-            dev_alloc(&p.ci32, (size_t)MP * KP) &&
-            hipMalloc(&p.twx, 2 * Nx * elt) == hipSuccess &&
-            hipMalloc(&p.twz, 2 * Nz * elt) == hipSuccess &&
-            dev_alloc(&p.infl, 4 * (size_t)p.nmodes) &&
-            hipMalloc(&p.ul, kNearSlices * 3 * (size_t)(q.max_tgt > 0 ? q.max_tgt : 1) * elt) ==
-                hipSuccess &&
-            hipMalloc(&p.phys, 6 * Ny * Nx * Nz * elt) == hipSuccess &&
-            hipMalloc(&p.specA, 6 * Ny * p.nmodes * 2 * elt) == hipSuccess &&
-            hipMalloc(&p.specB, 6 * Ny * p.nmodes * 2 * elt) == hipSuccess &&
-            hipMalloc(&p.wall_phys, 6 * Nx * Nz * elt) == hipSuccess &&
-            hipMalloc(&p.wall_part, kWallSlices * 6 * Nx * Nz * elt) == hipSuccess &&
-            hipMalloc(&p.wall_spec, 6 * (size_t)p.nmodes * 2 * elt) == hipSuccess &&
-            dev_alloc(&p.tau_scr, 2 * 9 * Ny * (size_t)p.nmodes) &&
-            dev_alloc(&p.nconst, 3 * Ny) &&
-            dev_alloc(&p.sweep, (6 * Ny + 2) * (size_t)p.nmodes) &&
-            dev_alloc(&p.gauge, (size_t)(q.max_src / 256 + 4)) && dev_alloc(&p.flags, 1) &&
-            dev_alloc(&p.item_count, 4) && dev_alloc(&p.work, 2) &&
-            hipHostMalloc((void**)&p.flags_host, sizeof(unsigned), 0) == hipSuccess &&
-            alloc_binned(p.src, q.max_src, g, elt) &&
-            alloc_binned(p.tgt, q.max_tgt, g, elt) &&
-            alloc_binned(p.wall, 2LL * q.Nx * q.Nz, g, elt) &&
-            hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking) == hipSuccess &&
-            // fork/join events order two streams of this device only: no
-            // system-scope fence (device-scope ordering is kept)
-            hipEventCreateWithFlags(&p.ev_fork, hipEventDisableTiming | hipEventDisableSystemFence) == hipSuccess &&
-            hipEventCreateWithFlags(&p.ev_wall, hipEventDisableTiming | hipEventDisableSystemFence) == hipSuccess &&
-            hipEventCreateWithFlags(&p.ev_near, hipEventDisableTiming | hipEventDisableSystemFence) == hipSuccess;
+  return GGEM_OK;
+}
+
+}  // namespace
+
+extern "C" int ggem_plan_create(const ggem_params* prm, void* hip_stream, ggem_plan_t* out) {
+  if (!prm || !out) return fail(GGEM_E_ARG, "null argument");
+  *out = nullptr;
+  ggem_plan_s* h = new (std::nothrow) ggem_plan_s();
+  if (!h) return fail(GGEM_E_NOMEM, "host allocation failed");
+  Plan& p = h->p;
+  if (int rc = init_plan(p, prm, (hipStream_t)hip_stream)) {
+    delete h;
+    return rc;
+  }
+  Carver sizing{nullptr, 0};
+  layout_plan(p, sizing);
+  p.block_bytes = sizing.off;
+  p.owns_block = true;
+  p.owns_flags_host = true;
+  bool ok = hipMalloc(&p.block, p.block_bytes) == hipSuccess;
+  if (ok) {
+    Carver c{(char*)p.block, 0};
+    layout_plan(p, c);
+  }
+  ok = ok && hipHostMalloc((void**)&p.flags_host, sizeof(unsigned), 0) == hipSuccess &&
+       hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking) == hipSuccess &&
+       // fork/join events order two streams of this device only: no
+       // system-scope fence (device-scope ordering is kept)
+       hipEventCreateWithFlags(&p.ev_fork, hipEventDisableTiming | hipEventDisableSystemFence) == hipSuccess &&
+       hipEventCreateWithFlags(&p.ev_wall, hipEventDisableTiming | hipEventDisableSystemFence) == hipSuccess &&
+       hipEventCreateWithFlags(&p.ev_near, hipEventDisableTiming | hipEventDisableSystemFence) == hipSuccess;
   if (!ok) {
     free_plan(p);
     delete h;
     return fail(GGEM_E_NOMEM, "device allocation failed");
   }
-  int rc = plan_constants(p);
+  HostStage sz{nullptr, 0, 0};
+  (void)plan_constants(p, sz);
+  std::vector<char> host(sz.off + 64);
+  HostStage hs{host.data(), 0, host.size()};
+  int rc = plan_constants(p, hs);
   if (rc != GGEM_OK) {
     free_plan(p);
     delete h;
@@ -626,4 +677,89 @@ extern "C" int ggem_plan_work(ggem_plan_t plan, unsigned long long* counts) {
                          p.stream));
   HIP_TRY(hipStreamSynchronize(p.stream));
   return GGEM_OK;
+}
+
+// ---- single layer without device allocation --------------------------------
+//
+// Workspace of ggem_single_layer_noalloc: one static array per GPU, resident
+// until the process ends.  Its name is a host-side stand-in in host code, so
+// the device address is looked up with hipGetSymbolAddress once per device
+// (with that device current) and only that address is used from then on.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+constexpr size_t kHostStageBytes = (size_t)2 << 20;
+
+struct StaticSlot {
+  char* dev;           // device address of this GPU's scratch (null: not looked up yet)
+  bool ready;          // the scratch holds the plan constants for `key`
+  ggem_params key;
+  Plan plan;
+  unsigned flags_host;
+};
+
+StaticSlot g_slots[kMaxDevices];
+char g_host_stage[kHostStageBytes];
+std::mutex g_static_mu;
+
+bool same_params(const ggem_params& a, const ggem_params& b) {
+  return a.Lx == b.Lx && a.Lz == b.Lz && a.H == b.H && a.alpha == b.alpha && a.rc == b.rc &&
+         a.Nx == b.Nx && a.Nz == b.Nz && a.Ny == b.Ny && a.precision == b.precision &&
+         a.sync_checks == b.sync_checks && a.max_src == b.max_src && a.max_tgt == b.max_tgt;
+}
+
+}  // namespace
+
+extern "C" int ggem_single_layer_noalloc(const ggem_params* prm, void* hip_stream, long long ns,
+                                         const double* xs, const double* f, long long nt,
+                                         const double* xt, double* u) {
+  if (!prm) return fail(GGEM_E_ARG, "null parameters");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(GGEM_E_ARG, "device %d outside 0..%d", dev, kMaxDevices - 1);
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  StaticSlot& s = g_slots[dev];
+  if (!s.dev) {
+    void* ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    s.dev = (char*)ptr;
+  }
+  if (!(s.ready && same_params(s.key, *prm))) {
+    s.ready = false;
+    Plan q;
+    if (int rc = init_plan(q, prm, (hipStream_t)hip_stream)) return rc;
+    Carver sizing{nullptr, 0};
+    layout_plan(q, sizing);
+    if (sizing.off > kScratchBytes)
+      return fail(GGEM_E_CAPACITY,
+                  "workspace of %zu bytes for this grid and these capacities exceeds the "
+                  "%zu-byte static scratch array",
+                  sizing.off, kScratchBytes);
+    HostStage hsz{nullptr, 0, 0};
+    (void)plan_constants(q, hsz);
+    if (hsz.off > kHostStageBytes)
+      return fail(GGEM_E_CAPACITY, "plan constants of %zu bytes exceed the %zu-byte host staging",
+                  hsz.off, kHostStageBytes);
+    Plan& p = s.plan;
+    p = q;
+    Carver c{s.dev, 0};
+    layout_plan(p, c);
+    p.block = s.dev;
+    p.block_bytes = sizing.off;
+    p.owns_block = false;
+    p.flags_host = &s.flags_host;
+    p.owns_flags_host = false;
+    HostStage hs{g_host_stage, 0, kHostStageBytes};
+    if (int rc = plan_constants(p, hs)) return rc;
+    s.key = *prm;
+    s.ready = true;
+  }
+  Plan& p = s.plan;
+  p.stream = (hipStream_t)hip_stream;
+  if (int rc = check_eval(p, ns, xs, f, nt, xt, u, GGEM_PART_ALL)) return rc;
+  return p.fp64 ? evaluate<double>(p, ns, xs, f, nt, xt, nullptr, u, GGEM_PART_ALL, false)
+                : evaluate<float>(p, ns, xs, f, nt, xt, nullptr, u, GGEM_PART_ALL, false);
 }

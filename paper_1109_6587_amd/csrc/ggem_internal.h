@@ -104,9 +104,15 @@ struct Plan {
   double* tau_scr;    // tau scratch (9 x Ny x nmodes, complex FP64)
   double* gauge;      // gauge partial sums and value
   unsigned* flags;    // device domain flags
-  unsigned* flags_host;  // pinned host copy
-  int* item_count;    // scratch
+  unsigned* flags_host;  // host copy (pinned for plans; static for the allocation-free entry)
   unsigned long long* work;  // [0]: local pairs at the targets, [1]: spread updates (last call)
+  double* wall_pos;   // wall node positions (2 Nx Nz x 3), input of their binning
+
+  // every device buffer above is carved out of this one block
+  void* block;
+  size_t block_bytes;
+  bool owns_block;    // false: the block is the library's static scratch array
+  bool owns_flags_host;
 
   // stage timing hook (host side)
   int timed_stage;    // -1: off

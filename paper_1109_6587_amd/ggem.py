@@ -36,7 +36,7 @@ EXPORTS = (
     "ggem_mlp_forward", "ggem_mlp_predict", "ggem_mlp_gradients", "ggem_mlp_train_step",
     "ggem_batch_create", "ggem_batch_destroy", "ggem_batch_single_layer",
     "ggem_batch_capture_single_layer", "ggem_batch_graph_launch", "ggem_batch_status",
-    "ggem_batch_branch", "ggem_last_error",
+    "ggem_batch_branch", "ggem_single_layer_noalloc", "ggem_last_error",
 )
 
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 13, 128, 3, 35203
@@ -85,6 +85,7 @@ def load_library(path: str = LIB_PATH):
     lib.ggem_single_layer.argtypes = [vp, ll, dp, dp, ll, dp, dp, ip]
     lib.ggem_double_layer.argtypes = [vp, ll, dp, dp, ll, dp, dp, dp, ip]
     lib.ggem_spread_grid.argtypes = [vp, ll, dp, dp, dp]
+    lib.ggem_single_layer_noalloc.argtypes = [ctypes.POINTER(Params), vp, ll, dp, dp, ll, dp, dp]
     lib.ggem_plan_time_stage.argtypes = [vp, ip, ip]
     lib.ggem_plan_stage_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int)]
@@ -240,6 +241,27 @@ class Plan:
         _check(_lib.ggem_spread_grid(self._h, ns, _dev_ptr(xs, "xs"), _dev_ptr(f, "f", ns),
                                      out.data_ptr()))
         return out
+
+
+def single_layer_noalloc(Lx, Lz, H, alpha, Nx, Nz, Ny, xs, f, xt, rc=0.0, precision="fp64",
+                         max_src=None, max_tgt=None, sync_checks=True, out=None, stream=None):
+    """ggem_single_layer_noalloc: the single layer without a plan object, in
+    the library's static per-GPU workspace (no device allocation inside the
+    library).  Capacities default to the sizes of this call."""
+    import torch
+    lib = load_library()
+    ns, nt = xs.shape[0], xt.shape[0]
+    prec = {"fp64": FP64, "mixed": MIXED}[precision] if isinstance(precision, str) else int(precision)
+    prm = Params(float(Lx), float(Lz), float(H), float(alpha), float(rc), int(Nx), int(Nz),
+                 int(Ny), prec, 1 if sync_checks else 0,
+                 int(max_src if max_src is not None else max(ns, 1)),
+                 int(max_tgt if max_tgt is not None else max(nt, 1)))
+    if out is None:
+        out = torch.empty((nt, 3), dtype=torch.float64, device=xt.device)
+    _check(lib.ggem_single_layer_noalloc(ctypes.byref(prm), _stream_handle(stream), ns,
+                                         _dev_ptr(xs, "xs"), _dev_ptr(f, "f", ns), nt,
+                                         _dev_ptr(xt, "xt"), _dev_ptr(out, "out", nt)))
+    return out
 
 
 class Surface:
