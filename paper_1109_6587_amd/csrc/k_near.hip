@@ -5,9 +5,14 @@
 // staged through LDS, and every lane accumulates its own target in registers
 // (no atomics, fixed order of summation).
 //
-// Displacements and the cutoff test are always formed in FP64 (so the set of
-// interacting pairs does not depend on the precision mode); the kernel values
-// are evaluated in T (double, or float in mixed mode).
+// FP64 mode forms every displacement and decides every cutoff and coincidence
+// in FP64, as the oracle does.  Mixed mode (FAST below) decides the cutoff in
+// FP32 relative to the target cell's corner, so pairs within an FP32 rounding
+// of r_c may be kept or dropped (their kernel is below 1e-7 of its peak).
+// Pairs with alpha r < 1e-2 are decided and evaluated in FP64 in mixed mode,
+// so only exactly coincident points take the self rule and no FP32
+// intermediate overflows.  Other kernel values are evaluated in T (double, or float in
+// mixed mode) from the displacement formed in FP64.
 #include "ggem_internal.h"
 
 namespace ggem {
@@ -117,6 +122,132 @@ struct Vec4<double> {
   using t = double4;
 };
 
+// Pairs with alpha r below 1e-2 (alpha^2 r^2 < kNear2 in the FP32 test) are
+// decided and evaluated in FP64: a coincident point takes the self rule, and
+// a distinct one cannot overflow the FP32 intermediates of the kernels (1/r^3,
+// 1/r^5).  There erfc and exp are their Taylor series (the first omitted term
+// is below 1e-17 of the sum), so this rare path needs no library call.
+constexpr double kNear2 = 1e-4;
+
+template <typename T, bool DL, typename V>
+__device__ void near_pair_fp64(double dx, double dy, double dz, const V& fv, T nx, T ny, T nz,
+                               double alpha, T& ux, T& uy, T& uz, T& sfx, T& sfy, T& sfz) {
+  const double r2 = dist2(dx, dy, dz);
+  if (r2 == 0.0) {
+    if (!DL) {
+      sfx += fv.x;
+      sfy += fv.y;
+      sfz += fv.z;
+    }
+    return;
+  }
+  const double sp = 1.7724538509055160273;  // sqrt(pi)
+  const double ir = 1.0 / sqrt(r2), r = r2 * ir, x = alpha * r, x2 = x * x;
+  // exp(-x^2) and erfc(x) = 1 - (2/sqrt(pi)) (x - x^3/3 + x^5/10 - x^7/42)
+  const double ex = 1.0 + x2 * (-1.0 + x2 * (0.5 + x2 * (-1.0 / 6.0)));
+  const double ec = 1.0 - (2.0 / sp) * x * (1.0 + x2 * (-1.0 / 3.0 + x2 * (0.1 + x2 * (-1.0 / 42.0))));
+  double vx, vy, vz;
+  if (DL) {
+    const double a3 = alpha * alpha * alpha;
+    const double A = -(6.0 * ec * ir * ir * ir * ir * ir + 12.0 * alpha / sp * ex * ir * ir * ir * ir +
+                       8.0 * a3 / sp * ex * ir * ir);
+    const double B = 4.0 * a3 / sp * ex;
+    const double qx = fv.x, qy = fv.y, qz = fv.z;
+    const double dq = dx * qx + dy * qy + dz * qz;
+    const double dn = dx * nx + dy * ny + dz * nz;
+    const double qn = qx * nx + qy * ny + qz * nz;
+    vx = A * dq * dn * dx + B * (dn * qx + dq * nx + qn * dx);
+    vy = A * dq * dn * dy + B * (dn * qy + dq * ny + qn * dy);
+    vz = A * dq * dn * dz + B * (dn * qz + dq * nz + qn * dz);
+  } else {
+    const double ce = 2.0 * alpha / sp * ex;
+    const double A = ec * ir - ce, B = (ec * ir + ce) * ir * ir;
+    const double df = dx * fv.x + dy * fv.y + dz * fv.z;
+    vx = A * fv.x + B * df * dx;
+    vy = A * fv.y + B * df * dy;
+    vz = A * fv.z + B * df * dz;
+  }
+  ux += (T)vx;
+  uy += (T)vy;
+  uz += (T)vz;
+}
+
+// Constants of the branch-free FP32 kernels: the exponent and the erfc
+// argument pre-multiplied.
+struct KcF {
+  double alpha;           // (FP64, for the near-coincident pairs)
+  float nl2a2;            // -alpha^2 log2(e): exp(-alpha^2 r^2) = 2^(nl2a2 r^2)
+  float pa;               // 0.3275911 alpha: t = 1/(1 + pa r)
+  float c2a, c12a, c8a3, c4a3;
+};
+
+__host__ inline KcF make_kcf(double alpha) {
+  const double sp = 1.7724538509055160273;
+  KcF k;
+  k.alpha = alpha;
+  k.nl2a2 = (float)(-alpha * alpha * 1.4426950408889634074);
+  k.pa = (float)(0.3275911 * alpha);
+  k.c2a = (float)(2.0 * alpha / sp);
+  k.c12a = (float)(12.0 * alpha / sp);
+  k.c8a3 = (float)(8.0 * alpha * alpha * alpha / sp);
+  k.c4a3 = (float)(4.0 * alpha * alpha * alpha / sp);
+  return k;
+}
+
+// (S erfc(alpha r), exp(-alpha^2 r^2)) in FP32, erfc by Abramowitz & Stegun
+// 7.1.26 with its coefficients scaled by S at compile time.
+template <int S>
+__device__ inline void erfc_exp_f(float r, float r2, const KcF& k, float& ec, float& ex) {
+  ex = __builtin_amdgcn_exp2f(k.nl2a2 * r2);
+  const float t = __builtin_amdgcn_rcpf(fmaf(k.pa, r, 1.0f));
+  float p = fmaf((float)(S * 1.061405429), t, (float)(S * -1.453152027));
+  p = fmaf(p, t, (float)(S * 1.421413741));
+  p = fmaf(p, t, (float)(S * -0.284496736));
+  p = fmaf(p, t, (float)(S * 0.254829592));
+  ec = p * t * ex;
+}
+
+// G^l(d) f for one pair, both coefficients zeroed unless ok (0 < r <= r_c),
+// so a lane can take every staged source: an excluded pair adds exact zeros.
+__device__ inline void stokeslet_masked(float dx, float dy, float dz, float r2, bool ok, float fx,
+                                        float fy, float fz, const KcF& k, float& ux, float& uy,
+                                        float& uz) {
+  const float ir = __builtin_amdgcn_rsqf(r2);
+  float ec, ex;
+  erfc_exp_f<1>(r2 * ir, r2, k, ec, ex);
+  const float er = ec * ir, ce = k.c2a * ex;
+  const float A = ok ? er - ce : 0.0f;
+  const float B = ok ? (er + ce) * (ir * ir) : 0.0f;
+  const float Bdf = B * (dx * fx + dy * fy + dz * fz);
+  ux = fmaf(Bdf, dx, fmaf(A, fx, ux));
+  uy = fmaf(Bdf, dy, fmaf(A, fy, uy));
+  uz = fmaf(Bdf, dz, fmaf(A, fz, uz));
+}
+
+// n . T^l(d) . q for one pair with the same mask; the (B q.d) n term is
+// summed into sn and multiplied by the target's normal once at the end.
+__device__ inline void stresslet_masked(float dx, float dy, float dz, float r2, bool ok, float qx,
+                                        float qy, float qz, float nx, float ny, float nz,
+                                        const KcF& k, float& vx, float& vy, float& vz, float& sn) {
+  const float ir = __builtin_amdgcn_rsqf(r2);
+  const float ir2 = ir * ir;
+  float ec6, ex;
+  erfc_exp_f<6>(r2 * ir, r2, k, ec6, ex);
+  // A = -6 erfc/r^5 - c12 e/r^4 - c8 e/r^2 (ec6 = 6 erfc), B = c4 e
+  const float Af = ir2 * fmaf(ir2, fmaf(ec6, ir, k.c12a * ex), k.c8a3 * ex);
+  const float Am = ok ? Af : 0.0f;  // -A
+  const float B = ok ? k.c4a3 * ex : 0.0f;
+  const float dq = dx * qx + dy * qy + dz * qz;
+  const float dn = dx * nx + dy * ny + dz * nz;
+  const float qn = qx * nx + qy * ny + qz * nz;
+  const float Ad = fmaf(-(Am * dq), dn, B * qn);
+  const float Bdn = B * dn;
+  sn = fmaf(B, dq, sn);
+  vx = fmaf(Bdn, qx, fmaf(Ad, dx, vx));
+  vy = fmaf(Bdn, qy, fmaf(Ad, dy, vy));
+  vz = fmaf(Bdn, qz, fmaf(Ad, dz, vz));
+}
+
 struct NearArgs {
   CellGeom g;
   double rc2;
@@ -157,11 +288,10 @@ struct NearArgs {
 // without a per-pair image search.  Otherwise every displacement is the FP64
 // minimum image and the cutoff is decided in FP64.
 template <typename T, bool DL, bool FAST, int W>
-__global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k) {
+__global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k, KcF kf) {
   // staged sources: FP64 position (x, y, z, unused) and strength (x, y, z,
   // unused), one vector read each
   __shared__ double4 lp[W][64];
-  __shared__ float4 lr[W][64];
   __shared__ typename Vec4<T>::t lf[W][64];
   __shared__ T part[W][3][64];
   const CellGeom& g = a.g;
@@ -178,8 +308,6 @@ __global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k) {
   const int iz = c % g.ncz;
   const int ix = (c / g.ncz) % g.ncx;
   const int iy = c / (g.ncz * g.ncx);
-  // target cell corner (FAST path reference point)
-  const double ox = ix / g.icx, oy = iy / g.icy - g.H, oz = iz / g.icz;
   double px = 0, py = 0, pz = 0;
   T nx = 0, ny = 0, nz = 0;
   if (active) {
@@ -193,8 +321,10 @@ __global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k) {
       nz = tn[2 * a.tcap + t];
     }
   }
-  const float prx = (float)(px - ox), pry = (float)(py - oy), prz = (float)(pz - oz);
   const float rc2f = (float)a.rc2;
+  const double alpha = kf.alpha;
+  const float near2f = (float)(kNear2 / (alpha * alpha));
+  const double near2 = kNear2 / (alpha * alpha);
   // bounding box of the item's targets (they share one cell, so no wrap)
   double bx0 = active ? px : 1e300, bx1 = active ? px : -1e300;
   double by0 = active ? py : 1e300, by1 = active ? py : -1e300;
@@ -214,7 +344,10 @@ __global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k) {
   const T* sf = (const T*)a.sf;
   T ux = 0, uy = 0, uz = 0;
   T sfx = 0, sfy = 0, sfz = 0;  // self contributions
-  unsigned npairs = 0;
+  float sn = 0.0f;              // FAST double layer: sum of B (q.d), times n at the end
+  unsigned npairs = 0;          // exact path: per lane
+  unsigned long long npairs_w = 0;  // FAST: per wave
+  const unsigned long long amask = __ballot(active);
   const int nxo = g.ncx >= 3 ? 3 : g.ncx, nzo = g.ncz >= 3 ? 3 : g.ncz;
   // wall targets only see the wall cell layer (cells are at least r_c high)
   const int oy0 = a.nplane ? 1 : 0, noy = a.nplane ? 1 : 3;
@@ -289,13 +422,17 @@ __global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k) {
       const unsigned long long km = __ballot(keep);
       const int cnt = __popcll(km);
       if (cnt == 0) continue;
+      const int cnt4 = (cnt + 3) & ~3;
       __builtin_amdgcn_wave_barrier();
-      if (FAST && lane >= cnt && lane < ((cnt + 3) & ~3))
-        lr[wave][lane] = make_float4(1e30f, 1e30f, 1e30f, 0.f);  // padding: out of range
+      if (FAST && lane >= cnt && lane < cnt4) {
+        // padding to a multiple of four: a far-away point of zero strength
+        lp[wave][lane] = make_double4(1e30, 1e30, 1e30, 0.0);
+        typename Vec4<T>::t z;
+        z.x = z.y = z.z = z.w = (T)0;
+        lf[wave][lane] = z;
+      }
       if (keep) {
         const int slot = __popcll(km & lt);
-        if (FAST)
-          lr[wave][slot] = make_float4((float)(qx - ox), (float)(qy - oy), (float)(qz - oz), 0.f);
         lp[wave][slot] = make_double4(qx, qy, qz, 0.0);
         typename Vec4<T>::t fv;
         fv.x = sf[si];
@@ -307,94 +444,101 @@ __global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      // pass 1: this lane's in-range sources of the batch as a bit mask
-      unsigned long long mask = 0;
-      if (FAST) {
-        // four staged sources per LDS round trip (the batch is padded to a
-        // multiple of four with far-away points); the mask is built without
-        // branches, and coincident points (r = 0) take a separate pass
-        unsigned mlo = 0u, mhi = 0u;
-        bool any_self = false;
-        for (int j0 = 0; j0 < cnt; j0 += 4) {
-          float4 qg[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) qg[u] = lr[wave][j0 + u];
+      if constexpr (FAST) {
+        // every lane takes every staged source, four per LDS round trip, in
+        // staged (sorted) order; pairs outside 0 < r <= r_c add exact zeros.
+        // The displacement is formed in FP64 and rounded per component;
+        // separations with alpha r < 1e-2 are left to the FP64 pass after the loop.
+        unsigned long long tiny_w = 0;
+        for (int j0 = 0; j0 < cnt4; j0 += 4) {
+          double4 qg[4];
+          float4 fg[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            const int j = j0 + u;
-            const float dx = prx - qg[u].x, dy = pry - qg[u].y, dz = prz - qg[u].z;
+            qg[u] = lp[wave][j0 + u];
+            fg[u] = lf[wave][j0 + u];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const float dx = (float)(px - qg[u].x), dy = (float)(py - qg[u].y),
+                        dz = (float)(pz - qg[u].z);
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            const bool in = r2 <= rc2f;
-            const unsigned bit = (in && r2 != 0.f) ? (1u << (j & 31)) : 0u;
-            if (j < 32) mlo |= bit;
-            else mhi |= bit;
-            any_self |= in && r2 == 0.f;
+            const bool ge = r2 >= near2f;
+            const bool ok = ge && r2 <= rc2f;
+            // lane masks stay scalar: every lane runs this loop
+            tiny_w |= ~__builtin_amdgcn_ballot_w64(ge);
+            if (a.work) npairs_w += __popcll(__builtin_amdgcn_ballot_w64(ok) & amask);
+            if (DL)
+              stresslet_masked(dx, dy, dz, r2, ok, fg[u].x, fg[u].y, fg[u].z, nx, ny, nz, kf, ux,
+                               uy, uz, sn);
+            else
+              stokeslet_masked(dx, dy, dz, r2, ok, fg[u].x, fg[u].y, fg[u].z, kf, ux, uy, uz);
           }
         }
-        mask = active ? (((unsigned long long)mhi << 32) | mlo) : 0ull;
-        if (!DL && __ballot(active && any_self)) {
+        if (tiny_w & amask) {
           for (int j = 0; j < cnt; ++j) {
-            const float4 q = lr[wave][j];
-            const float dx = prx - q.x, dy = pry - q.y, dz = prz - q.z;
+            const double4 qp = lp[wave][j];
+            const double ddx = px - qp.x, ddy = py - qp.y, ddz = pz - qp.z;
+            const float dx = (float)ddx, dy = (float)ddy, dz = (float)ddz;
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            if (active && r2 == 0.f) {
-              sfx += lf[wave][j].x;
-              sfy += lf[wave][j].y;
-              sfz += lf[wave][j].z;
-            }
+            if (active && r2 < near2f)
+              near_pair_fp64<T, DL>(ddx, ddy, ddz, lf[wave][j], nx, ny, nz, alpha, ux, uy, uz, sfx,
+                                    sfy, sfz);
           }
         }
-      } else if (active) {
-        for (int j = 0; j < cnt; ++j) {
-          bool in, self;
-          {
+      } else {
+        // exact path: the lane's in-range sources as a bit mask, decided on
+        // the FP64 minimum-image displacement, then kernel evaluations for
+        // those only, in source order
+        unsigned long long mask = 0;
+        if (active) {
+          for (int j = 0; j < cnt; ++j) {
             const double4 q = lp[wave][j];
             const double dx = min_image(px - q.x, g.Lx, g.invLx);
             const double dy = py - q.y;
             const double dz = min_image(pz - q.z, g.Lz, g.invLz);
             const double r2 = dist2(dx, dy, dz);
-            in = r2 <= a.rc2;
-            self = r2 == 0.0;
-          }
-          if (in) {
-            if (!self) {
-              mask |= 1ull << j;
-            } else if (!DL) {
-              sfx += lf[wave][j].x;
-              sfy += lf[wave][j].y;
-              sfz += lf[wave][j].z;
+            if (r2 <= a.rc2) {
+              if (sizeof(T) == 4 && r2 < near2) {
+                near_pair_fp64<T, DL>(dx, dy, dz, lf[wave][j], nx, ny, nz, alpha, ux, uy, uz, sfx,
+                                      sfy, sfz);
+              } else if (r2 != 0.0) {
+                mask |= 1ull << j;
+              } else if (!DL) {
+                sfx += lf[wave][j].x;
+                sfy += lf[wave][j].y;
+                sfz += lf[wave][j].z;
+              }
             }
           }
         }
-      }
-      // pass 2: kernel evaluations only for in-range pairs, in source order
-      npairs += __popcll(mask);
-      while (mask) {
-        const int j = __builtin_ctzll(mask);
-        mask &= mask - 1;
-        const double4 q = lp[wave][j];
-        double dx, dy, dz;
-        if (FAST) {
-          dx = px - q.x;
-          dy = py - q.y;
-          dz = pz - q.z;
-        } else {
-          dx = min_image(px - q.x, g.Lx, g.invLx);
-          dy = py - q.y;
-          dz = min_image(pz - q.z, g.Lz, g.invLz);
+        npairs += __popcll(mask);
+        while (mask) {
+          const int j = __builtin_ctzll(mask);
+          mask &= mask - 1;
+          const double4 q = lp[wave][j];
+          const double dx = min_image(px - q.x, g.Lx, g.invLx);
+          const double dy = py - q.y;
+          const double dz = min_image(pz - q.z, g.Lz, g.invLz);
+          const typename Vec4<T>::t fv = lf[wave][j];
+          // the displacement is formed in FP64; in FP32 its square is taken
+          // from the rounded components
+          const T tdx = (T)dx, tdy = (T)dy, tdz = (T)dz;
+          const T r2 = sizeof(T) == 4 ? tdx * tdx + tdy * tdy + tdz * tdz : (T)dist2(dx, dy, dz);
+          if (DL)
+            stresslet_acc<T>(tdx, tdy, tdz, r2, fv.x, fv.y, fv.z, nx, ny, nz, k, ux, uy, uz);
+          else
+            stokeslet_acc<T>(tdx, tdy, tdz, r2, fv.x, fv.y, fv.z, k, ux, uy, uz);
         }
-        const typename Vec4<T>::t fv = lf[wave][j];
-        // the displacement is formed in FP64; in FP32 mode its square is taken
-        // from the rounded components (the cutoff was decided in pass 1)
-        const T tdx = (T)dx, tdy = (T)dy, tdz = (T)dz;
-        const T r2 = sizeof(T) == 4 ? tdx * tdx + tdy * tdy + tdz * tdz : (T)dist2(dx, dy, dz);
-        if (DL)
-          stresslet_acc<T>(tdx, tdy, tdz, r2, fv.x, fv.y, fv.z, nx, ny, nz, k, ux, uy, uz);
-        else
-          stokeslet_acc<T>(tdx, tdy, tdz, r2, fv.x, fv.y, fv.z, k, ux, uy, uz);
       }
     }
   }
+  if (FAST && DL) {
+    ux = fmaf(sn, nx, ux);
+    uy = fmaf(sn, ny, uy);
+    uz = fmaf(sn, nz, uz);
+  }
+  if (a.work && FAST && lane == 0 && npairs_w) atomicAdd(a.work, npairs_w);
   if (a.work) wave_count_add(a.work, npairs);
   part[wave][0][lane] = ux + k.selfc * sfx;
   part[wave][1][lane] = uy + k.selfc * sfy;
@@ -424,8 +568,14 @@ template <typename T, bool DL, int W>
 static void launch_near_w(Plan& p, const NearArgs& a, unsigned grid) {
   const bool fast = sizeof(T) == 4 && p.cg.ncx >= 3 && p.cg.ncz >= 3;
   const dim3 g(grid, (unsigned)a.nslice);
-  if (fast) near_field<T, DL, true, W><<<g, 64 * W, 0, p.stream>>>(a, make_kc<T>(p.p.alpha));
-  else near_field<T, DL, false, W><<<g, 64 * W, 0, p.stream>>>(a, make_kc<T>(p.p.alpha));
+  const KcF kf = make_kcf(p.p.alpha);
+  if constexpr (sizeof(T) == 4) {
+    if (fast) {
+      near_field<T, DL, true, W><<<g, 64 * W, 0, p.stream>>>(a, make_kc<T>(p.p.alpha), kf);
+      return;
+    }
+  }
+  near_field<T, DL, false, W><<<g, 64 * W, 0, p.stream>>>(a, make_kc<T>(p.p.alpha), kf);
 }
 
 // grid = an upper bound of the work items (targets/64 + cells)
