@@ -58,7 +58,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--precision", choices=["mixed", "fp64", "mixed_bf16"], default="mixed")
     ap.add_argument("--workload", choices=["capsules_dl", "capsules_sl", "batched"],
                     default="capsules_dl")
     ap.add_argument("--extras", default=",".join(EXTRAS),
@@ -334,6 +334,61 @@ def measure_case(c, args, precision, with_other=True, golden_parts=True):
     return res
 
 
+def cheb_stage_rates(plan, call, c, steps):
+    """HIP-event times of the forward and inverse Chebyshev stages and their
+    achieved HBM rate: each reads and writes its fields once (FP32 complex
+    half spectrum: Ny x 2 Nx (Nz/2 + 1) reals per field)."""
+    dl = c.normals is not None
+    per_field = c.Ny * 2 * c.Nx * (c.Nz // 2 + 1) * 4 * 2
+    out = {}
+    for st, nf in (("cheb_fwd", 3), ("cheb_inv", 6 if dl else 3)):
+        _, ms = time_steps(plan, call, steps, 2, stage=st)
+        out[st] = {"ms": round(ms, 5), "bytes": nf * per_field,
+                   "GB_per_s": round(nf * per_field / (ms * 1e-3) / 1e9, 1)}
+    return out
+
+
+def measure_variant(c, args, precision):
+    """Throughput, error against the stored oracle sample and Chebyshev stage
+    rates of one more precision mode on the same workload."""
+    import numpy as np
+    import torch
+
+    import paper_1109_6587_amd as G
+
+    dev = torch.device("cuda:0")
+    dl = c.normals is not None
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)  # noqa: E731
+    xs, f = t(c.xs), t(c.f)
+    nrm = t(c.normals) if dl else None
+    out = torch.empty((c.nt, 3), dtype=torch.float64, device=dev)
+    plan = G.Plan.from_case(c, precision=precision, sync_checks=False)
+
+    def caller(parts=G.PART_ALL):
+        if dl:
+            return lambda: plan.double_layer(xs, f, xs, nrm, parts=parts, out=out)
+        return lambda: plan.single_layer(xs, f, xs, parts=parts, out=out)
+
+    res = {}
+    ref = golden(c)
+    if ref is not None:
+        sel = np.asarray(ref["targets"])
+        err = {}
+        for key, parts in (("total", G.PART_ALL), ("local", G.PART_LOCAL),
+                           ("global", G.PART_GLOBAL)):
+            caller(parts)()
+            plan.status()
+            o = out.cpu().numpy()[sel]
+            err[key] = {"rel_l2": rel_l2(o, np.asarray(ref[key])),
+                        "rel_max": rel_max(o, np.asarray(ref[key]))}
+        res["err_vs_oracle"] = err
+    ms, _ = time_steps(plan, caller(), max(5, args.steps // 2), 2)
+    res.update(ms_per_step=round(ms, 5), mpoints_per_s=round(c.nt / (ms * 1e-3) / 1e6, 3),
+               chebyshev=cheb_stage_rates(plan, caller(), c, max(5, args.steps // 2)))
+    plan.close()
+    return res
+
+
 def extra_small(args):
     """64 forces + 1,000 probes: microseconds per call (latency-bound)."""
     import numpy as np
@@ -500,6 +555,11 @@ def bench_single(args):
         if k in r:
             line[k] = r[k]
     line["roofline"] = r["roofline"]
+    if args.precision == "mixed":
+        # the same workload with the Chebyshev transforms as BF16 hi + lo
+        # split products (and the FP32-MFMA transforms' rates beside them)
+        line["mixed_bf16"] = measure_variant(c, args, "mixed_bf16")
+        line["mixed_chebyshev"] = measure_variant(c, args, "mixed")["chebyshev"]
     return c, line
 
 

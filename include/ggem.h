@@ -40,8 +40,12 @@ typedef struct ggem_plan_s* ggem_plan_t;
 
 enum ggem_precision {
   GGEM_FP64 = 0,   /* every stage in double precision                       */
-  GGEM_MIXED = 1   /* FP32 near field, spread, FFT, interpolation; FP32 MFMA
+  GGEM_MIXED = 1,  /* FP32 near field, spread, FFT, interpolation; FP32 MFMA
                       Chebyshev transforms; FP64 tau solves                   */
+  GGEM_MIXED_BF16 = 2  /* as GGEM_MIXED, but the Chebyshev transforms are
+                      BF16 hi + lo split products (A_hi B_hi + A_hi B_lo +
+                      A_lo B_hi) on the BF16 matrix cores with FP32
+                      accumulation (about 4e-6 relative error per transform) */
 };
 
 enum ggem_status {
@@ -70,7 +74,7 @@ typedef struct {
   int Nx, Nz;           /* Fourier nodes in x and z: even, 8..512, products of
                            2, 3 and 5                                          */
   int Ny;               /* Chebyshev Gauss-Lobatto nodes in y: 5..129          */
-  int precision;        /* GGEM_FP64 or GGEM_MIXED                            */
+  int precision;        /* GGEM_FP64, GGEM_MIXED or GGEM_MIXED_BF16           */
   int sync_checks;      /* 1: wait and report domain errors; 0: asynchronous  */
   long long max_src;    /* capacity reserved at plan time (sources)           */
   long long max_tgt;    /* capacity reserved at plan time (targets)           */

@@ -122,6 +122,11 @@ void layout_plan(Plan& p, Carver& c) {
   p.ci64 = c.take<double>(MP * KP);
   p.cf32 = c.take<float>(MP * KP);
   p.ci32 = c.take<float>(MP * KP);
+  const size_t KP32 = ((q.Ny + 31) / 32) * 32;
+  p.cf_hi = c.take<unsigned short>(MP * KP32);
+  p.cf_lo = c.take<unsigned short>(MP * KP32);
+  p.ci_hi = c.take<unsigned short>(MP * KP32);
+  p.ci_lo = c.take<unsigned short>(MP * KP32);
   p.twx = c.take_bytes(2 * Nx * elt);
   p.twz = c.take_bytes(2 * Nz * elt);
   p.infl = c.take<double>(4 * nm);
@@ -139,6 +144,7 @@ void layout_plan(Plan& p, Carver& c) {
   p.flags = c.take<unsigned>(1);
   p.work = c.take<unsigned long long>(2);
   p.wall_pos = c.take<double>(3 * 2 * Nx * Nz);
+  p.norder = c.take<int>(mt);
   carve_binned(c, p.src, q.max_src, p.cg, elt);
   carve_binned(c, p.tgt, q.max_tgt, p.cg, elt);
   carve_binned(c, p.wall, 2LL * q.Nx * q.Nz, p.cg, elt);
@@ -164,6 +170,19 @@ void free_plan(Plan& p) {
 double cospi_frac(long m, int N) {
   m %= 2L * N;
   return cos(M_PI * (double)m / (double)N);
+}
+
+// bfloat16 of a float, rounded to nearest even, and back (host)
+unsigned short bf16_round(float x) {
+  unsigned u;
+  memcpy(&u, &x, 4);
+  return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+double bf16_value(unsigned short h) {
+  const unsigned u = (unsigned)h << 16;
+  float f;
+  memcpy(&f, &u, 4);
+  return f;
 }
 
 // normals of coinciding targets, in the sources' sorted order
@@ -197,6 +216,8 @@ int plan_constants(Plan& p, HostStage& hs) {
   double* ci64 = hs.take<double>((size_t)MP * KP);
   float* cf32 = hs.take<float>((size_t)MP * KP);
   float* ci32 = hs.take<float>((size_t)MP * KP);
+  const int KP32 = ((Ny + 31) / 32) * 32;
+  unsigned short* bsplit = hs.take<unsigned short>(4 * (size_t)MP * KP32);
   double* tw = hs.take<double>(2 * (size_t)(Nx > Nz ? Nx : Nz));
   float* tf = hs.take<float>(2 * (size_t)(Nx > Nz ? Nx : Nz));
   double* nc = hs.take<double>(3 * (size_t)Ny);
@@ -220,6 +241,23 @@ int plan_constants(Plan& p, HostStage& hs) {
     cf32[i] = (float)cf64[i];
     ci32[i] = (float)ci64[i];
   }
+  // BF16 hi and lo halves of the two matrices, [MP][KP32], zero padded
+  for (size_t i = 0; i < 4 * (size_t)MP * KP32; ++i) bsplit[i] = 0;
+  for (int r = 0; r < Ny; ++r)
+    for (int k = 0; k < Ny; ++k)
+      for (int m = 0; m < 2; ++m) {
+        const double v = m == 0 ? cf64[(size_t)r * KP + k] : ci64[(size_t)r * KP + k];
+        const unsigned short hi = bf16_round((float)v);
+        const unsigned short lo = bf16_round((float)(v - bf16_value(hi)));
+        const size_t o = (size_t)r * KP32 + k;
+        bsplit[(size_t)(2 * m) * MP * KP32 + o] = hi;
+        bsplit[(size_t)(2 * m + 1) * MP * KP32 + o] = lo;
+      }
+  const size_t nb = (size_t)MP * KP32 * sizeof(unsigned short);
+  HIP_TRY(hipMemcpy(p.cf_hi, bsplit, nb, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p.cf_lo, bsplit + (size_t)MP * KP32, nb, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p.ci_hi, bsplit + 2 * (size_t)MP * KP32, nb, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p.ci_lo, bsplit + 3 * (size_t)MP * KP32, nb, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(p.cf64, cf64, (size_t)MP * KP * 8, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(p.ci64, ci64, (size_t)MP * KP * 8, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(p.cf32, cf32, (size_t)MP * KP * 4, hipMemcpyHostToDevice));
@@ -462,8 +500,8 @@ int init_plan(Plan& p, const ggem_params* prm, hipStream_t stream) {
       !factor_radices(q.Nx, rx, &nrx) || !factor_radices(q.Nz, rz, &nrz))
     return fail(GGEM_E_ARG, "Nx, Nz must be even, 8..512 and products of 2, 3, 5");
   if (q.Ny < 5 || q.Ny > kMaxNy) return fail(GGEM_E_ARG, "Ny must be in 5..129");
-  if (q.precision != GGEM_FP64 && q.precision != GGEM_MIXED)
-    return fail(GGEM_E_ARG, "precision must be GGEM_FP64 or GGEM_MIXED");
+  if (q.precision != GGEM_FP64 && q.precision != GGEM_MIXED && q.precision != GGEM_MIXED_BF16)
+    return fail(GGEM_E_ARG, "precision must be GGEM_FP64, GGEM_MIXED or GGEM_MIXED_BF16");
   if (q.max_src < 0 || q.max_tgt < 0 || q.max_src > (1LL << 30) || q.max_tgt > (1LL << 30))
     return fail(GGEM_E_ARG, "capacities must be in 0..2^30");
 
@@ -472,6 +510,7 @@ int init_plan(Plan& p, const ggem_params* prm, hipStream_t stream) {
   p.stream = stream;
   (void)hipGetDevice(&p.device);
   p.fp64 = q.precision == GGEM_FP64;
+  p.bf16 = q.precision == GGEM_MIXED_BF16;
   p.timed_stage = -1;
   p.rc = q.rc;
   p.rc2 = q.rc * q.rc;

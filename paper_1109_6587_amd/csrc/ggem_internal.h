@@ -69,6 +69,7 @@ struct Plan {
   hipEvent_t ev_fork, ev_wall, ev_near;
   int device;
   bool fp64;
+  bool bf16;         // mixed precision with BF16 hi + lo split Chebyshev products
   double rc, rc2;
   double dx, dz;
   int Nzh;           // Nz/2 + 1
@@ -83,6 +84,10 @@ struct Plan {
   double* ci64;       // inverse Chebyshev (Ny x Ny)
   float* cf32;
   float* ci32;
+  unsigned short* cf_hi;   // BF16 hi and lo halves of the two matrices ([MP][KP32])
+  unsigned short* cf_lo;
+  unsigned short* ci_hi;
+  unsigned short* ci_lo;
   void* twx;          // twiddles exp(-2 pi i t/Nx), complex T
   void* twz;
   double* infl;       // per mode: 2x2 inverse influence matrix (4 doubles)
@@ -107,6 +112,7 @@ struct Plan {
   unsigned* flags_host;  // host copy (pinned for plans; static for the allocation-free entry)
   unsigned long long* work;  // [0]: local pairs at the targets, [1]: spread updates (last call)
   double* wall_pos;   // wall node positions (2 Nx Nz x 3), input of their binning
+  int* norder;        // targets of each cell in Morton order (near-field items, max_tgt)
 
   // every device buffer above is carved out of this one block
   void* block;

@@ -15,6 +15,8 @@ LIB_PATH = os.path.join(PKG, "libggem.so")
 
 FP64 = 0
 MIXED = 1
+MIXED_BF16 = 2
+PRECISIONS = {"fp64": FP64, "mixed": MIXED, "mixed_bf16": MIXED_BF16}
 PART_LOCAL = 1
 PART_GLOBAL = 2
 PART_ALL = 3
@@ -160,7 +162,7 @@ class Plan:
     def __init__(self, Lx, Lz, H, alpha, Nx, Nz, Ny, rc=0.0, precision="fp64",
                  max_src=1, max_tgt=1, sync_checks=True, stream=None):
         lib = load_library()
-        prec = {"fp64": FP64, "mixed": MIXED}[precision] if isinstance(precision, str) else int(precision)
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self.params = Params(float(Lx), float(Lz), float(H), float(alpha), float(rc),
                              int(Nx), int(Nz), int(Ny), prec, 1 if sync_checks else 0,
                              int(max_src), int(max_tgt))
@@ -251,7 +253,7 @@ def single_layer_noalloc(Lx, Lz, H, alpha, Nx, Nz, Ny, xs, f, xt, rc=0.0, precis
     import torch
     lib = load_library()
     ns, nt = xs.shape[0], xt.shape[0]
-    prec = {"fp64": FP64, "mixed": MIXED}[precision] if isinstance(precision, str) else int(precision)
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     prm = Params(float(Lx), float(Lz), float(H), float(alpha), float(rc), int(Nx), int(Nz),
                  int(Ny), prec, 1 if sync_checks else 0,
                  int(max_src if max_src is not None else max(ns, 1)),
@@ -494,7 +496,7 @@ class Batch:
 
     def __init__(self, cases, precision="mixed", n_branches=4):
         lib = load_library()
-        prec = {"fp64": FP64, "mixed": MIXED}[precision]
+        prec = PRECISIONS[precision]
         arr = (Params * len(cases))()
         for i, c in enumerate(cases):
             arr[i] = Params(float(c.Lx), float(c.Lz), float(c.H), float(c.alpha), float(c.rc),

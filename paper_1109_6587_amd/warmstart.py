@@ -4,19 +4,21 @@
    the shape (positions, normals, Lap x), the right-hand side, the previous
    stage's density (the plain warm start) and the converged density.
 2. Train the per-node network (ggem_mlp_*) on the solves of the first
-   `train_steps` steps to predict q - q_prev from the node features
-   (position relative to the drop centroid, normal, curvature term,
-   previous density and its last change).
+   `train_steps` steps to predict what linear extrapolation of the density
+   misses, q - (q_prev + dq_prev) (dq_prev: the last change of the density),
+   from the node features (position relative to the drop centroid, normal,
+   curvature term, previous density and its last change).
 3. On every solve of the remaining steps, solve from the same recorded
    state with each start and report products and times:
-   plain (previous density), extrapolated (previous density plus its last
-   change), learned_direct (previous density plus the prediction),
-   learned_blend (ggem_fredholm_solve_guided on every solve: the least-squares
-   step along the prediction, never worse than plain, one extra product) and
+   plain (previous density, the paper's start), extrapolated (previous
+   density plus its last change), learned_direct (the extrapolation plus the
+   prediction), learned_blend (ggem_fredholm_solve_guided from the
+   extrapolation on every solve: the least-squares step along the
+   prediction, never worse than the extrapolation, one extra product) and
    learned_judged (the deployed rule: every `judge_every`-th solve is a
-   guided one whose step c judges the network against the plain start; the
-   solves in between start from the prediction while the last c >= 1/2,
-   else from the plain start).
+   guided one whose step c judges the network against the extrapolated
+   start; the solves in between start from the extrapolation plus the
+   prediction while the last c >= 1/2, else from the extrapolation).
 
 Data preparation (the two normalisation scalars and the target differences)
 uses torch tensor operations; the network's features, forward and backward
@@ -88,22 +90,25 @@ def run(case, steps=200, train_steps=150, precision="mixed", tol=1e-6, restart=2
     ntrain = 2 * train_steps
     train, test = S[first:ntrain], S[ntrain:]
 
-    # normalisation from the training solves
+    # normalisation from the training solves; the target is the residual of
+    # linear extrapolation
+    resid = lambda sv: sv["q"] - sv["q_prev"] - sv["dq_prev"]  # noqa: E731
     with torch.no_grad():
         c_all = torch.cat([-(sv["lap"] * sv["nrm"]).sum(1) for sv in train])
         qp_all = torch.cat([sv["q_prev"] for sv in train])
         dq_all = torch.cat([sv["q"] - sv["q_prev"] for sv in train])
+        r_all = torch.cat([resid(sv) for sv in train])
         s_c = 1.0 / float(c_all.pow(2).mean().sqrt())
         s_q = 1.0 / float(qp_all.pow(2).mean().sqrt())
         sigma = float(dq_all.pow(2).mean().sqrt())
-        del c_all, qp_all, dq_all
+        sigma_r = float(r_all.pow(2).mean().sqrt())
+        del c_all, qp_all, dq_all, r_all
     scales = [1.0] * 6 + [s_c] + [s_q] * 3 + [1.0 / sigma] * 3
     mlp = B.MLP(max(n, batch), torch.as_tensor(he_uniform(seed), device=dev))
     X = {k: mlp.features(sv["x"], sv["nrm"], sv["lap"], sv["q_prev"], sv["dq_prev"], case.nv,
                          scales)
          for k, sv in enumerate(S) if k >= first}
-    T = {k: ((S[k]["q"] - S[k]["q_prev"]) / sigma).float().contiguous()
-         for k in range(first, ntrain)}
+    T = {k: (resid(S[k]) / sigma_r).float().contiguous() for k in range(first, ntrain)}
 
     # training: mini-batches of `batch` consecutive nodes of one solve, in a
     # seeded random order; learning rate decays linearly to lr/10
@@ -127,7 +132,7 @@ def run(case, steps=200, train_steps=150, precision="mixed", tol=1e-6, restart=2
     names = ("plain", "extrapolated", "learned_direct", "learned_blend", "learned_judged")
     res_it = {m: [] for m in names}
     res_t = {m: [] for m in names}
-    pred_err, blend = [], []
+    pred_err, extrap_err, blend = [], [], []
     use_learned = True
     for k in range(ntrain, len(S)):
         sv = S[k]
@@ -140,27 +145,33 @@ def run(case, steps=200, train_steps=150, precision="mixed", tol=1e-6, restart=2
             extra = 0
             if m == "plain":
                 its, rr = sim.solver.solve(surf, sv["b"], q, tol=tol, max_iter=sim.max_iter)
-            elif m == "extrapolated":
-                sim.solver.advance(sv["q_prev"], sv["dq_prev"], 1.0, out=q)
-                its, rr = sim.solver.solve(surf, sv["b"], q, tol=tol, max_iter=sim.max_iter)
             else:
-                dq = mlp.predict(X[k], sigma)
-                judged_now = m == "learned_judged" and (k - ntrain) % judge_every == 0
-                if m == "learned_blend" or judged_now:
-                    its, rr, c = sim.solver.solve_guided(surf, sv["b"], q, dq, tol=tol,
-                                                         max_iter=sim.max_iter)
-                    extra = 1
-                    if judged_now:
-                        use_learned = c >= 0.5
-                    else:
-                        blend.append(c)
-                elif m == "learned_direct" or use_learned:
-                    sim.solver.advance(sv["q_prev"], dq, 1.0, out=q)
+                # linear extrapolation, the base of every other start
+                sim.solver.advance(sv["q_prev"], sv["dq_prev"], 1.0, out=q)
+                if m == "extrapolated":
                     its, rr = sim.solver.solve(surf, sv["b"], q, tol=tol, max_iter=sim.max_iter)
                 else:
-                    its, rr = sim.solver.solve(surf, sv["b"], q, tol=tol, max_iter=sim.max_iter)
-                if m == "learned_direct":
-                    pred_err.append(float(torch.linalg.norm(dq - true) / torch.linalg.norm(true)))
+                    dq = mlp.predict(X[k], sigma_r)
+                    judged_now = m == "learned_judged" and (k - ntrain) % judge_every == 0
+                    if m == "learned_blend" or judged_now:
+                        its, rr, c = sim.solver.solve_guided(surf, sv["b"], q, dq, tol=tol,
+                                                             max_iter=sim.max_iter)
+                        extra = 1
+                        if judged_now:
+                            use_learned = c >= 0.5
+                        else:
+                            blend.append(c)
+                    elif m == "learned_direct" or use_learned:
+                        sim.solver.advance(q, dq, 1.0, out=q)
+                        its, rr = sim.solver.solve(surf, sv["b"], q, tol=tol,
+                                                   max_iter=sim.max_iter)
+                    else:
+                        its, rr = sim.solver.solve(surf, sv["b"], q, tol=tol,
+                                                   max_iter=sim.max_iter)
+                    if m == "learned_direct":
+                        nt = float(torch.linalg.norm(true))
+                        pred_err.append(float(torch.linalg.norm(sv["dq_prev"] + dq - true)) / nt)
+                        extrap_err.append(float(torch.linalg.norm(sv["dq_prev"] - true)) / nt)
             torch.cuda.synchronize()
             res_t[m].append(time.perf_counter() - ta)
             res_it[m].append(its + extra)
@@ -176,10 +187,15 @@ def run(case, steps=200, train_steps=150, precision="mixed", tol=1e-6, restart=2
         "train_minibatches": nstep, "judge_every": judge_every,
         "starts": summary,
         "prediction_rel_err_mean": float(np.mean(pred_err)),
+        "extrapolation_rel_err_mean": float(np.mean(extrap_err)),
         "blend_step_mean": float(np.mean(blend)),
         "products_saved_per_solve": summary["plain"]["products_mean"]
         - summary["learned_judged"]["products_mean"],
+        "products_saved_vs_extrapolated": summary["extrapolated"]["products_mean"]
+        - summary["learned_judged"]["products_mean"],
         "speedup_vs_plain": summary["plain"]["seconds_mean"] / summary["learned_judged"]["seconds_mean"],
+        "speedup_vs_extrapolated": summary["extrapolated"]["seconds_mean"]
+        / summary["learned_judged"]["seconds_mean"],
     }
     return res, sim
 

@@ -79,11 +79,12 @@ def test_capsules_sl_fp64(capsules_sl):
 
 
 @pytest.mark.timeout(300)
-def test_capsules_sl_mixed(capsules_sl):
+@pytest.mark.parametrize("precision", ["mixed", "mixed_bf16"])
+def test_capsules_sl_mixed(capsules_sl, precision):
     c, ref = capsules_sl
     sel = np.asarray(ref["targets"])
-    print(f"case {c.name} mixed, {sel.size} sampled targets", flush=True)
-    u = run(c, "mixed")[sel]
+    print(f"case {c.name} {precision}, {sel.size} sampled targets", flush=True)
+    u = run(c, precision)[sel]
     assert rel_l2(u, np.asarray(ref["total"])) < TOLMIX
 
 
@@ -106,9 +107,10 @@ def test_capsules_dl_fp64(capsules_dl):
 
 
 @pytest.mark.timeout(300)
-def test_capsules_dl_mixed(capsules_dl):
+@pytest.mark.parametrize("precision", ["mixed", "mixed_bf16"])
+def test_capsules_dl_mixed(capsules_dl, precision):
     c, ref = capsules_dl
     sel = np.asarray(ref["targets"])
-    print(f"case {c.name} mixed, {sel.size} sampled targets", flush=True)
-    v = run(c, "mixed")[sel]
+    print(f"case {c.name} {precision}, {sel.size} sampled targets", flush=True)
+    v = run(c, precision)[sel]
     assert rel_l2(v, np.asarray(ref["total"])) < TOLMIX

@@ -140,25 +140,41 @@ def test_empty_inputs():
     assert out.shape == (0, 3)
 
 
+MIXED_MODES = ["mixed", "mixed_bf16"]   # FP32 MFMA / BF16 hi+lo split Chebyshev products
+
+
+@pytest.mark.parametrize("precision", MIXED_MODES)
 @pytest.mark.parametrize("cfg", DL_CASES + [(13, 300, 100, 5.0, 1.5, 2.0, 2.0, 40, 40, 33, None)])
-def test_double_layer_mixed(cfg):
+def test_double_layer_mixed(cfg, precision):
     seed, ns, nt, L, H, alpha, rc, Nx, Nz, Ny, Lz = cfg
     c = random_case(seed, ns, nt, L, H, alpha, rc, Nx, Nz, Ny, Lz=Lz, dl=True)
-    print(f"case {c.name} double layer mixed", flush=True)
+    print(f"case {c.name} double layer {precision}", flush=True)
     g = O.SlitGrid.from_case(c)
     ref = O.double_layer(g, c.xs, c.f, c.xt, c.normals)
-    plan = G.Plan.from_case(c, precision="mixed")
+    plan = G.Plan.from_case(c, precision=precision)
     v = plan.double_layer(dev(c.xs), dev(c.f), dev(c.xt), dev(c.normals)).cpu().numpy()
     assert rel_l2(v, ref) < TOLMIX
 
 
+@pytest.mark.parametrize("precision", MIXED_MODES)
 @pytest.mark.parametrize("cfg", SL_CASES)
-def test_single_layer_random_mixed(cfg):
+def test_single_layer_random_mixed(cfg, precision):
     seed, ns, nt, L, H, alpha, rc, Nx, Nz, Ny, Lz = cfg
     c = random_case(seed, ns, nt, L, H, alpha, rc, Nx, Nz, Ny, Lz=Lz)
-    print(f"case {c.name} single layer random mixed", flush=True)
+    print(f"case {c.name} single layer random {precision}", flush=True)
     g = O.SlitGrid.from_case(c)
     ref = O.single_layer(g, c.xs, c.f, c.xt)
-    plan = G.Plan.from_case(c, precision="mixed")
+    plan = G.Plan.from_case(c, precision=precision)
     u = plan.single_layer(dev(c.xs), dev(c.f), dev(c.xt)).cpu().numpy()
     assert rel_l2(u, ref) < TOLMIX
+
+
+@pytest.mark.parametrize("precision", MIXED_MODES)
+def test_global_part_mixed(c0, precision):
+    """The global part alone (where the Chebyshev products act), against the
+    oracle's global part."""
+    c, g, ref = c0
+    print(f"case {c.name} global part {precision}", flush=True)
+    plan = G.Plan.from_case(c, precision=precision)
+    u = plan.single_layer(dev(c.xs), dev(c.f), dev(c.xt), parts=G.PART_GLOBAL).cpu().numpy()
+    assert rel_l2(u, ref["global"]) < TOLMIX
