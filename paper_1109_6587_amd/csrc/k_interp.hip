@@ -5,7 +5,9 @@
 // Stencil: x nodes i0-2..i0+2 (periodic) with i0 = floor(x/dx + 1/2), z
 // likewise; y nodes j0-2..j0+2 of the Gauss-Lobatto grid with
 // j0 = clamp(rint(arccos(y/H) (Ny-1)/pi), 2, Ny-3).  Indices and weights are
-// formed in FP64 from FP64 positions in both precision modes.
+// formed in FP64 from FP64 positions in both precision modes; the sums run in
+// the grid's precision, each stencil row's five z nodes first, then times the
+// row's x-y weight.
 #include "ggem_internal.h"
 
 namespace ggem {
@@ -84,8 +86,8 @@ __global__ void __launch_bounds__(256) interp_combine(InterpArgs a) {
       res[c] = v;
     }
   }
-  double acc[NC];
-  for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+  T acc[NC];
+  for (int c = 0; c < NC; ++c) acc[c] = (T)0;
   if (GLOBAL && valid) {
     const double x = a.tx[t], y = a.ty[t], z = a.tz[t];
     const double fx = floor(x / a.dx + 0.5), fz = floor(z / a.dz + 0.5);
@@ -103,15 +105,19 @@ __global__ void __launch_bounds__(256) interp_combine(InterpArgs a) {
     for (int q = 0; q < 5; ++q) kk[q] = wrap1(k0 - 2 + q, a.Nz);
     const T* g = (const T*)a.grid;
     const size_t fs = (size_t)a.Ny * a.Nx * a.Nz;
+    T tz[5];
+    for (int q = 0; q < 5; ++q) tz[q] = (T)wz[q];
     for (int row = r; row < 25; row += kGrp) {
       const int qa = row / 5, qb = row % 5;
       const int ii = wrap1(i0 - 2 + qb, a.Nx);
       const size_t base = ((size_t)(j0 - 2 + qa) * a.Nx + ii) * a.Nz;
-      const double wab = wy[qa] * wx[qb];
-      for (int qc = 0; qc < 5; ++qc) {
-        const double w = wab * wz[qc];
-        const size_t idx = base + kk[qc];
-        for (int c = 0; c < NC; ++c) acc[c] += w * (double)g[c * fs + idx];
+      const T wab = (T)(wy[qa] * wx[qb]);
+      // the row's five z nodes first, then its x-y weight
+      for (int c = 0; c < NC; ++c) {
+        const T* gc = g + c * fs + base;
+        T zr = tz[0] * gc[kk[0]];
+        for (int qc = 1; qc < 5; ++qc) zr = fma(tz[qc], gc[kk[qc]], zr);
+        acc[c] = fma(wab, zr, acc[c]);
       }
     }
   }
@@ -136,6 +142,124 @@ __global__ void __launch_bounds__(256) interp_combine(InterpArgs a) {
     }
   }
   const size_t o = 3 * (size_t)slot;
+  a.out[o] = res[0];
+  a.out[o + 1] = res[1];
+  a.out[o + 2] = res[2];
+}
+
+// Large target sets: one thread per target, 256 consecutive sorted targets
+// per block (they share one or two cells).  The box of grid nodes that their
+// stencils cover is staged in LDS one field at a time and every thread sums
+// its 125 nodes from there, in the order of interp_combine.  Blocks whose box
+// exceeds 56 KiB of LDS (targets far apart in the sorted order, e.g. across
+// a row of cells) gather from global memory as interp_combine does.
+constexpr int kBoxBytes = 56 * 1024;
+
+template <typename T, bool STRESS>
+__global__ void __launch_bounds__(256) interp_staged(InterpArgs a) {
+  extern __shared__ unsigned char smem[];
+  T* box = (T*)smem;
+  __shared__ double ly[kMaxNy];
+  __shared__ int lo[3], hi[3];
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  const bool valid = t < a.nt;
+  constexpr int NC = STRESS ? 6 : 3;
+  for (int j = threadIdx.x; j < a.Ny; j += 256) ly[j] = a.y[j];
+  if (threadIdx.x < 3) {
+    lo[threadIdx.x] = 1 << 30;
+    hi[threadIdx.x] = -(1 << 30);
+  }
+  __syncthreads();
+  const T* ul = (const T*)a.ul;
+  double res[3] = {0.0, 0.0, 0.0};
+  double wx[5], wz[5], wy[5];
+  int i0 = 0, k0 = 0, j0 = 2;
+  if (valid) {
+    for (int c = 0; c < 3; ++c) {
+      double v = 0.0;
+      for (int s = 0; s < kNearSlices; ++s) v += (double)ul[(size_t)(3 * s + c) * a.tcap + t];
+      res[c] = v;
+    }
+    const double x = a.tx[t], y = a.ty[t], z = a.tz[t];
+    const double fx = floor(x / a.dx + 0.5), fz = floor(z / a.dz + 0.5);
+    lagrange5_uniform(x / a.dx - fx, wx);
+    lagrange5_uniform(z / a.dz - fz, wz);
+    const int N = a.Ny - 1;
+    j0 = (int)rint(acos(y / a.H) * N / 3.141592653589793);
+    j0 = j0 < 2 ? 2 : (j0 > a.Ny - 3 ? a.Ny - 3 : j0);
+    double ny[5];
+    for (int q = 0; q < 5; ++q) ny[q] = ly[j0 - 2 + q];
+    lagrange5(y, ny, wy);
+    i0 = (int)fx - 2;   // first stencil node, unwrapped: in [-2, Nx - 2]
+    k0 = (int)fz - 2;
+    atomicMin(&lo[0], j0 - 2);
+    atomicMax(&hi[0], j0 - 2);
+    atomicMin(&lo[1], i0);
+    atomicMax(&hi[1], i0);
+    atomicMin(&lo[2], k0);
+    atomicMax(&hi[2], k0);
+  }
+  __syncthreads();
+  const int bj = hi[0] - lo[0] + 5, bi = hi[1] - lo[1] + 5, bk = hi[2] - lo[2] + 5;
+  const int nbox = bj * bi * bk;
+  const size_t fs = (size_t)a.Ny * a.Nx * a.Nz;
+  const T* g = (const T*)a.grid;
+  T acc[NC];
+  for (int c = 0; c < NC; ++c) acc[c] = (T)0;
+  // weights in T: the z weights and the 25 x-y products (formed in FP64)
+  T tz[5], twab[25];
+  for (int q = 0; q < 5; ++q) tz[q] = (T)wz[q];
+  for (int row = 0; row < 25; ++row) twab[row] = (T)(wy[row / 5] * wx[row % 5]);
+  if (nbox * (int)sizeof(T) <= kBoxBytes) {
+    const int oj = j0 - 2 - lo[0], oi = i0 - lo[1], ok = k0 - lo[2];
+    for (int c = 0; c < NC; ++c) {
+      for (int e = threadIdx.x; e < nbox; e += 256) {
+        const int kb = e % bk, r = e / bk, ib = r % bi, jb = r / bi;
+        const int gi = wrap1(lo[1] + ib, a.Nx), gk = wrap1(lo[2] + kb, a.Nz);
+        box[e] = g[c * fs + ((size_t)(lo[0] + jb) * a.Nx + gi) * a.Nz + gk];
+      }
+      __syncthreads();
+      if (valid) {
+        T sum = (T)0;
+        for (int row = 0; row < 25; ++row) {
+          const int qa = row / 5, qb = row % 5;
+          const int base = ((oj + qa) * bi + oi + qb) * bk + ok;
+          T zr = tz[0] * box[base];
+          for (int qc = 1; qc < 5; ++qc) zr = fma(tz[qc], box[base + qc], zr);
+          sum = fma(twab[row], zr, sum);
+        }
+        acc[c] = sum;
+      }
+      __syncthreads();
+    }
+  } else if (valid) {
+    int kk[5];
+    for (int q = 0; q < 5; ++q) kk[q] = wrap1(k0 + q, a.Nz);
+    for (int row = 0; row < 25; ++row) {
+      const int qa = row / 5, qb = row % 5;
+      const int ii = wrap1(i0 + qb, a.Nx);
+      const size_t base = ((size_t)(j0 - 2 + qa) * a.Nx + ii) * a.Nz;
+      for (int c = 0; c < NC; ++c) {
+        const T* gc = g + c * fs + base;
+        T zr = tz[0] * gc[kk[0]];
+        for (int qc = 1; qc < 5; ++qc) zr = fma(tz[qc], gc[kk[qc]], zr);
+        acc[c] = fma(twab[row], zr, acc[c]);
+      }
+    }
+  }
+  if (!valid) return;
+  if (!STRESS) {
+    res[0] += acc[0];
+    res[1] += acc[1];
+    res[2] += acc[2];
+  } else {
+    const T* tn = (const T*)a.tn;
+    const double nx = tn[t], nyv = tn[a.tcap + t], nz = tn[2 * a.tcap + t];
+    res[0] += acc[0] * nx + acc[3] * nyv + acc[4] * nz;
+    res[1] += acc[3] * nx + acc[1] * nyv + acc[5] * nz;
+    res[2] += acc[4] * nx + acc[5] * nyv + acc[2] * nz;
+  }
+  const size_t o = 3 * (size_t)a.perm[t];
   a.out[o] = res[0];
   a.out[o + 1] = res[1];
   a.out[o + 2] = res[2];
@@ -170,9 +294,16 @@ hipError_t launch_interp(Plan& p, int nt, double* out, bool stress, bool with_gl
   a.ul = p.ul;
   a.grid = p.phys;
   a.out = out;
-  if (nt < 65536) launch_interp_g<T, 16>(p, a, nt, stress, with_global);
-  else if (nt < 262144) launch_interp_g<T, 4>(p, a, nt, stress, with_global);
-  else launch_interp_g<T, 1>(p, a, nt, stress, with_global);
+  if (nt < 65536) {
+    launch_interp_g<T, 16>(p, a, nt, stress, with_global);
+  } else if (!with_global) {
+    launch_interp_g<T, 1>(p, a, nt, stress, with_global);
+  } else {
+    const unsigned nb = (unsigned)((nt + 255) / 256);
+    const size_t lds = kBoxBytes;
+    if (stress) interp_staged<T, true><<<nb, 256, lds, p.stream>>>(a);
+    else interp_staged<T, false><<<nb, 256, lds, p.stream>>>(a);
+  }
   return hipGetLastError();
 }
 

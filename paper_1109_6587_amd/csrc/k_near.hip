@@ -269,6 +269,7 @@ struct NearArgs {
   size_t sstride;          // elements between the slices' partial outputs
   double scale;            // output factor
   unsigned long long* work;  // pair counter (null: not counted)
+  const int* order;        // targets of each cell in the order items take them (null: sorted)
 };
 
 // Work item: up to 64 sorted targets of one cell (one per lane).  Its
@@ -303,8 +304,10 @@ __global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k, KcF kf
   const int c = a.item_cell[item];
   const int t0 = a.tcell[c] + (item - a.item_start[c]) * 64;
   const int t1 = min(a.tcell[c + 1], t0 + 64);
-  const int t = t0 + lane;
-  const bool active = t < t1;
+  const bool active = t0 + lane < t1;
+  // the lane's target (sorted index): items take a cell's targets in the
+  // cell's Morton order when one is given, so that they are compact
+  const int t = active && a.order ? a.order[t0 + lane] : t0 + lane;
   const int iz = c % g.ncz;
   const int ix = (c / g.ncz) % g.ncx;
   const int iy = c / (g.ncz * g.ncx);
@@ -422,10 +425,10 @@ __global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k, KcF kf
       const unsigned long long km = __ballot(keep);
       const int cnt = __popcll(km);
       if (cnt == 0) continue;
-      const int cnt4 = (cnt + 3) & ~3;
+      const int cnt2 = (cnt + 1) & ~1;
       __builtin_amdgcn_wave_barrier();
-      if (FAST && lane >= cnt && lane < cnt4) {
-        // padding to a multiple of four: a far-away point of zero strength
+      if (FAST && lane >= cnt && lane < cnt2) {
+        // padding to a multiple of two: a far-away point of zero strength
         lp[wave][lane] = make_double4(1e30, 1e30, 1e30, 0.0);
         typename Vec4<T>::t z;
         z.x = z.y = z.z = z.w = (T)0;
@@ -445,21 +448,21 @@ __global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k, KcF kf
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       if constexpr (FAST) {
-        // every lane takes every staged source, four per LDS round trip, in
+        // every lane takes every staged source, two per LDS round trip, in
         // staged (sorted) order; pairs outside 0 < r <= r_c add exact zeros.
         // The displacement is formed in FP64 and rounded per component;
         // separations with alpha r < 1e-2 are left to the FP64 pass after the loop.
         unsigned long long tiny_w = 0;
-        for (int j0 = 0; j0 < cnt4; j0 += 4) {
-          double4 qg[4];
-          float4 fg[4];
+        for (int j0 = 0; j0 < cnt2; j0 += 2) {
+          double4 qg[2];
+          float4 fg[2];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
+          for (int u = 0; u < 2; ++u) {
             qg[u] = lp[wave][j0 + u];
             fg[u] = lf[wave][j0 + u];
           }
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
+          for (int u = 0; u < 2; ++u) {
             const float dx = (float)(px - qg[u].x), dy = (float)(py - qg[u].y),
                         dz = (float)(pz - qg[u].z);
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
@@ -651,10 +654,79 @@ static NearArgs near_args(Plan& p, const Binned& tg, void* out, size_t ostride) 
   a.sstride = 3 * ostride;
   a.scale = 0.039788735772973833942;  // 1/(8 pi)
   a.work = nullptr;
+  a.order = nullptr;
   return a;
 }
 
 static unsigned near_grid(Plan& p, int nt) { return (unsigned)((nt + 63) / 64 + p.cg.ncells); }
+
+// Order of the targets inside each cell for the near-field work items: by
+// the Morton code of their position on an 8 x 8 x 8 lattice over the cell
+// (bits of x, y and z interleaved), stable, so that 64 consecutive targets
+// are close together and their bounding box admits fewer candidate sources.
+// One wave per cell: a histogram of the 512 codes, its exclusive scan, then
+// a scatter in input order with equal codes ranked by wave ballots.
+__global__ void __launch_bounds__(64) near_order(CellGeom g, const int* __restrict__ tcell,
+                                                 const double* __restrict__ tx,
+                                                 const double* __restrict__ ty,
+                                                 const double* __restrict__ tz,
+                                                 int* __restrict__ order) {
+  __shared__ int hist[512];
+  const int c = blockIdx.x, lane = threadIdx.x;
+  const int s0 = tcell[c], s1 = tcell[c + 1], n = s1 - s0;
+  if (n <= 0) return;
+  if (n <= 64) {  // one work item: any order
+    if (lane < n) order[s0 + lane] = s0 + lane;
+    return;
+  }
+  const int iz = c % g.ncz, ix = (c / g.ncz) % g.ncx, iy = c / (g.ncz * g.ncx);
+  auto code = [&](int i) {
+    const int a = min(7, max(0, (int)((tx[i] * g.icx - ix) * 8.0)));
+    const int b = min(7, max(0, (int)(((ty[i] + g.H) * g.icy - iy) * 8.0)));
+    const int d = min(7, max(0, (int)((tz[i] * g.icz - iz) * 8.0)));
+    int m = 0;
+    for (int k = 0; k < 3; ++k)
+      m |= (((a >> k) & 1) << (3 * k)) | (((b >> k) & 1) << (3 * k + 1)) | (((d >> k) & 1) << (3 * k + 2));
+    return m;
+  };
+  for (int k = lane; k < 512; k += 64) hist[k] = 0;
+  __syncthreads();
+  for (int i = s0 + lane; i < s1; i += 64) atomicAdd(&hist[code(i)], 1);
+  __syncthreads();
+  if (lane == 0) {
+    int run = 0;
+    for (int k = 0; k < 512; ++k) {
+      const int v = hist[k];
+      hist[k] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  for (int base = s0; base < s1; base += 64) {
+    const int i = base + lane;
+    const bool valid = i < s1;
+    const int key = valid ? code(i) : 0;
+    unsigned long long m = __ballot(valid);
+    for (int b = 0; b < 9; ++b) {
+      const bool bit = (key >> b) & 1;
+      const unsigned long long bm = __ballot(bit);
+      m &= bit ? bm : ~bm;
+    }
+    const int rank = __popcll(m & lt);
+    const int before = valid ? hist[key] : 0;
+    __builtin_amdgcn_wave_barrier();
+    if (valid && rank == 0) hist[key] = before + __popcll(m);
+    __builtin_amdgcn_wave_barrier();
+    if (valid) order[s0 + before + rank] = i;
+  }
+}
+
+static const int* launch_near_order(Plan& p, const Binned& tg) {
+  near_order<<<(unsigned)p.cg.ncells, 64, 0, p.stream>>>(p.cg, tg.cell_start, tg.x, tg.y, tg.z,
+                                                        p.norder);
+  return p.norder;
+}
 
 template <typename T>
 hipError_t launch_near_sl(Plan& p, int nt) {
@@ -662,6 +734,7 @@ hipError_t launch_near_sl(Plan& p, int nt) {
   NearArgs a = near_args(p, *p.tview, p.ul, (size_t)p.p.max_tgt);
   a.tcap = (size_t)p.p.max_tgt;
   a.work = p.work;
+  a.order = launch_near_order(p, *p.tview);
   launch_near_kernel<T, false>(p, a, near_grid(p, nt));
   return hipGetLastError();
 }
@@ -673,6 +746,7 @@ hipError_t launch_near_dl(Plan& p, int nt) {
   a.tn = p.tnrm;
   a.tcap = (size_t)p.p.max_tgt;
   a.work = p.work;
+  a.order = launch_near_order(p, *p.tview);
   launch_near_kernel<T, true>(p, a, near_grid(p, nt));
   return hipGetLastError();
 }
