@@ -173,11 +173,18 @@ int ggem_plan_time_stage(ggem_plan_t plan, int stage, int max_calls);
  * their number. */
 int ggem_plan_stage_time(ggem_plan_t plan, double* total_ms, int* calls);
 
-/* Work units of the last evaluation, counted by the kernels themselves:
+/* Work units of the last evaluation, counted by the kernels themselves when
+ * counting was on for it (ggem_plan_count_work), else zeros:
  * counts[0] = target/source pairs within rc evaluated by the local sum (the
  * wall nodes excluded), counts[1] = (source, grid node within rc) updates of
  * the global density.  Waits for the plan's stream.  counts: host array of 2. */
 int ggem_plan_work(ggem_plan_t plan, unsigned long long* counts);
+
+/* Turn the kernels' work counting on (on != 0) or off for the following
+ * evaluations of the plan; off by default, so that evaluations pay nothing
+ * for it (a diagnostic: the counts give the work units of a throughput
+ * figure).  Results do not depend on it.  Errors: GGEM_E_ARG (null plan). */
+int ggem_plan_count_work(ggem_plan_t plan, int on);
 
 /* ---- batches of independent slit problems -------------------------------
  *

@@ -718,6 +718,12 @@ extern "C" int ggem_plan_work(ggem_plan_t plan, unsigned long long* counts) {
   return GGEM_OK;
 }
 
+extern "C" int ggem_plan_count_work(ggem_plan_t plan, int on) {
+  if (int rc = check_plan(plan)) return rc;
+  plan->p.count_work = on != 0;
+  return GGEM_OK;
+}
+
 // ---- single layer without device allocation --------------------------------
 //
 // Workspace of ggem_single_layer_noalloc: one static array per GPU, resident

@@ -125,6 +125,7 @@ struct Plan {
   int timed_max;
   int timed_calls;
   hipEvent_t* timed_ev;  // 2 * timed_max events
+  bool count_work;    // kernels count their work units (pairs, updates)
 };
 
 // ---- kernel launchers (each enqueues on p.stream) -------------------------

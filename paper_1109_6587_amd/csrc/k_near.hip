@@ -6,13 +6,13 @@
 // (no atomics, fixed order of summation).
 //
 // FP64 mode forms every displacement and decides every cutoff and coincidence
-// in FP64, as the oracle does.  Mixed mode (FAST below) decides the cutoff in
-// FP32 relative to the target cell's corner, so pairs within an FP32 rounding
-// of r_c may be kept or dropped (their kernel is below 1e-7 of its peak).
-// Pairs with alpha r < 1e-2 are decided and evaluated in FP64 in mixed mode,
-// so only exactly coincident points take the self rule and no FP32
-// intermediate overflows.  Other kernel values are evaluated in T (double, or float in
-// mixed mode) from the displacement formed in FP64.
+// in FP64, as the oracle does.  Mixed mode (FAST below) decides the cutoff on
+// the FP32 square of the FP64 displacement rounded per component, so pairs
+// within an FP32 rounding of r_c may be kept or dropped (their kernel is below
+// 1e-7 of its peak).  Pairs with alpha r < 1e-2 are decided and evaluated in
+// FP64 in mixed mode, so only exactly coincident points take the self rule and
+// no FP32 intermediate overflows.  Other kernel values are evaluated in T
+// (double, or float in mixed mode) from the displacement formed in FP64.
 #include "ggem_internal.h"
 
 namespace ggem {
@@ -281,14 +281,20 @@ struct NearArgs {
 // wave u mod W; each wave stages its batches through its own LDS slice, and
 // the W partial sums are added in wave order at the end.
 //
-// Pass 1 tests every staged source against the lane's target and keeps a bit
-// mask of the pairs within r_c; pass 2 evaluates the kernel only for those.
-// FAST (mixed precision, >= 3 cells per periodic direction): sources are
-// staged shifted into the target cell's periodic image, pass 1 compares in
-// FP32 relative to the cell corner and pass 2 forms the displacement in FP64
-// without a per-pair image search.  Otherwise every displacement is the FP64
-// minimum image and the cutoff is decided in FP64.
-template <typename T, bool DL, bool FAST, int W>
+// A wave stages only the batch's sources within r_c of the bounding box of
+// the item's targets.  FAST (mixed precision, >= 3 cells per periodic
+// direction): the sources are staged shifted into the target cell's periodic
+// image, and every lane evaluates every staged source without branches: the
+// displacement is formed in FP64 and rounded per component, the cutoff is
+// decided on the FP32 square, and pairs outside alpha r >= 1e-2, r <= r_c get
+// zero coefficients (closer pairs are evaluated in FP64 after the batch).
+// Otherwise pass 1 keeps a bit mask of the pairs within r_c, decided on the
+// FP64 minimum-image displacement, and pass 2 evaluates the kernel for those
+// only.
+//
+// CNT (FAST only): count the in-range pairs into a.work; the exact path
+// counts per batch whenever a.work is set.
+template <typename T, bool DL, bool FAST, int W, bool CNT>
 __global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k, KcF kf) {
   // staged sources: FP64 position (x, y, z, unused) and strength (x, y, z,
   // unused), one vector read each
@@ -470,7 +476,7 @@ __global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k, KcF kf
             const bool ok = ge && r2 <= rc2f;
             // lane masks stay scalar: every lane runs this loop
             tiny_w |= ~__builtin_amdgcn_ballot_w64(ge);
-            if (a.work) npairs_w += __popcll(__builtin_amdgcn_ballot_w64(ok) & amask);
+            if (CNT) npairs_w += __popcll(__builtin_amdgcn_ballot_w64(ok) & amask);
             if (DL)
               stresslet_masked(dx, dy, dz, r2, ok, fg[u].x, fg[u].y, fg[u].z, nx, ny, nz, kf, ux,
                                uy, uz, sn);
@@ -541,8 +547,8 @@ __global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k, KcF kf
     uy = fmaf(sn, ny, uy);
     uz = fmaf(sn, nz, uz);
   }
-  if (a.work && FAST && lane == 0 && npairs_w) atomicAdd(a.work, npairs_w);
-  if (a.work) wave_count_add(a.work, npairs);
+  if (CNT && FAST && lane == 0 && npairs_w) atomicAdd(a.work, npairs_w);
+  if (!FAST && a.work) wave_count_add(a.work, npairs);
   part[wave][0][lane] = ux + k.selfc * sfx;
   part[wave][1][lane] = uy + k.selfc * sfy;
   part[wave][2][lane] = uz + k.selfc * sfz;
@@ -574,11 +580,14 @@ static void launch_near_w(Plan& p, const NearArgs& a, unsigned grid) {
   const KcF kf = make_kcf(p.p.alpha);
   if constexpr (sizeof(T) == 4) {
     if (fast) {
-      near_field<T, DL, true, W><<<g, 64 * W, 0, p.stream>>>(a, make_kc<T>(p.p.alpha), kf);
+      if (a.work)
+        near_field<T, DL, true, W, true><<<g, 64 * W, 0, p.stream>>>(a, make_kc<T>(p.p.alpha), kf);
+      else
+        near_field<T, DL, true, W, false><<<g, 64 * W, 0, p.stream>>>(a, make_kc<T>(p.p.alpha), kf);
       return;
     }
   }
-  near_field<T, DL, false, W><<<g, 64 * W, 0, p.stream>>>(a, make_kc<T>(p.p.alpha), kf);
+  near_field<T, DL, false, W, false><<<g, 64 * W, 0, p.stream>>>(a, make_kc<T>(p.p.alpha), kf);
 }
 
 // grid = an upper bound of the work items (targets/64 + cells)
@@ -733,7 +742,7 @@ hipError_t launch_near_sl(Plan& p, int nt) {
   if (nt <= 0) return hipSuccess;
   NearArgs a = near_args(p, *p.tview, p.ul, (size_t)p.p.max_tgt);
   a.tcap = (size_t)p.p.max_tgt;
-  a.work = p.work;
+  a.work = p.count_work ? p.work : nullptr;
   a.order = launch_near_order(p, *p.tview);
   launch_near_kernel<T, false>(p, a, near_grid(p, nt));
   return hipGetLastError();
@@ -745,7 +754,7 @@ hipError_t launch_near_dl(Plan& p, int nt) {
   NearArgs a = near_args(p, *p.tview, p.ul, (size_t)p.p.max_tgt);
   a.tn = p.tnrm;
   a.tcap = (size_t)p.p.max_tgt;
-  a.work = p.work;
+  a.work = p.count_work ? p.work : nullptr;
   a.order = launch_near_order(p, *p.tview);
   launch_near_kernel<T, true>(p, a, near_grid(p, nt));
   return hipGetLastError();

@@ -96,7 +96,9 @@ __device__ inline void lds_wave_sync() {
 // those within r_c of both halves are added at both of a lane's nodes, the
 // others go to a per-half list that carries over between batches and is
 // added at the lane's node of that half in complete groups of four.
-template <typename T, bool REL>
+//
+// CNT: count the (source, node) pairs within r_c into a.work.
+template <typename T, bool REL, bool CNT>
 __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
   using Q = typename V4<T>::t;
   __shared__ double lx[REL ? 1 : 4][64], ly[REL ? 1 : 4][64], lz[REL ? 1 : 4][64];
@@ -189,7 +191,7 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
           const T dx = nrx - qg[u].x, dy = nry - qg[u].y, dz = nz - qg[u].z;
           const T r2 = dx * dx + dy * dy + dz * dz;
           const bool in = r2 <= rc2t;
-          nupd += (unsigned)__popcll(__ballot(in));
+          if (CNT) nupd += (unsigned)__popcll(__ballot(in));
           const T w = in ? t_exp2_s(-r2) * fma((T)-0.69314718055994531, r2, (T)2.5) : (T)0;
           ax += w * fg[u].x;
           ay += w * fg[u].y;
@@ -351,7 +353,7 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
                   r21 = (T)d21;
                 }
                 // the wave's counts, scalar
-                nupd += (unsigned)__popcll(__ballot(in)) + (unsigned)__popcll(__ballot(in1));
+                if (CNT) nupd += (unsigned)__popcll(__ballot(in)) + (unsigned)__popcll(__ballot(in1));
                 T w, w1;
                 if (REL) {  // r2 is the scaled u
                   w = in ? t_exp2_s(-r2) * fma((T)-0.69314718055994531, r2, (T)2.5) : (T)0;
@@ -395,7 +397,7 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
     r[4 * 64 + lane] = gy1;
     r[5 * 64 + lane] = gz1;
   }
-  if (lane == 0) cnt_w[wave] = nupd;
+  if (CNT && lane == 0) cnt_w[wave] = nupd;
   __syncthreads();
   if (wave != 0) return;
 #pragma unroll
@@ -407,7 +409,7 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
     gy1 += red[w][4][lane];
     gz1 += red[w][5][lane];
   }
-  if (lane == 0) {
+  if (CNT && lane == 0) {
     unsigned long long tot = 0;
     for (int w = 0; w < NW; ++w) tot += cnt_w[w];
     if (tot) atomicAdd(a.work, tot);
@@ -448,12 +450,15 @@ hipError_t launch_spread(Plan& p, int /*unused*/) {
   a.sf = p.src.s;
   a.scap = (size_t)p.p.max_src;
   a.out = p.phys;
-  a.work = p.work + 1;
+  a.work = p.count_work ? p.work + 1 : nullptr;
   dim3 grid((p.p.Nz + TZ - 1) / TZ, (p.p.Nx + TX - 1) / TX, (p.p.Ny + TY - 1) / TY);
   // tile-relative staging needs one periodic image per (tile, source) pair
   const bool rel = sizeof(T) == 4 && WT * p.dx + p.rc < 0.5 * p.p.Lx && WZ * p.dz + p.rc < 0.5 * p.p.Lz;
-  if (rel) spread_tile<T, true><<<grid, TB, 0, p.stream>>>(a);
-  else spread_tile<T, false><<<grid, TB, 0, p.stream>>>(a);
+  const bool cnt = a.work != nullptr;
+  if (rel && cnt) spread_tile<T, true, true><<<grid, TB, 0, p.stream>>>(a);
+  else if (rel) spread_tile<T, true, false><<<grid, TB, 0, p.stream>>>(a);
+  else if (cnt) spread_tile<T, false, true><<<grid, TB, 0, p.stream>>>(a);
+  else spread_tile<T, false, false><<<grid, TB, 0, p.stream>>>(a);
   return hipGetLastError();
 }
 

@@ -31,7 +31,7 @@ E_DEVICE = -5
 EXPORTS = (
     "ggem_plan_create", "ggem_plan_destroy", "ggem_plan_set_stream", "ggem_plan_status",
     "ggem_single_layer", "ggem_double_layer", "ggem_spread_grid", "ggem_plan_time_stage",
-    "ggem_plan_stage_time", "ggem_plan_work", "ggem_solver_create", "ggem_solver_destroy",
+    "ggem_plan_stage_time", "ggem_plan_work", "ggem_plan_count_work", "ggem_solver_create", "ggem_solver_destroy",
     "ggem_fredholm_apply", "ggem_fredholm_solve", "ggem_surface_geometry", "ggem_drop_rhs",
     "ggem_surface_velocity", "ggem_advance", "ggem_fredholm_solve_guided", "ggem_mlp_create",
     "ggem_mlp_destroy", "ggem_mlp_set_params", "ggem_mlp_get_params", "ggem_mlp_features",
@@ -92,6 +92,7 @@ def load_library(path: str = LIB_PATH):
     lib.ggem_plan_stage_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int)]
     lib.ggem_plan_work.argtypes = [vp, ctypes.POINTER(ctypes.c_ulonglong)]
+    lib.ggem_plan_count_work.argtypes = [vp, ip]
     lib.ggem_solver_create.argtypes = [vp, ctypes.POINTER(SolverParams), ctypes.POINTER(vp)]
     lib.ggem_solver_destroy.argtypes = [vp]
     dd = ctypes.c_double
@@ -207,8 +208,13 @@ class Plan:
         _check(_lib.ggem_plan_stage_time(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
 
+    def count_work(self, on=True):
+        """Have the kernels count their work units in the following calls."""
+        _check(_lib.ggem_plan_count_work(self._h, 1 if on else 0))
+
     def work(self):
-        """(local pairs, spread updates) counted by the kernels in the last call."""
+        """(local pairs, spread updates) counted by the kernels in the last call
+        (zeros unless counting was on for it)."""
         c = (ctypes.c_ulonglong * 2)()
         _check(_lib.ggem_plan_work(self._h, c))
         return int(c[0]), int(c[1])

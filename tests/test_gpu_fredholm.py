@@ -207,12 +207,21 @@ def test_learned_warm_start_pipeline():
 
 
 def test_learned_warm_start_gains():
-    """On the 100-drop workload (first 40 steps: train on 30, test on 10), the
-    judged learned start needs fewer products than the plain warm start."""
+    """On the 100-drop workload (first 40 steps: train on 30, test on 10).
+
+    The fair baseline is the extrapolated start q_prev + dq_prev, not the
+    previous stage's density.  The network, trained on what extrapolation
+    misses, does NOT beat extrapolation on this workload: both starts need the
+    same number of products (and the judged rule pays its guided product every
+    fourth solve).  Asserted: extrapolation beats the plain start, the learned
+    start is not worse than extrapolation, and the judged rule costs at most
+    its extra product."""
     from paper_1109_6587_amd.warmstart import run
     print("warm start gain (100 drops, 40 steps)", flush=True)
     res, _ = run(case_shear_drops(4), steps=40, train_steps=30, log=lambda m: print(m, flush=True))
     st = res["starts"]
-    print(st, flush=True)
-    assert st["learned_judged"]["products_mean"] < st["plain"]["products_mean"] - 0.5
-    assert st["learned_direct"]["products_mean"] < st["plain"]["products_mean"]
+    print(st, res["prediction_rel_err_mean"], res["extrapolation_rel_err_mean"], flush=True)
+    prod = {k: v["products_mean"] for k, v in st.items()}
+    assert prod["extrapolated"] < prod["plain"] - 0.5
+    assert prod["learned_direct"] <= prod["extrapolated"] + 0.25
+    assert prod["learned_judged"] <= prod["extrapolated"] + 1.0 / res["judge_every"] + 0.25
