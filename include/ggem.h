@@ -237,7 +237,7 @@ int ggem_batch_branch(ggem_batch_t batch, int instance);
  * kappa = (lambda - 1)/(lambda + 1).  The surface integral uses the three
  * interior Gauss points of every triangle (barycentric (2/3,1/6,1/6) and
  * permutations, weight area/3); each matrix-vector product is one GGEM double
- * layer on the plan.  Solved by restarted GMRES (Sec. 3.5) with FP64 Krylov
+ * layer on the plan.  Solved by restarted GMRES (Sec. 5) with FP64 Krylov
  * vectors and norms.  A solver owns its workspace (allocated at creation). */
 typedef struct ggem_solver_s* ggem_solver_t;
 
@@ -252,7 +252,7 @@ int ggem_solver_destroy(ggem_solver_t solver);
 
 /* y = (I + kappa/4pi D) x for nodal vectors x, y (n_nodes, 3) float64.
  * nodes (n_nodes,3), normals (n_nodes,3) (the paper's area-averaged node
- * normals, Sec. 3.4.2), kappa (n_nodes) or NULL to use kappa0, tri (n_tri,3)
+ * normals, Sec. 3.5.2), kappa (n_nodes) or NULL to use kappa0, tri (n_tri,3)
  * int32 node indices: all device arrays owned by the caller, read on the
  * plan's stream.  Node positions may be unwrapped (x and z are wrapped by the
  * evaluation); every triangle must be contiguous in space.  Triangle indices
@@ -286,7 +286,7 @@ int ggem_fredholm_solve(ggem_solver_t solver, long long n_nodes, const double* n
  * membranes with uniform tension) on the device; they run on the solver's
  * plan stream and use its Gauss-point workspace.
  *
- * ggem_surface_geometry: per node, the area-averaged normal (Sec. 3.4.2),
+ * ggem_surface_geometry: per node, the area-averaged normal (Sec. 3.5.2),
  * the node area A_p (one third of every incident triangle, Sec. 4) and the
  * cotangent Laplace-Beltrami of the position
  *   (Lap x)_p = 1/(2 A_p) sum_j (cot a_pj + cot b_pj)(x_j - x_p)
@@ -342,7 +342,7 @@ int ggem_fredholm_solve_guided(ggem_solver_t solver, long long n_nodes, const do
 /* ---- learned warm start: a per-node network ------------------------------
  *
  * Not in the paper, whose warm start is the previous stage's density
- * (Sec. 3.5).  A network of GGEM_MLP_IN inputs, three hidden layers of
+ * (Sec. 5).  A network of GGEM_MLP_IN inputs, three hidden layers of
  * GGEM_MLP_HIDDEN units with SiLU, and GGEM_MLP_OUT outputs, trained by mean
  * squared error with Adam (beta1 0.9, beta2 0.999, eps 1e-8).  Products run
  * with bfloat16 operands and FP32 accumulation; master weights, biases and

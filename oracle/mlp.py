@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY (see the package header).
 
 Network (the learned warm start of the Fredholm solve; not in the paper,
-whose warm start is the previous stage's density, Sec. 3.5):
+whose warm start is the previous stage's density, Sec. 5):
     h0 = x (13 features), z_l = W_l h_{l-1} + b_l, h_l = silu(z_l) (l = 1..3),
     y = W_4 h_3 + b_4  (3 outputs),  silu(z) = z / (1 + exp(-z)),
 loss = mean over samples and outputs of (y - t)^2, minimised by Adam

@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY (see the package header).
 
 * Node normals: the area-averaged normal of the triangles a node belongs to
-  (Sec. 3.4.2), i.e. the normalised sum of their area vectors.
+  (Sec. 3.5.2), i.e. the normalised sum of their area vectors.
 * Node areas: one third of the area of every incident triangle (Sec. 4).
 * Cotangent Laplace-Beltrami of the position,
       (Lap_s x)_i = 1/(2 A_i) sum_j (cot a_ij + cot b_ij) (x_j - x_i),

@@ -1,7 +1,7 @@
 // Fredholm second-kind equation for the single-layer density (Eq. qa,
-// discretised as in Sec. 3.5): at every element node x_b
+// discretised as in Sec. 5): at every element node x_b
 //   q_j(x_b) + (kappa_b/4pi) n_k(x_b) sum_n int q_i(x) T_jik(x_b, x) dS(x) = b_j(x_b),
-// i.e. (I + kappa/4pi D) q = b, solved by restarted GMRES (Sec. 3.5) with
+// i.e. (I + kappa/4pi D) q = b, solved by restarted GMRES (Sec. 5) with
 // every matrix-vector product evaluated by the GGEM double layer.
 //
 // Surface integral: q is linear on each flat triangle (Sec. 3.3.1); the
@@ -441,7 +441,7 @@ extern "C" int ggem_fredholm_solve_guided(ggem_solver_t s, long long n_nodes, co
 
 namespace {
 
-// Per node: area-averaged normal (Sec. 3.4.2), node area (one third of each
+// Per node: area-averaged normal (Sec. 3.5.2), node area (one third of each
 // incident triangle, Sec. 4) and the cotangent Laplace-Beltrami of the
 // position, (Lap x)_i = 1/(2 A_i) sum (cot a + cot b)(x_j - x_i), gathered
 // over the node's incident triangles (fixed order, no atomics).  A node

@@ -302,7 +302,13 @@ __global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k, KcF kf
   __shared__ typename Vec4<T>::t lf[W][64];
   __shared__ T part[W][3][64];
   const CellGeom& g = a.g;
-  const int item = blockIdx.x;
+  // XCD-aware: block b runs on XCD b % 8; each XCD takes chunks of 16
+  // consecutive work items in turn (the grid is a multiple of 128)
+  int item = blockIdx.x;
+  if ((gridDim.x & 127) == 0) {
+    const int q = blockIdx.x >> 3;
+    item = (q >> 4) * 128 + (blockIdx.x & 7) * 16 + (q & 15);
+  }
   const int nitems = a.item_start[g.ncells];
   if (item >= nitems) return;
   const int lane = threadIdx.x & 63;
@@ -667,7 +673,10 @@ static NearArgs near_args(Plan& p, const Binned& tg, void* out, size_t ostride) 
   return a;
 }
 
-static unsigned near_grid(Plan& p, int nt) { return (unsigned)((nt + 63) / 64 + p.cg.ncells); }
+static unsigned near_grid(Plan& p, int nt) {
+  const unsigned n = (unsigned)((nt + 63) / 64 + p.cg.ncells);
+  return (n + 127) & ~127u;
+}
 
 // Order of the targets inside each cell for the near-field work items: by
 // the Morton code of their position on an 8 x 8 x 8 lattice over the cell

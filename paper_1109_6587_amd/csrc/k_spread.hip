@@ -111,7 +111,14 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
   const CellGeom& g = a.g;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int k_lo = blockIdx.x * TZ;
+  // XCD-aware: blocks are dealt round-robin to the 8 XCDs, so block b runs on
+  // XCD b % 8; give each XCD a contiguous run of z tiles
+  int bx = blockIdx.x;
+  if ((gridDim.x & 7) == 0) {
+    const int per = gridDim.x >> 3;
+    bx = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  }
+  const int k_lo = bx * TZ;
   const int i_lo = blockIdx.y * TX;
   const int j_lo = blockIdx.z * TY;
   const int k = k_lo + (lane & 3), i = i_lo + ((lane >> 2) & 3), j = j_lo + (lane >> 4);

@@ -1,7 +1,7 @@
 // Learned warm start of the Fredholm solve: a per-node network
 //   13 -> 128 -> 128 -> 128 -> 3, SiLU on the hidden layers,
 // trained by mean squared error with Adam.  Not in the paper (its warm start
-// is the previous stage's density, Sec. 3.5); the plain warm start stays the
+// is the previous stage's density, Sec. 5); the plain warm start stays the
 // fallback (ggem_fredholm_solve_guided).
 //
 // Every product runs on the matrix cores as v_mfma_f32_16x16x16_bf16:

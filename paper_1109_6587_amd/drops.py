@@ -1,6 +1,6 @@
 """Drops in simple shear between walls, time-stepped on the device.
 
-Each stage of the explicit midpoint rule (Sec. 3.5):
+Each stage of the explicit midpoint rule (Sec. 5):
   1. node normals, node areas and Lap x of the current shape
      (ggem_surface_geometry);
   2. the right-hand side b of Eq. qa for drops with tension 1/Ca

@@ -296,7 +296,7 @@ def random_case(seed: int, ns: int, nt: int, L: float, H: float, alpha: float,
 
 def node_normals(V, F):
     """Area-averaged node normals of a triangulation (the node normal of the
-    paper's double layer, Sec. 3.4.2): sum of the adjacent triangles' area
+    paper's double layer, Sec. 3.5.2): sum of the adjacent triangles' area
     vectors, normalised."""
     a, b, c = V[F[:, 0]], V[F[:, 1]], V[F[:, 2]]
     cr = np.cross(b - a, c - a)          # 2 * area * outward normal
