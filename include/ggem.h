@@ -280,6 +280,68 @@ int ggem_fredholm_solve(ggem_solver_t solver, long long n_nodes, const double* n
                         long long n_tri, const int* tri, const double* b, double* q,
                         double tol, int max_iter, int* iters, double* rel_res);
 
+/* ---- boundary-integral single layer and rigid particles (Sec. 3.4, 6.1) --
+ *
+ * The paper's own discretisation of the single layer on a triangulated
+ * surface with the traction f linear on flat triangles (Sec. 3.3.1), at the
+ * mesh nodes z:
+ *   w(z) = (1/8pi) [ sum_k int_{S_k} f G^l(z - x) dS + sum_b G^g(z, x_b) f_b A_b ].
+ * Local part (Sec. 3.4.1, Eq. int_l): each triangle whose nearest vertex lies
+ * within r_c of z (minimum image) is integrated whole over its parent
+ * triangle, xi in [0, 1 - eta], with the product of two 4-point
+ * Gauss-Legendre rules; when z is a vertex of the triangle the parent
+ * triangle is taken in polar coordinates about it (the Jacobian removes the
+ * 1/r singularity).  Always FP64.  Global part (Sec. 3.4.2): the nodal
+ * trapezoid strengths f_b A_b (A_b one third of the areas of the triangles
+ * at b) through the plan's global problem (its precision), whose wall data
+ * is the local sum of those point forces.
+ *
+ * A rigid solver owns its workspace: node areas, the two parts, and a
+ * GMRES(restart) basis of 3 max_nodes + 6.  It runs on the plan's stream; the
+ * plan's capacities must cover max_nodes sources and targets.  Errors:
+ * GGEM_E_ARG (null pointer, restart outside 1..400, capacities out of
+ * range), GGEM_E_CAPACITY, GGEM_E_NOMEM. */
+typedef struct ggem_rigid_s* ggem_rigid_t;
+
+int ggem_rigid_create(ggem_plan_t plan, long long max_nodes, long long max_tri, int restart,
+                      ggem_rigid_t* out);
+int ggem_rigid_destroy(ggem_rigid_t rigid);
+
+/* w = the discretised single layer above, at every node.  nodes (n_nodes,3)
+ * float64 (any periodic image in x and z; every triangle contiguous in
+ * space), tri (n_tri,3) int32, inc_off (n_nodes + 1) and inc_tri
+ * (inc_off[n_nodes]) int32 the triangles incident to each node (CSR), f and
+ * w (n_nodes,3) float64: device arrays owned by the caller.  The mesh arrays
+ * are checked on the device first (an index out of range, or a triangle
+ * listed at a node it does not contain, gives GGEM_E_ARG; one stream
+ * synchronisation).  Errors also: GGEM_E_CAPACITY, GGEM_E_DOMAIN (a node
+ * outside the slit), GGEM_E_DEVICE. */
+int ggem_bi_single_layer(ggem_rigid_t rigid, long long n_nodes, const double* nodes,
+                         long long n_tri, const int* tri, const int* inc_off, const int* inc_tri,
+                         const double* f, double* w);
+
+/* Force- and torque-free rigid particle in the undisturbed flow u_inf
+ * (Sec. 6.1, Eq. sl_r): unknowns the nodal tractions f, the translational
+ * velocity U and the angular velocity Omega about center (host, 3);
+ *   U + Omega x (x_b - center) + w(x_b) = u_inf(x_b)   at every node,
+ *   sum_b A_b f_b = 0,   sum_b A_b (x_b - center) x f_b = 0,
+ * solved by GMRES(restart) (Sec. 5) in FP64 on the 3 n_nodes + 6 unknowns.
+ * uinf (n_nodes,3) device; f (n_nodes,3) device holds the initial guess on
+ * entry and the solution on exit; motion (host, 6) = (U, Omega) likewise.
+ * Stops when the true relative residual is <= tol or after max_iter Krylov
+ * products; *iters and *rel_res as for ggem_fredholm_solve (non-convergence
+ * is not an error).  Returns after the plan's stream has finished.  Errors
+ * as for ggem_bi_single_layer, plus GGEM_E_ARG for tol <= 0 or max_iter < 1. */
+int ggem_rigid_solve(ggem_rigid_t rigid, long long n_nodes, const double* nodes, long long n_tri,
+                     const int* tri, const int* inc_off, const int* inc_tri, const double* center,
+                     const double* uinf, double* f, double* motion, double tol, int max_iter,
+                     int* iters, double* rel_res);
+
+/* Undisturbed pressure-driven flow between the plan's walls (Appendix B):
+ * u = U0 (1 - y^2/H^2) e_x at the n points x (n,3) float64 -> u (n,3),
+ * device arrays, on the plan's stream.  Errors: GGEM_E_ARG. */
+int ggem_poiseuille(ggem_plan_t plan, double U0, long long n, const double* x, double* u);
+
 /* ---- surface quantities of a drop suspension in simple shear ------------
  *
  * Helpers that keep a time-stepped suspension of drops (closed triangulated

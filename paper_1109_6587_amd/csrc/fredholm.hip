@@ -12,8 +12,8 @@
 // and the operator is y = q + 2 kappa v.  Nodes never coincide with Gauss
 // points, so no pair is singular.
 //
-// GMRES(m) with classical Gram-Schmidt applied twice; Krylov vectors, dot
-// products and norms in FP64 with fixed-order reductions; the small
+// GMRES(m) of gmres.h: classical Gram-Schmidt applied twice; Krylov vectors,
+// dot products and norms in FP64 with fixed-order reductions; the small
 // Hessenberg problem (Givens rotations) on the host.
 #include <math.h>
 #include <string.h>
@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "ggem_internal.h"
+#include "gmres.h"
 
 using namespace ggem;
 
@@ -97,62 +98,6 @@ __global__ void fill_ints(int* __restrict__ p, int n, int v) {
   if (i < n) p[i] = v;
 }
 
-constexpr int kDotBlock = 256;
-constexpr int kDotBlocks = 256;
-
-// part[i][b] = sum over block b's range of V_i . w  (fixed order)
-__global__ void __launch_bounds__(kDotBlock) dots_partial(int n, const double* __restrict__ V,
-                                                          size_t ldv, const double* __restrict__ w,
-                                                          double* __restrict__ part) {
-  __shared__ double red[kDotBlock];
-  const int i = blockIdx.y;
-  const double* vi = V + (size_t)i * ldv;
-  double s = 0.0;
-  for (int j = blockIdx.x * kDotBlock + threadIdx.x; j < n; j += kDotBlocks * kDotBlock)
-    s = fma(vi[j], w[j], s);
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = kDotBlock / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[(size_t)i * kDotBlocks + blockIdx.x] = red[0];
-}
-
-__global__ void __launch_bounds__(kDotBlock) dots_final(const double* __restrict__ part,
-                                                        double* __restrict__ out) {
-  __shared__ double red[kDotBlock];
-  const int i = blockIdx.x;
-  red[threadIdx.x] = part[(size_t)i * kDotBlocks + threadIdx.x];
-  __syncthreads();
-  for (int o = kDotBlock / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[i] = red[0];
-}
-
-// w -= sum_i c_i V_i   (or, with add, x += sum_i c_i V_i)
-__global__ void multi_axpy(int n, int k, const double* __restrict__ V, size_t ldv,
-                           const double* __restrict__ c, double sign, double* __restrict__ w) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  double s = 0.0;
-  for (int i = 0; i < k; ++i) s = fma(c[i], V[(size_t)i * ldv + j], s);
-  w[j] = fma(sign, s, w[j]);
-}
-
-__global__ void scale_copy(int n, double a, const double* __restrict__ x, double* __restrict__ y) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < n) y[j] = a * x[j];
-}
-
-__global__ void sub_into(int n, const double* __restrict__ b, const double* __restrict__ ax,
-                         double* __restrict__ r) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < n) r[j] = b[j] - ax[j];
-}
-
 }  // namespace
 
 struct ggem_solver_s {
@@ -160,9 +105,8 @@ struct ggem_solver_s {
   long long max_nodes, max_tri;
   int restart;
   double *gpos, *gw, *gs;  // Gauss points, weights, strengths
-  double *V, *w, *v, *r;   // Krylov basis (restart + 1 vectors), work vectors
-  double *part, *dots, *coef;
-  double* dots_host;
+  double* v;               // double-layer output of one product
+  gm::Work W;              // GMRES workspace (Krylov basis of 3 max_nodes)
   int *bad, *bad_host;  // triangle index check
   // geometry of the current solve
   int n_nodes, n_tri;
@@ -184,12 +128,11 @@ static thread_local char g_solver_err[256];
   } while (0)
 
 static void free_solver(ggem_solver_s* s) {
-  void* ptrs[] = {s->gpos, s->gw, s->gs, s->V,    s->w,   s->v,
-                  s->r,    s->part, s->dots, s->coef, s->bad};
+  void* ptrs[] = {s->gpos, s->gw, s->gs, s->v, s->bad};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
-  if (s->dots_host) (void)hipHostFree(s->dots_host);
   if (s->bad_host) (void)hipHostFree(s->bad_host);
+  gm::free_work(s->W);
 }
 
 extern "C" int ggem_solver_create(ggem_plan_t plan, const ggem_solver_params* prm,
@@ -212,20 +155,14 @@ extern "C" int ggem_solver_create(ggem_plan_t plan, const ggem_solver_params* pr
   s->max_tri = prm->max_tri;
   s->restart = prm->restart;
   const size_t n3 = 3 * (size_t)prm->max_nodes, ng = 3 * (size_t)prm->max_tri;
-  const size_t m1 = (size_t)prm->restart + 1;
   bool ok = hipMalloc((void**)&s->gpos, 3 * ng * 8) == hipSuccess &&
             hipMalloc((void**)&s->gw, ng * 8) == hipSuccess &&
             hipMalloc((void**)&s->gs, 3 * ng * 8) == hipSuccess &&
-            hipMalloc((void**)&s->V, m1 * n3 * 8) == hipSuccess &&
-            hipMalloc((void**)&s->w, n3 * 8) == hipSuccess &&
             hipMalloc((void**)&s->v, n3 * 8) == hipSuccess &&
-            hipMalloc((void**)&s->r, n3 * 8) == hipSuccess &&
-            hipMalloc((void**)&s->part, m1 * kDotBlocks * 8) == hipSuccess &&
-            hipMalloc((void**)&s->dots, m1 * 8) == hipSuccess &&
-            hipMalloc((void**)&s->coef, m1 * 8) == hipSuccess &&
             hipMalloc((void**)&s->bad, sizeof(int)) == hipSuccess &&
-            hipHostMalloc((void**)&s->dots_host, m1 * 8, 0) == hipSuccess &&
-            hipHostMalloc((void**)&s->bad_host, sizeof(int), 0) == hipSuccess;
+            hipHostMalloc((void**)&s->bad_host, sizeof(int), 0) == hipSuccess &&
+            gm::alloc_work(s->W, n3, prm->restart) == GGEM_OK;
+  s->W.st = plan->p.stream;
   if (!ok) {
     free_solver(s);
     delete s;
@@ -282,18 +219,6 @@ static int apply(ggem_solver_s* s, const double* x, double* y) {
   return GGEM_OK;
 }
 
-// k dot products V_i . w, returned on the host
-static int dots(ggem_solver_s* s, const double* V, size_t ldv, int k, const double* w, int n,
-                double* host) {
-  hipStream_t st = s->plan->p.stream;
-  dots_partial<<<dim3(kDotBlocks, k), kDotBlock, 0, st>>>(n, V, ldv, w, s->part);
-  dots_final<<<k, kDotBlock, 0, st>>>(s->part, s->dots);
-  SOLVER_TRY(hipMemcpyAsync(s->dots_host, s->dots, k * 8, hipMemcpyDeviceToHost, st));
-  SOLVER_TRY(hipStreamSynchronize(st));
-  memcpy(host, s->dots_host, k * 8);
-  return GGEM_OK;
-}
-
 extern "C" int ggem_fredholm_apply(ggem_solver_t s, long long n_nodes, const double* nodes,
                                    const double* normals, const double* kappa, double kappa0,
                                    long long n_tri, const int* tri, const double* x, double* y) {
@@ -313,109 +238,27 @@ static int solve_impl(ggem_solver_t s, long long n_nodes, const double* nodes,
   if (!b || !q) return ggem_set_error(GGEM_E_ARG, "null vector");
   if (!(tol > 0) || max_iter < 1) return ggem_set_error(GGEM_E_ARG, "bad tolerance or max_iter");
   if (int rc = set_geometry(s, n_nodes, nodes, normals, kappa, kappa0, n_tri, tri)) return rc;
-  hipStream_t st = s->plan->p.stream;
+  gm::Work& W = s->W;
+  W.st = s->plan->p.stream;
   const int n = 3 * (int)n_nodes;
-  const int m = s->restart;
-  const size_t ldv = 3 * (size_t)s->max_nodes;
-  const unsigned nb = (unsigned)((n + 255) / 256);
-  double bnorm2;
-  if (int rc = dots(s, b, 0, 1, b, n, &bnorm2)) return rc;
-  const double bnorm = sqrt(bnorm2);
-  if (bnorm == 0.0) {
-    scale_copy<<<nb, 256, 0, st>>>(n, 0.0, b, q);
-    if (iters) *iters = 0;
-    if (rel_res) *rel_res = 0.0;
-    SOLVER_TRY(hipStreamSynchronize(st));
-    return GGEM_OK;
-  }
-  std::vector<double> Hm((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), h(m + 1), h2(m + 1), y(m);
-  int total = 0;
-  double res = 0.0;
-  bool first = true;
   if (step) *step = 0.0;
-  for (;;) {
-    // true residual r = b - A q; stop on it (the Arnoldi estimate can be
-    // optimistic when the products carry FP32 rounding)
-    if (int rc = apply(s, q, s->w)) return rc;
-    sub_into<<<nb, 256, 0, st>>>(n, b, s->w, s->r);
-    if (first && dq) {
-      // c = argmin |r - c A dq| over c >= 0; q += c dq, r -= c A dq
-      if (int rc = apply(s, dq, s->w)) return rc;
-      double rw, ww;
-      if (int rc = dots(s, s->r, 0, 1, s->w, n, &rw)) return rc;
-      if (int rc = dots(s, s->w, 0, 1, s->w, n, &ww)) return rc;
-      const double c = (ww > 0.0 && rw > 0.0) ? rw / ww : 0.0;
-      if (c > 0.0) {
-        SOLVER_TRY(hipMemcpyAsync(s->coef, &c, 8, hipMemcpyHostToDevice, st));
-        multi_axpy<<<nb, 256, 0, st>>>(n, 1, dq, 0, s->coef, 1.0, q);
-        multi_axpy<<<nb, 256, 0, st>>>(n, 1, s->w, 0, s->coef, -1.0, s->r);
-        SOLVER_TRY(hipStreamSynchronize(st));  // c lives on this stack frame
-      }
-      if (step) *step = c;
+  auto op = [s](const double* x, double* y) { return apply(s, x, y); };
+  // guided start: c = argmin |r - c A dq| over c >= 0; q += c dq, r -= c A dq
+  auto guide = [&](double* r) -> int {
+    if (!dq) return GGEM_OK;
+    if (int rc = apply(s, dq, W.w)) return rc;
+    double rw, ww;
+    if (int rc = gm::dots(W, r, 0, 1, W.w, n, &rw)) return rc;
+    if (int rc = gm::dots(W, W.w, 0, 1, W.w, n, &ww)) return rc;
+    const double c = (ww > 0.0 && rw > 0.0) ? rw / ww : 0.0;
+    if (c > 0.0) {
+      if (int rc = gm::axpy_host(W, n, c, dq, q)) return rc;
+      if (int rc = gm::axpy_host(W, n, -c, W.w, r)) return rc;
     }
-    first = false;
-    double beta2;
-    if (int rc = dots(s, s->r, 0, 1, s->r, n, &beta2)) return rc;
-    const double beta = sqrt(beta2);
-    res = beta / bnorm;
-    if (res <= tol || total >= max_iter) break;
-    scale_copy<<<nb, 256, 0, st>>>(n, 1.0 / beta, s->r, s->V);
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    int j = 0;
-    for (; j < m && total < max_iter; ++j) {
-      ++total;
-      double* Vj = s->V + (size_t)j * ldv;
-      if (int rc = apply(s, Vj, s->w)) return rc;
-      // classical Gram-Schmidt, twice
-      if (int rc = dots(s, s->V, ldv, j + 1, s->w, n, h.data())) return rc;
-      SOLVER_TRY(hipMemcpyAsync(s->coef, h.data(), (j + 1) * 8, hipMemcpyHostToDevice, st));
-      multi_axpy<<<nb, 256, 0, st>>>(n, j + 1, s->V, ldv, s->coef, -1.0, s->w);
-      if (int rc = dots(s, s->V, ldv, j + 1, s->w, n, h2.data())) return rc;
-      SOLVER_TRY(hipMemcpyAsync(s->coef, h2.data(), (j + 1) * 8, hipMemcpyHostToDevice, st));
-      multi_axpy<<<nb, 256, 0, st>>>(n, j + 1, s->V, ldv, s->coef, -1.0, s->w);
-      for (int i = 0; i <= j; ++i) h[i] += h2[i];
-      double wn2;
-      if (int rc = dots(s, s->w, 0, 1, s->w, n, &wn2)) return rc;
-      h[j + 1] = sqrt(wn2);
-      if (h[j + 1] > 0.0)
-        scale_copy<<<nb, 256, 0, st>>>(n, 1.0 / h[j + 1], s->w, s->V + (size_t)(j + 1) * ldv);
-      // Givens rotations on the new Hessenberg column
-      for (int i = 0; i < j; ++i) {
-        const double t = cs[i] * h[i] + sn[i] * h[i + 1];
-        h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
-        h[i] = t;
-      }
-      const double den = hypot(h[j], h[j + 1]);
-      if (!(den > 0)) break;  // A V_j = 0 within the basis: keep the j columns so far
-      cs[j] = h[j] / den;
-      sn[j] = h[j + 1] / den;
-      h[j] = den;
-      h[j + 1] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      for (int i = 0; i <= j; ++i) Hm[(size_t)i * m + j] = h[i];
-      if (fabs(g[j + 1]) / bnorm <= tol) {
-        ++j;
-        break;
-      }
-    }
-    // q += V y with H y = g (upper triangular, j columns)
-    const int k = j;
-    for (int i = k - 1; i >= 0; --i) {
-      double t = g[i];
-      for (int l = i + 1; l < k; ++l) t -= Hm[(size_t)i * m + l] * y[l];
-      y[i] = t / Hm[(size_t)i * m + i];
-    }
-    if (k > 0) {
-      SOLVER_TRY(hipMemcpyAsync(s->coef, y.data(), k * 8, hipMemcpyHostToDevice, st));
-      multi_axpy<<<nb, 256, 0, st>>>(n, k, s->V, ldv, s->coef, 1.0, q);
-      SOLVER_TRY(hipGetLastError());
-    }
-  }
-  if (iters) *iters = total;
-  if (rel_res) *rel_res = res;
-  return GGEM_OK;
+    if (step) *step = c;
+    return GGEM_OK;
+  };
+  return gm::solve(W, n, b, q, tol, max_iter, op, guide, iters, rel_res);
 }
 
 extern "C" int ggem_fredholm_solve(ggem_solver_t s, long long n_nodes, const double* nodes,

@@ -1,0 +1,553 @@
+// Boundary-integral single layer on a triangulated surface and the
+// rigid-particle problem.
+//
+// Single layer at the mesh nodes (Sec. 3.4), traction f linear on flat
+// triangles (basis of Sec. 3.3.1: phi1 = 1 - xi - eta, phi2 = xi, phi3 = eta):
+//
+//   w(z) = (1/8pi) [ sum_k int_{S_k} f G^l(z - x) dS  +  sum_b G^g(z, x_b) f_b A_b ]
+//
+// Local part (Sec. 3.4.1, Eq. int_l): every element within r_c of z (its
+// nearest vertex within r_c) is integrated over its parent triangle with the
+// product of two 4-point Gauss-Legendre rules (xi in [0, 1 - eta] for each
+// eta); when z is a vertex of the element the parent triangle is taken in
+// polar coordinates about that vertex, which removes the 1/r singularity.
+// Global part (Sec. 3.4.2): nodal trapezoid strengths f_b A_b (A_b one third
+// of the areas of the triangles at b) through the GGEM global problem.
+//
+// Rigid particle (Sec. 6.1, Eq. sl_r): unknowns f at the nodes, U and Omega;
+// at every node U + Omega x (x_b - x_c) + w(x_b) = u_inf(x_b), with
+// sum_b A_b f_b = 0 and sum_b A_b (x_b - x_c) x f_b = 0; solved by GMRES (Sec. 5).
+#include <math.h>
+#include <string.h>
+
+#include <new>
+
+#include "ggem_internal.h"
+#include "gmres.h"
+
+using namespace ggem;
+
+namespace {
+
+constexpr double kInv8Pi = 0.039788735772973833942;  // 1/(8 pi)
+constexpr double kSqrtPi = 1.7724538509055160273;
+
+// 4-point Gauss-Legendre rule on [0, 1]
+__constant__ double kGLt[4] = {0.069431844202973712, 0.33000947820757187, 0.66999052179242813,
+                               0.93056815579702629};
+__constant__ double kGLw[4] = {0.17392742256872693, 0.32607257743127307, 0.32607257743127307,
+                               0.17392742256872693};
+
+__device__ inline double min_img(double d, double L, double invL) {
+  return fma(-L, rint(d * invL), d);
+}
+
+__device__ inline double d2(double dx, double dy, double dz) {
+#pragma clang fp contract(off)
+  return (dx * dx + dy * dy) + dz * dz;
+}
+
+struct BiArgs {
+  CellGeom g;
+  double rc2, alpha;
+  int n, ntri;
+  const double* x;        // nodes (n, 3), any periodic image
+  const int* tri;         // (ntri, 3)
+  const int* off;         // node -> incident triangles (CSR, n + 1)
+  const int* adj;
+  const int* keys;        // bucket of every node (binning of the nodes)
+  const int* cell_start;  // sorted ranges per cell
+  const int* perm;        // sorted -> original
+  const double* f;        // (n, 3)
+  double* out;            // (n, 3)
+};
+
+// displacement x[q] - z by the minimum image in x and z
+__device__ inline void rel(const BiArgs& a, int q, double zx, double zy, double zz, double& dx,
+                           double& dy, double& dz) {
+  dx = min_img(a.x[3 * (size_t)q] - zx, a.g.Lx, a.g.invLx);
+  dy = a.x[3 * (size_t)q + 1] - zy;
+  dz = min_img(a.x[3 * (size_t)q + 2] - zz, a.g.Lz, a.g.invLz);
+}
+
+__device__ inline bool within(const BiArgs& a, int q, double zx, double zy, double zz) {
+  double dx, dy, dz;
+  rel(a, q, zx, zy, zz, dx, dy, dz);
+  return d2(dx, dy, dz) <= a.rc2;
+}
+
+// acc += w * G^l(d) fv,  G^l = (I/r + dd/r^3) erfc(alpha r) - c (I - dd/r^2) e^{-alpha^2 r^2}
+__device__ inline void add_stokeslet(double dx, double dy, double dz, double fx, double fy,
+                                     double fz, double alpha, double w, double* acc) {
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  const double r = sqrt(r2);
+  const double ec = erfc(alpha * r), ex = exp(-alpha * alpha * r2);
+  const double c = 2.0 * alpha / kSqrtPi * ex;
+  const double A = ec / r - c;                 // coefficient of I
+  const double B = (ec / r + c) / r2;          // coefficient of d d^T
+  const double df = dx * fx + dy * fy + dz * fz;
+  acc[0] += w * (A * fx + B * df * dx);
+  acc[1] += w * (A * fy + B * df * dy);
+  acc[2] += w * (A * fz + B * df * dz);
+}
+
+// int over one element of f G^l(z - x) dS; e[v] vertex positions relative to
+// z, fe[v] nodal tractions, local vertex 0 is z itself when polar
+__device__ void element_integral(const double (&e)[3][3], const double (&fe)[3][3], bool polar,
+                                 double alpha, double* acc) {
+  const double u1x = e[1][0] - e[0][0], u1y = e[1][1] - e[0][1], u1z = e[1][2] - e[0][2];
+  const double u2x = e[2][0] - e[0][0], u2y = e[2][1] - e[0][1], u2z = e[2][2] - e[0][2];
+  const double cx = u1y * u2z - u1z * u2y, cy = u1z * u2x - u1x * u2z, cz = u1x * u2y - u1y * u2x;
+  const double omega = sqrt(cx * cx + cy * cy + cz * cz);
+  for (int o = 0; o < 4; ++o) {
+    double c = 1.0, s = 0.0, rmax = 1.0, wo;
+    if (polar) {
+      const double th = 0.5 * M_PI * kGLt[o];
+      c = cos(th);
+      s = sin(th);
+      rmax = 1.0 / (c + s);
+      wo = 0.5 * M_PI * kGLw[o];
+    } else {
+      wo = kGLw[o];
+    }
+    for (int i = 0; i < 4; ++i) {
+      double xi, eta, w;
+      if (polar) {
+        const double rho = rmax * kGLt[i];
+        xi = rho * c;
+        eta = rho * s;
+        w = wo * rmax * kGLw[i] * rho * omega;
+      } else {
+        eta = kGLt[o];
+        xi = (1.0 - eta) * kGLt[i];
+        w = wo * kGLw[i] * (1.0 - eta) * omega;
+      }
+      const double p0 = 1.0 - xi - eta, p1 = xi, p2 = eta;
+      // d = z - x(xi, eta)
+      const double dx = -(p0 * e[0][0] + p1 * e[1][0] + p2 * e[2][0]);
+      const double dy = -(p0 * e[0][1] + p1 * e[1][1] + p2 * e[2][1]);
+      const double dz = -(p0 * e[0][2] + p1 * e[1][2] + p2 * e[2][2]);
+      add_stokeslet(dx, dy, dz, p0 * fe[0][0] + p1 * fe[1][0] + p2 * fe[2][0],
+                    p0 * fe[0][1] + p1 * fe[1][1] + p2 * fe[2][1],
+                    p0 * fe[0][2] + p1 * fe[1][2] + p2 * fe[2][2], alpha, w, acc);
+    }
+  }
+}
+
+// One wave per target node z.  The wave walks the nodes of the cells around
+// z in sorted order, 64 at a time; a lane whose node v lies within r_c of z
+// integrates every triangle at v for which v is the first of the triangle's
+// vertices (in their stored order) within r_c of z, so each element within
+// r_c is integrated exactly once.  Lane sums are added in a fixed tree order.
+__global__ void __launch_bounds__(256) bi_sl_local(BiArgs a) {
+  __shared__ double red[4][3][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int t = blockIdx.x * 4 + wave;
+  if (t >= a.n) return;
+  const CellGeom& g = a.g;
+  const double zx = a.x[3 * (size_t)t], zy = a.x[3 * (size_t)t + 1], zz = a.x[3 * (size_t)t + 2];
+  const int c = a.keys[t] / g.nzs;
+  const int iz = c % g.ncz, ix = (c / g.ncz) % g.ncx, iy = c / (g.ncz * g.ncx);
+  const int nxo = g.ncx >= 3 ? 3 : g.ncx, nzo = g.ncz >= 3 ? 3 : g.ncz;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int oy = -1; oy <= 1; ++oy) {
+    const int cy = iy + oy;
+    if (cy < 0 || cy >= g.ncy) continue;
+    for (int oxi = 0; oxi < nxo; ++oxi) {
+      const int cx = g.ncx >= 3 ? (ix + oxi - 1 + g.ncx) % g.ncx : oxi;
+      for (int ozi = 0; ozi < nzo; ++ozi) {
+        const int cz = g.ncz >= 3 ? (iz + ozi - 1 + g.ncz) % g.ncz : ozi;
+        const int cc = (cy * g.ncx + cx) * g.ncz + cz;
+        const int s0 = a.cell_start[cc], s1 = a.cell_start[cc + 1];
+        for (int b = s0; b < s1; b += 64) {
+          const int j = b + lane;
+          if (j >= s1) continue;
+          const int v = a.perm[j];
+          if (!within(a, v, zx, zy, zz)) continue;
+          for (int q = a.off[v]; q < a.off[v + 1]; ++q) {
+            const int k = a.adj[q];
+            const int ia = a.tri[3 * (size_t)k], ib = a.tri[3 * (size_t)k + 1],
+                      ic = a.tri[3 * (size_t)k + 2];
+            // skip unless v is the first vertex within r_c
+            if (ia != v && within(a, ia, zx, zy, zz)) continue;
+            if (ia != v && ib != v && within(a, ib, zx, zy, zz)) continue;
+            // vertices relative to z, z as local vertex 0 when it is one of them
+            int vv[3] = {ia, ib, ic};
+            int rot = 0;
+            const bool polar = ia == t || ib == t || ic == t;
+            if (ib == t) rot = 1;
+            if (ic == t) rot = 2;
+            int w3[3] = {vv[rot], vv[(rot + 1) % 3], vv[(rot + 2) % 3]};
+            double e[3][3], fe[3][3];
+            double e0x, e0y, e0z;
+            rel(a, ia, zx, zy, zz, e0x, e0y, e0z);
+            double ea[3][3];
+            ea[0][0] = e0x;
+            ea[0][1] = e0y;
+            ea[0][2] = e0z;
+            for (int m = 1; m < 3; ++m) {
+              const int q2 = vv[m];
+              ea[m][0] = e0x + min_img(a.x[3 * (size_t)q2] - a.x[3 * (size_t)ia], g.Lx, g.invLx);
+              ea[m][1] = e0y + (a.x[3 * (size_t)q2 + 1] - a.x[3 * (size_t)ia + 1]);
+              ea[m][2] = e0z + min_img(a.x[3 * (size_t)q2 + 2] - a.x[3 * (size_t)ia + 2], g.Lz,
+                                       g.invLz);
+            }
+            for (int m = 0; m < 3; ++m) {
+              const int src = (rot + m) % 3;
+              for (int d = 0; d < 3; ++d) {
+                e[m][d] = (polar && m == 0) ? 0.0 : ea[src][d];
+                fe[m][d] = a.f[3 * (size_t)w3[m] + d];
+              }
+            }
+            element_integral(e, fe, polar, a.alpha, acc);
+          }
+        }
+      }
+    }
+  }
+  for (int d = 0; d < 3; ++d) red[wave][d][lane] = acc[d];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int o = 32; o > 0; o >>= 1) {
+    if (lane < o)
+      for (int d = 0; d < 3; ++d) red[wave][d][lane] += red[wave][d][lane + o];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  if (lane == 0)
+    for (int d = 0; d < 3; ++d) a.out[3 * (size_t)t + d] = kInv8Pi * red[wave][d][0];
+}
+
+// Node areas A_b (one third of the areas of the triangles at b, in incidence
+// order) and checks of the mesh arrays: an index out of range, or a triangle
+// listed at a node it does not contain, raises *bad.
+__global__ void bi_node_areas(int n, int ntri, const double* __restrict__ x,
+                              const int* __restrict__ tri, const int* __restrict__ off,
+                              const int* __restrict__ adj, double* __restrict__ area,
+                              int* __restrict__ bad) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n) return;
+  double s = 0.0;
+  const int q0 = off[b], q1 = off[b + 1];
+  if (q0 < 0 || q1 < q0) {
+    atomicOr(bad, 1);
+    area[b] = 0.0;
+    return;
+  }
+  for (int q = q0; q < q1; ++q) {
+    const int k = adj[q];
+    if ((unsigned)k >= (unsigned)ntri) {
+      atomicOr(bad, 1);
+      continue;
+    }
+    const int ia = tri[3 * (size_t)k], ib = tri[3 * (size_t)k + 1], ic = tri[3 * (size_t)k + 2];
+    if ((unsigned)ia >= (unsigned)n || (unsigned)ib >= (unsigned)n || (unsigned)ic >= (unsigned)n ||
+        (ia != b && ib != b && ic != b)) {
+      atomicOr(bad, 1);
+      continue;
+    }
+    double u[3], w[3];
+    for (int d = 0; d < 3; ++d) {
+      u[d] = x[3 * (size_t)ib + d] - x[3 * (size_t)ia + d];
+      w[d] = x[3 * (size_t)ic + d] - x[3 * (size_t)ia + d];
+    }
+    const double cx = u[1] * w[2] - u[2] * w[1], cy = u[2] * w[0] - u[0] * w[2],
+                 cz = u[0] * w[1] - u[1] * w[0];
+    s += sqrt(cx * cx + cy * cy + cz * cz) / 6.0;
+  }
+  area[b] = s;
+}
+
+__global__ void bi_scale(int n, const double* __restrict__ area, const double* __restrict__ f,
+                         double* __restrict__ q) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 3 * n) q[i] = area[i / 3] * f[i];
+}
+
+__global__ void bi_add(int n, const double* __restrict__ a, const double* __restrict__ b,
+                       double* __restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a[i] + b[i];
+}
+
+// velocity rows of the rigid system: y_b = U + Omega x (x_b - x_c) + w_l + w_g
+__global__ void bi_rigid_rows(int n, const double* __restrict__ x, double xc0, double xc1,
+                              double xc2, const double* __restrict__ motion,
+                              const double* __restrict__ wl, const double* __restrict__ wg,
+                              double* __restrict__ y) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n) return;
+  const double r0 = x[3 * (size_t)b] - xc0, r1 = x[3 * (size_t)b + 1] - xc1,
+               r2 = x[3 * (size_t)b + 2] - xc2;
+  const double U0 = motion[0], U1 = motion[1], U2 = motion[2];
+  const double O0 = motion[3], O1 = motion[4], O2 = motion[5];
+  y[3 * (size_t)b] = U0 + (O1 * r2 - O2 * r1) + wl[3 * (size_t)b] + wg[3 * (size_t)b];
+  y[3 * (size_t)b + 1] = U1 + (O2 * r0 - O0 * r2) + wl[3 * (size_t)b + 1] + wg[3 * (size_t)b + 1];
+  y[3 * (size_t)b + 2] = U2 + (O0 * r1 - O1 * r0) + wl[3 * (size_t)b + 2] + wg[3 * (size_t)b + 2];
+}
+
+constexpr int kMomBlock = 256, kMomBlocks = 64;
+
+// part[m][blk]: block sums over its node range of the force A f (m = 0..2)
+// and the torque A r x f (m = 3..5)
+__global__ void __launch_bounds__(kMomBlock) bi_moments_partial(int n, const double* __restrict__ x,
+                                                                double xc0, double xc1, double xc2,
+                                                                const double* __restrict__ area,
+                                                                const double* __restrict__ f,
+                                                                double* __restrict__ part) {
+  __shared__ double red[6][kMomBlock];
+  double s[6] = {0, 0, 0, 0, 0, 0};
+  for (int b = blockIdx.x * kMomBlock + threadIdx.x; b < n; b += kMomBlocks * kMomBlock) {
+    const double A = area[b];
+    const double f0 = A * f[3 * (size_t)b], f1 = A * f[3 * (size_t)b + 1],
+                 f2 = A * f[3 * (size_t)b + 2];
+    const double r0 = x[3 * (size_t)b] - xc0, r1 = x[3 * (size_t)b + 1] - xc1,
+                 r2 = x[3 * (size_t)b + 2] - xc2;
+    s[0] += f0;
+    s[1] += f1;
+    s[2] += f2;
+    s[3] += r1 * f2 - r2 * f1;
+    s[4] += r2 * f0 - r0 * f2;
+    s[5] += r0 * f1 - r1 * f0;
+  }
+  for (int m = 0; m < 6; ++m) red[m][threadIdx.x] = s[m];
+  __syncthreads();
+  for (int o = kMomBlock / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o)
+      for (int m = 0; m < 6; ++m) red[m][threadIdx.x] += red[m][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) part[threadIdx.x * kMomBlocks + blockIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(64) bi_moments_final(const double* __restrict__ part,
+                                                       double* __restrict__ out) {
+  const int m = blockIdx.x;  // one block per moment, 64 lanes over the 64 partials
+  __shared__ double red[64];
+  red[threadIdx.x] = part[m * kMomBlocks + threadIdx.x];
+  __syncthreads();
+  for (int o = 32; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[m] = red[0];
+}
+
+// Poiseuille flow between the walls y = -H and y = +H (Appendix B)
+__global__ void poiseuille_kernel(int n, double U0, double H, const double* __restrict__ x,
+                                  double* __restrict__ u) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n) return;
+  const double s = x[3 * (size_t)b + 1] / H;
+  u[3 * (size_t)b] = U0 * (1.0 - s * s);
+  u[3 * (size_t)b + 1] = 0.0;
+  u[3 * (size_t)b + 2] = 0.0;
+}
+
+__global__ void fill_int(int* p, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+}  // namespace
+
+struct ggem_rigid_s {
+  ggem_plan_s* plan;
+  long long max_nodes, max_tri;
+  double *area, *wl, *wg, *q, *part;
+  double *xsys, *bsys;  // solution and right-hand side of the rigid system (3n + 6)
+  int *bad, *bad_host;
+  gm::Work W;
+  // current surface
+  int n, ntri;
+  const double* x;
+  const int *tri, *off, *adj;
+  double xc[3];
+};
+
+#define RIGID_TRY(expr)                                              \
+  do {                                                               \
+    hipError_t e_ = (expr);                                          \
+    if (e_ != hipSuccess) return gm::device_error(e_, #expr);        \
+  } while (0)
+
+static void free_rigid(ggem_rigid_s* r) {
+  void* ptrs[] = {r->area, r->wl, r->wg, r->q, r->part, r->xsys, r->bsys, r->bad};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (r->bad_host) (void)hipHostFree(r->bad_host);
+  gm::free_work(r->W);
+}
+
+extern "C" int ggem_rigid_create(ggem_plan_t plan, long long max_nodes, long long max_tri,
+                                 int restart, ggem_rigid_t* out) {
+  if (!plan || !out) return ggem_set_error(GGEM_E_ARG, "null argument");
+  *out = nullptr;
+  if (restart < 1 || restart > 400) return ggem_set_error(GGEM_E_ARG, "restart must be in 1..400");
+  if (max_nodes < 1 || max_tri < 1 || max_nodes > (1LL << 26) || max_tri > (1LL << 27))
+    return ggem_set_error(GGEM_E_ARG, "capacities out of range");
+  if (max_nodes > plan->p.p.max_src || max_nodes > plan->p.p.max_tgt)
+    return ggem_set_error(GGEM_E_CAPACITY, "plan capacity must cover the nodes");
+  ggem_rigid_s* r = new (std::nothrow) ggem_rigid_s();
+  if (!r) return ggem_set_error(GGEM_E_NOMEM, "host allocation failed");
+  memset(r, 0, sizeof *r);
+  r->plan = plan;
+  r->max_nodes = max_nodes;
+  r->max_tri = max_tri;
+  const size_t n3 = 3 * (size_t)max_nodes, ns = n3 + 6;
+  const bool ok = hipMalloc((void**)&r->area, max_nodes * 8) == hipSuccess &&
+                  hipMalloc((void**)&r->wl, n3 * 8) == hipSuccess &&
+                  hipMalloc((void**)&r->wg, n3 * 8) == hipSuccess &&
+                  hipMalloc((void**)&r->q, n3 * 8) == hipSuccess &&
+                  hipMalloc((void**)&r->part, 6 * kMomBlocks * 8) == hipSuccess &&
+                  hipMalloc((void**)&r->xsys, ns * 8) == hipSuccess &&
+                  hipMalloc((void**)&r->bsys, ns * 8) == hipSuccess &&
+                  hipMalloc((void**)&r->bad, sizeof(int)) == hipSuccess &&
+                  hipHostMalloc((void**)&r->bad_host, sizeof(int), 0) == hipSuccess &&
+                  gm::alloc_work(r->W, ns, restart) == GGEM_OK;
+  if (!ok) {
+    free_rigid(r);
+    delete r;
+    return ggem_set_error(GGEM_E_NOMEM, "device allocation failed");
+  }
+  *out = r;
+  return GGEM_OK;
+}
+
+extern "C" int ggem_rigid_destroy(ggem_rigid_t r) {
+  if (!r) return ggem_set_error(GGEM_E_ARG, "null rigid solver");
+  (void)hipStreamSynchronize(r->plan->p.stream);
+  free_rigid(r);
+  delete r;
+  return GGEM_OK;
+}
+
+// Validate the surface, compute the node areas and keep the arrays.
+static int set_surface(ggem_rigid_s* r, long long n, const double* x, long long ntri,
+                       const int* tri, const int* off, const int* adj) {
+  if (n < 1 || ntri < 1) return ggem_set_error(GGEM_E_ARG, "empty surface");
+  if (n > r->max_nodes || ntri > r->max_tri)
+    return ggem_set_error(GGEM_E_CAPACITY, "surface exceeds the solver capacity");
+  if (!x || !tri || !off || !adj) return ggem_set_error(GGEM_E_ARG, "null surface array");
+  r->n = (int)n;
+  r->ntri = (int)ntri;
+  r->x = x;
+  r->tri = tri;
+  r->off = off;
+  r->adj = adj;
+  hipStream_t st = r->plan->p.stream;
+  fill_int<<<1, 64, 0, st>>>(r->bad, 0);
+  bi_node_areas<<<(r->n + 255) / 256, 256, 0, st>>>(r->n, r->ntri, x, tri, off, adj, r->area,
+                                                    r->bad);
+  RIGID_TRY(hipGetLastError());
+  RIGID_TRY(hipMemcpyAsync(r->bad_host, r->bad, sizeof(int), hipMemcpyDeviceToHost, st));
+  RIGID_TRY(hipStreamSynchronize(st));
+  if (*r->bad_host) return ggem_set_error(GGEM_E_ARG, "mesh index out of range or inconsistent incidence");
+  return GGEM_OK;
+}
+
+// w = discretised single layer of f at the nodes (local part into r->wl,
+// global part into r->wg, their sum into w when w is given)
+static int single_layer(ggem_rigid_s* r, const double* f, double* w) {
+  Plan& p = r->plan->p;
+  hipStream_t st = p.stream;
+  const int n = r->n;
+  // local part: bin the nodes, then one wave per node
+  RIGID_TRY(launch_bin(p, p.src, n, r->x, nullptr, nullptr, true, true));
+  BiArgs a;
+  a.g = p.cg;
+  a.rc2 = p.rc2;
+  a.alpha = p.p.alpha;
+  a.n = n;
+  a.ntri = r->ntri;
+  a.x = r->x;
+  a.tri = r->tri;
+  a.off = r->off;
+  a.adj = r->adj;
+  a.keys = p.src.keys;
+  a.cell_start = p.src.cell_start;
+  a.perm = p.src.perm;
+  a.f = f;
+  a.out = r->wl;
+  bi_sl_local<<<(n + 3) / 4, 256, 0, st>>>(a);
+  RIGID_TRY(hipGetLastError());
+  // global part: nodal trapezoid strengths through the GGEM global problem
+  bi_scale<<<(3 * n + 255) / 256, 256, 0, st>>>(n, r->area, f, r->q);
+  RIGID_TRY(hipGetLastError());
+  if (int rc = ggem_single_layer(r->plan, n, r->x, r->q, n, r->x, r->wg, GGEM_PART_GLOBAL))
+    return rc;
+  if (w) {
+    bi_add<<<(3 * n + 255) / 256, 256, 0, st>>>(3 * n, r->wl, r->wg, w);
+    RIGID_TRY(hipGetLastError());
+  }
+  return GGEM_OK;
+}
+
+extern "C" int ggem_bi_single_layer(ggem_rigid_t r, long long n_nodes, const double* nodes,
+                                    long long n_tri, const int* tri, const int* inc_off,
+                                    const int* inc_tri, const double* f, double* w) {
+  if (!r) return ggem_set_error(GGEM_E_ARG, "null rigid solver");
+  if (!f || !w) return ggem_set_error(GGEM_E_ARG, "null vector");
+  if (int rc = set_surface(r, n_nodes, nodes, n_tri, tri, inc_off, inc_tri)) return rc;
+  return single_layer(r, f, w);
+}
+
+// y = A x for x = (f, U, Omega)
+static int rigid_apply(ggem_rigid_s* r, const double* x, double* y) {
+  hipStream_t st = r->plan->p.stream;
+  const int n = r->n;
+  if (int rc = single_layer(r, x, nullptr)) return rc;
+  bi_rigid_rows<<<(n + 255) / 256, 256, 0, st>>>(n, r->x, r->xc[0], r->xc[1], r->xc[2],
+                                                 x + 3 * (size_t)n, r->wl, r->wg, y);
+  bi_moments_partial<<<kMomBlocks, kMomBlock, 0, st>>>(n, r->x, r->xc[0], r->xc[1], r->xc[2],
+                                                       r->area, x, r->part);
+  bi_moments_final<<<6, 64, 0, st>>>(r->part, y + 3 * (size_t)n);
+  RIGID_TRY(hipGetLastError());
+  return GGEM_OK;
+}
+
+extern "C" int ggem_rigid_solve(ggem_rigid_t r, long long n_nodes, const double* nodes,
+                                long long n_tri, const int* tri, const int* inc_off,
+                                const int* inc_tri, const double* center, const double* uinf,
+                                double* f, double* motion, double tol, int max_iter, int* iters,
+                                double* rel_res) {
+  if (!r) return ggem_set_error(GGEM_E_ARG, "null rigid solver");
+  if (!center || !uinf || !f || !motion) return ggem_set_error(GGEM_E_ARG, "null argument");
+  if (!(tol > 0) || max_iter < 1) return ggem_set_error(GGEM_E_ARG, "bad tolerance or max_iter");
+  if (int rc = set_surface(r, n_nodes, nodes, n_tri, tri, inc_off, inc_tri)) return rc;
+  for (int d = 0; d < 3; ++d) r->xc[d] = center[d];
+  hipStream_t st = r->plan->p.stream;
+  const int n = r->n;
+  const size_t n3 = 3 * (size_t)n;
+  // system vectors: x = (f, U, Omega), b = (u_inf, 0, 0)
+  const double zero[6] = {0, 0, 0, 0, 0, 0};
+  RIGID_TRY(hipMemcpyAsync(r->xsys, f, n3 * 8, hipMemcpyDeviceToDevice, st));
+  RIGID_TRY(hipMemcpyAsync(r->xsys + n3, motion, 6 * 8, hipMemcpyHostToDevice, st));
+  RIGID_TRY(hipMemcpyAsync(r->bsys, uinf, n3 * 8, hipMemcpyDeviceToDevice, st));
+  RIGID_TRY(hipMemcpyAsync(r->bsys + n3, zero, 6 * 8, hipMemcpyHostToDevice, st));
+  RIGID_TRY(hipStreamSynchronize(st));
+  gm::Work& W = r->W;
+  W.st = st;
+  auto op = [r](const double* x, double* y) { return rigid_apply(r, x, y); };
+  auto none = [](double*) { return (int)GGEM_OK; };
+  if (int rc = gm::solve(W, (int)n3 + 6, r->bsys, r->xsys, tol, max_iter, op, none, iters,
+                         rel_res))
+    return rc;
+  RIGID_TRY(hipMemcpyAsync(f, r->xsys, n3 * 8, hipMemcpyDeviceToDevice, st));
+  RIGID_TRY(hipMemcpyAsync(motion, r->xsys + n3, 6 * 8, hipMemcpyDeviceToHost, st));
+  RIGID_TRY(hipStreamSynchronize(st));
+  return GGEM_OK;
+}
+
+extern "C" int ggem_poiseuille(ggem_plan_t plan, double U0, long long n, const double* x,
+                               double* u) {
+  if (!plan) return ggem_set_error(GGEM_E_ARG, "null plan");
+  if (n < 0) return ggem_set_error(GGEM_E_ARG, "negative point count");
+  if (n == 0) return GGEM_OK;
+  if (!x || !u) return ggem_set_error(GGEM_E_ARG, "null array");
+  Plan& p = plan->p;
+  poiseuille_kernel<<<(unsigned)((n + 255) / 256), 256, 0, p.stream>>>((int)n, U0, p.p.H, x, u);
+  RIGID_TRY(hipGetLastError());
+  return GGEM_OK;
+}

@@ -38,7 +38,8 @@ EXPORTS = (
     "ggem_mlp_forward", "ggem_mlp_predict", "ggem_mlp_gradients", "ggem_mlp_train_step",
     "ggem_batch_create", "ggem_batch_destroy", "ggem_batch_single_layer",
     "ggem_batch_capture_single_layer", "ggem_batch_graph_launch", "ggem_batch_status",
-    "ggem_batch_branch", "ggem_single_layer_noalloc", "ggem_last_error",
+    "ggem_batch_branch", "ggem_single_layer_noalloc", "ggem_rigid_create", "ggem_rigid_destroy",
+    "ggem_bi_single_layer", "ggem_rigid_solve", "ggem_poiseuille", "ggem_last_error",
 )
 
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 13, 128, 3, 35203
@@ -103,6 +104,13 @@ def load_library(path: str = LIB_PATH):
     lib.ggem_drop_rhs.argtypes = [vp, ll, dp, dp, dd, dd, dd, dp]
     lib.ggem_surface_velocity.argtypes = [vp, ll, dp, ll, dp, dp, dd, dp]
     lib.ggem_advance.argtypes = [vp, ll, dp, dp, dd, dp]
+    lib.ggem_rigid_create.argtypes = [vp, ll, ll, ip, ctypes.POINTER(vp)]
+    lib.ggem_rigid_destroy.argtypes = [vp]
+    lib.ggem_bi_single_layer.argtypes = [vp, ll, dp, ll, dp, dp, dp, dp, dp]
+    lib.ggem_rigid_solve.argtypes = [vp, ll, dp, ll, dp, dp, dp, ctypes.POINTER(dd), dp, dp,
+                                     ctypes.POINTER(dd), dd, ip, ctypes.POINTER(ip),
+                                     ctypes.POINTER(dd)]
+    lib.ggem_poiseuille.argtypes = [vp, dd, ll, dp, dp]
     fp = ctypes.POINTER(ctypes.c_float)
     lib.ggem_fredholm_solve_guided.argtypes = [vp, ll, dp, dp, dp, dd, ll, dp, dp, dp, dp, dd, ip,
                                                ctypes.POINTER(ip), ctypes.POINTER(dd),
@@ -554,3 +562,67 @@ class Batch:
         if r < 0:
             _check(r)
         return r
+
+
+class RigidParticle:
+    """Boundary-integral single layer on a triangulated surface and the
+    force- and torque-free rigid particle (see include/ggem.h)."""
+
+    def __init__(self, plan, max_nodes, max_tri, restart=100):
+        self.plan = plan
+        self._h = ctypes.c_void_p()
+        _check(_lib.ggem_rigid_create(plan._h, int(max_nodes), int(max_tri), int(restart),
+                                      ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            _check(_lib.ggem_rigid_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            if self._h and _lib is not None:
+                _lib.ggem_rigid_destroy(self._h)
+        except Exception:
+            pass
+
+    @staticmethod
+    def _mesh(nodes, tri, inc_off, inc_tri):
+        n = nodes.shape[0]
+        _int_dev(tri, "tri", 2)
+        _int_dev(inc_off, "inc_off", 1, n + 1)
+        _int_dev(inc_tri, "inc_tri", 1)
+        return (n, _dev_ptr(nodes, "nodes"), tri.shape[0], tri.data_ptr(), inc_off.data_ptr(),
+                inc_tri.data_ptr())
+
+    def single_layer(self, nodes, tri, inc_off, inc_tri, f, out=None):
+        """(1/8pi) int f G dS at the nodes (ggem_bi_single_layer)."""
+        import torch
+        m = self._mesh(nodes, tri, inc_off, inc_tri)
+        out = torch.empty_like(nodes) if out is None else out
+        _check(_lib.ggem_bi_single_layer(self._h, *m, _dev_ptr(f, "f", m[0]),
+                                         _dev_ptr(out, "out", m[0])))
+        return out
+
+    def solve(self, nodes, tri, inc_off, inc_tri, center, uinf, f, motion=None, tol=1e-10,
+              max_iter=400):
+        """Solve in place into f (initial guess on entry); returns
+        (U, Omega, iters, rel_res)."""
+        m = self._mesh(nodes, tri, inc_off, inc_tri)
+        c = (ctypes.c_double * 3)(*[float(v) for v in center])
+        mo = (ctypes.c_double * 6)(*([0.0] * 6 if motion is None else [float(v) for v in motion]))
+        it = ctypes.c_int()
+        rr = ctypes.c_double()
+        _check(_lib.ggem_rigid_solve(self._h, *m, c, _dev_ptr(uinf, "uinf", m[0]),
+                                     _dev_ptr(f, "f", m[0]), mo, float(tol), int(max_iter),
+                                     ctypes.byref(it), ctypes.byref(rr)))
+        return list(mo[:3]), list(mo[3:]), it.value, rr.value
+
+
+def poiseuille(plan, U0, x, out=None):
+    """Undisturbed pressure-driven flow at the points x (ggem_poiseuille)."""
+    import torch
+    out = torch.empty_like(x) if out is None else out
+    _check(_lib.ggem_poiseuille(plan._h, float(U0), x.shape[0], _dev_ptr(x, "x"),
+                                _dev_ptr(out, "out", x.shape[0])))
+    return out

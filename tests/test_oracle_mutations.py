@@ -12,9 +12,11 @@ import numpy as np
 import pytest
 
 import oracle
+import oracle.bi
 import oracle.fredholm
 import oracle.ggem
 import oracle.surface
+import test_oracle_bi as BI
 import test_oracle_invariants as INV
 import test_oracle_kernels as KER
 import test_oracle_physics as PHY
@@ -56,6 +58,15 @@ MUTATIONS = {
     "stresslet B term sign": ("ggem",
         "+ 4.0 * alpha ** 3 / SQRT_PI * (dI - 2.0 * ddd / e(r2)) * e(ex))",
         "- 4.0 * alpha ** 3 / SQRT_PI * (dI - 2.0 * ddd / e(r2)) * e(ex))"),
+    "dropped (1 - eta) Jacobian of the parent triangle": ("bi",
+        "wts.append(wi * wj * (1.0 - tj))",
+        "wts.append(wi * wj)"),
+    "dropped polar Jacobian rho": ("bi",
+        "wts.append((0.5 * math.pi * wk) * (rmax * wi) * rho)",
+        "wts.append((0.5 * math.pi * wk) * (rmax * wi))"),
+    "torque row with r and f swapped": ("bi",
+        "T = (A[:, None] * np.cross(r, f)).sum(axis=0)",
+        "T = (A[:, None] * np.cross(f, r)).sum(axis=0)"),
     "index of the Lagrange stencil in y": ("ggem",
         "wy = _lagrange(xt[:, 1], g.y[jj])",
         "wy = _lagrange(xt[:, 1], g.y[jj[:, ::-1]])"),
@@ -77,7 +88,7 @@ def install(monkeypatch, mod):
     for name, val in vars(mod).items():
         if name.startswith("__") or not callable(val) and not isinstance(val, (int, float)):
             continue
-        for target in (oracle.ggem, oracle, oracle.fredholm, oracle.surface):
+        for target in (oracle.ggem, oracle, oracle.fredholm, oracle.surface, oracle.bi):
             if hasattr(target, name):
                 monkeypatch.setattr(target, name, val)
 
@@ -103,6 +114,12 @@ def alpha_independence():
         assert np.abs(a - b).max() < 1e-8 * np.abs(a).max()
 
 
+def bi_sphere():
+    V, F = BI.icosphere(1)
+    xc = np.array([1.0, 0.0, 1.0])
+    return oracle.SlitGrid(2.0, 2.0, 0.75, 8.0, 0.5, 32, 32, 33), V * 0.3 + xc, F, xc
+
+
 def interpolation_of_polynomials():
     SPE.test_interpolation_reproduces_polynomials(np.random.default_rng(7))
 
@@ -110,6 +127,9 @@ def interpolation_of_polynomials():
 # cheapest first: a mutant stops at the first pin that fails
 CHECKS = [
     ("G^l is Stokes flow", lambda: KER.test_local_pair_is_stokes_flow(0)),
+    ("element rule on polynomials", BI.test_regular_rule_exact_for_polynomials),
+    ("vertex element in closed form",
+     lambda: BI.test_vertex_element_singular_integral(((0.3, 0.05, 0.0), (0.1, 0.25, 0.02)))),
     ("T^l is the Newtonian stress", lambda: KER.test_stresslet_is_newtonian_stress(3)),
     ("manufactured Stokes mode", lambda: SPE.test_stokes_mode_manufactured((3, 1), np.random.default_rng(1))),
     ("manufactured zero mode", lambda: SPE.test_stokes_zero_mode_manufactured(np.random.default_rng(2))),
@@ -119,6 +139,7 @@ CHECKS = [
     ("wall force balance", PHY.test_wall_force_balance),
     ("Fredholm operator on q = n", PHY.test_fredholm_uniform_normal_density),
     ("surface velocity of a uniform density", PHY.test_surface_velocity_uniform_density_translates_sphere),
+    ("torque of a rotational traction", lambda: BI.test_torque_of_a_rotational_traction(bi_sphere())),
 ]
 
 
