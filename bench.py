@@ -46,7 +46,7 @@ FLOP_NEAR_DL = 65.0
 FLOP_SPREAD = 12.0
 
 METRIC = "GGEM Mpoints/s (mixed vs FP64, rel err 1e-5); Fredholm solve s to 1e-6"
-EXTRAS = ("small", "capsules_sl", "batched", "fredholm")
+EXTRAS = ("small", "capsules_sl", "batched", "fredholm", "rigid")
 
 
 def log(msg):
@@ -536,6 +536,57 @@ def fredholm(steps):
     }
 
 
+def rigid_sphere():
+    """The rigid-particle validation (workloads.case_rigid_sphere): the
+    translational velocity at L = 3, 4, 5 wall spacings, its L^-2
+    extrapolation beside the paper's 0.871, the GMRES products and seconds
+    per solve, and the time of one boundary-integral single layer (element
+    quadrature + global part, 2,562 nodes, 5,120 triangles, FP64)."""
+    import numpy as np
+    import torch
+
+    import paper_1109_6587_amd as G
+    from paper_1109_6587_amd.drops import incidence
+    from workloads import case_rigid_sphere
+
+    dev = torch.device("cuda:0")
+    by_L = []
+    for L in (3.0, 4.0, 5.0):
+        c = case_rigid_sphere(L)
+        off, adj = incidence(c.tri, len(c.nodes))
+        ti = lambda a: torch.as_tensor(a, dtype=torch.int32, device=dev)  # noqa: E731
+        m = (torch.as_tensor(c.nodes, dtype=torch.float64, device=dev), ti(c.tri), ti(off),
+             ti(adj))
+        plan = G.Plan(c.Lx, c.Lz, c.H, c.alpha, c.Nx, c.Nz, c.Ny, rc=c.rc, precision="fp64",
+                      max_src=len(c.nodes), max_tgt=len(c.nodes))
+        rp = G.RigidParticle(plan, len(c.nodes), len(c.tri), restart=100)
+        uinf = G.poiseuille(plan, c.U0, m[0])
+        f = torch.zeros_like(m[0])
+        rp.single_layer(*m, uinf, out=f)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            rp.single_layer(*m, uinf, out=f)
+        torch.cuda.synchronize()
+        prod_ms = (time.perf_counter() - t0) / 5 * 1e3
+        f.zero_()
+        t0 = time.perf_counter()
+        U, W, iters, rel = rp.solve(*m, c.center, uinf, f, tol=1e-8, max_iter=800)
+        solve_s = time.perf_counter() - t0
+        log(f"rigid sphere L={L:g}: U/U0 {U[0]:.6f}, {iters} products, {solve_s:.3f} s")
+        by_L.append({"L": L, "grid": [c.Nx, c.Nz, c.Ny], "U_over_U0": round(U[0], 6),
+                     "Omega_max": max(abs(w) for w in W), "gmres_products": iters,
+                     "rel_res": rel, "solve_s": round(solve_s, 4),
+                     "single_layer_ms": round(prod_ms, 3)})
+        rp.close()
+        plan.close()
+    Ls = np.array([r["L"] for r in by_L])
+    c1, c0 = np.polyfit(Ls ** -2.0, np.array([r["U_over_U0"] for r in by_L]), 1)
+    return {"workload": "rigid_sphere_5120", "nodes": 2562, "triangles": 5120,
+            "extrapolated_U_over_U0": round(float(c0), 5), "paper_U_over_U0": 0.871,
+            "by_L": by_L}
+
+
 def base_line(args, value, ms, dtype, config):
     return {
         "metric": METRIC, "value": round(value, 3), "unit": "Mpoints/s", "n_gpus": 1,
@@ -650,6 +701,9 @@ def main():
         if "fredholm" in extras:
             log("extra: fredholm")
             line["fredholm"] = fredholm(args.fredholm_steps)
+        if "rigid" in extras:
+            log("extra: rigid_sphere")
+            line["rigid_sphere"] = rigid_sphere()
         if not args.no_cpu_baseline:
             log("cpu baseline (oracle)")
             line["cpu_baseline"] = cpu_baseline(c)

@@ -280,7 +280,7 @@ int ggem_fredholm_solve(ggem_solver_t solver, long long n_nodes, const double* n
                         long long n_tri, const int* tri, const double* b, double* q,
                         double tol, int max_iter, int* iters, double* rel_res);
 
-/* ---- boundary-integral single layer and rigid particles (Sec. 3.4, 6.1) --
+/* ---- boundary-integral layers and rigid particles (Sec. 3.4, 3.5, 6.1) --
  *
  * The paper's own discretisation of the single layer on a triangulated
  * surface with the traction f linear on flat triangles (Sec. 3.3.1), at the
@@ -319,6 +319,19 @@ int ggem_rigid_destroy(ggem_rigid_t rigid);
 int ggem_bi_single_layer(ggem_rigid_t rigid, long long n_nodes, const double* nodes,
                          long long n_tri, const int* tri, const int* inc_off, const int* inc_tri,
                          const double* f, double* w);
+
+/* v = the discretised double layer at every node (Sec. 3.5):
+ *   v_j(z) = (1/8pi) n_k(z) [ sum_k int_{S_k} q_i T^l_jik(z - x) dS + sigma^g_jk(z) ],
+ * the same elements, rules and nodal strengths q_b A_b as the single layer,
+ * with n(z) the node normals (n_nodes,3) given by the caller (the paper's
+ * area-averaged normals, Sec. 3.5.2).  On an element that has z as a vertex
+ * the normal is replaced inside the integral by
+ * n~(x) = n_D phi_z + n(z)(1 - phi_z) (Eq. dbl_l1, Eq. ntilde), n_D the
+ * element's unit normal on the side of n(z), and the polar rule is used.
+ * q, v (n_nodes,3) float64, device.  Errors as for ggem_bi_single_layer. */
+int ggem_bi_double_layer(ggem_rigid_t rigid, long long n_nodes, const double* nodes,
+                         long long n_tri, const int* tri, const int* inc_off, const int* inc_tri,
+                         const double* normals, const double* q, double* v);
 
 /* Force- and torque-free rigid particle in the undisturbed flow u_inf
  * (Sec. 6.1, Eq. sl_r): unknowns the nodal tractions f, the translational

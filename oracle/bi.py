@@ -21,6 +21,17 @@ the strength f_b A_b at node b, A_b one third of the areas of the triangles
 at b; the GGEM global problem of these point forces (spread, slit solve with
 wall data from their local sum, interpolation) gives the velocity at z.
 
+Double layer at the nodes (Sec. 3.5), normal n(z) of the target (the
+area-averaged node normal, Sec. 3.5.2):
+
+    v_j(z) = (1/8pi) [ n_k(z) sum_k int_{S_k} q_i T^l_jik(z - x) dS
+                       + n_k(z) sigma^g_jk(z) of the point forces q_b A_b ].
+
+On an element that has z as a vertex the normal outside the integral is
+replaced inside it by n~(x) = n_D phi_z + n(z) (1 - phi_z) (Eq. dbl_l1,
+Eq. ntilde), n_D the element's unit normal and phi_z the basis function of
+the vertex z; that element is integrated with the polar rule.
+
 Rigid particle (Sec. 6.1, Eq. sl_r): U + Omega x (x_b - x_c) + w_b = u_inf(x_b)
 at every node, with the force- and torque-free conditions
 sum_b A_b f_b = 0 and sum_b A_b (x_b - x_c) x f_b = 0.
@@ -32,6 +43,9 @@ Readings where the paper is silent or garbled:
   * the torque-free condition uses the same nodal weights A_b as the force;
   * the wall data of the global problem is the local sum of the nodal point
     forces (the same point forces that make the global density);
+  * n_D is oriented to the side of n(z) (the sign of the cross product of
+    the edges depends on the vertex order); the element with z as a vertex
+    takes the polar rule, as in the single layer;
   * the undisturbed Poiseuille flow has centre-line velocity U0 between the
     walls at y = -H and y = +H: u_inf = U0 (1 - y^2/H^2) e_x (Appendix B).
 """
@@ -41,7 +55,7 @@ import math
 
 import numpy as np
 
-from .ggem import GLOBAL, INV_8PI, single_layer, stokeslet_local
+from .ggem import GLOBAL, INV_8PI, double_layer, single_layer, stokeslet_local, stresslet_local
 from .surface import node_areas
 
 
@@ -104,6 +118,35 @@ def element_local(e, fe, alpha, vertex=None, n=4):
     return np.einsum("vij,vj->i", element_blocks(e, alpha, vertex, n), np.asarray(fe))
 
 
+def element_dl_blocks(e, alpha, nz, vertex=None, n=4):
+    """int over one flat triangle of phi_v(x) T^l_jik(z - x) m_k(x) dS for its
+    three vertices v: (3, 3 (j), 3 (i)), without 1/8pi.  m = n(z) (nz) when z
+    is not a vertex; when it is (local index `vertex`), m = n~(x) of
+    Eq. ntilde and the polar rule about z."""
+    e = np.asarray(e, dtype=np.float64)
+    nz = np.asarray(nz, dtype=np.float64)
+    order = [0, 1, 2] if vertex is None else [(vertex + i) % 3 for i in range(3)]
+    e = e[order]
+    if vertex is not None:
+        e[0] = 0.0
+    cr = np.cross(e[1] - e[0], e[2] - e[0])
+    omega = np.linalg.norm(cr)
+    xi, eta, wts = triangle_rule(n, polar=vertex is not None)
+    phi = np.stack([1.0 - xi - eta, xi, eta], axis=1)           # (q, 3)
+    T = stresslet_local(-(phi @ e), alpha)                       # (q, 3, 3, 3)
+    if vertex is None:
+        m = np.broadcast_to(nz, (len(wts), 3))
+    else:
+        nD = cr / omega
+        if nD @ nz < 0.0:
+            nD = -nD
+        m = phi[:, :1] * nD + (1.0 - phi[:, :1]) * nz
+    B = np.einsum("q,qv,qjik,qk->vji", omega * wts, phi, T, m)
+    out = np.empty_like(B)
+    out[order] = B
+    return out
+
+
 def element_images(g, z, xv):
     """Vertex positions relative to z: the first vertex by the minimum image,
     the others by the minimum image of their offset from the first."""
@@ -146,6 +189,34 @@ def sl_local_elements(g, nodes, tri, f, n=4):
         out[zi] += INV_8PI * element_local(element_images(g, nodes[zi], nodes[tri[k]]),
                                            f[tri[k]], g.alpha, vertex, n)
     return out
+
+
+def dl_local_elements(g, nodes, tri, normals, q, n=4):
+    """(1/8pi) local double layer of Sec. 3.5.2 over the elements within r_c
+    of every node, at every node."""
+    nodes = np.asarray(nodes, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    normals = np.asarray(normals, dtype=np.float64)
+    tri = np.asarray(tri)
+    out = np.zeros_like(nodes)
+    for zi, k, vertex in _local_pairs(g, nodes, tri):
+        B = element_dl_blocks(element_images(g, nodes[zi], nodes[tri[k]]), g.alpha,
+                              normals[zi], vertex, n)
+        out[zi] += INV_8PI * np.einsum("vji,vi->j", B, q[tri[k]])
+    return out
+
+
+def dl_global_nodal(g, nodes, tri, normals, q):
+    """Global double layer of the nodal trapezoid strengths q_b A_b."""
+    A = node_areas(nodes, tri)
+    return double_layer(g, nodes, A[:, None] * np.asarray(q, dtype=np.float64), nodes,
+                        np.asarray(normals, dtype=np.float64), parts=GLOBAL)
+
+
+def dl_bi(g, nodes, tri, normals, q, n=4):
+    """The discretised double layer n_k(z) (1/8pi) int q_i T_jik dS at the nodes."""
+    return dl_local_elements(g, nodes, tri, normals, q, n) + dl_global_nodal(g, nodes, tri,
+                                                                             normals, q)
 
 
 def sl_global_nodal(g, nodes, tri, f):

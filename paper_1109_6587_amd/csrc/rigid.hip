@@ -14,6 +14,15 @@
 // Global part (Sec. 3.4.2): nodal trapezoid strengths f_b A_b (A_b one third
 // of the areas of the triangles at b) through the GGEM global problem.
 //
+// Double layer at the nodes (Sec. 3.5), normal n(z) at the target:
+//
+//   v_j(z) = (1/8pi) [ n_k(z) sum_k int_{S_k} q_i T^l_jik(z - x) dS + n_k(z) sigma^g_jk(z) ],
+//
+// with the same elements and rules; on an element that has z as a vertex the
+// normal is replaced inside the integral by n~(x) = n_D phi_z + n(z)(1 - phi_z)
+// (Eq. dbl_l1, Eq. ntilde), n_D the element normal on the side of n(z), and
+// the global stress is that of the nodal point forces q_b A_b.
+//
 // Rigid particle (Sec. 6.1, Eq. sl_r): unknowns f at the nodes, U and Omega;
 // at every node U + Omega x (x_b - x_c) + w(x_b) = u_inf(x_b), with
 // sum_b A_b f_b = 0 and sum_b A_b (x_b - x_c) x f_b = 0; solved by GMRES (Sec. 5).
@@ -58,7 +67,8 @@ struct BiArgs {
   const int* keys;        // bucket of every node (binning of the nodes)
   const int* cell_start;  // sorted ranges per cell
   const int* perm;        // sorted -> original
-  const double* f;        // (n, 3)
+  const double* f;        // (n, 3) traction (single layer) or density (double layer)
+  const double* nrm;      // (n, 3) node normals (double layer)
   double* out;            // (n, 3)
 };
 
@@ -91,14 +101,45 @@ __device__ inline void add_stokeslet(double dx, double dy, double dz, double fx,
   acc[2] += w * (A * fz + B * df * dz);
 }
 
-// int over one element of f G^l(z - x) dS; e[v] vertex positions relative to
-// z, fe[v] nodal tractions, local vertex 0 is z itself when polar
+// acc += w * T^l_jik(d) q_i m_k = w [C d (d.q)(d.m) + D (d (q.m) + q (d.m) + m (d.q))],
+// C = -6 erfc/r^5 - (12 alpha/sqrt(pi)) e/r^4 - (8 alpha^3/sqrt(pi)) e/r^2,
+// D = (4 alpha^3/sqrt(pi)) e,  e = exp(-alpha^2 r^2)
+__device__ inline void add_stresslet(double dx, double dy, double dz, double qx, double qy,
+                                     double qz, double mx, double my, double mz, double alpha,
+                                     double w, double* acc) {
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  const double r = sqrt(r2);
+  const double ec = erfc(alpha * r), ex = exp(-alpha * alpha * r2);
+  const double a3 = alpha * alpha * alpha / kSqrtPi;
+  const double C = -6.0 * ec / (r2 * r2 * r) - 12.0 * alpha / kSqrtPi * ex / (r2 * r2) -
+                   8.0 * a3 * ex / r2;
+  const double D = 4.0 * a3 * ex;
+  const double dq = dx * qx + dy * qy + dz * qz, dm = dx * mx + dy * my + dz * mz;
+  const double qm = qx * mx + qy * my + qz * mz;
+  const double cd = C * dq * dm;
+  acc[0] += w * (cd * dx + D * (dx * qm + qx * dm + mx * dq));
+  acc[1] += w * (cd * dy + D * (dy * qm + qy * dm + my * dq));
+  acc[2] += w * (cd * dz + D * (dz * qm + qz * dm + mz * dq));
+}
+
+// int over one element of f G^l(z - x) dS (DL: of q_i T^l_jik(z - x) m_k dS,
+// m = n(z), or n~ when polar); e[v] vertex positions relative to z, fe[v]
+// nodal values, local vertex 0 is z itself when polar
+template <bool DL>
 __device__ void element_integral(const double (&e)[3][3], const double (&fe)[3][3], bool polar,
-                                 double alpha, double* acc) {
+                                 double alpha, const double* nz, double* acc) {
   const double u1x = e[1][0] - e[0][0], u1y = e[1][1] - e[0][1], u1z = e[1][2] - e[0][2];
   const double u2x = e[2][0] - e[0][0], u2y = e[2][1] - e[0][1], u2z = e[2][2] - e[0][2];
   const double cx = u1y * u2z - u1z * u2y, cy = u1z * u2x - u1x * u2z, cz = u1x * u2y - u1y * u2x;
   const double omega = sqrt(cx * cx + cy * cy + cz * cz);
+  // element normal on the side of n(z)
+  double nD[3] = {0.0, 0.0, 0.0};
+  if (DL) {
+    const double sg = (cx * nz[0] + cy * nz[1] + cz * nz[2]) < 0.0 ? -1.0 / omega : 1.0 / omega;
+    nD[0] = sg * cx;
+    nD[1] = sg * cy;
+    nD[2] = sg * cz;
+  }
   for (int o = 0; o < 4; ++o) {
     double c = 1.0, s = 0.0, rmax = 1.0, wo;
     if (polar) {
@@ -127,9 +168,16 @@ __device__ void element_integral(const double (&e)[3][3], const double (&fe)[3][
       const double dx = -(p0 * e[0][0] + p1 * e[1][0] + p2 * e[2][0]);
       const double dy = -(p0 * e[0][1] + p1 * e[1][1] + p2 * e[2][1]);
       const double dz = -(p0 * e[0][2] + p1 * e[1][2] + p2 * e[2][2]);
-      add_stokeslet(dx, dy, dz, p0 * fe[0][0] + p1 * fe[1][0] + p2 * fe[2][0],
-                    p0 * fe[0][1] + p1 * fe[1][1] + p2 * fe[2][1],
-                    p0 * fe[0][2] + p1 * fe[1][2] + p2 * fe[2][2], alpha, w, acc);
+      const double vx = p0 * fe[0][0] + p1 * fe[1][0] + p2 * fe[2][0];
+      const double vy = p0 * fe[0][1] + p1 * fe[1][1] + p2 * fe[2][1];
+      const double vz = p0 * fe[0][2] + p1 * fe[1][2] + p2 * fe[2][2];
+      if (DL) {
+        const double a0 = polar ? p0 : 0.0, a1 = 1.0 - a0;  // n~ = n_D phi_z + n(z)(1 - phi_z)
+        add_stresslet(dx, dy, dz, vx, vy, vz, a0 * nD[0] + a1 * nz[0], a0 * nD[1] + a1 * nz[1],
+                      a0 * nD[2] + a1 * nz[2], alpha, w, acc);
+      } else {
+        add_stokeslet(dx, dy, dz, vx, vy, vz, alpha, w, acc);
+      }
     }
   }
 }
@@ -139,7 +187,8 @@ __device__ void element_integral(const double (&e)[3][3], const double (&fe)[3][
 // integrates every triangle at v for which v is the first of the triangle's
 // vertices (in their stored order) within r_c of z, so each element within
 // r_c is integrated exactly once.  Lane sums are added in a fixed tree order.
-__global__ void __launch_bounds__(256) bi_sl_local(BiArgs a) {
+template <bool DL>
+__global__ void __launch_bounds__(256) bi_local(BiArgs a) {
   __shared__ double red[4][3][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int t = blockIdx.x * 4 + wave;
@@ -149,6 +198,9 @@ __global__ void __launch_bounds__(256) bi_sl_local(BiArgs a) {
   const int c = a.keys[t] / g.nzs;
   const int iz = c % g.ncz, ix = (c / g.ncz) % g.ncx, iy = c / (g.ncz * g.ncx);
   const int nxo = g.ncx >= 3 ? 3 : g.ncx, nzo = g.ncz >= 3 ? 3 : g.ncz;
+  double nz[3] = {0.0, 0.0, 0.0};
+  if (DL)
+    for (int d = 0; d < 3; ++d) nz[d] = a.nrm[3 * (size_t)t + d];
   double acc[3] = {0.0, 0.0, 0.0};
   for (int oy = -1; oy <= 1; ++oy) {
     const int cy = iy + oy;
@@ -199,7 +251,7 @@ __global__ void __launch_bounds__(256) bi_sl_local(BiArgs a) {
                 fe[m][d] = a.f[3 * (size_t)w3[m] + d];
               }
             }
-            element_integral(e, fe, polar, a.alpha, acc);
+            element_integral<DL>(e, fe, polar, a.alpha, nz, acc);
           }
         }
       }
@@ -447,9 +499,10 @@ static int set_surface(ggem_rigid_s* r, long long n, const double* x, long long 
   return GGEM_OK;
 }
 
-// w = discretised single layer of f at the nodes (local part into r->wl,
-// global part into r->wg, their sum into w when w is given)
-static int single_layer(ggem_rigid_s* r, const double* f, double* w) {
+// w = discretised single layer of f at the nodes, or with normals the double
+// layer of f (local part into r->wl, global part into r->wg, their sum into w
+// when w is given)
+static int layer(ggem_rigid_s* r, const double* f, const double* normals, double* w) {
   Plan& p = r->plan->p;
   hipStream_t st = p.stream;
   const int n = r->n;
@@ -469,14 +522,21 @@ static int single_layer(ggem_rigid_s* r, const double* f, double* w) {
   a.cell_start = p.src.cell_start;
   a.perm = p.src.perm;
   a.f = f;
+  a.nrm = normals;
   a.out = r->wl;
-  bi_sl_local<<<(n + 3) / 4, 256, 0, st>>>(a);
+  if (normals)
+    bi_local<true><<<(n + 3) / 4, 256, 0, st>>>(a);
+  else
+    bi_local<false><<<(n + 3) / 4, 256, 0, st>>>(a);
   RIGID_TRY(hipGetLastError());
   // global part: nodal trapezoid strengths through the GGEM global problem
   bi_scale<<<(3 * n + 255) / 256, 256, 0, st>>>(n, r->area, f, r->q);
   RIGID_TRY(hipGetLastError());
-  if (int rc = ggem_single_layer(r->plan, n, r->x, r->q, n, r->x, r->wg, GGEM_PART_GLOBAL))
-    return rc;
+  const int rc = normals ? ggem_double_layer(r->plan, n, r->x, r->q, n, r->x, normals, r->wg,
+                                             GGEM_PART_GLOBAL)
+                         : ggem_single_layer(r->plan, n, r->x, r->q, n, r->x, r->wg,
+                                             GGEM_PART_GLOBAL);
+  if (rc) return rc;
   if (w) {
     bi_add<<<(3 * n + 255) / 256, 256, 0, st>>>(3 * n, r->wl, r->wg, w);
     RIGID_TRY(hipGetLastError());
@@ -490,14 +550,24 @@ extern "C" int ggem_bi_single_layer(ggem_rigid_t r, long long n_nodes, const dou
   if (!r) return ggem_set_error(GGEM_E_ARG, "null rigid solver");
   if (!f || !w) return ggem_set_error(GGEM_E_ARG, "null vector");
   if (int rc = set_surface(r, n_nodes, nodes, n_tri, tri, inc_off, inc_tri)) return rc;
-  return single_layer(r, f, w);
+  return layer(r, f, nullptr, w);
+}
+
+extern "C" int ggem_bi_double_layer(ggem_rigid_t r, long long n_nodes, const double* nodes,
+                                    long long n_tri, const int* tri, const int* inc_off,
+                                    const int* inc_tri, const double* normals, const double* q,
+                                    double* v) {
+  if (!r) return ggem_set_error(GGEM_E_ARG, "null rigid solver");
+  if (!normals || !q || !v) return ggem_set_error(GGEM_E_ARG, "null vector");
+  if (int rc = set_surface(r, n_nodes, nodes, n_tri, tri, inc_off, inc_tri)) return rc;
+  return layer(r, q, normals, v);
 }
 
 // y = A x for x = (f, U, Omega)
 static int rigid_apply(ggem_rigid_s* r, const double* x, double* y) {
   hipStream_t st = r->plan->p.stream;
   const int n = r->n;
-  if (int rc = single_layer(r, x, nullptr)) return rc;
+  if (int rc = layer(r, x, nullptr, nullptr)) return rc;
   bi_rigid_rows<<<(n + 255) / 256, 256, 0, st>>>(n, r->x, r->xc[0], r->xc[1], r->xc[2],
                                                  x + 3 * (size_t)n, r->wl, r->wg, y);
   bi_moments_partial<<<kMomBlocks, kMomBlock, 0, st>>>(n, r->x, r->xc[0], r->xc[1], r->xc[2],

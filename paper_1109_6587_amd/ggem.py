@@ -31,7 +31,8 @@ E_DEVICE = -5
 EXPORTS = (
     "ggem_plan_create", "ggem_plan_destroy", "ggem_plan_set_stream", "ggem_plan_status",
     "ggem_single_layer", "ggem_double_layer", "ggem_spread_grid", "ggem_plan_time_stage",
-    "ggem_plan_stage_time", "ggem_plan_work", "ggem_plan_count_work", "ggem_solver_create", "ggem_solver_destroy",
+    "ggem_plan_stage_time", "ggem_plan_work", "ggem_plan_count_work", "ggem_solver_create",
+    "ggem_solver_destroy",
     "ggem_fredholm_apply", "ggem_fredholm_solve", "ggem_surface_geometry", "ggem_drop_rhs",
     "ggem_surface_velocity", "ggem_advance", "ggem_fredholm_solve_guided", "ggem_mlp_create",
     "ggem_mlp_destroy", "ggem_mlp_set_params", "ggem_mlp_get_params", "ggem_mlp_features",
@@ -39,7 +40,8 @@ EXPORTS = (
     "ggem_batch_create", "ggem_batch_destroy", "ggem_batch_single_layer",
     "ggem_batch_capture_single_layer", "ggem_batch_graph_launch", "ggem_batch_status",
     "ggem_batch_branch", "ggem_single_layer_noalloc", "ggem_rigid_create", "ggem_rigid_destroy",
-    "ggem_bi_single_layer", "ggem_rigid_solve", "ggem_poiseuille", "ggem_last_error",
+    "ggem_bi_single_layer", "ggem_bi_double_layer", "ggem_rigid_solve", "ggem_poiseuille",
+    "ggem_last_error",
 )
 
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 13, 128, 3, 35203
@@ -107,6 +109,7 @@ def load_library(path: str = LIB_PATH):
     lib.ggem_rigid_create.argtypes = [vp, ll, ll, ip, ctypes.POINTER(vp)]
     lib.ggem_rigid_destroy.argtypes = [vp]
     lib.ggem_bi_single_layer.argtypes = [vp, ll, dp, ll, dp, dp, dp, dp, dp]
+    lib.ggem_bi_double_layer.argtypes = [vp, ll, dp, ll, dp, dp, dp, dp, dp, dp]
     lib.ggem_rigid_solve.argtypes = [vp, ll, dp, ll, dp, dp, dp, ctypes.POINTER(dd), dp, dp,
                                      ctypes.POINTER(dd), dd, ip, ctypes.POINTER(ip),
                                      ctypes.POINTER(dd)]
@@ -602,6 +605,16 @@ class RigidParticle:
         out = torch.empty_like(nodes) if out is None else out
         _check(_lib.ggem_bi_single_layer(self._h, *m, _dev_ptr(f, "f", m[0]),
                                          _dev_ptr(out, "out", m[0])))
+        return out
+
+    def double_layer(self, nodes, tri, inc_off, inc_tri, normals, q, out=None):
+        """(1/8pi) n(z) . int q T dS at the nodes, n~ on the elements at z
+        (ggem_bi_double_layer)."""
+        import torch
+        m = self._mesh(nodes, tri, inc_off, inc_tri)
+        out = torch.empty_like(nodes) if out is None else out
+        _check(_lib.ggem_bi_double_layer(self._h, *m, _dev_ptr(normals, "normals", m[0]),
+                                         _dev_ptr(q, "q", m[0]), _dev_ptr(out, "out", m[0])))
         return out
 
     def solve(self, nodes, tri, inc_off, inc_tri, center, uinf, f, motion=None, tol=1e-10,

@@ -7,7 +7,7 @@ import pytest
 
 import oracle as O
 import oracle.bi as bi
-from workloads.inputs import icosphere
+from workloads.inputs import case_rigid_sphere, icosphere
 
 pytestmark = pytest.mark.gpu
 
@@ -37,6 +37,27 @@ def small_grid():
     return O.SlitGrid(2.0, 2.0, 0.75, 8.0, 0.5, 32, 32, 33)
 
 
+_REF = {}
+
+
+def reference(kind, center):
+    """Oracle value of one layer on the level-2 sphere at `center` (cached:
+    the same for both precisions)."""
+    key = (kind, center)
+    if key not in _REF:
+        g = small_grid()
+        V, F = icosphere(2)
+        nodes = V * 0.3 + np.asarray(center)
+        if kind == "sl":
+            f = np.random.default_rng(11).standard_normal(nodes.shape)
+            _REF[key] = (f, None, bi.sl_bi(g, nodes, F, f))
+        else:
+            nrm = O.node_normals(nodes, F)
+            q = np.random.default_rng(12).standard_normal(nodes.shape)
+            _REF[key] = (q, nrm, bi.dl_bi(g, nodes, F, nrm, q))
+    return _REF[key]
+
+
 def make(g, n, ntri, precision="fp64", restart=60):
     plan = G.Plan(g.Lx, g.Lz, g.H, g.alpha, g.Nx, g.Nz, g.Ny, rc=g.rc, precision=precision,
                   max_src=n, max_tgt=n)
@@ -52,17 +73,25 @@ def test_bi_single_layer(precision, tol, center):
     print(f"bi single layer {precision} {center}", flush=True)
     g = small_grid()
     nodes, F, m = mesh(2, 0.3, center)
-    f = np.random.default_rng(11).standard_normal(nodes.shape)
+    f, _, ref = reference("sl", center)
     plan, rp = make(g, len(nodes), len(F), precision)
     u = rp.single_layer(*m, dev(f)).cpu().numpy()
-    ref = bi.sl_bi(g, nodes, F, f)
     assert np.abs(u - ref).max() < tol * np.abs(ref).max()
-    if precision == "fp64":
-        # the local part alone is FP64 in both modes
-        loc = bi.sl_local_elements(g, nodes, F, f)
-        ug = O.single_layer(g, nodes, O.node_areas(nodes, F)[:, None] * f, nodes,
-                            parts=O.GLOBAL)
-        assert np.abs(loc + ug - ref).max() < 1e-14 * np.abs(ref).max()
+    rp.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+@pytest.mark.parametrize("center", [(1.0, 0.05, 1.0), (0.12, -0.1, 1.93)])
+def test_bi_double_layer(precision, tol, center):
+    """The element double layer with n~ on the elements at the target, and
+    the stress of the nodal point forces, against the oracle."""
+    print(f"bi double layer {precision} {center}", flush=True)
+    g = small_grid()
+    nodes, F, m = mesh(2, 0.3, center)
+    q, nrm, ref = reference("dl", center)
+    plan, rp = make(g, len(nodes), len(F), precision)
+    v = rp.double_layer(*m, dev(nrm), dev(q)).cpu().numpy()
+    assert np.abs(v - ref).max() < tol * np.abs(ref).max()
     rp.close()
 
 
@@ -108,21 +137,17 @@ def test_rigid_errors():
 
 
 def sphere_velocity(L, level=4):
-    """Translational velocity of a force- and torque-free sphere, 2a/(2H) =
-    0.6, centred between the walls in Poiseuille flow of centre-line
-    velocity 1; the GGEM parameters of Sec. 6.1: r_c = 0.5 a = 4/alpha,
-    N_y = 61, equal mean mesh spacings (alpha dy_m = 0.44), L_x = L_z = L."""
-    H, a = 0.5, 0.3
-    alpha = 4.0 / (0.5 * a)
-    N = int(round(L * 60))
-    xc = np.array([L / 2, 0.0, L / 2])
-    nodes, F, m = mesh(level, a, xc)
-    plan = G.Plan(L, L, H, alpha, N, N, 61, rc=0.5 * a, precision="fp64", max_src=len(nodes),
-                  max_tgt=len(nodes))
-    rp = G.RigidParticle(plan, len(nodes), len(F), restart=100)
-    uinf = G.poiseuille(plan, 1.0, m[0])
+    """Translational velocity of the force- and torque-free sphere of the
+    rigid-particle validation (workloads.case_rigid_sphere)."""
+    c = case_rigid_sphere(L, level)
+    off, adj = incidence(c.tri, len(c.nodes))
+    m = (dev(c.nodes), dev(c.tri, torch.int32), dev(off, torch.int32), dev(adj, torch.int32))
+    plan = G.Plan(c.Lx, c.Lz, c.H, c.alpha, c.Nx, c.Nz, c.Ny, rc=c.rc, precision="fp64",
+                  max_src=len(c.nodes), max_tgt=len(c.nodes))
+    rp = G.RigidParticle(plan, len(c.nodes), len(c.tri), restart=100)
+    uinf = G.poiseuille(plan, c.U0, m[0])
     f = torch.zeros_like(m[0])
-    U, W, iters, rel = rp.solve(*m, xc, uinf, f, tol=1e-8, max_iter=800)
+    U, W, iters, rel = rp.solve(*m, c.center, uinf, f, tol=1e-8, max_iter=800)
     rp.close()
     plan.close()
     return U, W, iters, rel

@@ -173,3 +173,69 @@ def test_torque_of_a_rotational_traction(sphere):
     a = np.linalg.norm(r, axis=1).mean()
     assert np.abs(Fo).max() < 1e-12
     assert np.abs(T - (2.0 / 3.0) * a * a * A.sum() * W0).max() < 0.02 * np.abs(T).max()
+
+
+def test_dl_vertex_element_with_ntilde():
+    """Double layer on an element that has z as a vertex, alpha -> 0 (T^l ->
+    -6 ddd/r^5), with n~ of Eq. ntilde: in polar coordinates about z the
+    in-plane d makes d . n_D = 0, so T n~ = 6 u u (u . n_z)(c + s)/(rho |u|^5)
+    (u = c e1 + s e2) and the rho-integral of each basis function is
+    elementary.  The remaining theta-integral by SciPy's adaptive quadrature
+    is the reference: the polar 4 x 4 rule is within 2e-3 of it (the
+    theta-integrand is not a polynomial), 48 x 48 within 1e-10."""
+    e = np.array([[0.0, 0.0, 0.0], [0.3, 0.05, 0.0], [0.1, 0.25, 0.02]])
+    nz = np.array([0.1, -0.2, 1.0])
+    nz /= np.linalg.norm(nz)
+    omega = np.linalg.norm(np.cross(e[1], e[2]))
+
+    def ref(v, j, i):
+        def f(th):
+            c, s = math.cos(th), math.sin(th)
+            R = 1.0 / (c + s)
+            u = c * e[1] + s * e[2]
+            phi_int = (R / 2, c * R * R / 2, s * R * R / 2)[v]
+            return 6.0 * omega * (c + s) * (u @ nz) * u[j] * u[i] / np.linalg.norm(u) ** 5 * phi_int
+        return integrate.quad(f, 0.0, 0.5 * math.pi, epsabs=1e-14, epsrel=1e-13)[0]
+
+    B4 = bi.element_dl_blocks(e, 1e-14, nz, vertex=0, n=4)
+    B48 = bi.element_dl_blocks(e, 1e-14, nz, vertex=0, n=48)
+    scale = np.abs(B48).max()
+    for v, j, i in ((0, 0, 0), (1, 0, 1), (2, 2, 1), (0, 1, 2), (2, 2, 2)):
+        r = ref(v, j, i)
+        assert abs(B48[v, j, i] - r) < 1e-10 * scale
+        assert abs(B4[v, j, i] - r) < 2e-3 * scale
+
+
+def test_dl_flat_patch_with_matching_normal_vanishes():
+    """With n(z) equal to the element normal, n~ is that normal everywhere
+    and every in-plane d has d . n = 0: as alpha -> 0 the double layer of the
+    element at its own vertex vanishes (the stresslet's remaining term
+    carries alpha^3)."""
+    e = np.array([[0.0, 0.0, 0.0], [0.3, 0.05, 0.0], [0.1, 0.25, 0.02]])
+    n = np.cross(e[1], e[2])
+    n /= np.linalg.norm(n)
+    B = bi.element_dl_blocks(e, 1e-14, n, vertex=0, n=4)
+    assert np.abs(B).max() < 1e-12
+    assert np.abs(bi.element_dl_blocks(e, 1e-14, -n, vertex=0, n=4)).max() < 1e-12
+
+
+def test_dl_regular_element_against_adaptive_quadrature():
+    alpha = 2.0
+    e = np.array([[0.25, 0.05, 0.1], [0.45, 0.1, 0.05], [0.3, 0.3, 0.2]])
+    nz = np.array([0.3, 0.9, -0.2])
+    nz /= np.linalg.norm(nz)
+    omega = np.linalg.norm(np.cross(e[1] - e[0], e[2] - e[0]))
+
+    def ref(v, j, i):
+        def f(xi, eta):
+            phi = np.array([1 - xi - eta, xi, eta])
+            return phi[v] * (O.stresslet_local(-(phi @ e), alpha)[j, i] @ nz) * omega
+        return integrate.dblquad(f, 0, 1, 0, lambda eta: 1 - eta, epsabs=1e-13, epsrel=1e-12)[0]
+
+    B16 = bi.element_dl_blocks(e, alpha, nz, n=16)
+    B4 = bi.element_dl_blocks(e, alpha, nz, n=4)
+    scale = np.abs(B16).max()
+    for v, j, i in ((0, 0, 0), (1, 0, 1), (2, 2, 1)):
+        r = ref(v, j, i)
+        assert abs(B16[v, j, i] - r) < 1e-10 * scale
+        assert abs(B4[v, j, i] - r) < 1e-3 * scale

@@ -64,6 +64,9 @@ MUTATIONS = {
     "dropped polar Jacobian rho": ("bi",
         "wts.append((0.5 * math.pi * wk) * (rmax * wi) * rho)",
         "wts.append((0.5 * math.pi * wk) * (rmax * wi))"),
+    "n(z) kept on the element at z (no n~)": ("bi",
+        "m = phi[:, :1] * nD + (1.0 - phi[:, :1]) * nz",
+        "m = np.broadcast_to(nz, (len(wts), 3))"),
     "torque row with r and f swapped": ("bi",
         "T = (A[:, None] * np.cross(r, f)).sum(axis=0)",
         "T = (A[:, None] * np.cross(f, r)).sum(axis=0)"),
@@ -130,6 +133,7 @@ CHECKS = [
     ("element rule on polynomials", BI.test_regular_rule_exact_for_polynomials),
     ("vertex element in closed form",
      lambda: BI.test_vertex_element_singular_integral(((0.3, 0.05, 0.0), (0.1, 0.25, 0.02)))),
+    ("double-layer vertex element with n~", BI.test_dl_vertex_element_with_ntilde),
     ("T^l is the Newtonian stress", lambda: KER.test_stresslet_is_newtonian_stress(3)),
     ("manufactured Stokes mode", lambda: SPE.test_stokes_mode_manufactured((3, 1), np.random.default_rng(1))),
     ("manufactured zero mode", lambda: SPE.test_stokes_zero_mode_manufactured(np.random.default_rng(2))),

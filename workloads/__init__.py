@@ -15,4 +15,6 @@ from .inputs import (  # noqa: F401
     case_small_surface,
     DropCase,
     case_shear_drops,
+    RigidSphereCase,
+    case_rigid_sphere,
 )

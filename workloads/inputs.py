@@ -394,3 +394,42 @@ def case_shear_drops(seed: int = 4, level: int = 3, ncap: int = 100, L: float = 
     return DropCase(f"shear_drops_{ncap}x{V.shape[0]}", L, L, H, 2.0, 2.0, N, N, Ny, nodes,
                     tri.astype(np.int32), ncap, V.shape[0], 5.0, 2.0, 1.0, 0.01, 200,
                     dict(seed=seed, level=level))
+
+
+@dataclass
+class RigidSphereCase:
+    """A rigid sphere between the walls in pressure-driven flow."""
+
+    name: str
+    Lx: float
+    Lz: float
+    H: float
+    alpha: float
+    rc: float
+    Nx: int
+    Nz: int
+    Ny: int
+    nodes: np.ndarray         # (n, 3) mesh nodes
+    tri: np.ndarray           # (ntri, 3) int32 triangles (outward)
+    center: np.ndarray        # (3,)
+    U0: float                 # centre-line velocity of the undisturbed flow
+    a: float
+
+
+def case_rigid_sphere(L: float = 5.0, level: int = 4) -> RigidSphereCase:
+    """The rigid-particle validation of Sec. 6.1 (no random draws).
+
+    Walls one unit apart (H = 0.5 here), a sphere of radius a = 0.3
+    (confinement 2a over the wall spacing = 0.6) centred between them (the
+    paper's y_c/H = 1/2) in Poiseuille flow of centre-line velocity 1;
+    level-4 icosphere (5,120 triangles, 2,562 nodes); r_c = 0.5 a = 4/alpha;
+    N_y = 61 and equal mean mesh spacings 1/60 in all directions
+    (alpha dy_m = 0.44); L_x = L_z = L (the paper takes L = 5 wall spacings
+    and extrapolates in L^-2)."""
+    H, a = 0.5, 0.3
+    rc = 0.5 * a
+    N = int(round(L * 60))
+    V, F = icosphere(level)
+    center = np.array([L / 2, 0.0, L / 2])
+    return RigidSphereCase(f"rigid_sphere_L{L:g}", L, L, H, 4.0 / rc, rc, N, N, 61,
+                           V * a + center, F.astype(np.int32), center, 1.0, a)
