@@ -350,6 +350,52 @@ int ggem_rigid_solve(ggem_rigid_t rigid, long long n_nodes, const double* nodes,
                      const double* uinf, double* f, double* motion, double tol, int max_iter,
                      int* iters, double* rel_res);
 
+/* ---- pressure and stress at probes, undisturbed-flow traction ----------
+ *
+ * ggem_probe: the velocity, pressure and stress of point forces at probes:
+ *   u = u^l + u^g,  p = p^l + p^g,  sigma = sigma^l + sigma^g,
+ * the local parts summed over the sources within r_c of a probe (minimum
+ * image) with the kernels of Eq. local (a)-(c) and the 1/8pi of the single
+ * layer (a coincident source adds -(4 alpha/sqrt(pi))/(8pi) f to the velocity
+ * only), the global parts the slit solution of Appendix C (velocity, pressure,
+ * and sigma = -p I + grad u + grad u^T formed in coefficient space)
+ * interpolated with the 4th-order Lagrange stencil of Sec. 3.2.2.  The
+ * pressure gauge is the double layer's: the lateral mean of the total
+ * pressure at y = -H is zero.  xs, f (ns,3) and xt (nt,3) float64 device
+ * arrays (x, z any periodic image; sources strictly inside the slit, probes
+ * with |y| <= H); outputs u (nt,3), p (nt), sigma (nt,6) in the order xx,
+ * yy, zz, xy, xz, yz, float64 device.  The local parts are summed in FP64,
+ * the grid fields keep the plan's precision.  Runs on the plan's stream
+ * without the second stream.  Errors: GGEM_E_ARG, GGEM_E_CAPACITY (ns above
+ * max_src), GGEM_E_DOMAIN (a source or probe outside the slit, reported as
+ * for the evaluations), GGEM_E_DEVICE. */
+int ggem_probe(ggem_plan_t plan, long long ns, const double* xs, const double* f, long long nt,
+               const double* xt, double* u, double* p, double* sigma);
+
+enum { GGEM_FLOW_SHEAR = 0, GGEM_FLOW_POISEUILLE = 1 };
+
+/* Traction f = sigma_inf . n of an undisturbed flow (Appendix B) at the n
+ * points x (n,3) with normals nrm (n,3) -> f (n,3), float64 device, on the
+ * plan's stream.  GGEM_FLOW_SHEAR: u = (rate y, 0, 0), sigma = rate e
+ * (e_xy = e_yx = 1).  GGEM_FLOW_POISEUILLE: centre-line velocity rate between
+ * the plan's walls, p = -(2 rate/H^2) x, sigma = (2 rate/H^2)(x I - y e)
+ * (x as given: the pressure is not periodic).  Errors: GGEM_E_ARG. */
+int ggem_undisturbed_traction(ggem_plan_t plan, int kind, double rate, long long n,
+                              const double* x, const double* nrm, double* f);
+
+/* Particle stress (Sec. 7.1, mu = 1) of the particles whose surfaces the
+ * mesh holds:
+ *   Sigma^p_ij = (1/V) sum int [df_i x_j + (lambda - 1)(u_i n_j + u_j n_i)] dS,
+ * the integral taken with the nodal weights A_b (one third of the areas of
+ * the triangles at b).  df: traction jump, u: surface velocity, normals: node
+ * normals, all (n_nodes,3) float64 device; volume V > 0 of the domain; out
+ * (host, 9) row-major Sigma^p.  Mesh arrays and errors as for
+ * ggem_bi_single_layer, plus GGEM_E_ARG for volume <= 0. */
+int ggem_particle_stress(ggem_rigid_t rigid, long long n_nodes, const double* nodes,
+                         long long n_tri, const int* tri, const int* inc_off, const int* inc_tri,
+                         const double* normals, const double* df, const double* u, double lambda,
+                         double volume, double* out);
+
 /* Undisturbed pressure-driven flow between the plan's walls (Appendix B):
  * u = U0 (1 - y^2/H^2) e_x at the n points x (n,3) float64 -> u (n,3),
  * device arrays, on the plan's stream.  Errors: GGEM_E_ARG. */

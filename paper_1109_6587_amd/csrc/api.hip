@@ -666,6 +666,57 @@ extern "C" int ggem_spread_grid(ggem_plan_t plan, long long ns, const double* xs
   return finish(p);
 }
 
+// Probes: the global problem with the double layer's gauge, its six stress
+// components interpolated first, then its velocity and pressure (the
+// coefficients tau keeps from the stress pass, transformed back through the
+// same buffers), each added onto the local parts.  All on the plan's stream.
+template <typename T>
+static int probe_eval(Plan& p, long long ns, const double* xs, const double* f, long long nt,
+                      const double* xt, double* u, double* pr, double* sigma) {
+  const int Ny = p.p.Ny;
+  HIP_TRY(launch_bin(p, p.src, ns, xs, f, nullptr, true, true));
+  HIP_TRY(launch_wall<T>(p));
+  HIP_TRY(launch_gauge(p));
+  HIP_TRY(launch_fft_forward<T>(p, p.wall_phys, p.wall_spec, 6));
+  HIP_TRY(launch_spread<T>(p, 0));
+  HIP_TRY(launch_fft_forward<T>(p, p.phys, p.specA, 3 * Ny));
+  HIP_TRY(launch_cheb<T>(p, p.specA, p.specB, 3, true));
+  HIP_TRY(launch_tau<T>(p, true));
+  HIP_TRY(launch_cheb<T>(p, p.specA, p.specB, 6, false));
+  HIP_TRY(launch_fft_inverse<T>(p, p.specB, p.phys, 6 * Ny));
+  HIP_TRY(launch_probe_local(p, (int)nt, xt, f, u, pr, sigma));
+  HIP_TRY(launch_probe_interp<T>(p, (int)nt, xt, 6, 6, sigma, 6, nullptr, 0));
+  HIP_TRY(launch_tau_export<T>(p));
+  HIP_TRY(launch_cheb<T>(p, p.specA, p.specB, 4, false));
+  HIP_TRY(launch_fft_inverse<T>(p, p.specB, p.phys, 4 * Ny));
+  HIP_TRY(launch_probe_interp<T>(p, (int)nt, xt, 4, 3, u, 3, pr, 1));
+  return finish(p);
+}
+
+extern "C" int ggem_probe(ggem_plan_t plan, long long ns, const double* xs, const double* f,
+                          long long nt, const double* xt, double* u, double* pr, double* sigma) {
+  if (int rc = check_plan(plan)) return rc;
+  Plan& p = plan->p;
+  if (ns < 0 || nt < 0) return fail(GGEM_E_ARG, "negative point count");
+  if (ns > p.p.max_src) return fail(GGEM_E_CAPACITY, "ns=%lld exceeds max_src=%lld", ns, p.p.max_src);
+  if (nt > (1LL << 30)) return fail(GGEM_E_ARG, "too many probes");
+  if (ns > 0 && (!xs || !f)) return fail(GGEM_E_ARG, "null source array");
+  if (nt > 0 && (!xt || !u || !pr || !sigma)) return fail(GGEM_E_ARG, "null probe array");
+  return p.fp64 ? probe_eval<double>(p, ns, xs, f, nt, xt, u, pr, sigma)
+                : probe_eval<float>(p, ns, xs, f, nt, xt, u, pr, sigma);
+}
+
+extern "C" int ggem_undisturbed_traction(ggem_plan_t plan, int kind, double rate, long long n,
+                                         const double* x, const double* nrm, double* f) {
+  if (int rc = check_plan(plan)) return rc;
+  if (kind != GGEM_FLOW_SHEAR && kind != GGEM_FLOW_POISEUILLE)
+    return fail(GGEM_E_ARG, "unknown flow kind %d", kind);
+  if (n < 0 || n > (1LL << 30)) return fail(GGEM_E_ARG, "point count out of range");
+  if (n > 0 && (!x || !nrm || !f)) return fail(GGEM_E_ARG, "null array");
+  HIP_TRY(launch_undisturbed_traction(plan->p, kind, rate, (int)n, x, nrm, f));
+  return GGEM_OK;
+}
+
 extern "C" int ggem_plan_time_stage(ggem_plan_t plan, int stage, int max_calls) {
   if (int rc = check_plan(plan)) return rc;
   Plan& p = plan->p;

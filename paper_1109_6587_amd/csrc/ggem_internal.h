@@ -128,6 +128,38 @@ struct Plan {
   bool count_work;    // kernels count their work units (pairs, updates)
 };
 
+// ---- 4th-order Lagrange interpolation (Sec. 3.2.2), shared by the
+// interpolation kernels ---------------------------------------------------
+
+// nodes at -2..2: w_q = prod_{p != q} (t - p + 2) / prod_{p != q} (q - p), the
+// denominators being 24, -6, 4, -6, 24
+__device__ inline void lagrange5_uniform(double t, double* w) {
+  const double d0 = t + 2.0, d1 = t + 1.0, d2 = t, d3 = t - 1.0, d4 = t - 2.0;
+  const double d01 = d0 * d1, d34 = d3 * d4;
+  w[0] = d1 * d2 * d34 * (1.0 / 24.0);
+  w[1] = d0 * d2 * d34 * (-1.0 / 6.0);
+  w[2] = d01 * d34 * 0.25;
+  w[3] = d01 * d2 * d4 * (-1.0 / 6.0);
+  w[4] = d01 * d2 * d3 * (1.0 / 24.0);
+}
+
+__device__ inline void lagrange5(double t, const double* nd, double* w) {
+  double d[5];
+  for (int p = 0; p < 5; ++p) d[p] = t - nd[p];
+  for (int q = 0; q < 5; ++q) {
+    double num = 1.0, den = 1.0;
+    for (int p = 0; p < 5; ++p)
+      if (p != q) {
+        num *= d[p];
+        den *= nd[q] - nd[p];
+      }
+    w[q] = num / den;
+  }
+}
+
+// v in [-n, 2n) mapped into [0, n)
+__device__ inline int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
 // ---- kernel launchers (each enqueues on p.stream) -------------------------
 // first: this binning opens an evaluation, so its scan also resets the
 // pair counters and overwrites the domain flags (later ones OR into them).
@@ -150,7 +182,16 @@ template <typename T>
 hipError_t launch_cheb(Plan& p, const void* in, void* out, int nfields, bool forward);
 template <typename T>
 hipError_t launch_tau(Plan& p, bool stress);
+template <typename T>
+hipError_t launch_tau_export(Plan& p);
 hipError_t launch_influence(Plan& p);
+hipError_t launch_probe_local(Plan& p, int nt, const double* xt, const double* f, double* u,
+                              double* pr, double* sigma);
+template <typename T>
+hipError_t launch_probe_interp(Plan& p, int nt, const double* xt, int ncomp, int split,
+                               double* out0, int stride0, double* out1, int stride1);
+hipError_t launch_undisturbed_traction(Plan& p, int kind, double rate, int n, const double* x,
+                                       const double* nrm, double* f);
 template <typename T>
 hipError_t launch_interp(Plan& p, int nt, double* out, bool stress, bool with_global);
 template <typename T>

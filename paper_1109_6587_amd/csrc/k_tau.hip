@@ -792,6 +792,37 @@ static void launch_tau_reg(Plan& p, const TauArgs& a, unsigned nb, unsigned nc, 
   }
 }
 
+// The global velocity and pressure coefficients that the stress pass of
+// tau_combine keeps in its work array (slots kU, kV, kW, kP), as four
+// coefficient fields [field][n][mode] of the grid's type (Nyquist modes zero).
+template <typename T>
+__global__ void __launch_bounds__(256) tau_export(TauArgs a) {
+  const size_t S = (size_t)a.nmodes;
+  const int Ny = a.N + 1;
+  const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (size_t)Ny * S) return;
+  const int n = (int)(idx / S);
+  const int q = (int)(idx - (size_t)n * S);
+  const Mode md = mode_of(a, q);
+  typename CT<T>::t* out = (typename CT<T>::t*)a.out;
+  const int slots[4] = {kU, kV, kW, kP};
+  for (int f = 0; f < 4; ++f) {
+    const double2 v = md.nyquist ? z2(0, 0) : a.scr[((size_t)slots[f] * Ny + n) * S + q];
+    out[((size_t)f * Ny + n) * S + q] = from_z<T>(v);
+  }
+}
+
+template <typename T>
+hipError_t launch_tau_export(Plan& p) {
+  TauArgs a = tau_args(p);
+  const size_t tot = (size_t)p.p.Ny * p.nmodes;
+  tau_export<T><<<(unsigned)((tot + 255) / 256), 256, 0, p.stream>>>(a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_tau_export<double>(Plan&);
+template hipError_t launch_tau_export<float>(Plan&);
+
 template <typename T>
 hipError_t launch_tau(Plan& p, bool stress) {
   TauArgs a = tau_args(p);

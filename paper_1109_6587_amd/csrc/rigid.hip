@@ -387,6 +387,32 @@ __global__ void __launch_bounds__(64) bi_moments_final(const double* __restrict_
   if (threadIdx.x == 0) out[m] = red[0];
 }
 
+// part[m][blk] (m = 3 i + j): block sums over its node range of
+// A_b [df_i x_j + (lambda - 1)(u_i n_j + u_j n_i)] (fixed order)
+__global__ void __launch_bounds__(kMomBlock) particle_stress_partial(
+    int n, const double* __restrict__ x, const double* __restrict__ area,
+    const double* __restrict__ nrm, const double* __restrict__ df, const double* __restrict__ u,
+    double lm1, double* __restrict__ part) {
+  __shared__ double red[9][kMomBlock];
+  double s[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = blockIdx.x * kMomBlock + threadIdx.x; b < n; b += kMomBlocks * kMomBlock) {
+    const double A = area[b];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        s[3 * i + j] += A * (df[3 * (size_t)b + i] * x[3 * (size_t)b + j] +
+                             lm1 * (u[3 * (size_t)b + i] * nrm[3 * (size_t)b + j] +
+                                    u[3 * (size_t)b + j] * nrm[3 * (size_t)b + i]));
+  }
+  for (int m = 0; m < 9; ++m) red[m][threadIdx.x] = s[m];
+  __syncthreads();
+  for (int o = kMomBlock / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o)
+      for (int m = 0; m < 9; ++m) red[m][threadIdx.x] += red[m][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x < 9) part[threadIdx.x * kMomBlocks + blockIdx.x] = red[threadIdx.x][0];
+}
+
 // Poiseuille flow between the walls y = -H and y = +H (Appendix B)
 __global__ void poiseuille_kernel(int n, double U0, double H, const double* __restrict__ x,
                                   double* __restrict__ u) {
@@ -408,6 +434,7 @@ struct ggem_rigid_s {
   ggem_plan_s* plan;
   long long max_nodes, max_tri;
   double *area, *wl, *wg, *q, *part;
+  double* stress;       // particle-stress partials (9 x kMomBlocks) and totals (9)
   double *xsys, *bsys;  // solution and right-hand side of the rigid system (3n + 6)
   int *bad, *bad_host;
   gm::Work W;
@@ -425,7 +452,7 @@ struct ggem_rigid_s {
   } while (0)
 
 static void free_rigid(ggem_rigid_s* r) {
-  void* ptrs[] = {r->area, r->wl, r->wg, r->q, r->part, r->xsys, r->bsys, r->bad};
+  void* ptrs[] = {r->area, r->wl, r->wg, r->q, r->part, r->stress, r->xsys, r->bsys, r->bad};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (r->bad_host) (void)hipHostFree(r->bad_host);
@@ -449,6 +476,7 @@ extern "C" int ggem_rigid_create(ggem_plan_t plan, long long max_nodes, long lon
   r->max_tri = max_tri;
   const size_t n3 = 3 * (size_t)max_nodes, ns = n3 + 6;
   const bool ok = hipMalloc((void**)&r->area, max_nodes * 8) == hipSuccess &&
+                  hipMalloc((void**)&r->stress, 9 * kMomBlocks * 8 + 9 * 8) == hipSuccess &&
                   hipMalloc((void**)&r->wl, n3 * 8) == hipSuccess &&
                   hipMalloc((void**)&r->wg, n3 * 8) == hipSuccess &&
                   hipMalloc((void**)&r->q, n3 * 8) == hipSuccess &&
@@ -619,5 +647,26 @@ extern "C" int ggem_poiseuille(ggem_plan_t plan, double U0, long long n, const d
   Plan& p = plan->p;
   poiseuille_kernel<<<(unsigned)((n + 255) / 256), 256, 0, p.stream>>>((int)n, U0, p.p.H, x, u);
   RIGID_TRY(hipGetLastError());
+  return GGEM_OK;
+}
+
+extern "C" int ggem_particle_stress(ggem_rigid_t r, long long n_nodes, const double* nodes,
+                                    long long n_tri, const int* tri, const int* inc_off,
+                                    const int* inc_tri, const double* normals, const double* df,
+                                    const double* u, double lambda, double volume,
+                                    double* out) {
+  if (!r) return ggem_set_error(GGEM_E_ARG, "null rigid solver");
+  if (!normals || !df || !u || !out) return ggem_set_error(GGEM_E_ARG, "null argument");
+  if (!(volume > 0)) return ggem_set_error(GGEM_E_ARG, "volume must be positive");
+  if (int rc = set_surface(r, n_nodes, nodes, n_tri, tri, inc_off, inc_tri)) return rc;
+  hipStream_t st = r->plan->p.stream;
+  particle_stress_partial<<<kMomBlocks, kMomBlock, 0, st>>>(r->n, r->x, r->area, normals, df, u,
+                                                            lambda - 1.0, r->stress);
+  double* tot = r->stress + 9 * kMomBlocks;
+  bi_moments_final<<<9, 64, 0, st>>>(r->stress, tot);
+  RIGID_TRY(hipGetLastError());
+  RIGID_TRY(hipMemcpyAsync(out, tot, 9 * 8, hipMemcpyDeviceToHost, st));
+  RIGID_TRY(hipStreamSynchronize(st));
+  for (int m = 0; m < 9; ++m) out[m] /= volume;
   return GGEM_OK;
 }

@@ -13,6 +13,9 @@ import os
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libggem.so")
 
+FLOW_SHEAR = 0
+FLOW_POISEUILLE = 1
+
 FP64 = 0
 MIXED = 1
 MIXED_BF16 = 2
@@ -41,7 +44,7 @@ EXPORTS = (
     "ggem_batch_capture_single_layer", "ggem_batch_graph_launch", "ggem_batch_status",
     "ggem_batch_branch", "ggem_single_layer_noalloc", "ggem_rigid_create", "ggem_rigid_destroy",
     "ggem_bi_single_layer", "ggem_bi_double_layer", "ggem_rigid_solve", "ggem_poiseuille",
-    "ggem_last_error",
+    "ggem_probe", "ggem_undisturbed_traction", "ggem_particle_stress", "ggem_last_error",
 )
 
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 13, 128, 3, 35203
@@ -114,6 +117,10 @@ def load_library(path: str = LIB_PATH):
                                      ctypes.POINTER(dd), dd, ip, ctypes.POINTER(ip),
                                      ctypes.POINTER(dd)]
     lib.ggem_poiseuille.argtypes = [vp, dd, ll, dp, dp]
+    lib.ggem_probe.argtypes = [vp, ll, dp, dp, ll, dp, dp, dp, dp]
+    lib.ggem_undisturbed_traction.argtypes = [vp, ip, dd, ll, dp, dp, dp]
+    lib.ggem_particle_stress.argtypes = [vp, ll, dp, ll, dp, dp, dp, dp, dp, dp, dd, dd,
+                                         ctypes.POINTER(dd)]
     fp = ctypes.POINTER(ctypes.c_float)
     lib.ggem_fredholm_solve_guided.argtypes = [vp, ll, dp, dp, dp, dd, ll, dp, dp, dp, dp, dd, ip,
                                                ctypes.POINTER(ip), ctypes.POINTER(dd),
@@ -229,6 +236,18 @@ class Plan:
         c = (ctypes.c_ulonglong * 2)()
         _check(_lib.ggem_plan_work(self._h, c))
         return int(c[0]), int(c[1])
+
+    def probe(self, xs, f, xt):
+        """Velocity (nt, 3), pressure (nt,) and stress (nt, 6: xx, yy, zz, xy,
+        xz, yz) of the point forces at the probes xt (ggem_probe)."""
+        import torch
+        ns, nt = xs.shape[0], xt.shape[0]
+        u = torch.empty((nt, 3), dtype=torch.float64, device=xt.device)
+        p = torch.empty((nt,), dtype=torch.float64, device=xt.device)
+        s = torch.empty((nt, 6), dtype=torch.float64, device=xt.device)
+        _check(_lib.ggem_probe(self._h, ns, _dev_ptr(xs, "xs"), _dev_ptr(f, "f", ns), nt,
+                               _dev_ptr(xt, "xt"), u.data_ptr(), p.data_ptr(), s.data_ptr()))
+        return u, p, s
 
     def single_layer(self, xs, f, xt, parts=PART_ALL, out=None):
         import torch
@@ -617,6 +636,15 @@ class RigidParticle:
                                          _dev_ptr(q, "q", m[0]), _dev_ptr(out, "out", m[0])))
         return out
 
+    def particle_stress(self, nodes, tri, inc_off, inc_tri, normals, df, u, lam, volume):
+        """Sigma^p (3 x 3 nested list) of Sec. 7.1 (ggem_particle_stress)."""
+        m = self._mesh(nodes, tri, inc_off, inc_tri)
+        out = (ctypes.c_double * 9)()
+        _check(_lib.ggem_particle_stress(self._h, *m, _dev_ptr(normals, "normals", m[0]),
+                                         _dev_ptr(df, "df", m[0]), _dev_ptr(u, "u", m[0]),
+                                         float(lam), float(volume), out))
+        return [list(out[3 * i:3 * i + 3]) for i in range(3)]
+
     def solve(self, nodes, tri, inc_off, inc_tri, center, uinf, f, motion=None, tol=1e-10,
               max_iter=400):
         """Solve in place into f (initial guess on entry); returns
@@ -630,6 +658,17 @@ class RigidParticle:
                                      _dev_ptr(f, "f", m[0]), mo, float(tol), int(max_iter),
                                      ctypes.byref(it), ctypes.byref(rr)))
         return list(mo[:3]), list(mo[3:]), it.value, rr.value
+
+
+def undisturbed_traction(plan, kind, rate, x, nrm, out=None):
+    """sigma_inf . n of simple shear (FLOW_SHEAR) or Poiseuille flow
+    (FLOW_POISEUILLE) at the points x (ggem_undisturbed_traction)."""
+    import torch
+    out = torch.empty_like(x) if out is None else out
+    n = x.shape[0]
+    _check(_lib.ggem_undisturbed_traction(plan._h, int(kind), float(rate), n, _dev_ptr(x, "x"),
+                                          _dev_ptr(nrm, "nrm", n), _dev_ptr(out, "out", n)))
+    return out
 
 
 def poiseuille(plan, U0, x, out=None):

@@ -15,11 +15,13 @@ import oracle
 import oracle.bi
 import oracle.fredholm
 import oracle.ggem
+import oracle.probes
 import oracle.surface
 import test_oracle_bi as BI
 import test_oracle_invariants as INV
 import test_oracle_kernels as KER
 import test_oracle_physics as PHY
+import test_oracle_probes as PRB
 import test_oracle_spectral as SPE
 
 pytestmark = pytest.mark.slow
@@ -67,6 +69,15 @@ MUTATIONS = {
     "n(z) kept on the element at z (no n~)": ("bi",
         "m = phi[:, :1] * nD + (1.0 - phi[:, :1]) * nz",
         "m = np.broadcast_to(nz, (len(wts), 3))"),
+    "probe pressure without the gauge": ("probes",
+        "dft_xz(g, gp), pressure_gauge(g, xs, f))",
+        "dft_xz(g, gp), 0.0)"),
+    "probe sigma_xy with the z wavenumber": ("probes",
+        "dy(u) + ikx * v, ikz * u + ikx * w, ikz * v + dy(w))",
+        "dy(u) + ikz * v, ikz * u + ikx * w, ikz * v + dy(w))"),
+    "particle stress with lambda + 1": ("probes",
+        "S += (lam - 1.0) * (",
+        "S += (lam + 1.0) * ("),
     "torque row with r and f swapped": ("bi",
         "T = (A[:, None] * np.cross(r, f)).sum(axis=0)",
         "T = (A[:, None] * np.cross(f, r)).sum(axis=0)"),
@@ -91,7 +102,8 @@ def install(monkeypatch, mod):
     for name, val in vars(mod).items():
         if name.startswith("__") or not callable(val) and not isinstance(val, (int, float)):
             continue
-        for target in (oracle.ggem, oracle, oracle.fredholm, oracle.surface, oracle.bi):
+        for target in (oracle.ggem, oracle, oracle.fredholm, oracle.surface, oracle.bi,
+                       oracle.probes):
             if hasattr(target, name):
                 monkeypatch.setattr(target, name, val)
 
@@ -123,6 +135,10 @@ def bi_sphere():
     return oracle.SlitGrid(2.0, 2.0, 0.75, 8.0, 0.5, 32, 32, 33), V * 0.3 + xc, F, xc
 
 
+def probe_field():
+    return PRB.field.__wrapped__()
+
+
 def interpolation_of_polynomials():
     SPE.test_interpolation_reproduces_polynomials(np.random.default_rng(7))
 
@@ -144,6 +160,9 @@ CHECKS = [
     ("Fredholm operator on q = n", PHY.test_fredholm_uniform_normal_density),
     ("surface velocity of a uniform density", PHY.test_surface_velocity_uniform_density_translates_sphere),
     ("torque of a rotational traction", lambda: BI.test_torque_of_a_rotational_traction(bi_sphere())),
+    ("particle stress on a sphere", PRB.test_particle_stress_on_a_sphere),
+    ("probe pressure gauge", lambda: PRB.test_pressure_gauge_at_the_lower_wall(probe_field())),
+    ("probe momentum balance", lambda: PRB.test_momentum_balance_away_from_sources(probe_field())),
 ]
 
 
