@@ -150,7 +150,16 @@ void layout_plan(Plan& p, Carver& c) {
   carve_binned(c, p.wall, 2LL * q.Nx * q.Nz, p.cg, elt);
 }
 
+void free_over(Plan& p) {
+  if (p.over_block) (void)hipFree(p.over_block);
+  delete p.over;
+  p.over = nullptr;
+  p.over_block = p.over_spec = p.over_phys = nullptr;
+  p.interp_mode = GGEM_INTERP_LAGRANGE;
+}
+
 void free_plan(Plan& p) {
+  free_over(p);
   if (p.block && p.owns_block) (void)hipFree(p.block);
   p.block = nullptr;
   if (p.flags_host && p.owns_flags_host) (void)hipHostFree(p.flags_host);
@@ -201,6 +210,16 @@ template <typename T>
 __global__ void fill_zero(T* p, size_t n) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = (T)0;
+}
+
+// FFT twiddles exp(-2 pi i t/n) = cos(pi 2t/n) - i sin(pi 2t/n), t < n,
+// as interleaved (re, im) pairs
+void fill_twiddles(int n, double* tw) {
+  for (int t = 0; t < n; ++t) {
+    const long m = (2L * t) % (2L * n);
+    tw[2 * t] = cos(M_PI * (double)m / n);
+    tw[2 * t + 1] = -sin(M_PI * (double)m / n);
+  }
 }
 
 // Host arrays of the plan constants, carved from `hs` (a sizing pass with
@@ -264,12 +283,7 @@ int plan_constants(Plan& p, HostStage& hs) {
   HIP_TRY(hipMemcpy(p.ci32, ci32, (size_t)MP * KP * 4, hipMemcpyHostToDevice));
   for (int ax = 0; ax < 2; ++ax) {
     const int n = ax == 0 ? Nx : Nz;
-    for (int t = 0; t < n; ++t) {
-      // exp(-2 pi i t/n) = cos(pi 2t/n) - i sin(pi 2t/n)
-      const long m = (2L * t) % (2L * n);
-      tw[2 * t] = cos(M_PI * (double)m / n);
-      tw[2 * t + 1] = -sin(M_PI * (double)m / n);
-    }
+    fill_twiddles(n, tw);
     void* dst = ax == 0 ? p.twx : p.twz;
     if (p.fp64) {
       HIP_TRY(hipMemcpy(dst, tw, 2 * (size_t)n * 8, hipMemcpyHostToDevice));
@@ -374,6 +388,7 @@ int evaluate(Plan& p, long long ns, const double* xs, const double* f, long long
   }
   const bool glob = (parts & GGEM_PART_GLOBAL) != 0 && nt > 0;
   const bool local = (parts & GGEM_PART_LOCAL) != 0;
+  const bool spectral = glob && p.interp_mode == GGEM_INTERP_SPECTRAL;
   if (!local) {
     int rc = zero_ul<T>(p, (int)nt);
     if (rc) return rc;
@@ -455,19 +470,29 @@ int evaluate(Plan& p, long long ns, const double* xs, const double* f, long long
       HIP_TRY(launch_tau<T>(p, dl));
     }
     const int nf = dl ? 6 : 3;
-    {
-      StageScope s(p, GGEM_STAGE_CHEB_INV);
-      HIP_TRY(launch_cheb<T>(p, p.specA, p.specB, nf, false));
-    }
-    {
+    if (spectral) {
+      // the Chebyshev coefficients stay in y; in x and z they are deconvolved,
+      // padded and transformed onto the oversampled grid
       StageScope s(p, GGEM_STAGE_FFT_INV);
-      HIP_TRY(launch_fft_inverse<T>(p, p.specB, p.phys, nf * Ny));
+      HIP_TRY(launch_nufft_pad<T>(p, nf));
+      p.over->stream = p.stream;
+      HIP_TRY(launch_fft_inverse<T>(*p.over, p.over_spec, p.over_phys, nf * Ny));
+    } else {
+      {
+        StageScope s(p, GGEM_STAGE_CHEB_INV);
+        HIP_TRY(launch_cheb<T>(p, p.specA, p.specB, nf, false));
+      }
+      {
+        StageScope s(p, GGEM_STAGE_FFT_INV);
+        HIP_TRY(launch_fft_inverse<T>(p, p.specB, p.phys, nf * Ny));
+      }
     }
   }
   if (fork && !(glob && one_join)) HIP_TRY(hipStreamWaitEvent(p.stream, p.ev_near, 0));
   {
     StageScope s(p, GGEM_STAGE_INTERP);
-    HIP_TRY(launch_interp<T>(p, (int)nt, out, dl, glob));
+    if (spectral) HIP_TRY(launch_spectral_eval<T>(p, (int)nt, out, dl));
+    else HIP_TRY(launch_interp<T>(p, (int)nt, out, dl, glob));
   }
   return finish(p);
 }
@@ -772,6 +797,85 @@ extern "C" int ggem_plan_work(ggem_plan_t plan, unsigned long long* counts) {
 extern "C" int ggem_plan_count_work(ggem_plan_t plan, int on) {
   if (int rc = check_plan(plan)) return rc;
   plan->p.count_work = on != 0;
+  return GGEM_OK;
+}
+
+extern "C" int ggem_plan_set_interp(ggem_plan_t plan, int mode, int msp) {
+  if (int rc = check_plan(plan)) return rc;
+  Plan& p = plan->p;
+  if (mode != GGEM_INTERP_LAGRANGE && mode != GGEM_INTERP_SPECTRAL)
+    return fail(GGEM_E_ARG, "mode must be GGEM_INTERP_LAGRANGE or GGEM_INTERP_SPECTRAL");
+  if (!p.owns_block) return fail(GGEM_E_ARG, "plan without its own device memory");
+  const int Nx = p.p.Nx, Nz = p.p.Nz, Ny = p.p.Ny, Mx = 2 * Nx, Mz = 2 * Nz;
+  int rx[12], rz[12], nrx = 0, nrz = 0;
+  if (mode == GGEM_INTERP_SPECTRAL) {
+    if (msp < 2 || msp > kMaxMsp || msp > Nx || msp > Nz)
+      return fail(GGEM_E_ARG, "msp=%d must be in 2..%d and at most Nx and Nz", msp, kMaxMsp);
+    if (Mx > kMaxFFT || Mz > kMaxFFT || !factor_radices(Mx, rx, &nrx) ||
+        !factor_radices(Mz, rz, &nrz))
+      return fail(GGEM_E_ARG, "spectral evaluation needs Nx, Nz <= %d", kMaxFFT / 2);
+  }
+  // the previous mode's buffers may still be in use by queued work
+  HIP_TRY(hipStreamSynchronize(p.stream));
+  if (p.side) HIP_TRY(hipStreamSynchronize(p.side));
+  free_over(p);
+  if (mode == GGEM_INTERP_LAGRANGE) return GGEM_OK;
+  Plan* o = new (std::nothrow) Plan();
+  if (!o) return fail(GGEM_E_NOMEM, "host allocation failed");
+  memset(o, 0, sizeof(Plan));
+  o->p = p.p;
+  o->p.Nx = Mx;
+  o->p.Nz = Mz;
+  o->Nzh = Mz / 2 + 1;
+  o->nmodes = Mx * o->Nzh;
+  o->nradx = nrx;
+  o->nradz = nrz;
+  for (int i = 0; i < 12; ++i) {
+    o->radx[i] = i < nrx ? rx[i] : 1;
+    o->radz[i] = i < nrz ? rz[i] : 1;
+  }
+  o->fp64 = p.fp64;
+  o->device = p.device;
+  o->timed_stage = -1;
+  const size_t elt = p.fp64 ? 8 : 4;
+  Carver sz{nullptr, 0};
+  (void)sz.take_bytes(2 * (size_t)Mx * elt);
+  (void)sz.take_bytes(2 * (size_t)Mz * elt);
+  (void)sz.take_bytes(6 * (size_t)Ny * Mx * o->Nzh * 2 * elt);
+  (void)sz.take_bytes(6 * (size_t)Ny * Mx * Mz * elt);
+  if (hipMalloc(&p.over_block, sz.off) != hipSuccess) {
+    p.over_block = nullptr;
+    delete o;
+    return fail(GGEM_E_NOMEM, "device allocation of the oversampled grid failed");
+  }
+  p.over = o;
+  Carver c{(char*)p.over_block, 0};
+  o->twx = c.take_bytes(2 * (size_t)Mx * elt);
+  o->twz = c.take_bytes(2 * (size_t)Mz * elt);
+  p.over_spec = c.take_bytes(6 * (size_t)Ny * Mx * o->Nzh * 2 * elt);
+  p.over_phys = c.take_bytes(6 * (size_t)Ny * Mx * Mz * elt);
+  std::vector<double> tw(2 * (size_t)(Mx > Mz ? Mx : Mz));
+  std::vector<float> tf(tw.size());
+  for (int ax = 0; ax < 2; ++ax) {
+    const int n = ax == 0 ? Mx : Mz;
+    fill_twiddles(n, tw.data());
+    void* dst = ax == 0 ? o->twx : o->twz;
+    hipError_t e;
+    if (p.fp64) {
+      e = hipMemcpy(dst, tw.data(), 2 * (size_t)n * 8, hipMemcpyHostToDevice);
+    } else {
+      for (int i = 0; i < 2 * n; ++i) tf[i] = (float)tw[i];
+      e = hipMemcpy(dst, tf.data(), 2 * (size_t)n * 4, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+      free_over(p);
+      return fail(GGEM_E_DEVICE, "%s", hipGetErrorString(e));
+    }
+  }
+  p.msp = msp;
+  p.tau_x = M_PI * msp / (3.0 * (double)Nx * Nx);
+  p.tau_z = M_PI * msp / (3.0 * (double)Nz * Nz);
+  p.interp_mode = GGEM_INTERP_SPECTRAL;
   return GGEM_OK;
 }
 

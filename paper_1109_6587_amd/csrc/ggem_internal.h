@@ -21,6 +21,7 @@ constexpr int kMaxChunks = 512;      // counting-sort chunks per point set (at m
 constexpr int kNearBlock = 64;       // targets per near-field work item
 constexpr int kMaxNy = 129;
 constexpr int kMaxFFT = 512;
+constexpr int kMaxMsp = 16;   // NUFFT window half-width (spectral_eval holds 2 kMaxMsp weights)
 
 // Domain flags raised on the device.
 enum : unsigned { kFlagNonFinite = 1u, kFlagOutside = 2u };
@@ -126,6 +127,17 @@ struct Plan {
   int timed_calls;
   hipEvent_t* timed_ev;  // 2 * timed_max events
   bool count_work;    // kernels count their work units (pairs, updates)
+
+  // off-mesh evaluation of the global part: GGEM_INTERP_LAGRANGE (the
+  // 4th-order stencil on the grid) or GGEM_INTERP_SPECTRAL (the
+  // Fourier-Chebyshev series, its x-z sums by Gaussian-gridding NUFFT)
+  int interp_mode;
+  int msp;            // NUFFT window: msp oversampled nodes on each side
+  double tau_x, tau_z;  // Gaussian widths pi msp / (3 N^2) in x and z
+  Plan* over;         // FFT descriptor of the 2 Nx x 2 Nz oversampled grid
+  void* over_block;   // its device buffers (one allocation of their own):
+  void* over_spec;    //   padded spectra (6 x Ny x 2Nx x (Nz+1), complex T)
+  void* over_phys;    //   oversampled fields (6 x Ny x 2Nx x 2Nz, T)
 };
 
 // ---- 4th-order Lagrange interpolation (Sec. 3.2.2), shared by the
@@ -196,6 +208,10 @@ template <typename T>
 hipError_t launch_interp(Plan& p, int nt, double* out, bool stress, bool with_global);
 template <typename T>
 hipError_t launch_grid_to_f64(Plan& p, double* out);
+template <typename T>
+hipError_t launch_nufft_pad(Plan& p, int nf);
+template <typename T>
+hipError_t launch_spectral_eval(Plan& p, int nt, double* out, bool stress);
 
 }  // namespace ggem
 

@@ -13,6 +13,8 @@ import os
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libggem.so")
 
+INTERP_LAGRANGE = 0
+INTERP_SPECTRAL = 1
 FLOW_SHEAR = 0
 FLOW_POISEUILLE = 1
 
@@ -34,7 +36,8 @@ E_DEVICE = -5
 EXPORTS = (
     "ggem_plan_create", "ggem_plan_destroy", "ggem_plan_set_stream", "ggem_plan_status",
     "ggem_single_layer", "ggem_double_layer", "ggem_spread_grid", "ggem_plan_time_stage",
-    "ggem_plan_stage_time", "ggem_plan_work", "ggem_plan_count_work", "ggem_solver_create",
+    "ggem_plan_stage_time", "ggem_plan_work", "ggem_plan_count_work", "ggem_plan_set_interp",
+    "ggem_solver_create",
     "ggem_solver_destroy",
     "ggem_fredholm_apply", "ggem_fredholm_solve", "ggem_surface_geometry", "ggem_drop_rhs",
     "ggem_surface_velocity", "ggem_advance", "ggem_fredholm_solve_guided", "ggem_mlp_create",
@@ -99,6 +102,7 @@ def load_library(path: str = LIB_PATH):
                                          ctypes.POINTER(ctypes.c_int)]
     lib.ggem_plan_work.argtypes = [vp, ctypes.POINTER(ctypes.c_ulonglong)]
     lib.ggem_plan_count_work.argtypes = [vp, ip]
+    lib.ggem_plan_set_interp.argtypes = [vp, ip, ip]
     lib.ggem_solver_create.argtypes = [vp, ctypes.POINTER(SolverParams), ctypes.POINTER(vp)]
     lib.ggem_solver_destroy.argtypes = [vp]
     dd = ctypes.c_double
@@ -229,6 +233,12 @@ class Plan:
     def count_work(self, on=True):
         """Have the kernels count their work units in the following calls."""
         _check(_lib.ggem_plan_count_work(self._h, 1 if on else 0))
+
+    def set_interp(self, mode, msp=12):
+        """Off-mesh evaluation of the global part: INTERP_LAGRANGE (4th-order
+        stencil) or INTERP_SPECTRAL (the Fourier-Chebyshev series by NUFFT,
+        msp oversampled nodes on each side)."""
+        _check(_lib.ggem_plan_set_interp(self._h, int(mode), int(msp)))
 
     def work(self):
         """(local pairs, spread updates) counted by the kernels in the last call
