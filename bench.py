@@ -46,7 +46,7 @@ FLOP_NEAR_DL = 65.0
 FLOP_SPREAD = 12.0
 
 METRIC = "GGEM Mpoints/s (mixed vs FP64, rel err 1e-5); Fredholm solve s to 1e-6"
-EXTRAS = ("small", "capsules_sl", "batched", "fredholm", "rigid")
+EXTRAS = ("small", "capsules_sl", "batched", "fredholm", "rigid", "spectral")
 
 
 def log(msg):
@@ -587,6 +587,62 @@ def rigid_sphere():
             "by_L": by_L}
 
 
+def spectral_eval(args):
+    """The 50-capsule single layer with the global part evaluated off the mesh
+    by its Fourier-Chebyshev series (Gaussian-gridding NUFFT, msp = 6 mixed,
+    12 FP64) beside the 4th-order Lagrange stencil: ms per step, the event
+    times of the evaluation kernel (interp stage) and of the deconvolution +
+    oversampled inverse FFT (fft_inv stage), and the error of each against
+    the oracle's series at the stored sample of targets."""
+    import numpy as np
+    import torch
+
+    import paper_1109_6587_amd as G
+    from workloads import case_capsules_sl
+
+    c = case_capsules_sl(1)
+    dev = torch.device("cuda:0")
+    xs = torch.as_tensor(c.xs, dtype=torch.float64, device=dev)
+    f = torch.as_tensor(c.f, dtype=torch.float64, device=dev)
+    out = torch.empty((c.nt, 3), dtype=torch.float64, device=dev)
+    ref = golden(c)
+    want = sel = None
+    path = os.path.join(ROOT, "tests", "golden", f"{c.name}_spectral_sampled.json")
+    if ref is not None and os.path.exists(path):
+        with open(path) as fh:
+            spec = json.load(fh)
+        if spec["targets"] == ref["targets"]:
+            sel = np.asarray(ref["targets"])
+            want = np.asarray(ref["local"]) + np.asarray(spec["global_spectral"])
+    res = {"workload": c.name, "points": c.nt, "grid": [c.Nx, c.Nz, c.Ny],
+           "oversampled_grid": [2 * c.Nx, 2 * c.Nz, c.Ny]}
+    steps = max(5, args.steps // 2)
+    for precision, msp in (("mixed", 6), ("fp64", 12)):
+        plan = G.Plan.from_case(c, precision=precision, sync_checks=False)
+        call = lambda: plan.single_layer(xs, f, xs, out=out)  # noqa: E731
+        r = {"msp": msp}
+        for mode, name in ((G.INTERP_LAGRANGE, "lagrange"), (G.INTERP_SPECTRAL, "spectral")):
+            plan.set_interp(mode, msp)
+            call()
+            plan.status()
+            e = {}
+            if want is not None:
+                o = out.cpu().numpy()[sel]
+                e = {"rel_l2_vs_series": rel_l2(o, want), "rel_max_vs_series": rel_max(o, want)}
+            ms, interp_ms = time_steps(plan, call, steps, 2, stage="interp")
+            _, inv_ms = time_steps(plan, call, steps, 2, stage="fft_inv")
+            r[name] = {"ms_per_step": round(ms, 5), "interp_ms": round(interp_ms, 5),
+                       "fft_inv_ms": round(inv_ms, 5), **e}
+        # window sums: one read of each of the (2 msp)^2 window nodes per
+        # field and Chebyshev order, one FMA each
+        win = 3 * c.Ny * (2 * msp) ** 2 * c.nt
+        r["window_reads_per_target"] = 3 * c.Ny * (2 * msp) ** 2
+        r["window_fma_tflops"] = round(2 * win / (r["spectral"]["interp_ms"] * 1e-3) / 1e12, 3)
+        res[precision] = r
+        plan.close()
+    return res
+
+
 def base_line(args, value, ms, dtype, config):
     return {
         "metric": METRIC, "value": round(value, 3), "unit": "Mpoints/s", "n_gpus": 1,
@@ -704,6 +760,9 @@ def main():
         if "rigid" in extras:
             log("extra: rigid_sphere")
             line["rigid_sphere"] = rigid_sphere()
+        if "spectral" in extras:
+            log("extra: spectral evaluation")
+            line["spectral_eval"] = spectral_eval(args)
         if not args.no_cpu_baseline:
             log("cpu baseline (oracle)")
             line["cpu_baseline"] = cpu_baseline(c)

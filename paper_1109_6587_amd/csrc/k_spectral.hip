@@ -12,9 +12,10 @@
 //   3. at each target, (1/M) sum over the 2 msp nearest oversampled nodes S_j
 //      of h(S_j) g_tau(s - S_j), in x and z,
 // with tau = pi msp / (3 N^2), for which aliasing and window truncation
-// errors are both about exp(-0.75 pi msp) (msp = 12: 5e-13; 6: 7e-7).  Then
-// the Chebyshev sum in y (Clenshaw) gives the field, and the local part and
-// the double layer's normal are combined as in the Lagrange path.
+// errors are both about exp(-0.75 pi msp) (msp = 12: 5e-13; 6: 7e-7).  The
+// window sums of every Chebyshev order, weighted by T_n(y/H), give the field;
+// the local part and the double layer's normal are combined as in the
+// Lagrange path.
 #include "ggem_internal.h"
 
 namespace ggem {
@@ -67,6 +68,7 @@ __global__ void __launch_bounds__(256) nufft_pad(PadArgs a) {
 
 struct EvalArgs {
   int nt, Mx, Mz, Ny, msp;
+  int per;                        // 4-target tiles per XCD
   double Lx, Lz, H, tx, tz;
   const int* perm;
   const double *tx_, *ty, *tz_;   // sorted wrapped targets
@@ -77,56 +79,74 @@ struct EvalArgs {
   double* out;                    // (nt, 3) in input order
 };
 
-// one thread per target: Gaussian window sums per field and order, then the
-// Chebyshev sum in y by Clenshaw's recurrence, then the combination
-template <typename T, bool STRESS>
+// One wave per target.  The W x W window (W = 2 msp) is flattened over the
+// 64 lanes, E entries per lane (W^2 <= 64 E): consecutive lanes read
+// consecutive z nodes of a row, so each load of a plane is a few contiguous
+// runs.  Each lane keeps its entries' weights wx_i wz_k and offsets, sums
+// its part of the window sum of every plane, and accumulates those against
+// T_n(y/H) (the three-term recurrence); a wave reduction per field ends it.
+// Block b serves 4-target tile (b mod 8) per + b/8, so that each XCD walks
+// a contiguous run of the cell-sorted targets and their windows overlap in
+// its L2.
+template <typename T, bool STRESS, int E>
 __global__ void __launch_bounds__(256) spectral_eval(EvalArgs a) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= a.nt) return;
+  const int tile = (int)(blockIdx.x & 7) * a.per + (int)(blockIdx.x >> 3);
+  const int t = tile * 4 + (int)(threadIdx.x >> 6);
+  if (t >= a.nt) return;  // uniform over the wave
+  const int lane = threadIdx.x & 63;
   constexpr int NC = STRESS ? 6 : 3;
   constexpr double kTwoPi = 6.283185307179586477;
-  const double x = a.tx_[t], y = a.ty[t], z = a.tz_[t];
-  // window weights: the 2 msp oversampled nodes nearest to s in x and z
-  const double sx = kTwoPi * x / a.Lx, sz = kTwoPi * z / a.Lz;
+  const double sx = kTwoPi * a.tx_[t] / a.Lx, sz = kTwoPi * a.tz_[t] / a.Lz;
+  const double yy = a.ty[t] / a.H;
   const double hx = kTwoPi / a.Mx, hz = kTwoPi / a.Mz;
-  const int ix0 = (int)floor(sx / hx) - a.msp + 1, iz0 = (int)floor(sz / hz) - a.msp + 1;
-  double wx[2 * kMaxMsp], wz[2 * kMaxMsp];
-  int ixs[2 * kMaxMsp], izs[2 * kMaxMsp];
   const int W = 2 * a.msp;
-  for (int j = 0; j < W; ++j) {
-    const double ddx = sx - (ix0 + j) * hx, ddz = sz - (iz0 + j) * hz;
-    wx[j] = exp(-ddx * ddx / (4.0 * a.tx));
-    wz[j] = exp(-ddz * ddz / (4.0 * a.tz));
-    ixs[j] = ((ix0 + j) % a.Mx + a.Mx) % a.Mx;
-    izs[j] = ((iz0 + j) % a.Mz + a.Mz) % a.Mz;
+  // lane j < W: weight and node of the j-th window point in x and in z
+  double wxl = 0.0, wzl = 0.0;
+  int ixl = 0, izl = 0;
+  if (lane < W) {
+    const int ix = (int)floor(sx / hx) - a.msp + 1 + lane;
+    const int iz = (int)floor(sz / hz) - a.msp + 1 + lane;
+    const double dx = sx - ix * hx, dz = sz - iz * hz;
+    wxl = exp(-dx * dx / (4.0 * a.tx));
+    wzl = exp(-dz * dz / (4.0 * a.tz));
+    ixl = ix < 0 ? ix + a.Mx : (ix >= a.Mx ? ix - a.Mx : ix);
+    izl = iz < 0 ? iz + a.Mz : (iz >= a.Mz ? iz - a.Mz : iz);
+  }
+  double w[E];
+  int off[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int q = lane + 64 * e;
+    const int i = q / W, k = q - i * W;  // i < 64 for every bucket
+    const double wi = __shfl(wxl, i), wk = __shfl(wzl, k);
+    const int xi = __shfl(ixl, i), zk = __shfl(izl, k);
+    const bool act = q < W * W;
+    w[e] = act ? wi * wk : 0.0;
+    off[e] = act ? xi * a.Mz + zk : 0;
   }
   const T* G = (const T*)a.grid;
   const size_t plane = (size_t)a.Mx * a.Mz;
-  const double yy = y / a.H;
-  double val[NC];
-  for (int c = 0; c < NC; ++c) {
-    // Clenshaw: b_n = a_n + 2 yy b_{n+1} - b_{n+2} down to n = 1, then
-    // sum_n a_n T_n(yy) = a_0 + yy b_1 - b_2
-    double b1 = 0.0, b2 = 0.0, a0 = 0.0;
-    for (int n = a.Ny - 1; n >= 0; --n) {
+  double acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+  double tm1 = 0.0, tn = 1.0;  // T_{n-1}, T_n
+  for (int n = 0; n < a.Ny; ++n) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
       const T* g = G + ((size_t)c * a.Ny + n) * plane;
-      double an = 0.0;
-      for (int i = 0; i < W; ++i) {
-        const T* row = g + (size_t)ixs[i] * a.Mz;
-        double r = 0.0;
-        for (int k = 0; k < W; ++k) r = fma(wz[k], (double)row[izs[k]], r);
-        an = fma(wx[i], r, an);
-      }
-      if (n > 0) {
-        const double b0 = fma(2.0 * yy, b1, an - b2);
-        b2 = b1;
-        b1 = b0;
-      } else {
-        a0 = an;
-      }
+      double s = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) s = fma(w[e], (double)g[off[e]], s);
+      acc[c] = fma(tn, s, acc[c]);
     }
-    val[c] = a0 + yy * b1 - b2;
+    const double tp = n == 0 ? yy : 2.0 * yy * tn - tm1;
+    tm1 = tn;
+    tn = tp;
   }
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+    for (int m = 32; m >= 1; m >>= 1) acc[c] += __shfl_xor(acc[c], m);
+  if (lane != 0) return;
   const T* ul = (const T*)a.ul;
   double res[3];
   for (int c = 0; c < 3; ++c) {
@@ -135,18 +155,24 @@ __global__ void __launch_bounds__(256) spectral_eval(EvalArgs a) {
     res[c] = v;
   }
   if (!STRESS) {
-    for (int c = 0; c < 3; ++c) res[c] += val[c];
+    for (int c = 0; c < 3; ++c) res[c] += acc[c];
   } else {
-    const T* tn = (const T*)a.tn;
-    const double nx = tn[t], ny = tn[a.tcap + t], nz = tn[2 * a.tcap + t];
-    res[0] += val[0] * nx + val[3] * ny + val[4] * nz;
-    res[1] += val[3] * nx + val[1] * ny + val[5] * nz;
-    res[2] += val[4] * nx + val[5] * ny + val[2] * nz;
+    const T* tnr = (const T*)a.tn;
+    const double nx = tnr[t], ny = tnr[a.tcap + t], nz = tnr[2 * a.tcap + t];
+    res[0] += acc[0] * nx + acc[3] * ny + acc[4] * nz;
+    res[1] += acc[3] * nx + acc[1] * ny + acc[5] * nz;
+    res[2] += acc[4] * nx + acc[5] * ny + acc[2] * nz;
   }
   const size_t o = 3 * (size_t)a.perm[t];
   a.out[o] = res[0];
   a.out[o + 1] = res[1];
   a.out[o + 2] = res[2];
+}
+
+template <typename T, int E>
+void launch_eval_e(const EvalArgs& a, unsigned nb, bool stress, hipStream_t st) {
+  if (stress) spectral_eval<T, true, E><<<nb, 256, 0, st>>>(a);
+  else spectral_eval<T, false, E><<<nb, 256, 0, st>>>(a);
 }
 
 }  // namespace
@@ -181,6 +207,8 @@ hipError_t launch_spectral_eval(Plan& p, int nt, double* out, bool stress) {
   a.Mz = 2 * p.p.Nz;
   a.Ny = p.p.Ny;
   a.msp = p.msp;
+  const int tiles = (nt + 3) / 4;
+  a.per = (tiles + 7) / 8;
   a.Lx = p.p.Lx;
   a.Lz = p.p.Lz;
   a.H = p.p.H;
@@ -195,9 +223,14 @@ hipError_t launch_spectral_eval(Plan& p, int nt, double* out, bool stress) {
   a.ul = p.ul;
   a.grid = p.over_phys;
   a.out = out;
-  const unsigned nb = (unsigned)((nt + 255) / 256);
-  if (stress) spectral_eval<T, true><<<nb, 256, 0, p.stream>>>(a);
-  else spectral_eval<T, false><<<nb, 256, 0, p.stream>>>(a);
+  const unsigned nb = 8u * (unsigned)a.per;
+  // entries per lane: the smallest bucket with 64 E >= W^2
+  const int W2 = 4 * p.msp * p.msp;
+  if (W2 <= 64) launch_eval_e<T, 1>(a, nb, stress, p.stream);
+  else if (W2 <= 128) launch_eval_e<T, 2>(a, nb, stress, p.stream);
+  else if (W2 <= 256) launch_eval_e<T, 4>(a, nb, stress, p.stream);
+  else if (W2 <= 576) launch_eval_e<T, 9>(a, nb, stress, p.stream);
+  else launch_eval_e<T, 16>(a, nb, stress, p.stream);
   return hipGetLastError();
 }
 

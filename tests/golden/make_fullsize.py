@@ -9,10 +9,14 @@ generators.
 
     python tests/golden/make_fullsize.py sl      # ~2 minutes on 8 cores
     python tests/golden/make_fullsize.py dl 8    # wall data on 8 processes
+    python tests/golden/make_fullsize.py sl_spectral
 
 Each file records the workload, the sample indices and, per target, the
 local part, the global part and their sum (single layer: velocity, Eq. u_g a;
-double layer: traction n_k sigma_jk, Eq. wdbl).
+double layer: traction n_k sigma_jk, Eq. wdbl).  ``sl_spectral`` writes the
+single layer's global part at the same targets as the direct sum of its
+Fourier-Chebyshev series (oracle/spectral.py), the reference of the
+spectrally accurate off-mesh evaluation.
 """
 from __future__ import annotations
 
@@ -65,7 +69,34 @@ def parallel_wall_data(g, xs, f, workers):
     return -ul[:n].T.reshape(3, g.Nx, g.Nz), -ul[n:].T.reshape(3, g.Nx, g.Nz)
 
 
+def main_spectral():
+    import oracle.spectral as S
+    c = case_capsules_sl()
+    g = O.SlitGrid.from_case(c)
+    sel = sample(c.xt.shape[0])
+    t0 = time.time()
+    xs = g.wrap(c.xs)
+    coef = S.global_coefficients(g, xs, np.asarray(c.f, dtype=np.float64))
+    print(f"coefficients done {time.time() - t0:.0f} s", flush=True)
+    glo = S.evaluate(g, coef, g.wrap(c.xt[sel]))
+    out = {
+        "workload": c.name,
+        "seed": int(c.meta["seed"]),
+        "grid": [c.Nx, c.Nz, c.Ny],
+        "sample_seed": SAMPLE_SEED,
+        "targets": [int(i) for i in sel],
+        "global_spectral": glo.tolist(),
+        "oracle_seconds": round(time.time() - t0, 1),
+    }
+    path = os.path.join(HERE, f"{c.name}_spectral_sampled.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=0)
+    print("wrote", path)
+
+
 def main(which, workers=1):
+    if which == "sl_spectral":
+        return main_spectral()
     c = case_capsules_sl() if which == "sl" else case_capsules_dl()
     g = O.SlitGrid.from_case(c)
     sel = sample(c.xt.shape[0])

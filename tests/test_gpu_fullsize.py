@@ -50,8 +50,10 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def run(c, precision, parts=G.PART_ALL):
+def run(c, precision, parts=G.PART_ALL, msp=0):
     plan = G.Plan.from_case(c, precision=precision)
+    if msp:
+        plan.set_interp(G.INTERP_SPECTRAL, msp)
     xs, f = dev(c.xs), dev(c.f)
     if c.normals is None:
         out = plan.single_layer(xs, f, xs, parts=parts)
@@ -86,6 +88,27 @@ def test_capsules_sl_mixed(capsules_sl, precision):
     print(f"case {c.name} {precision}, {sel.size} sampled targets", flush=True)
     u = run(c, precision)[sel]
     assert rel_l2(u, np.asarray(ref["total"])) < TOLMIX
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("precision,msp", [("fp64", 12), ("mixed", 6)])
+def test_capsules_sl_spectral(capsules_sl, precision, msp):
+    """The spectrally accurate off-mesh evaluation against the oracle's
+    direct series at the sampled targets (its global part, plus the stored
+    local part)."""
+    c, ref = capsules_sl
+    spec = load(f"{c.name}_spectral")
+    assert spec["targets"] == ref["targets"] and spec["seed"] == c.meta["seed"]
+    sel = np.asarray(ref["targets"])
+    print(f"case {c.name} {precision} spectral msp={msp}", flush=True)
+    want = np.asarray(ref["local"]) + np.asarray(spec["global_spectral"])
+    u = run(c, precision, msp=msp)[sel]
+    if precision == "fp64":
+        assert rel_max(u, want) < TOL64
+        g = run(c, precision, G.PART_GLOBAL, msp=msp)[sel]
+        assert rel_max(g, np.asarray(spec["global_spectral"])) < TOL64
+    else:
+        assert rel_l2(u, want) < TOLMIX
 
 
 @pytest.fixture(scope="module")
