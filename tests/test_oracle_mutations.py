@@ -13,11 +13,13 @@ import pytest
 
 import oracle
 import oracle.bi
+import oracle.capsule
 import oracle.fredholm
 import oracle.ggem
 import oracle.probes
 import oracle.surface
 import test_oracle_bi as BI
+import test_oracle_capsule as CAP
 import test_oracle_invariants as INV
 import test_oracle_kernels as KER
 import test_oracle_physics as PHY
@@ -81,6 +83,18 @@ MUTATIONS = {
     "torque row with r and f swapped": ("bi",
         "T = (A[:, None] * np.cross(r, f)).sum(axis=0)",
         "T = (A[:, None] * np.cross(f, r)).sum(axis=0)"),
+    "principal-stretch derivative with swapped exponents": ("capsule",
+        "dW = G * (lam - 1.0 / (lam ** 3 * lam[::-1] ** 2))",
+        "dW = G * (lam - 1.0 / (lam ** 2 * lam[::-1] ** 3))"),
+    "traction jump over the reference node areas": ("capsule",
+        "return -F / node_areas(nodes, tri)[:, None], energy",
+        "return -F / node_areas(ref_nodes, tri)[:, None], energy"),
+    "membrane force left in the element's x direction": ("capsule",
+        "np.outer(f2[:, 0], t1) + np.outer(f2[:, 1], t2)",
+        "np.outer(f2[:, 0], t1) + np.outer(f2[:, 1], t1)"),
+    "volume correction of the wrong sign": ("capsule",
+        "out[sl] += (v0[c] - v[c]) / area[sl].sum() * normals[sl]",
+        "out[sl] += (v[c] - v0[c]) / area[sl].sum() * normals[sl]"),
     "index of the Lagrange stencil in y": ("ggem",
         "wy = _lagrange(xt[:, 1], g.y[jj])",
         "wy = _lagrange(xt[:, 1], g.y[jj[:, ::-1]])"),
@@ -103,7 +117,7 @@ def install(monkeypatch, mod):
         if name.startswith("__") or not callable(val) and not isinstance(val, (int, float)):
             continue
         for target in (oracle.ggem, oracle, oracle.fredholm, oracle.surface, oracle.bi,
-                       oracle.probes):
+                       oracle.probes, oracle.capsule):
             if hasattr(target, name):
                 monkeypatch.setattr(target, name, val)
 
@@ -163,6 +177,10 @@ CHECKS = [
     ("particle stress on a sphere", PRB.test_particle_stress_on_a_sphere),
     ("probe pressure gauge", lambda: PRB.test_pressure_gauge_at_the_lower_wall(probe_field())),
     ("probe momentum balance", lambda: PRB.test_momentum_balance_away_from_sources(probe_field())),
+    ("membrane forces are the energy gradient", CAP.test_forces_are_minus_the_energy_gradient),
+    ("uniformly inflated capsule", CAP.test_uniform_inflation_is_a_uniform_tension),
+    ("membrane rigid-motion invariance", CAP.test_rigid_motion_invariance),
+    ("volume correction", CAP.test_volume_correction),
 ]
 
 
