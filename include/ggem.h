@@ -484,6 +484,86 @@ int ggem_fredholm_solve_guided(ggem_solver_t solver, long long n_nodes, const do
                                const double* dq, double tol, int max_iter, int* iters,
                                double* rel_res, double* step);
 
+/* Right-hand side of Eq. qa for a given traction jump df (e.g. a capsule
+ * membrane's, ggem_membrane_traction) in the simple shear u_inf =
+ * (shear_rate y, 0, 0):  b = -(1/4pi) (df/(lambda + 1) + kappa f_inf),
+ * kappa = (lambda - 1)/(lambda + 1), f_inf = shear_rate (n_y, n_x, 0)
+ * (App. B).  With lambda = 1 the operator of Eq. qa is the identity and
+ * q = b.  normals, df, b: (n_nodes,3) float64 device arrays.  Errors:
+ * GGEM_E_ARG, GGEM_E_CAPACITY. */
+int ggem_traction_rhs(ggem_solver_t solver, long long n_nodes, const double* normals,
+                      const double* df, double lambda, double shear_rate, double* b);
+
+/* ---- neo-Hookean capsules (Sec. 4, Sec. 5, Sec. 7.1) ----------------------
+ *
+ * n_capsules capsules are consecutive, equal groups of nodes_per_capsule
+ * nodes and tri_per_capsule triangles (rows of tri, global node ids; every
+ * triangle names nodes of its own capsule; outward orientation).  The
+ * membrane is infinitely thin and neo-Hookean with two-dimensional shear
+ * modulus G: each flat element stores A0 W with
+ *   W = (G/2)(l1^2 + l2^2 + 1/(l1^2 l2^2) - 3)   (Eq. WNH),
+ * A0 its reference area and l1, l2 the principal stretches of its uniform
+ * deformation from the reference (stress-free) element.  All calls run on
+ * the solver's plan stream; arrays are device float64 unless stated. */
+typedef struct ggem_membrane_s* ggem_membrane_t;
+
+/* Reference state: tri (n_capsules * tri_per_capsule, 3) int32 (copied),
+ * ref_nodes (n_capsules * nodes_per_capsule, 3) the stress-free node
+ * positions (read here only).  The solver's capacities must cover the
+ * nodes and triangles.  Errors: GGEM_E_ARG (a triangle naming a node of
+ * another capsule, counts, G <= 0), GGEM_E_CAPACITY, GGEM_E_NOMEM. */
+int ggem_membrane_create(ggem_solver_t solver, long long n_capsules, int nodes_per_capsule,
+                         int tri_per_capsule, const int* tri, const double* ref_nodes,
+                         double shear_modulus, ggem_membrane_t* out);
+int ggem_membrane_destroy(ggem_membrane_t membrane);
+
+/* Traction jump at the nodes (Eq. cntr2): the reaction force of the
+ * membrane energy at a node, F_p = -dE/dx_p (the finite-element virtual work
+ * of Charrier, Shrivastava and Wu, summed over the node's elements), over the
+ * node's area A_p (one third of its elements' current areas):
+ * df_p = -F_p / A_p.  node_tri_off / node_tri: the node-triangle incidence
+ * lists of ggem_surface_geometry.  energy (host, may be NULL): the total
+ * membrane energy.  Waits for the stream (the incidence lists are checked on
+ * the device).  Errors: GGEM_E_ARG (null, inconsistent incidence lists). */
+int ggem_membrane_traction(ggem_membrane_t membrane, const double* nodes, const int* node_tri_off,
+                           const int* node_tri, double* df, double* energy);
+
+/* Volume of every capsule, (1/6) sum of x_a . (x_b x x_c) over its
+ * triangles (divergence theorem), into vol (n_capsules, device). */
+int ggem_capsule_volumes(ggem_membrane_t membrane, const double* nodes, double* vol);
+
+/* Volume correction (Sec. 5): every capsule whose volume V differs from
+ * v0 (n_capsules, device, e.g. its initial volume) by more than tol |v0| has
+ * each node moved along its normal by (v0 - V)/A, A the sum of its node
+ * areas (normals, area: ggem_surface_geometry of the same nodes).  The
+ * paper cites this correction without defining it; this uniform normal
+ * shift is exact to first order.  nodes is updated in place.  n_corrected
+ * (host, may be NULL; then no wait): the number of capsules moved. */
+int ggem_volume_correct(ggem_membrane_t membrane, double* nodes, const double* normals,
+                        const double* area, const double* v0, double tol, int* n_corrected);
+
+/* The minimum node separation of the time-step rule gamma_dot dt =
+ * 0.5 Ca h_s^m / a (Sec. 5): *min_edge (host) the shortest mesh edge, and
+ * *min_gap (host) the smallest node-to-node distance between two capsules
+ * (minimum image in x and z with periods Lx, Lz) when it is below reach,
+ * else +inf (pairs whose bounding spheres are farther apart than reach are
+ * not examined; h_s^m = min(min_edge, min_gap) with reach = min_edge).
+ * Waits for the stream.  Errors: GGEM_E_ARG, GGEM_E_CAPACITY (more than 64
+ * close pairs per capsule). */
+int ggem_capsule_separation(ggem_membrane_t membrane, const double* nodes, double Lx, double Lz,
+                            double reach, double* min_edge, double* min_gap);
+
+/* Overlap correction (Sec. 7.1): in each sweep, every capsule pair whose
+ * node-to-node gap is below h_min (in increasing (i, j) order) moves both
+ * capsules rigidly apart along their line of centres (minimum image), each
+ * by half the shortfall, and every capsule closer than h_min to a wall
+ * (y = +-H) moves away from it by the shortfall; the moves of a sweep are
+ * applied together.  Sweeps repeat until none is needed or max_sweeps.
+ * nodes is updated in place; *sweeps (host, may be NULL): sweeps that moved
+ * something.  Waits for the stream.  Errors as ggem_capsule_separation. */
+int ggem_overlap_correct(ggem_membrane_t membrane, double* nodes, double Lx, double Lz, double H,
+                         double h_min, int max_sweeps, int* sweeps);
+
 /* ---- learned warm start: a per-node network ------------------------------
  *
  * Not in the paper, whose warm start is the previous stage's density

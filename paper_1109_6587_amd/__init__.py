@@ -7,5 +7,5 @@ script and a ctypes binding with the same entry points.
 from .ggem import (  # noqa: F401
     FP64, MIXED, PART_ALL, PART_GLOBAL, PART_LOCAL, EXPORTS, GGEMError, Plan, load_library,
     FredholmSolver, Surface, MLP, MLP_PARAMS, Batch, single_layer_noalloc, RigidParticle,
-    poiseuille, undisturbed_traction, FLOW_SHEAR, FLOW_POISEUILLE, INTERP_LAGRANGE, INTERP_SPECTRAL,
+    poiseuille, undisturbed_traction, FLOW_SHEAR, FLOW_POISEUILLE, INTERP_LAGRANGE, INTERP_SPECTRAL, Membrane,
 )

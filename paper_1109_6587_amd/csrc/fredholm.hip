@@ -115,6 +115,12 @@ struct ggem_solver_s {
   const int* tri;
 };
 
+namespace ggem {
+hipStream_t solver_stream(ggem_solver_t s) { return s->plan->p.stream; }
+long long solver_max_nodes(ggem_solver_t s) { return s->max_nodes; }
+long long solver_max_tri(ggem_solver_t s) { return s->max_tri; }
+}  // namespace ggem
+
 static thread_local char g_solver_err[256];
 
 #define SOLVER_TRY(expr)                                                              \
@@ -375,6 +381,19 @@ __global__ void drop_rhs_kernel(int nnode, const double* __restrict__ nrm,
   }
 }
 
+// b = -(1/4pi) (dF/(lambda+1) + kappa f_inf) for a given traction jump dF
+__global__ void traction_rhs_kernel(int nnode, const double* __restrict__ nrm,
+                                    const double* __restrict__ df, double lam, double shear,
+                                    double* __restrict__ b) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nnode) return;
+  const double kappa = (lam - 1.0) / (lam + 1.0);
+  const double s = -1.0 / (4.0 * M_PI);
+  const double fi[3] = {shear * nrm[3 * (size_t)i + 1], shear * nrm[3 * (size_t)i], 0.0};
+  for (int d = 0; d < 3; ++d)
+    b[3 * (size_t)i + d] = s * (df[3 * (size_t)i + d] / (lam + 1.0) + kappa * fi[d]);
+}
+
 // u = (shear y, 0, 0) + 8 pi u_sl
 __global__ void velocity_finish(int nnode, const double* __restrict__ xn, double shear,
                                 double* __restrict__ u) {
@@ -433,6 +452,21 @@ extern "C" int ggem_drop_rhs(ggem_solver_t s, long long n_nodes, const double* n
   const int n = (int)n_nodes;
   drop_rhs_kernel<<<(n + 255) / 256, 256, 0, s->plan->p.stream>>>(n, normals, lap, lambda, inv_ca,
                                                                   shear_rate, b);
+  SOLVER_TRY(hipGetLastError());
+  return GGEM_OK;
+}
+
+extern "C" int ggem_traction_rhs(ggem_solver_t s, long long n_nodes, const double* normals,
+                                 const double* df, double lambda, double shear_rate, double* b) {
+  if (!s) return ggem_set_error(GGEM_E_ARG, "null solver");
+  if (n_nodes < 1 || n_nodes > s->max_nodes)
+    return ggem_set_error(GGEM_E_CAPACITY, "node count outside 1..capacity");
+  if (!normals || !df || !b) return ggem_set_error(GGEM_E_ARG, "null array");
+  if (!(lambda > 0) || !isfinite(lambda) || !isfinite(shear_rate))
+    return ggem_set_error(GGEM_E_ARG, "lambda must be positive, shear finite");
+  const int n = (int)n_nodes;
+  traction_rhs_kernel<<<(n + 255) / 256, 256, 0, s->plan->p.stream>>>(n, normals, df, lambda,
+                                                                      shear_rate, b);
   SOLVER_TRY(hipGetLastError());
   return GGEM_OK;
 }

@@ -208,6 +208,10 @@ template <typename T>
 hipError_t launch_interp(Plan& p, int nt, double* out, bool stress, bool with_global);
 template <typename T>
 hipError_t launch_grid_to_f64(Plan& p, double* out);
+// The Fredholm solver's stream (its plan's) and capacities.
+hipStream_t solver_stream(ggem_solver_t s);
+long long solver_max_nodes(ggem_solver_t s);
+long long solver_max_tri(ggem_solver_t s);
 template <typename T>
 hipError_t launch_nufft_pad(Plan& p, int nf);
 template <typename T>

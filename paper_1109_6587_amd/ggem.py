@@ -47,7 +47,10 @@ EXPORTS = (
     "ggem_batch_capture_single_layer", "ggem_batch_graph_launch", "ggem_batch_status",
     "ggem_batch_branch", "ggem_single_layer_noalloc", "ggem_rigid_create", "ggem_rigid_destroy",
     "ggem_bi_single_layer", "ggem_bi_double_layer", "ggem_rigid_solve", "ggem_poiseuille",
-    "ggem_probe", "ggem_undisturbed_traction", "ggem_particle_stress", "ggem_last_error",
+    "ggem_probe", "ggem_undisturbed_traction", "ggem_particle_stress", "ggem_traction_rhs",
+    "ggem_membrane_create", "ggem_membrane_destroy", "ggem_membrane_traction",
+    "ggem_capsule_volumes", "ggem_volume_correct", "ggem_capsule_separation",
+    "ggem_overlap_correct", "ggem_last_error",
 )
 
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 13, 128, 3, 35203
@@ -113,6 +116,15 @@ def load_library(path: str = LIB_PATH):
     lib.ggem_drop_rhs.argtypes = [vp, ll, dp, dp, dd, dd, dd, dp]
     lib.ggem_surface_velocity.argtypes = [vp, ll, dp, ll, dp, dp, dd, dp]
     lib.ggem_advance.argtypes = [vp, ll, dp, dp, dd, dp]
+    lib.ggem_traction_rhs.argtypes = [vp, ll, dp, dp, dd, dd, dp]
+    lib.ggem_membrane_create.argtypes = [vp, ll, ip, ip, dp, dp, dd, ctypes.POINTER(vp)]
+    lib.ggem_membrane_destroy.argtypes = [vp]
+    lib.ggem_membrane_traction.argtypes = [vp, dp, dp, dp, dp, ctypes.POINTER(dd)]
+    lib.ggem_capsule_volumes.argtypes = [vp, dp, dp]
+    lib.ggem_volume_correct.argtypes = [vp, dp, dp, dp, dp, dd, ctypes.POINTER(ip)]
+    lib.ggem_capsule_separation.argtypes = [vp, dp, dd, dd, dd, ctypes.POINTER(dd),
+                                            ctypes.POINTER(dd)]
+    lib.ggem_overlap_correct.argtypes = [vp, dp, dd, dd, dd, dd, ip, ctypes.POINTER(ip)]
     lib.ggem_rigid_create.argtypes = [vp, ll, ll, ip, ctypes.POINTER(vp)]
     lib.ggem_rigid_destroy.argtypes = [vp]
     lib.ggem_bi_single_layer.argtypes = [vp, ll, dp, ll, dp, dp, dp, dp, dp]
@@ -412,6 +424,16 @@ class FredholmSolver:
                                   float(lam), float(inv_ca), float(shear), _dev_ptr(out, "out", n)))
         return out
 
+    def traction_rhs(self, normals, df, lam, shear, out=None):
+        """b of Eq. qa for a given traction jump (ggem_traction_rhs)."""
+        import torch
+        n = normals.shape[0]
+        out = torch.empty_like(normals) if out is None else out
+        _check(_lib.ggem_traction_rhs(self._h, n, _dev_ptr(normals, "normals"),
+                                      _dev_ptr(df, "df", n), float(lam), float(shear),
+                                      _dev_ptr(out, "out", n)))
+        return out
+
     def velocity(self, nodes, tri, q, shear, out=None):
         import torch
         n = nodes.shape[0]
@@ -429,6 +451,87 @@ class FredholmSolver:
         _check(_lib.ggem_advance(self._h, 3 * n, _dev_ptr(x, "x"), _dev_ptr(u, "u", n), float(dt),
                                  _dev_ptr(out, "out", n)))
         return out
+
+
+class Membrane:
+    """Neo-Hookean membranes of equal capsules on a Fredholm solver's stream
+    (ggem_membrane_* in include/ggem.h)."""
+
+    def __init__(self, solver, n_capsules, tri, ref_nodes, shear_modulus):
+        n_tri, n_nodes = tri.shape[0], ref_nodes.shape[0]
+        _int_dev(tri, "tri", 2)
+        if n_tri % n_capsules or n_nodes % n_capsules:
+            raise ValueError("nodes and triangles must split into equal capsules")
+        self.solver = solver
+        self.ncap = int(n_capsules)
+        self.n_nodes = n_nodes
+        self._h = ctypes.c_void_p()
+        _check(_lib.ggem_membrane_create(solver._h, self.ncap, n_nodes // self.ncap,
+                                         n_tri // self.ncap, tri.data_ptr(),
+                                         _dev_ptr(ref_nodes, "ref_nodes"), float(shear_modulus),
+                                         ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            _check(_lib.ggem_membrane_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            if self._h and _lib is not None:
+                _lib.ggem_membrane_destroy(self._h)
+        except Exception:
+            pass
+
+    def traction(self, nodes, node_tri_off, node_tri, out=None, energy=False):
+        """Traction jump (n, 3); with energy=True also the total energy."""
+        import torch
+        out = torch.empty_like(nodes) if out is None else out
+        _int_dev(node_tri_off, "node_tri_off", 1, self.n_nodes + 1)
+        _int_dev(node_tri, "node_tri", 1)
+        e = ctypes.c_double()
+        _check(_lib.ggem_membrane_traction(self._h, _dev_ptr(nodes, "nodes", self.n_nodes),
+                                           node_tri_off.data_ptr(), node_tri.data_ptr(),
+                                           _dev_ptr(out, "out", self.n_nodes),
+                                           ctypes.byref(e) if energy else None))
+        return (out, e.value) if energy else out
+
+    def volumes(self, nodes, out=None):
+        import torch
+        out = torch.empty((self.ncap,), dtype=torch.float64, device=nodes.device) if out is None else out
+        _check(_lib.ggem_capsule_volumes(self._h, _dev_ptr(nodes, "nodes", self.n_nodes),
+                                         out.data_ptr()))
+        return out
+
+    def volume_correct(self, nodes, normals, area, v0, tol=1e-4):
+        """Correct in place; returns the number of capsules moved."""
+        import torch
+        for t, name, n in ((area, "area", self.n_nodes), (v0, "v0", self.ncap)):
+            if (not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64
+                    or t.shape != (n,) or not t.is_contiguous()):
+                raise TypeError(f"{name} must be a contiguous ({n},) float64 device tensor")
+        k = ctypes.c_int()
+        _check(_lib.ggem_volume_correct(self._h, _dev_ptr(nodes, "nodes", self.n_nodes),
+                                        _dev_ptr(normals, "normals", self.n_nodes),
+                                        area.data_ptr(), v0.data_ptr(), float(tol),
+                                        ctypes.byref(k)))
+        return k.value
+
+    def separation(self, nodes, Lx, Lz, reach):
+        """(shortest edge, smallest gap between capsules below reach or inf)."""
+        a, b = ctypes.c_double(), ctypes.c_double()
+        _check(_lib.ggem_capsule_separation(self._h, _dev_ptr(nodes, "nodes", self.n_nodes),
+                                            float(Lx), float(Lz), float(reach), ctypes.byref(a),
+                                            ctypes.byref(b)))
+        return a.value, b.value
+
+    def overlap_correct(self, nodes, Lx, Lz, H, h_min, max_sweeps=100):
+        """Correct in place; returns the number of sweeps that moved something."""
+        k = ctypes.c_int()
+        _check(_lib.ggem_overlap_correct(self._h, _dev_ptr(nodes, "nodes", self.n_nodes),
+                                         float(Lx), float(Lz), float(H), float(h_min),
+                                         int(max_sweeps), ctypes.byref(k)))
+        return k.value
 
 
 def _int_dev(t, name, dim, n=None):

@@ -17,4 +17,6 @@ from .inputs import (  # noqa: F401
     case_shear_drops,
     RigidSphereCase,
     case_rigid_sphere,
+    CapsuleCase,
+    case_capsule_suspension,
 )

@@ -433,3 +433,58 @@ def case_rigid_sphere(L: float = 5.0, level: int = 4) -> RigidSphereCase:
     center = np.array([L / 2, 0.0, L / 2])
     return RigidSphereCase(f"rigid_sphere_L{L:g}", L, L, H, 4.0 / rc, rc, N, N, 61,
                            V * a + center, F.astype(np.int32), center, 1.0, a)
+
+
+@dataclass
+class CapsuleCase:
+    """Neo-Hookean capsules in simple shear between the walls."""
+    name: str
+    Lx: float
+    Lz: float
+    H: float
+    alpha: float
+    rc: float
+    Nx: int
+    Nz: int
+    Ny: int
+    nodes: np.ndarray        # (ncap * nv, 3) initial (pre-inflated) positions
+    ref_nodes: np.ndarray    # (ncap * nv, 3) stress-free positions
+    tri: np.ndarray          # (ncap * nf, 3) int32, outward orientation
+    ncap: int
+    nv: int
+    a: float                 # radius after pre-inflation
+    lam: float               # viscosity ratio
+    ca: float                # capillary number mu shear a / G
+    G: float                 # membrane shear modulus
+    shear: float
+    h_min: float             # minimum gap between surfaces (and to the walls)
+    meta: dict
+
+
+def case_capsule_suspension(ncap: int = 120, lam: float = 1.0, seed: int = 5, level: int = 2,
+                            phi: float = 0.15, ca: float = 0.5) -> CapsuleCase:
+    """Capsules of the suspension runs of Sec. 7.1: ncap spheres of 320
+    triangles (level-2 icosphere, 162 nodes), pre-inflated by 5 % to radius
+    a = 1, volume fraction phi in a cubic slit (Lx = Lz = 2H), simple shear
+    of rate 1 at Ca = 0.5 (G = 2), r_c = a = 4/alpha, mean mesh spacing
+    0.5/alpha in every direction (Nx = Nz the smallest even 2^a 3^b 5^c
+    >= L/0.125, Ny - 1 = ceil(2H/0.125)), minimum gap 0.05 a.
+
+    Draw order: the centres by random sequential addition (``_place_spheres``
+    with centre distance >= 2.1 a and |y_c| <= H - 1.1 a), nothing else."""
+    a, G, shear = 1.0, 1.0 / ca, 1.0
+    L = (ncap * 4.0 * math.pi / 3.0 / phi) ** (1.0 / 3.0)
+    H = 0.5 * L
+    alpha = 4.0
+    dx = 0.5 / alpha
+    N = smooth_nodes(L, dx)
+    Ny = int(math.ceil(2 * H / dx - 1e-12)) + 1
+    rng = np.random.default_rng(seed)
+    cen = _place_spheres(rng, ncap, L, H - 1.1 * a, 2.1 * a)
+    V, F = icosphere(level)
+    nodes = (cen[:, None, :] + a * V[None]).reshape(-1, 3)
+    ref = (cen[:, None, :] + (a / 1.05) * V[None]).reshape(-1, 3)
+    tri = (F[None] + (np.arange(ncap) * V.shape[0])[:, None, None]).reshape(-1, 3)
+    return CapsuleCase(f"capsules_nh_{ncap}x{V.shape[0]}_lam{lam:g}", L, L, H, alpha, 1.0, N, N, Ny,
+                       nodes, ref, tri.astype(np.int32), ncap, V.shape[0], a, float(lam), ca, G,
+                       shear, 0.05 * a, dict(seed=seed, level=level, phi=phi))
