@@ -46,7 +46,7 @@ FLOP_NEAR_DL = 65.0
 FLOP_SPREAD = 12.0
 
 METRIC = "GGEM Mpoints/s (mixed vs FP64, rel err 1e-5); Fredholm solve s to 1e-6"
-EXTRAS = ("small", "capsules_sl", "batched", "fredholm", "rigid", "spectral")
+EXTRAS = ("small", "capsules_sl", "batched", "fredholm", "rigid", "spectral", "capsules")
 
 
 def log(msg):
@@ -643,6 +643,48 @@ def spectral_eval(args):
     return res
 
 
+def capsule_stages(steps=4):
+    """The timing study of the capsule suspensions (Sec. 7.2, Fig. tscale):
+    wall-clock ms per stage of the midpoint rule for 15, 30, 60 and 120
+    neo-Hookean capsules of 320 triangles at volume fraction 0.15 and
+    lambda = 1, 2, 5 (mixed precision, GMRES to the paper's relative
+    residual 1e-4, warm started from the previous stage), after one warm-up
+    step; with the GMRES products per solve, the adaptive time step, the
+    volume corrections and the largest volume drift before correction."""
+    import torch
+
+    from paper_1109_6587_amd.capsules import CapsuleSuspension
+    from workloads import case_capsule_suspension
+
+    rows = []
+    for lam in (1.0, 2.0, 5.0):
+        for n in (15, 30, 60, 120):
+            c = case_capsule_suspension(n, lam)
+            sim = CapsuleSuspension(c, precision="mixed", tol=1e-4)
+            sim.step()
+            first = len(sim.stages)
+            for _ in range(steps):
+                sim.step()
+            st = sim.stages[first:]
+            solves = [r.iters for r in st]
+            v = sim.membrane.volumes(sim.x)
+            drift = float(torch.max(torch.abs(v / sim.v0 - 1.0)))
+            row = {"capsules": n, "lambda": lam, "grid": [c.Nx, c.Nz, c.Ny],
+                   "nodes": int(c.nodes.shape[0]), "triangles": int(c.tri.shape[0]),
+                   "ms_per_stage": round(1e3 * statistics.median(r.seconds for r in st), 3),
+                   "gmres_products_per_solve": round(statistics.mean(solves), 2),
+                   "dt": round(sim.steps[-1].dt, 5),
+                   "volume_corrections": sum(r.volume_corrections for r in sim.steps),
+                   "overlap_sweeps": sum(r.overlap_sweeps for r in sim.steps),
+                   "volume_drift_max": drift}
+            log(f"capsules {n} lambda {lam:g}: {row['ms_per_stage']} ms/stage, "
+                f"{row['gmres_products_per_solve']} products")
+            rows.append(row)
+            sim.close()
+    return {"workload": "capsule_suspensions_320", "steps_timed": steps, "gmres_tol": 1e-4,
+            "rows": rows}
+
+
 def base_line(args, value, ms, dtype, config):
     return {
         "metric": METRIC, "value": round(value, 3), "unit": "Mpoints/s", "n_gpus": 1,
@@ -763,6 +805,9 @@ def main():
         if "spectral" in extras:
             log("extra: spectral evaluation")
             line["spectral_eval"] = spectral_eval(args)
+        if "capsules" in extras:
+            log("extra: capsule suspensions")
+            line["capsule_stages"] = capsule_stages()
         if not args.no_cpu_baseline:
             log("cpu baseline (oracle)")
             line["cpu_baseline"] = cpu_baseline(c)

@@ -357,6 +357,30 @@ int ggem_bi_double_layer(ggem_rigid_t rigid, long long n_nodes, const double* no
                          long long n_tri, const int* tri, const int* inc_off, const int* inc_tri,
                          const double* normals, const double* q, double* v);
 
+/* Velocity of Eq. bi_ua at the nodes on this discretisation (the procedure
+ * the paper uses for the node velocities, Sec. 5):
+ *   u = u_inf + 8 pi w(q),  u_inf = (shear_rate y, 0, 0),
+ * w the discretised single layer above of the density q.  q, u: (n_nodes,3)
+ * float64 device arrays.  Errors as ggem_bi_single_layer. */
+int ggem_bi_surface_velocity(ggem_rigid_t rigid, long long n_nodes, const double* nodes,
+                             long long n_tri, const int* tri, const int* inc_off,
+                             const int* inc_tri, const double* q, double shear_rate, double* u);
+
+/* GMRES for Eq. qa on this discretisation: q + 2 kappa v(q) = b, v the
+ * discretised double layer above with the node normals (kappa =
+ * (lambda-1)/(lambda+1); with the 1/8pi of v, 2 kappa v = (kappa/4pi) D q).
+ * q: the initial guess on entry, the solution on return; b unchanged.
+ * GMRES(restart of ggem_rigid_create) as ggem_fredholm_solve: *iters Krylov
+ * products, *rel_res the true relative residual (non-convergence is not an
+ * error).  The basis must hold 3 n_nodes (the rigid solver's capacity).
+ * Errors as ggem_bi_double_layer, plus GGEM_E_ARG for tol <= 0,
+ * max_iter < 1 or a non-finite kappa. */
+int ggem_bi_fredholm_solve(ggem_rigid_t rigid, long long n_nodes, const double* nodes,
+                           long long n_tri, const int* tri, const int* inc_off,
+                           const int* inc_tri, const double* normals, double kappa,
+                           const double* b, double* q, double tol, int max_iter, int* iters,
+                           double* rel_res);
+
 /* Force- and torque-free rigid particle in the undisturbed flow u_inf
  * (Sec. 6.1, Eq. sl_r): unknowns the nodal tractions f, the translational
  * velocity U and the angular velocity Omega about center (host, 3);

@@ -8,8 +8,14 @@ Each stage of the explicit midpoint rule:
   3. the right-hand side b of Eq. qa (ggem_traction_rhs);
   4. q = b when the viscosities match (lambda = 1: the operator of Eq. qa is
      the identity), else GMRES to the relative residual `tol`, warm started
-     from the previous stage's density (ggem_fredholm_solve);
-  5. the node velocity of Eq. bi_ua (ggem_surface_velocity).
+     from the previous stage's density;
+  5. the node velocity of Eq. bi_ua.
+With discretisation="bi" (the default) steps 4 and 5 use the paper's own
+boundary-integral discretisation, element quadrature of the local part and
+nodal trapezoid strengths for the global part (ggem_bi_fredholm_solve,
+ggem_bi_surface_velocity); with "gauss" they use the three interior Gauss
+points per triangle as point sources (ggem_fredholm_solve,
+ggem_surface_velocity), the discretisation of the drop workload.
 The step dt follows gamma_dot dt = 0.5 Ca h_s^m / a with h_s^m the minimum
 node separation (ggem_capsule_separation).  After each step the volume of a
 capsule that drifted by more than 1e-4 is corrected (ggem_volume_correct)
@@ -48,10 +54,13 @@ class StepRecord:
 
 class CapsuleSuspension:
     def __init__(self, case, precision="mixed", restart=20, tol=1e-6, max_iter=300,
-                 vol_tol=1e-4, device="cuda:0"):
+                 vol_tol=1e-4, discretisation="bi", device="cuda:0"):
         import torch
 
+        if discretisation not in ("bi", "gauss"):
+            raise ValueError("discretisation must be 'bi' or 'gauss'")
         self.c = case
+        self.bi = discretisation == "bi"
         self.dev = torch.device(device)
         self.tol = tol
         self.max_iter = max_iter
@@ -69,6 +78,7 @@ class CapsuleSuspension:
         self.adj = t(adj, torch.int32)
         self.x = t(case.nodes)
         self.membrane = B.Membrane(self.solver, case.ncap, self.tri, t(case.ref_nodes), case.G)
+        self.rigid = B.RigidParticle(self.plan, n, m, restart=restart) if self.bi else None
         self.v0 = self.membrane.volumes(self.x).clone()
         self.q = torch.zeros_like(self.x)
         self.kappa = (case.lam - 1.0) / (case.lam + 1.0)
@@ -99,16 +109,24 @@ class CapsuleSuspension:
         nrm, _, _ = self.solver.geometry(x, self.tri, self.off, self.adj)
         df = self.membrane.traction(x, self.off, self.adj)
         b = self.solver.traction_rhs(nrm, df, c.lam, c.shear)
+        mesh = (x, self.tri, self.off, self.adj)
         if c.lam == 1.0:
             q, it, rr = b, 0, 0.0
         else:
             q = q0.clone()
-            it, rr = self.solver.solve(B.Surface(x, nrm, self.tri, self.kappa), b, q,
-                                       tol=self.tol, max_iter=self.max_iter)
+            if self.bi:
+                it, rr = self.rigid.fredholm_solve(*mesh, nrm, self.kappa, b, q, tol=self.tol,
+                                                   max_iter=self.max_iter)
+            else:
+                it, rr = self.solver.solve(B.Surface(x, nrm, self.tri, self.kappa), b, q,
+                                           tol=self.tol, max_iter=self.max_iter)
             if rr > self.tol:
                 raise RuntimeError(f"GMRES stalled at step {self.step_index} stage {stage}: "
                                    f"relative residual {rr:.3e} after {it} products")
-        u = self.solver.velocity(x, self.tri, q, c.shear)
+        if self.bi:
+            u = self.rigid.surface_velocity(*mesh, q, c.shear)
+        else:
+            u = self.solver.velocity(x, self.tri, q, c.shear)
         torch.cuda.synchronize(self.dev)
         self.stages.append(StageRecord(self.step_index, stage, it, rr, time.perf_counter() - t0))
         return u, q
@@ -136,6 +154,8 @@ class CapsuleSuspension:
         return dt
 
     def close(self):
+        if self.rigid is not None:
+            self.rigid.close()
         self.membrane.close()
         self.solver.close()
         self.plan.close()

@@ -428,6 +428,28 @@ __global__ void fill_int(int* p, int v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
+// y = x + k2 (wl + wg): the operator of Eq. qa, k2 = 2 kappa with the 1/8pi
+// of the discretised double layer
+__global__ void bi_fredholm_combine(int n3, const double* __restrict__ x,
+                                    const double* __restrict__ wl, const double* __restrict__ wg,
+                                    double k2, double* __restrict__ y) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n3) y[j] = fma(k2, wl[j] + wg[j], x[j]);
+}
+
+// u = (shear y, 0, 0) + 8 pi (wl + wg)
+__global__ void bi_velocity_finish(int n, const double* __restrict__ x,
+                                   const double* __restrict__ wl, const double* __restrict__ wg,
+                                   double shear, double* __restrict__ u) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double e = 8.0 * M_PI;
+  const size_t j = 3 * (size_t)i;
+  u[j] = fma(e, wl[j] + wg[j], shear * x[j + 1]);
+  u[j + 1] = e * (wl[j + 1] + wg[j + 1]);
+  u[j + 2] = e * (wl[j + 2] + wg[j + 2]);
+}
+
 }  // namespace
 
 struct ggem_rigid_s {
@@ -589,6 +611,45 @@ extern "C" int ggem_bi_double_layer(ggem_rigid_t r, long long n_nodes, const dou
   if (!normals || !q || !v) return ggem_set_error(GGEM_E_ARG, "null vector");
   if (int rc = set_surface(r, n_nodes, nodes, n_tri, tri, inc_off, inc_tri)) return rc;
   return layer(r, q, normals, v);
+}
+
+extern "C" int ggem_bi_surface_velocity(ggem_rigid_t r, long long n_nodes, const double* nodes,
+                                        long long n_tri, const int* tri, const int* inc_off,
+                                        const int* inc_tri, const double* q, double shear_rate,
+                                        double* u) {
+  if (!r) return ggem_set_error(GGEM_E_ARG, "null rigid solver");
+  if (!q || !u) return ggem_set_error(GGEM_E_ARG, "null vector");
+  if (!isfinite(shear_rate)) return ggem_set_error(GGEM_E_ARG, "shear rate must be finite");
+  if (int rc = set_surface(r, n_nodes, nodes, n_tri, tri, inc_off, inc_tri)) return rc;
+  if (int rc = layer(r, q, nullptr, nullptr)) return rc;
+  bi_velocity_finish<<<(r->n + 255) / 256, 256, 0, r->plan->p.stream>>>(r->n, r->x, r->wl, r->wg,
+                                                                      shear_rate, u);
+  RIGID_TRY(hipGetLastError());
+  return GGEM_OK;
+}
+
+extern "C" int ggem_bi_fredholm_solve(ggem_rigid_t r, long long n_nodes, const double* nodes,
+                                      long long n_tri, const int* tri, const int* inc_off,
+                                      const int* inc_tri, const double* normals, double kappa,
+                                      const double* b, double* q, double tol, int max_iter,
+                                      int* iters, double* rel_res) {
+  if (!r) return ggem_set_error(GGEM_E_ARG, "null rigid solver");
+  if (!normals || !b || !q) return ggem_set_error(GGEM_E_ARG, "null vector");
+  if (!(tol > 0) || max_iter < 1 || !isfinite(kappa))
+    return ggem_set_error(GGEM_E_ARG, "bad tolerance, max_iter or kappa");
+  if (int rc = set_surface(r, n_nodes, nodes, n_tri, tri, inc_off, inc_tri)) return rc;
+  hipStream_t st = r->plan->p.stream;
+  const int n3 = 3 * r->n;
+  gm::Work& W = r->W;
+  W.st = st;
+  auto op = [r, normals, kappa, n3, st](const double* x, double* y) {
+    if (int rc = layer(r, x, normals, nullptr)) return rc;
+    bi_fredholm_combine<<<(n3 + 255) / 256, 256, 0, st>>>(n3, x, r->wl, r->wg, 2.0 * kappa, y);
+    RIGID_TRY(hipGetLastError());
+    return (int)GGEM_OK;
+  };
+  auto none = [](double*) { return (int)GGEM_OK; };
+  return gm::solve(W, n3, b, q, tol, max_iter, op, none, iters, rel_res);
 }
 
 // y = A x for x = (f, U, Omega)

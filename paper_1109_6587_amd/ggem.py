@@ -50,7 +50,8 @@ EXPORTS = (
     "ggem_probe", "ggem_undisturbed_traction", "ggem_particle_stress", "ggem_traction_rhs",
     "ggem_membrane_create", "ggem_membrane_destroy", "ggem_membrane_traction",
     "ggem_capsule_volumes", "ggem_volume_correct", "ggem_capsule_separation",
-    "ggem_overlap_correct", "ggem_last_error",
+    "ggem_overlap_correct", "ggem_bi_surface_velocity", "ggem_bi_fredholm_solve",
+    "ggem_last_error",
 )
 
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 13, 128, 3, 35203
@@ -117,6 +118,9 @@ def load_library(path: str = LIB_PATH):
     lib.ggem_surface_velocity.argtypes = [vp, ll, dp, ll, dp, dp, dd, dp]
     lib.ggem_advance.argtypes = [vp, ll, dp, dp, dd, dp]
     lib.ggem_traction_rhs.argtypes = [vp, ll, dp, dp, dd, dd, dp]
+    lib.ggem_bi_surface_velocity.argtypes = [vp, ll, dp, ll, dp, dp, dp, dp, dd, dp]
+    lib.ggem_bi_fredholm_solve.argtypes = [vp, ll, dp, ll, dp, dp, dp, dp, dd, dp, dp, dd, ip,
+                                           ctypes.POINTER(ip), ctypes.POINTER(dd)]
     lib.ggem_membrane_create.argtypes = [vp, ll, ip, ip, dp, dp, dd, ctypes.POINTER(vp)]
     lib.ggem_membrane_destroy.argtypes = [vp]
     lib.ggem_membrane_traction.argtypes = [vp, dp, dp, dp, dp, ctypes.POINTER(dd)]
@@ -748,6 +752,28 @@ class RigidParticle:
         _check(_lib.ggem_bi_double_layer(self._h, *m, _dev_ptr(normals, "normals", m[0]),
                                          _dev_ptr(q, "q", m[0]), _dev_ptr(out, "out", m[0])))
         return out
+
+    def surface_velocity(self, nodes, tri, inc_off, inc_tri, q, shear, out=None):
+        """u = (shear y, 0, 0) + 8 pi w(q) at the nodes (ggem_bi_surface_velocity)."""
+        import torch
+        m = self._mesh(nodes, tri, inc_off, inc_tri)
+        out = torch.empty_like(nodes) if out is None else out
+        _check(_lib.ggem_bi_surface_velocity(self._h, *m, _dev_ptr(q, "q", m[0]), float(shear),
+                                             _dev_ptr(out, "out", m[0])))
+        return out
+
+    def fredholm_solve(self, nodes, tri, inc_off, inc_tri, normals, kappa, b, q, tol=1e-6,
+                       max_iter=200):
+        """q + 2 kappa v(q) = b in place into q (guess on entry); returns
+        (iters, rel_res) (ggem_bi_fredholm_solve)."""
+        m = self._mesh(nodes, tri, inc_off, inc_tri)
+        it = ctypes.c_int()
+        rr = ctypes.c_double()
+        _check(_lib.ggem_bi_fredholm_solve(self._h, *m, _dev_ptr(normals, "normals", m[0]),
+                                           float(kappa), _dev_ptr(b, "b", m[0]),
+                                           _dev_ptr(q, "q", m[0]), float(tol), int(max_iter),
+                                           ctypes.byref(it), ctypes.byref(rr)))
+        return it.value, rr.value
 
     def particle_stress(self, nodes, tri, inc_off, inc_tri, normals, df, u, lam, volume):
         """Sigma^p (3 x 3 nested list) of Sec. 7.1 (ggem_particle_stress)."""

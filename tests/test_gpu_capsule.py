@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+import oracle.bi as BI
 import oracle.capsule as C
 from oracle.surface import node_normals, surface_velocity
 from workloads.inputs import CapsuleCase, icosphere
@@ -149,26 +150,37 @@ def small_case(lam):
                        lam, 0.5, 2.0, 1.0, 0.025, {})
 
 
-def oracle_stage(c, g, x):
+def oracle_velocity(c, g, x, q, disc):
+    """u of Eq. bi_ua: the paper's element discretisation (u_inf + 8 pi times
+    the discretised single layer) or the Gauss-point one."""
+    if disc == "gauss":
+        return surface_velocity(g, x, c.tri, q, c.shear)
+    u = 8.0 * np.pi * BI.sl_bi(g, x, c.tri, q)
+    u[:, 0] += c.shear * x[:, 1]
+    return u
+
+
+def oracle_stage(c, g, x, disc):
     nrm = node_normals(x, c.tri)
     df, _ = C.membrane_traction(c.ref_nodes, x, c.tri, c.G)
     b = C.traction_rhs(nrm, df, c.lam, c.shear)
-    return surface_velocity(g, x, c.tri, b, c.shear)
+    return oracle_velocity(c, g, x, b, disc)
 
 
-def test_capsule_step_matches_the_oracle():
+@pytest.mark.parametrize("disc", ["bi", "gauss"])
+def test_capsule_step_matches_the_oracle(disc):
     """One midpoint step of the matched-viscosity suspension (q = b), FP64,
     with the oracle's dt rule, against the oracle's step."""
     c = small_case(1.0)
-    sim = CapsuleSuspension(c, precision="fp64")
+    sim = CapsuleSuspension(c, precision="fp64", discretisation=disc)
     g = O.SlitGrid(c.Lx, c.Lz, c.H, c.alpha, c.rc, c.Nx, c.Nz, c.Ny)
     h = C.min_separation(c.nodes, c.tri, 2, c.Lx, c.Lz)
     assert abs(sim.min_separation() - h) < 1e-14
     dt = sim.step()
     assert abs(dt - C.time_step(h, c.ca, c.a, c.shear)) < 1e-15
     x = c.nodes
-    u1 = oracle_stage(c, g, x)
-    u2 = oracle_stage(c, g, x + 0.5 * dt * u1)
+    u1 = oracle_stage(c, g, x, disc)
+    u2 = oracle_stage(c, g, x + 0.5 * dt * u1, disc)
     x1 = x + dt * u2
     # the coarse, perturbed meshes drift by about 4e-3 in one step, so the
     # volume correction acts on both capsules; no overlap is corrected
@@ -181,11 +193,12 @@ def test_capsule_step_matches_the_oracle():
     sim.close()
 
 
-def test_capsule_stage_with_viscosity_contrast():
+@pytest.mark.parametrize("disc", ["bi", "gauss"])
+def test_capsule_stage_with_viscosity_contrast(disc):
     """lambda = 3: the GMRES density satisfies the oracle's Eq. qa and the
     velocity is the oracle's for that density."""
     c = small_case(3.0)
-    sim = CapsuleSuspension(c, precision="fp64", tol=1e-10)
+    sim = CapsuleSuspension(c, precision="fp64", tol=1e-10, discretisation=disc)
     u, q = sim.stage(sim.x, sim.q, 0)
     x = c.nodes
     nrm = node_normals(x, c.tri)
@@ -194,9 +207,12 @@ def test_capsule_stage_with_viscosity_contrast():
     g = O.SlitGrid(c.Lx, c.Lz, c.H, c.alpha, c.rc, c.Nx, c.Nz, c.Ny)
     qn = q.cpu().numpy()
     kappa = (c.lam - 1) / (c.lam + 1)
-    r = O.fredholm_apply(g, x, nrm, c.tri, kappa, qn) - b
+    if disc == "gauss":
+        r = O.fredholm_apply(g, x, nrm, c.tri, kappa, qn) - b
+    else:
+        r = qn + 2.0 * kappa * BI.dl_bi(g, x, c.tri, nrm, qn) - b
     assert np.abs(r).max() < 1e-8 * np.abs(b).max()
-    want = surface_velocity(g, x, c.tri, qn, c.shear)
+    want = oracle_velocity(c, g, x, qn, disc)
     assert np.abs(u.cpu().numpy() - want).max() < 1e-10 * np.abs(want).max()
     assert sim.stages[0].iters > 1
     sim.close()
