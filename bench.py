@@ -46,7 +46,8 @@ FLOP_NEAR_DL = 65.0
 FLOP_SPREAD = 12.0
 
 METRIC = "GGEM Mpoints/s (mixed vs FP64, rel err 1e-5); Fredholm solve s to 1e-6"
-EXTRAS = ("small", "capsules_sl", "batched", "fredholm", "rigid", "spectral", "capsules")
+EXTRAS = ("small", "capsules_sl", "batched", "fredholm", "rigid", "spectral", "capsules",
+          "probes")
 
 
 def log(msg):
@@ -643,6 +644,47 @@ def spectral_eval(args):
     return res
 
 
+def probe_fields(args):
+    """Velocity, pressure and stress at probes (ggem_probe): c0 (64 forces,
+    1,000 probes; microseconds per call) and the 50-capsule forces of c1 at
+    100,000 seeded probes (ms per call and probes per second), FP64 and
+    mixed.  A call solves the global problem once for the stress (with the
+    pressure gauge) and transforms the kept velocity and pressure
+    coefficients back once more."""
+    import numpy as np
+    import torch
+
+    import paper_1109_6587_amd as G
+    from workloads import case_capsules_sl, case_small_sl
+
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)  # noqa: E731
+    res = {}
+    c0 = case_small_sl(0)
+    c1 = case_capsules_sl(1)
+    rng = np.random.default_rng(17)
+    npr = 100_000
+    probes = np.stack([rng.uniform(0, c1.Lx, npr), rng.uniform(-c1.H, c1.H, npr),
+                       rng.uniform(0, c1.Lz, npr)], 1)
+    for name, c, xt in (("small_sl_64", c0, c0.xt), ("capsules_sl_50x642", c1, probes)):
+        xs, f, xtd = t(c.xs), t(c.f), t(xt)
+        nt = xt.shape[0]
+        out = (torch.empty((nt, 3), dtype=torch.float64, device=dev),
+               torch.empty((nt,), dtype=torch.float64, device=dev),
+               torch.empty((nt, 6), dtype=torch.float64, device=dev))
+        r = {"sources": c.ns, "probes": nt, "grid": [c.Nx, c.Nz, c.Ny]}
+        for p in ("fp64", "mixed"):
+            plan = G.Plan(c.Lx, c.Lz, c.H, c.alpha, c.Nx, c.Nz, c.Ny, rc=c.rc, precision=p,
+                          max_src=c.ns, max_tgt=nt, sync_checks=False)
+            call = lambda: plan.probe(xs, f, xtd, out=out)  # noqa: E731
+            ms, _ = time_steps(plan, call, max(5, args.steps // 2), 2)
+            r[p] = {"ms_per_call": round(ms, 4),
+                    "mprobes_per_s": round(nt / (ms * 1e-3) / 1e6, 3)}
+            plan.close()
+        res[name] = r
+    return res
+
+
 def capsule_stages(steps=4):
     """The timing study of the capsule suspensions (Sec. 7.2, Fig. tscale):
     wall-clock ms per stage of the midpoint rule for 15, 30, 60 and 120
@@ -808,6 +850,9 @@ def main():
         if "capsules" in extras:
             log("extra: capsule suspensions")
             line["capsule_stages"] = capsule_stages()
+        if "probes" in extras:
+            log("extra: probes")
+            line["probe_fields"] = probe_fields(args)
         if not args.no_cpu_baseline:
             log("cpu baseline (oracle)")
             line["cpu_baseline"] = cpu_baseline(c)

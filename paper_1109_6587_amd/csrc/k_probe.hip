@@ -9,7 +9,9 @@
 // a coincident source adding -(4 alpha/sqrt(pi))/(8pi) g to the velocity only.
 // The global parts are the slit solution of Appendix C interpolated with the
 // 4th-order Lagrange stencil of Sec. 3.2.2.  One thread per probe, FP64 sums
-// (probes are few; the grid fields keep the plan's precision).
+// (the grid fields keep the plan's precision).  The local sums take the
+// probes in the cell order of their binning, so that neighbouring lanes walk
+// the same cells; each probe's own sum is unchanged by that order.
 //
 // Undisturbed flows (Appendix B), walls at y = -H and y = +H:
 //   simple shear sigma = rate e;  Poiseuille (centre-line velocity U0)
@@ -36,6 +38,7 @@ struct ProbeArgs {
   double rc2, alpha;
   int nt;
   const double* xt;        // probes (nt, 3), any periodic image
+  const int* order;        // probes in cell order (their binning's permutation)
   const int* cell_start;   // binned sources
   const int* perm;
   const double *sx, *sy, *sz;
@@ -47,8 +50,9 @@ struct ProbeArgs {
 };
 
 __global__ void __launch_bounds__(256) probe_local(ProbeArgs a) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= a.nt) return;
+  const int ts = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ts >= a.nt) return;
+  const int t = a.order[ts];
   const CellGeom& g = a.g;
   double px = a.xt[3 * (size_t)t], py = a.xt[3 * (size_t)t + 1], pz = a.xt[3 * (size_t)t + 2];
   double u[3] = {0, 0, 0}, pr = 0.0, s[6] = {0, 0, 0, 0, 0, 0};
@@ -198,12 +202,16 @@ __global__ void undisturbed_traction_kernel(int n, int kind, double rate, double
 hipError_t launch_probe_local(Plan& p, int nt, const double* xt, const double* f, double* u,
                               double* pr, double* sigma) {
   if (nt <= 0) return hipSuccess;
+  // cell order of the probes (p.tgt.perm); non-finite or outside probes are
+  // flagged here as in an evaluation and again by the kernel
+  if (hipError_t e = launch_bin(p, p.tgt, nt, xt, nullptr, nullptr, false, false)) return e;
   ProbeArgs a;
   a.g = p.cg;
   a.rc2 = p.rc2;
   a.alpha = p.p.alpha;
   a.nt = nt;
   a.xt = xt;
+  a.order = p.tgt.perm;
   a.cell_start = p.src.cell_start;
   a.perm = p.src.perm;
   a.sx = p.src.x;

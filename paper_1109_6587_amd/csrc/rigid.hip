@@ -122,151 +122,201 @@ __device__ inline void add_stresslet(double dx, double dy, double dz, double qx,
   acc[2] += w * (cd * dz + D * (dz * qm + qz * dm + mz * dq));
 }
 
-// int over one element of f G^l(z - x) dS (DL: of q_i T^l_jik(z - x) m_k dS,
-// m = n(z), or n~ when polar); e[v] vertex positions relative to z, fe[v]
-// nodal values, local vertex 0 is z itself when polar
+// One quadrature point (o, i) of the product rule over an element:
+// acc += w f G^l(z - x) (DL: w q_i T^l_jik(z - x) m_k, m = n(z), or n~ when
+// polar).  e[v]: vertex positions relative to z, fe[v]: nodal values; local
+// vertex 0 is z itself when polar.
 template <bool DL>
-__device__ void element_integral(const double (&e)[3][3], const double (&fe)[3][3], bool polar,
-                                 double alpha, const double* nz, double* acc) {
+__device__ void element_point(const double (&e)[3][3], const double (&fe)[3][3], bool polar, int o,
+                              int i, double alpha, const double* nz, double* acc) {
   const double u1x = e[1][0] - e[0][0], u1y = e[1][1] - e[0][1], u1z = e[1][2] - e[0][2];
   const double u2x = e[2][0] - e[0][0], u2y = e[2][1] - e[0][1], u2z = e[2][2] - e[0][2];
   const double cx = u1y * u2z - u1z * u2y, cy = u1z * u2x - u1x * u2z, cz = u1x * u2y - u1y * u2x;
   const double omega = sqrt(cx * cx + cy * cy + cz * cz);
-  // element normal on the side of n(z)
-  double nD[3] = {0.0, 0.0, 0.0};
-  if (DL) {
-    const double sg = (cx * nz[0] + cy * nz[1] + cz * nz[2]) < 0.0 ? -1.0 / omega : 1.0 / omega;
-    nD[0] = sg * cx;
-    nD[1] = sg * cy;
-    nD[2] = sg * cz;
+  double xi, eta, w;
+  if (polar) {
+    const double th = 0.5 * M_PI * kGLt[o];
+    const double c = cos(th), s = sin(th);
+    const double rmax = 1.0 / (c + s);
+    const double rho = rmax * kGLt[i];
+    xi = rho * c;
+    eta = rho * s;
+    w = (0.5 * M_PI * kGLw[o]) * rmax * kGLw[i] * rho * omega;
+  } else {
+    eta = kGLt[o];
+    xi = (1.0 - eta) * kGLt[i];
+    w = kGLw[o] * kGLw[i] * (1.0 - eta) * omega;
   }
-  for (int o = 0; o < 4; ++o) {
-    double c = 1.0, s = 0.0, rmax = 1.0, wo;
-    if (polar) {
-      const double th = 0.5 * M_PI * kGLt[o];
-      c = cos(th);
-      s = sin(th);
-      rmax = 1.0 / (c + s);
-      wo = 0.5 * M_PI * kGLw[o];
-    } else {
-      wo = kGLw[o];
-    }
-    for (int i = 0; i < 4; ++i) {
-      double xi, eta, w;
-      if (polar) {
-        const double rho = rmax * kGLt[i];
-        xi = rho * c;
-        eta = rho * s;
-        w = wo * rmax * kGLw[i] * rho * omega;
-      } else {
-        eta = kGLt[o];
-        xi = (1.0 - eta) * kGLt[i];
-        w = wo * kGLw[i] * (1.0 - eta) * omega;
-      }
-      const double p0 = 1.0 - xi - eta, p1 = xi, p2 = eta;
-      // d = z - x(xi, eta)
-      const double dx = -(p0 * e[0][0] + p1 * e[1][0] + p2 * e[2][0]);
-      const double dy = -(p0 * e[0][1] + p1 * e[1][1] + p2 * e[2][1]);
-      const double dz = -(p0 * e[0][2] + p1 * e[1][2] + p2 * e[2][2]);
-      const double vx = p0 * fe[0][0] + p1 * fe[1][0] + p2 * fe[2][0];
-      const double vy = p0 * fe[0][1] + p1 * fe[1][1] + p2 * fe[2][1];
-      const double vz = p0 * fe[0][2] + p1 * fe[1][2] + p2 * fe[2][2];
-      if (DL) {
-        const double a0 = polar ? p0 : 0.0, a1 = 1.0 - a0;  // n~ = n_D phi_z + n(z)(1 - phi_z)
-        add_stresslet(dx, dy, dz, vx, vy, vz, a0 * nD[0] + a1 * nz[0], a0 * nD[1] + a1 * nz[1],
-                      a0 * nD[2] + a1 * nz[2], alpha, w, acc);
-      } else {
-        add_stokeslet(dx, dy, dz, vx, vy, vz, alpha, w, acc);
-      }
-    }
+  const double p0 = 1.0 - xi - eta, p1 = xi, p2 = eta;
+  // d = z - x(xi, eta)
+  const double dx = -(p0 * e[0][0] + p1 * e[1][0] + p2 * e[2][0]);
+  const double dy = -(p0 * e[0][1] + p1 * e[1][1] + p2 * e[2][1]);
+  const double dz = -(p0 * e[0][2] + p1 * e[1][2] + p2 * e[2][2]);
+  const double vx = p0 * fe[0][0] + p1 * fe[1][0] + p2 * fe[2][0];
+  const double vy = p0 * fe[0][1] + p1 * fe[1][1] + p2 * fe[2][1];
+  const double vz = p0 * fe[0][2] + p1 * fe[1][2] + p2 * fe[2][2];
+  if (DL) {
+    // element normal on the side of n(z); n~ = n_D phi_z + n(z)(1 - phi_z)
+    const double sg = (cx * nz[0] + cy * nz[1] + cz * nz[2]) < 0.0 ? -1.0 / omega : 1.0 / omega;
+    const double a0 = polar ? p0 : 0.0, a1 = 1.0 - a0;
+    add_stresslet(dx, dy, dz, vx, vy, vz, a0 * (sg * cx) + a1 * nz[0], a0 * (sg * cy) + a1 * nz[1],
+                  a0 * (sg * cz) + a1 * nz[2], alpha, w, acc);
+  } else {
+    add_stokeslet(dx, dy, dz, vx, vy, vz, alpha, w, acc);
   }
 }
 
-// One wave per target node z.  The wave walks the nodes of the cells around
-// z in sorted order, 64 at a time; a lane whose node v lies within r_c of z
-// integrates every triangle at v for which v is the first of the triangle's
-// vertices (in their stored order) within r_c of z, so each element within
-// r_c is integrated exactly once.  Lane sums are added in a fixed tree order.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int kElemCap = 256;  // element list of a wave (LDS ints)
+
+// The 16 quadrature points of each listed element, one lane per (element,
+// point), four elements per round; each lane accumulates its points in list
+// order.
+template <bool DL>
+__device__ void eval_list(const BiArgs& a, const int* list, int cnt, int t, double zx, double zy,
+                          double zz, const double* nz, int lane, double* acc) {
+  const CellGeom& g = a.g;
+  const int o = (lane & 15) >> 2, i = lane & 3;
+  for (int base = 0; base < cnt; base += 4) {
+    const int idx = base + (lane >> 4);
+    if (idx >= cnt) continue;
+    const int k = list[idx];
+    const int ia = a.tri[3 * (size_t)k], ib = a.tri[3 * (size_t)k + 1], ic = a.tri[3 * (size_t)k + 2];
+    const int vv[3] = {ia, ib, ic};
+    const bool polar = ia == t || ib == t || ic == t;
+    const int rot = ib == t ? 1 : (ic == t ? 2 : 0);
+    double e0x, e0y, e0z;
+    rel(a, ia, zx, zy, zz, e0x, e0y, e0z);
+    double ea[3][3];
+    ea[0][0] = e0x;
+    ea[0][1] = e0y;
+    ea[0][2] = e0z;
+    for (int m = 1; m < 3; ++m) {
+      const int q2 = vv[m];
+      ea[m][0] = e0x + min_img(a.x[3 * (size_t)q2] - a.x[3 * (size_t)ia], g.Lx, g.invLx);
+      ea[m][1] = e0y + (a.x[3 * (size_t)q2 + 1] - a.x[3 * (size_t)ia + 1]);
+      ea[m][2] = e0z + min_img(a.x[3 * (size_t)q2 + 2] - a.x[3 * (size_t)ia + 2], g.Lz, g.invLz);
+    }
+    double e[3][3], fe[3][3];
+    for (int m = 0; m < 3; ++m) {
+      const int src = (rot + m) % 3;
+      const int node = vv[src];
+      for (int d = 0; d < 3; ++d) {
+        e[m][d] = (polar && m == 0) ? 0.0 : ea[src][d];
+        fe[m][d] = a.f[3 * (size_t)node + d];
+      }
+    }
+    element_point<DL>(e, fe, polar, o, i, a.alpha, nz, acc);
+  }
+}
+
+// One wave per target node z.  (1) The nodes of the cells around z are taken
+// as one flat range over the (up to 27) cells, 64 at a time; a lane whose
+// node v lies within r_c of z lists every triangle at v for which v is the
+// first of the triangle's vertices (in their stored order) within r_c of z,
+// so that each element within r_c is listed exactly once; one triangle per
+// lane and round, compacted by ballot into the wave's list in lane order.
+// (2) Whenever the list could overflow, and at the end, its elements are
+// integrated with one lane per (element, quadrature point).  Lane sums are
+// added in a fixed tree order: the result depends only on the inputs.
 template <bool DL>
 __global__ void __launch_bounds__(256) bi_local(BiArgs a) {
+  __shared__ int elist[4][kElemCap];
+  __shared__ int cstart[4][27], cpref[4][28];
   __shared__ double red[4][3][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int t = blockIdx.x * 4 + wave;
-  if (t >= a.n) return;
+  if (t >= a.n) return;  // uniform over the wave
   const CellGeom& g = a.g;
   const double zx = a.x[3 * (size_t)t], zy = a.x[3 * (size_t)t + 1], zz = a.x[3 * (size_t)t + 2];
   const int c = a.keys[t] / g.nzs;
   const int iz = c % g.ncz, ix = (c / g.ncz) % g.ncx, iy = c / (g.ncz * g.ncx);
   const int nxo = g.ncx >= 3 ? 3 : g.ncx, nzo = g.ncz >= 3 ? 3 : g.ncz;
+  const int ncell = 3 * nxo * nzo;
   double nz[3] = {0.0, 0.0, 0.0};
   if (DL)
     for (int d = 0; d < 3; ++d) nz[d] = a.nrm[3 * (size_t)t + d];
-  double acc[3] = {0.0, 0.0, 0.0};
-  for (int oy = -1; oy <= 1; ++oy) {
+  // the neighbour cells' ranges and their running total
+  int cnt = 0, s0 = 0;
+  if (lane < ncell) {
+    const int oy = lane / (nxo * nzo) - 1, oxi = (lane / nzo) % nxo, ozi = lane % nzo;
     const int cy = iy + oy;
-    if (cy < 0 || cy >= g.ncy) continue;
-    for (int oxi = 0; oxi < nxo; ++oxi) {
+    if (cy >= 0 && cy < g.ncy) {
       const int cx = g.ncx >= 3 ? (ix + oxi - 1 + g.ncx) % g.ncx : oxi;
-      for (int ozi = 0; ozi < nzo; ++ozi) {
-        const int cz = g.ncz >= 3 ? (iz + ozi - 1 + g.ncz) % g.ncz : ozi;
-        const int cc = (cy * g.ncx + cx) * g.ncz + cz;
-        const int s0 = a.cell_start[cc], s1 = a.cell_start[cc + 1];
-        for (int b = s0; b < s1; b += 64) {
-          const int j = b + lane;
-          if (j >= s1) continue;
-          const int v = a.perm[j];
-          if (!within(a, v, zx, zy, zz)) continue;
-          for (int q = a.off[v]; q < a.off[v + 1]; ++q) {
-            const int k = a.adj[q];
-            const int ia = a.tri[3 * (size_t)k], ib = a.tri[3 * (size_t)k + 1],
-                      ic = a.tri[3 * (size_t)k + 2];
-            // skip unless v is the first vertex within r_c
-            if (ia != v && within(a, ia, zx, zy, zz)) continue;
-            if (ia != v && ib != v && within(a, ib, zx, zy, zz)) continue;
-            // vertices relative to z, z as local vertex 0 when it is one of them
-            int vv[3] = {ia, ib, ic};
-            int rot = 0;
-            const bool polar = ia == t || ib == t || ic == t;
-            if (ib == t) rot = 1;
-            if (ic == t) rot = 2;
-            int w3[3] = {vv[rot], vv[(rot + 1) % 3], vv[(rot + 2) % 3]};
-            double e[3][3], fe[3][3];
-            double e0x, e0y, e0z;
-            rel(a, ia, zx, zy, zz, e0x, e0y, e0z);
-            double ea[3][3];
-            ea[0][0] = e0x;
-            ea[0][1] = e0y;
-            ea[0][2] = e0z;
-            for (int m = 1; m < 3; ++m) {
-              const int q2 = vv[m];
-              ea[m][0] = e0x + min_img(a.x[3 * (size_t)q2] - a.x[3 * (size_t)ia], g.Lx, g.invLx);
-              ea[m][1] = e0y + (a.x[3 * (size_t)q2 + 1] - a.x[3 * (size_t)ia + 1]);
-              ea[m][2] = e0z + min_img(a.x[3 * (size_t)q2 + 2] - a.x[3 * (size_t)ia + 2], g.Lz,
-                                       g.invLz);
-            }
-            for (int m = 0; m < 3; ++m) {
-              const int src = (rot + m) % 3;
-              for (int d = 0; d < 3; ++d) {
-                e[m][d] = (polar && m == 0) ? 0.0 : ea[src][d];
-                fe[m][d] = a.f[3 * (size_t)w3[m] + d];
-              }
-            }
-            element_integral<DL>(e, fe, polar, a.alpha, nz, acc);
-          }
-        }
-      }
+      const int cz = g.ncz >= 3 ? (iz + ozi - 1 + g.ncz) % g.ncz : ozi;
+      const int cc = (cy * g.ncx + cx) * g.ncz + cz;
+      s0 = a.cell_start[cc];
+      cnt = a.cell_start[cc + 1] - s0;
     }
   }
+  int pref = cnt;  // inclusive scan over the lanes
+  for (int o = 1; o < 32; o <<= 1) {
+    const int v = __shfl_up(pref, o);
+    if (lane >= o) pref += v;
+  }
+  if (lane < ncell) {
+    cstart[wave][lane] = s0;
+    cpref[wave][lane + 1] = pref;
+  }
+  if (lane == 0) cpref[wave][0] = 0;
+  wave_sync();
+  const int total = cpref[wave][ncell];
+  double acc[3] = {0.0, 0.0, 0.0};
+  int listed = 0;
+  for (int b = 0; b < total; b += 64) {
+    const int ii = b + lane;
+    int v = -1, q0 = 0, q1 = 0;
+    if (ii < total) {
+      int lo = 0, hi = ncell - 1;  // the cell m with cpref[m] <= ii < cpref[m + 1]
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cpref[wave][mid] <= ii) lo = mid;
+        else hi = mid - 1;
+      }
+      const int node = a.perm[cstart[wave][lo] + (ii - cpref[wave][lo])];
+      if (within(a, node, zx, zy, zz)) {
+        v = node;
+        q0 = a.off[v];
+        q1 = a.off[v + 1];
+      }
+    }
+    // rounds: the r-th incident triangle of every lane
+    int rounds = q1 - q0;
+    for (int o = 32; o > 0; o >>= 1) rounds = max(rounds, __shfl_xor(rounds, o));
+    for (int r = 0; r < rounds; ++r) {
+      bool take = false;
+      int k = 0;
+      if (v >= 0 && q0 + r < q1) {
+        k = a.adj[q0 + r];
+        const int ia = a.tri[3 * (size_t)k], ib = a.tri[3 * (size_t)k + 1];
+        take = !((ia != v && within(a, ia, zx, zy, zz)) ||
+                 (ia != v && ib != v && within(a, ib, zx, zy, zz)));
+      }
+      const unsigned long long m = __ballot(take);
+      const int nnew = __popcll(m);
+      if (nnew == 0) continue;
+      if (listed + nnew > kElemCap) {
+        eval_list<DL>(a, elist[wave], listed, t, zx, zy, zz, nz, lane, acc);
+        wave_sync();
+        listed = 0;
+      }
+      if (take) elist[wave][listed + __popcll(m & ((1ull << lane) - 1))] = k;
+      listed += nnew;
+      wave_sync();
+    }
+  }
+  eval_list<DL>(a, elist[wave], listed, t, zx, zy, zz, nz, lane, acc);
   for (int d = 0; d < 3; ++d) red[wave][d][lane] = acc[d];
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  wave_sync();
   for (int o = 32; o > 0; o >>= 1) {
     if (lane < o)
       for (int d = 0; d < 3; ++d) red[wave][d][lane] += red[wave][d][lane + o];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_sync();
   }
   if (lane == 0)
     for (int d = 0; d < 3; ++d) a.out[3 * (size_t)t + d] = kInv8Pi * red[wave][d][0];

@@ -263,14 +263,22 @@ class Plan:
         _check(_lib.ggem_plan_work(self._h, c))
         return int(c[0]), int(c[1])
 
-    def probe(self, xs, f, xt):
+    def probe(self, xs, f, xt, out=None):
         """Velocity (nt, 3), pressure (nt,) and stress (nt, 6: xx, yy, zz, xy,
-        xz, yz) of the point forces at the probes xt (ggem_probe)."""
+        xz, yz) of the point forces at the probes xt (ggem_probe); `out` may
+        give the three arrays."""
         import torch
         ns, nt = xs.shape[0], xt.shape[0]
-        u = torch.empty((nt, 3), dtype=torch.float64, device=xt.device)
-        p = torch.empty((nt,), dtype=torch.float64, device=xt.device)
-        s = torch.empty((nt, 6), dtype=torch.float64, device=xt.device)
+        if out is None:
+            u = torch.empty((nt, 3), dtype=torch.float64, device=xt.device)
+            p = torch.empty((nt,), dtype=torch.float64, device=xt.device)
+            s = torch.empty((nt, 6), dtype=torch.float64, device=xt.device)
+        else:
+            u, p, s = out
+            for t, shape in ((u, (nt, 3)), (p, (nt,)), (s, (nt, 6))):
+                if (not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64
+                        or t.shape != shape or not t.is_contiguous()):
+                    raise TypeError(f"probe outputs must be contiguous float64 {shape} device tensors")
         _check(_lib.ggem_probe(self._h, ns, _dev_ptr(xs, "xs"), _dev_ptr(f, "f", ns), nt,
                                _dev_ptr(xt, "xt"), u.data_ptr(), p.data_ptr(), s.data_ptr()))
         return u, p, s
