@@ -154,7 +154,8 @@ void free_over(Plan& p) {
   if (p.over_block) (void)hipFree(p.over_block);
   delete p.over;
   p.over = nullptr;
-  p.over_block = p.over_spec = p.over_phys = nullptr;
+  p.over_block = p.over_spec = p.over_phys = p.over_t = nullptr;
+  p.over_s = 0;
   p.interp_mode = GGEM_INTERP_LAGRANGE;
 }
 
@@ -477,6 +478,7 @@ int evaluate(Plan& p, long long ns, const double* xs, const double* f, long long
       HIP_TRY(launch_nufft_pad<T>(p, nf));
       p.over->stream = p.stream;
       HIP_TRY(launch_fft_inverse<T>(*p.over, p.over_spec, p.over_phys, nf * Ny));
+      if (p.over_s) HIP_TRY(launch_nufft_transpose<T>(p, nf));
     } else {
       {
         StageScope s(p, GGEM_STAGE_CHEB_INV);
@@ -843,6 +845,17 @@ extern "C" int ggem_plan_set_interp(ggem_plan_t plan, int mode, int msp) {
   (void)sz.take_bytes(2 * (size_t)Mz * elt);
   (void)sz.take_bytes(6 * (size_t)Ny * Mx * o->Nzh * 2 * elt);
   (void)sz.take_bytes(6 * (size_t)Ny * Mx * Mz * elt);
+  // the transposed copy with its z halo, for the FP32 grid when the window
+  // rows fit the gather's register budget (16 loads of 16 bytes per lane and
+  // row).  An FP64 grid keeps the gather of the untransposed planes: its
+  // window rows are read at the same rate either way (the transposed rows
+  // measured 2.12 against 1.60 ms on 32,100 targets, msp 12).
+  const int V = (int)(16 / elt), W = 2 * msp;
+  const int nyp = (Ny + V - 1) / V * V, zp = Mz + W;
+  const int S = (W * nyp + 64 * V - 1) / (64 * V);
+  const int Sb = p.fp64 ? 0 : (S <= 2 ? 2 : (S <= 4 ? 4 : (S <= 8 ? 8 : (S <= 16 ? 16 : 0))));
+  const size_t tbytes = Sb ? (6 * (size_t)Mx * zp * nyp + 64 * (size_t)Sb * V) * elt : 0;
+  if (Sb) (void)sz.take_bytes(tbytes);
   if (hipMalloc(&p.over_block, sz.off) != hipSuccess) {
     p.over_block = nullptr;
     delete o;
@@ -854,6 +867,15 @@ extern "C" int ggem_plan_set_interp(ggem_plan_t plan, int mode, int msp) {
   o->twz = c.take_bytes(2 * (size_t)Mz * elt);
   p.over_spec = c.take_bytes(6 * (size_t)Ny * Mx * o->Nzh * 2 * elt);
   p.over_phys = c.take_bytes(6 * (size_t)Ny * Mx * Mz * elt);
+  p.over_t = Sb ? c.take_bytes(tbytes) : nullptr;
+  p.over_zp = zp;
+  p.over_nyp = nyp;
+  p.over_s = Sb;
+  // the slack after the last row is read with zero weights: keep it finite
+  if (Sb && hipMemset(p.over_t, 0, tbytes) != hipSuccess) {
+    free_over(p);
+    return fail(GGEM_E_DEVICE, "clearing the oversampled grid failed");
+  }
   std::vector<double> tw(2 * (size_t)(Mx > Mz ? Mx : Mz));
   std::vector<float> tf(tw.size());
   for (int ax = 0; ax < 2; ++ax) {

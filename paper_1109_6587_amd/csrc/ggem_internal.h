@@ -138,6 +138,10 @@ struct Plan {
   void* over_block;   // its device buffers (one allocation of their own):
   void* over_spec;    //   padded spectra (6 x Ny x 2Nx x (Nz+1), complex T)
   void* over_phys;    //   oversampled fields (6 x Ny x 2Nx x 2Nz, T)
+  void* over_t;       //   the same, [field][X][Z + halo][n] (null: no such copy)
+  int over_zp;        // Z extent of over_t: 2 Nz + 2 msp (periodic halo)
+  int over_nyp;       // n extent of over_t: Ny padded to 16 bytes
+  int over_s;         // 16-byte loads per lane and window row in spectral_eval
 };
 
 // ---- 4th-order Lagrange interpolation (Sec. 3.2.2), shared by the
@@ -214,6 +218,8 @@ long long solver_max_nodes(ggem_solver_t s);
 long long solver_max_tri(ggem_solver_t s);
 template <typename T>
 hipError_t launch_nufft_pad(Plan& p, int nf);
+template <typename T>
+hipError_t launch_nufft_transpose(Plan& p, int nf);
 template <typename T>
 hipError_t launch_spectral_eval(Plan& p, int nt, double* out, bool stress);
 
