@@ -231,3 +231,23 @@ def test_capsule_at_rest_stays_at_rest():
     tau = c.G * (1 - 1.05 ** -6)
     assert np.abs(u.cpu().numpy()).max() < 2e-2 * tau
     sim.close()
+
+
+def test_capsule_edge_cases():
+    """A single capsule (no pairs), zero sweeps, a zero volume tolerance."""
+    V, F = icosphere(1)
+    x = V + [2.0, 0.0, 2.0]
+    s = Setup(x, x, F.astype(np.int32), 1, L=8.0, H=2.0)
+    xd = dev(x)
+    e, g = s.mem.separation(xd, 8.0, 8.0, 1.0)
+    assert abs(e - C.min_edge(x, F)) < 1e-14 and g == np.inf
+    near_wall = dev(V + [2.0, 1.0, 2.0])          # 1.0 from y = +2 minus the radius 1: gap 0
+    assert s.mem.overlap_correct(near_wall, 8.0, 8.0, 2.0, 0.05, max_sweeps=0) == 0
+    assert torch.equal(near_wall, dev(V + [2.0, 1.0, 2.0]))
+    assert s.mem.overlap_correct(near_wall, 8.0, 8.0, 2.0, 0.05) == 1
+    assert abs(near_wall[:, 1].max().item() - (2.0 - 0.05)) < 1e-14
+    nrm, area, _ = s.solver.geometry(xd, s.tri, s.off, s.adj)
+    v0 = s.mem.volumes(xd) * (1 + 1e-9)
+    assert s.mem.volume_correct(xd, nrm, area, v0, 0.0) == 1
+    assert s.mem.volume_correct(xd, nrm, area, s.mem.volumes(xd).clone(), 0.0) == 0
+    s.close()

@@ -180,3 +180,33 @@ def test_spectral_parity_medium(medium):
     ul = p.single_layer(dev(xs), dev(f), dev(nodes)).cpu().numpy()
     assert np.abs(us - ul).max() < 1e-10 * np.abs(ul).max()
     p.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("grid", [(40, 24, 33), (32, 32, 65)])
+def test_window_width_error_law(precision, grid):
+    """Every window width the kernels specialise for (FP64: 1, 2, 4, 9 and 16
+    entries per lane; FP32: 2, 4, 8 and 16 vectors per lane and row) has the
+    error of Gaussian gridding with oversampling 2, below exp(-0.75 pi msp)
+    of the largest value, down to the rounding floor of the grid's type."""
+    Nx, Nz, Ny = grid
+    rng = np.random.default_rng(41)
+    Lx, Lz, H, alpha = 3.0, 2.4, 1.0, 4.0
+    g = O.SlitGrid(Lx, Lz, H, alpha, 1.0, Nx, Nz, Ny)
+    ns, nt = 60, 257
+    xs = np.stack([rng.uniform(0, Lx, ns), rng.uniform(-0.95, 0.95, ns), rng.uniform(0, Lz, ns)], 1)
+    f = rng.standard_normal((ns, 3))
+    xt = np.stack([rng.uniform(0, Lx, nt), rng.uniform(-H, H, nt), rng.uniform(0, Lz, nt)], 1)
+    nrm = unit(rng, nt)
+    ref = S.single_layer_spectral(g, xs, f, xt)
+    refd = S.double_layer_spectral(g, xs, f, xt, nrm)
+    floor = 1e-13 if precision == "fp64" else 1e-6
+    for msp in (2, 4, 5, 8, 10, 16):
+        print(f"grid {grid} {precision} msp {msp}", flush=True)
+        bound = np.exp(-0.75 * np.pi * msp) + floor
+        p = plan_for(g, precision, ns, nt, msp)
+        u = p.single_layer(dev(xs), dev(f), dev(xt)).cpu().numpy()
+        v = p.double_layer(dev(xs), dev(f), dev(xt), dev(nrm)).cpu().numpy()
+        assert np.abs(u - ref).max() < bound * np.abs(ref).max(), msp
+        assert np.abs(v - refd).max() < bound * np.abs(refd).max(), msp
+        p.close()
