@@ -251,3 +251,28 @@ def test_capsule_edge_cases():
     assert s.mem.volume_correct(xd, nrm, area, v0, 0.0) == 1
     assert s.mem.volume_correct(xd, nrm, area, s.mem.volumes(xd).clone(), 0.0) == 0
     s.close()
+
+
+def test_capsule_entry_point_errors():
+    V, F = icosphere(1)
+    x = V + [2.0, 0.0, 2.0]
+    s = Setup(x, x, F.astype(np.int32), 1, L=8.0, H=2.0)
+    xd = dev(x)
+    nrm = dev(node_normals(x, F))
+    rp = G.RigidParticle(s.plan, len(x), len(F))
+    cases = [
+        lambda: s.solver.traction_rhs(nrm, nrm, 0.0, 1.0),                 # lambda <= 0
+        lambda: s.solver.traction_rhs(nrm, nrm, 2.0, float("nan")),        # shear not finite
+        lambda: s.mem.separation(xd, 8.0, 8.0, 0.0),                       # reach <= 0
+        lambda: s.mem.overlap_correct(xd, 8.0, 8.0, 2.0, 0.0),             # h_min <= 0
+        lambda: s.mem.overlap_correct(xd, 8.0, 0.0, 2.0, 0.05),            # bad box
+        lambda: rp.surface_velocity(xd, s.tri, s.off, s.adj, nrm, float("inf")),
+        lambda: rp.fredholm_solve(xd, s.tri, s.off, s.adj, nrm, 0.5, nrm, nrm.clone(), tol=0.0),
+        lambda: rp.fredholm_solve(xd, s.tri, s.off, s.adj, nrm, float("nan"), nrm, nrm.clone()),
+    ]
+    for k, call in enumerate(cases):
+        with pytest.raises(G.GGEMError) as e:
+            call()
+        assert e.value.code == G.ggem.E_ARG, k
+    rp.close()
+    s.close()
