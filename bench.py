@@ -63,8 +63,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", choices=["mixed", "fp64", "mixed_bf16"], default="mixed")
-    ap.add_argument("--workload", choices=["capsules_dl", "capsules_sl", "batched"],
-                    default="capsules_dl")
+    ap.add_argument("--workload", choices=["capsules_dl", "capsules_sl", "batched", "extras"],
+                    default="capsules_dl",
+                    help="'extras': only the extra workloads of --extras, as one JSON line "
+                         "(for per-workload profiles), without the headline evaluation")
     ap.add_argument("--extras", default=",".join(EXTRAS),
                     help="comma-separated extra workloads in the line: "
                          f"{', '.join(EXTRAS)}, or 'none'")
@@ -881,6 +883,22 @@ def main():
         if e not in EXTRAS:
             print(f"unknown extra workload {e!r}", file=sys.stderr)
             sys.exit(2)
+    if args.workload == "extras":
+        runs = {"small": ("small_sl_64", lambda: extra_small(args)),
+                "capsules_sl": ("capsules_sl_50x642", lambda: extra_capsules_sl(args)),
+                "batched": ("batched_48", lambda: batched(args, args.steps)),
+                "fredholm": ("fredholm", lambda: fredholm(args.fredholm_steps)),
+                "rigid": ("rigid_sphere", rigid_sphere),
+                "spectral": ("spectral_eval", lambda: spectral_eval(args)),
+                "capsules": ("capsule_stages", capsule_stages),
+                "probes": ("probe_fields", lambda: probe_fields(args))}
+        line = {"metric": "extra workloads only (no headline evaluation)", "n_gpus": 1}
+        for e in extras:
+            key, run = runs[e]
+            log(f"extra: {key}")
+            line[key] = run()
+        print(json.dumps(line), flush=True)
+        return
     if args.workload == "batched":
         r = batched(args, args.steps)
         line = base_line(args, r["mpoints_per_s"], r["ms_per_step"],
