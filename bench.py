@@ -50,7 +50,7 @@ FLOP_SPREAD = 12.0
 
 METRIC = "GGEM Mpoints/s (mixed vs FP64, rel err 1e-5); Fredholm solve s to 1e-6"
 EXTRAS = ("small", "capsules_sl", "batched", "fredholm", "rigid", "spectral", "capsules",
-          "probes")
+          "probes", "convergence")
 
 
 def log(msg):
@@ -717,6 +717,56 @@ def probe_fields(args):
     return res
 
 
+def convergence_study():
+    """The convergence experiment of Sec. 3.2.3 (Fig. ggem_conv) on the GPU,
+    FP64: a point force (F, F, F) at (L/4, L/4, L/4) of a slit with
+    L_x = L_z = wall spacing = L = 1, alpha = 80/3, observed at the mesh
+    point (L/2, L/2, L/2) and at the off-mesh point (0.4312, 0.3734, 0.5234) L
+    (the paper's frame, y from the lower wall), for r_c = C/alpha, C = 4, 5,
+    6, and N_y from 17 to 129 with equal mean spacings (N_x = N_z = N_y - 1);
+    relative error of u_x against N_y = 129 with r_c = 13/alpha (the paper's
+    reference uses N_y = 225 and r_c = L/2; N_y is at most 129 here and r_c
+    must stay below L/2), each off-mesh value with the Lagrange stencil and
+    with the spectral evaluation (msp 12)."""
+    import numpy as np
+    import torch
+
+    import paper_1109_6587_amd as G
+
+    dev = torch.device("cuda:0")
+    L, alpha = 1.0, 80.0 / 3.0
+    H = 0.5 * L
+    xs = torch.tensor([[0.25 * L, 0.25 * L - H, 0.25 * L]], dtype=torch.float64, device=dev)
+    f = torch.ones((1, 3), dtype=torch.float64, device=dev)
+    xt = torch.tensor([[0.5 * L, 0.5 * L - H, 0.5 * L], [0.4312 * L, 0.3734 * L - H, 0.5234 * L]],
+                      dtype=torch.float64, device=dev)
+
+    def ux(Ny, C, spectral):
+        p = G.Plan(L, L, H, alpha, Ny - 1, Ny - 1, Ny, rc=C / alpha, precision="fp64",
+                   max_src=1, max_tgt=2)
+        if spectral:
+            p.set_interp(G.INTERP_SPECTRAL, 12)
+        u = p.single_layer(xs, f, xt).cpu().numpy()[:, 0]
+        p.close()
+        return u
+
+    ref = ux(129, 13.0, True)
+    rows = []
+    for C in (4.0, 5.0, 6.0):
+        for Ny in (17, 25, 33, 41, 49, 65, 81, 97, 121):
+            ul, us = ux(Ny, C, False), ux(Ny, C, True)
+            rows.append({"C": C, "Ny": Ny, "inv_alpha_dy": round((Ny - 1) / (alpha * L), 4),
+                         "mesh_point": float(abs(ul[0] - ref[0]) / abs(ref[0])),
+                         "off_mesh_lagrange": float(abs(ul[1] - ref[1]) / abs(ref[1])),
+                         "off_mesh_spectral": float(abs(us[1] - ref[1]) / abs(ref[1]))})
+    log("convergence study: " + ", ".join(f"C={r['C']:g} Ny={r['Ny']}: {r['mesh_point']:.1e}/"
+                                          f"{r['off_mesh_lagrange']:.1e}/{r['off_mesh_spectral']:.1e}"
+                                          for r in rows if r["Ny"] in (33, 121)))
+    return {"workload": "point_force_convergence", "reference": {"Ny": 129, "C": 13.0,
+                                                                 "u_x": [float(v) for v in ref]},
+            "rows": rows}
+
+
 def capsule_stages(steps=4):
     """The timing study of the capsule suspensions (Sec. 7.2, Fig. tscale):
     wall-clock ms per stage of the midpoint rule for 15, 30, 60 and 120
@@ -891,7 +941,8 @@ def main():
                 "rigid": ("rigid_sphere", rigid_sphere),
                 "spectral": ("spectral_eval", lambda: spectral_eval(args)),
                 "capsules": ("capsule_stages", capsule_stages),
-                "probes": ("probe_fields", lambda: probe_fields(args))}
+                "probes": ("probe_fields", lambda: probe_fields(args)),
+                "convergence": ("convergence", convergence_study)}
         line = {"metric": "extra workloads only (no headline evaluation)", "n_gpus": 1}
         for e in extras:
             key, run = runs[e]
@@ -936,6 +987,9 @@ def main():
         if "probes" in extras:
             log("extra: probes")
             line["probe_fields"] = probe_fields(args)
+        if "convergence" in extras:
+            log("extra: convergence study")
+            line["convergence"] = convergence_study()
         if not args.no_cpu_baseline:
             log("cpu baseline (oracle)")
             line["cpu_baseline"] = cpu_baseline(c)
