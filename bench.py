@@ -622,11 +622,12 @@ def rigid_sphere():
 
 def spectral_eval(args):
     """The 50-capsule single layer with the global part evaluated off the mesh
-    by its Fourier-Chebyshev series (Gaussian-gridding NUFFT, msp = 6 mixed,
-    12 FP64) beside the 4th-order Lagrange stencil: ms per step, the event
-    times of the evaluation kernel (interp stage) and of the deconvolution +
-    oversampled inverse FFT (fft_inv stage), and the error of each against
-    the oracle's series at the stored sample of targets."""
+    by its Fourier-Chebyshev series (Gaussian-gridding NUFFT in x, theta and
+    z, msp = 6 mixed, 12 FP64) beside the 4th-order Lagrange stencil: ms per
+    step, the event times of the evaluation kernel (interp stage) and of the
+    deconvolution, oversampled inverse FFT and theta transform (fft_inv
+    stage), and the error of each against the oracle's series at the stored
+    sample of targets."""
     import numpy as np
     import torch
 
@@ -666,10 +667,10 @@ def spectral_eval(args):
             _, inv_ms = time_steps(plan, call, steps, 2, stage="fft_inv")
             r[name] = {"ms_per_step": round(ms, 5), "interp_ms": round(interp_ms, 5),
                        "fft_inv_ms": round(inv_ms, 5), **e}
-        # window sums: one read of each of the (2 msp)^2 window nodes per
-        # field and Chebyshev order, one FMA each
-        win = 3 * c.Ny * (2 * msp) ** 2 * c.nt
-        r["window_reads_per_target"] = 3 * c.Ny * (2 * msp) ** 2
+        # window sums: one read and one FMA for each of the (2 msp)^3 window
+        # nodes per field
+        win = 3 * (2 * msp) ** 3 * c.nt
+        r["window_reads_per_target"] = 3 * (2 * msp) ** 3
         r["window_fma_tflops"] = round(2 * win / (r["spectral"]["interp_ms"] * 1e-3) / 1e12, 3)
         res[precision] = r
         plan.close()

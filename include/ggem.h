@@ -191,18 +191,19 @@ int ggem_plan_count_work(ggem_plan_t plan, int on);
  * whose error falls only as h^5 off the mesh, and notes that the
  * non-uniform FFT keeps the spectral accuracy of the mesh points there too.
  * GGEM_INTERP_SPECTRAL evaluates the Fourier-Chebyshev series of the global
- * velocity (or stress, for the double layer) at each target: Clenshaw's
- * recurrence in y, and in x and z a type-2 NUFFT by Gaussian gridding
- * (Greengard and Lee) on the 2 Nx x 2 Nz oversampled grid, with msp
- * oversampled nodes on each side of the target (error about
- * exp(-0.75 pi msp): msp = 12 for FP64, 6 for the mixed modes). */
+ * velocity (or stress, for the double layer) at each target as a type-2 NUFFT
+ * by Gaussian gridding (Greengard and Lee) in x, z and theta = arccos(y/H)
+ * (T_n(y/H) = cos(n theta)): oversampling 2 in each variable and msp nodes
+ * on each side of the target (error about exp(-0.75 pi msp): msp = 12 for
+ * FP64, 6 for the mixed modes). */
 enum ggem_interp { GGEM_INTERP_LAGRANGE = 0, GGEM_INTERP_SPECTRAL = 1 };
 
 /* Select the off-mesh evaluation for the following single- and double-layer
  * evaluations of the plan (and everything built on them: rigid particles,
- * Fredholm solves).  GGEM_INTERP_SPECTRAL allocates the oversampled grid
- * here (6 Ny (2 Nx)(2 Nz) reals and their padded spectra, in the plan's
- * precision; one hipMalloc, freed by the next call or ggem_plan_destroy);
+ * Fredholm solves).  GGEM_INTERP_SPECTRAL allocates the oversampled grids
+ * here (6 Ny (2 Nx)(2 Nz) reals, their padded spectra and 6 (2 Ny)(2 Nx)(2 Nz)
+ * reals on the theta grid, in the plan's precision; one hipMalloc, freed by
+ * the next call or ggem_plan_destroy);
  * GGEM_INTERP_LAGRANGE (the default) frees it.  msp: 2..16, at most Nx and
  * Nz (ignored for GGEM_INTERP_LAGRANGE).  Waits for the plan's streams.
  * Probes (ggem_probe) keep the Lagrange stencil.  Errors: GGEM_E_ARG (mode,

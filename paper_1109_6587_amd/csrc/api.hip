@@ -154,8 +154,7 @@ void free_over(Plan& p) {
   if (p.over_block) (void)hipFree(p.over_block);
   delete p.over;
   p.over = nullptr;
-  p.over_block = p.over_spec = p.over_phys = p.over_t = nullptr;
-  p.over_s = 0;
+  p.over_block = p.over_spec = p.over_phys = p.over_theta = p.cth = nullptr;
   p.interp_mode = GGEM_INTERP_LAGRANGE;
 }
 
@@ -478,7 +477,8 @@ int evaluate(Plan& p, long long ns, const double* xs, const double* f, long long
       HIP_TRY(launch_nufft_pad<T>(p, nf));
       p.over->stream = p.stream;
       HIP_TRY(launch_fft_inverse<T>(*p.over, p.over_spec, p.over_phys, nf * Ny));
-      if (p.over_s) HIP_TRY(launch_nufft_transpose<T>(p, nf));
+      HIP_TRY(launch_row_gemm<T>(p, (const T*)p.cth, p.th_kp, Ny, p.th_planes, p.over_phys,
+                                 p.over_theta, 4L * p.p.Nx * p.p.Nz, nf));
     } else {
       {
         StageScope s(p, GGEM_STAGE_CHEB_INV);
@@ -845,17 +845,13 @@ extern "C" int ggem_plan_set_interp(ggem_plan_t plan, int mode, int msp) {
   (void)sz.take_bytes(2 * (size_t)Mz * elt);
   (void)sz.take_bytes(6 * (size_t)Ny * Mx * o->Nzh * 2 * elt);
   (void)sz.take_bytes(6 * (size_t)Ny * Mx * Mz * elt);
-  // the transposed copy with its z halo, for the FP32 grid when the window
-  // rows fit the gather's register budget (16 loads of 16 bytes per lane and
-  // row).  An FP64 grid keeps the gather of the untransposed planes: its
-  // window rows are read at the same rate either way (the transposed rows
-  // measured 2.12 against 1.60 ms on 32,100 targets, msp 12).
-  const int V = (int)(16 / elt), W = 2 * msp;
-  const int nyp = (Ny + V - 1) / V * V, zp = Mz + W;
-  const int S = (W * nyp + 64 * V - 1) / (64 * V);
-  const int Sb = p.fp64 ? 0 : (S <= 2 ? 2 : (S <= 4 ? 4 : (S <= 8 ? 8 : (S <= 16 ? 16 : 0))));
-  const size_t tbytes = Sb ? (6 * (size_t)Mx * zp * nyp + 64 * (size_t)Sb * V) * elt : 0;
-  if (Sb) (void)sz.take_bytes(tbytes);
+  // theta = arccos(y/H): the Chebyshev series is the even Fourier series
+  // sum_n a_n cos(n theta), band |n| <= Ny - 1, gridded on th_m = 2 (2N + 1)
+  // nodes; planes j = 0 .. th_m/2 are stored, the rest by symmetry
+  const int Nc = Ny - 1, thm = 2 * (2 * Nc + 1), thp = thm / 2 + 1;
+  const int kp = (Ny + 3) / 4 * 4, rows = (thp + 143) / 144 * 144;
+  (void)sz.take_bytes(6 * (size_t)thp * Mx * Mz * elt);
+  (void)sz.take_bytes((size_t)rows * kp * elt);
   if (hipMalloc(&p.over_block, sz.off) != hipSuccess) {
     p.over_block = nullptr;
     delete o;
@@ -867,14 +863,33 @@ extern "C" int ggem_plan_set_interp(ggem_plan_t plan, int mode, int msp) {
   o->twz = c.take_bytes(2 * (size_t)Mz * elt);
   p.over_spec = c.take_bytes(6 * (size_t)Ny * Mx * o->Nzh * 2 * elt);
   p.over_phys = c.take_bytes(6 * (size_t)Ny * Mx * Mz * elt);
-  p.over_t = Sb ? c.take_bytes(tbytes) : nullptr;
-  p.over_zp = zp;
-  p.over_nyp = nyp;
-  p.over_s = Sb;
-  // the slack after the last row is read with zero weights: keep it finite
-  if (Sb && hipMemset(p.over_t, 0, tbytes) != hipSuccess) {
-    free_over(p);
-    return fail(GGEM_E_DEVICE, "clearing the oversampled grid failed");
+  p.over_theta = c.take_bytes(6 * (size_t)thp * Mx * Mz * elt);
+  p.cth = c.take_bytes((size_t)rows * kp * elt);
+  p.th_m = thm;
+  p.th_planes = thp;
+  p.th_kp = kp;
+  p.tau_th = M_PI * msp / (3.0 * (2.0 * Nc + 1.0) * (2.0 * Nc + 1.0));
+  {
+    // cth[j][n] = (1/th_m) sqrt(pi/tau) exp(n^2 tau) cos(2 pi n j / th_m): the
+    // deconvolved coefficients summed on the theta grid (zero padded rows)
+    std::vector<double> m((size_t)rows * kp, 0.0);
+    const double sc = sqrt(M_PI / p.tau_th) / thm;
+    for (int j = 0; j < thp; ++j)
+      for (int n = 0; n < Ny; ++n) {
+        const long q = (2L * n * j) % (2L * thm);  // cos(pi q / th_m), q reduced exactly
+        m[(size_t)j * kp + n] = sc * exp((double)n * n * p.tau_th) * cos(M_PI * (double)q / thm);
+      }
+    hipError_t e;
+    if (p.fp64) {
+      e = hipMemcpy(p.cth, m.data(), m.size() * 8, hipMemcpyHostToDevice);
+    } else {
+      std::vector<float> mf(m.begin(), m.end());
+      e = hipMemcpy(p.cth, mf.data(), mf.size() * 4, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+      free_over(p);
+      return fail(GGEM_E_DEVICE, "%s", hipGetErrorString(e));
+    }
   }
   std::vector<double> tw(2 * (size_t)(Mx > Mz ? Mx : Mz));
   std::vector<float> tf(tw.size());

@@ -138,10 +138,12 @@ struct Plan {
   void* over_block;   // its device buffers (one allocation of their own):
   void* over_spec;    //   padded spectra (6 x Ny x 2Nx x (Nz+1), complex T)
   void* over_phys;    //   oversampled fields (6 x Ny x 2Nx x 2Nz, T)
-  void* over_t;       //   the same, [field][X][Z + halo][n] (null: no such copy)
-  int over_zp;        // Z extent of over_t: 2 Nz + 2 msp (periodic halo)
-  int over_nyp;       // n extent of over_t: Ny padded to 16 bytes
-  int over_s;         // 16-byte loads per lane and window row in spectral_eval
+  void* over_theta;   //   the fields on the oversampled theta grid (6 x th_planes x 2Nx x 2Nz, T)
+  void* cth;          // theta transform (th_rows x th_kp, T): deconvolution, cosines, 1/M_theta
+  int th_m;           // oversampled theta nodes over [0, 2 pi): 2 (2 (Ny - 1) + 1)
+  int th_planes;      // stored theta planes j = 0 .. th_m / 2 (the series is even in theta)
+  int th_kp;          // columns of cth (Ny padded to 4)
+  double tau_th;      // Gaussian width in theta
 };
 
 // ---- 4th-order Lagrange interpolation (Sec. 3.2.2), shared by the
@@ -219,7 +221,8 @@ long long solver_max_tri(ggem_solver_t s);
 template <typename T>
 hipError_t launch_nufft_pad(Plan& p, int nf);
 template <typename T>
-hipError_t launch_nufft_transpose(Plan& p, int nf);
+hipError_t launch_row_gemm(Plan& p, const T* A, int KP, int Kin, int Mout, const void* in,
+                           void* out, long ncols, int nfields);
 template <typename T>
 hipError_t launch_spectral_eval(Plan& p, int nt, double* out, bool stress);
 

@@ -39,16 +39,19 @@ struct Acc<float> {
   using t = f4;
 };
 
-// out[f][r][c] = sum_k A[r][k] in[f][k][c];  A is MP x KP, zero padded.
+// out[f][r][c] = sum_k A[r][k] in[f][k][c] for k < Kin, r < Mout; A is
+// zero padded to KP columns and to whole 16-row tiles; blockIdx.z takes the
+// rows from 16 RT blockIdx.z on (one z block when Mout <= 16 RT).
 template <typename T, int RT>
-__global__ void __launch_bounds__(256) cheb_gemm(const T* __restrict__ A, int MP, int KP, int Ny,
+__global__ void __launch_bounds__(256) cheb_gemm(const T* __restrict__ A, int KP, int Kin, int Mout,
                                                  const T* __restrict__ in, T* __restrict__ out,
                                                  long ncols) {
   using V = typename Acc<T>::t;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const size_t fstride = (size_t)Ny * ncols;
-  const T* src = in + blockIdx.y * fstride;
-  T* dst = out + blockIdx.y * fstride;
+  const int r0 = blockIdx.z * 16 * RT;
+  const T* src = in + blockIdx.y * (size_t)Kin * ncols;
+  T* dst = out + blockIdx.y * (size_t)Mout * ncols;
+  A += (size_t)r0 * KP;
   const long col0 = (long)blockIdx.x * (4 * 16 * kColTiles) + wave * 16 * kColTiles;
   const int li = lane & 15, lk = lane >> 4;
   V acc[RT][kColTiles];
@@ -62,7 +65,7 @@ __global__ void __launch_bounds__(256) cheb_gemm(const T* __restrict__ A, int MP
 #pragma unroll
     for (int c = 0; c < kColTiles; ++c) {
       const long col = col0 + c * 16 + li;
-      b[c] = (k < Ny && col < ncols) ? src[(size_t)k * ncols + col] : (T)0;
+      b[c] = (k < Kin && col < ncols) ? src[(size_t)k * ncols + col] : (T)0;
     }
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
@@ -80,8 +83,8 @@ __global__ void __launch_bounds__(256) cheb_gemm(const T* __restrict__ A, int MP
       for (int v = 0; v < 4; ++v) {
         // accumulator layout: FP32 16x16x4 holds rows 4*(lane/16)+v of column
         // lane%16; FP64 16x16x4 holds rows lane/16 + 4*v.
-        const int row = t * 16 + (sizeof(T) == 8 ? lk + 4 * v : 4 * lk + v);
-        if (row < Ny && col < ncols) dst[(size_t)row * ncols + col] = acc[t][c][v];
+        const int row = r0 + t * 16 + (sizeof(T) == 8 ? lk + 4 * v : 4 * lk + v);
+        if (row < Mout && col < ncols) dst[(size_t)row * ncols + col] = acc[t][c][v];
       }
     }
 }
@@ -217,7 +220,7 @@ hipError_t launch_cheb(Plan& p, const void* in, void* out, int nfields, bool for
   switch (rt) {
 #define GGEM_CASE(R)                                                                            \
   case R:                                                                                       \
-    cheb_gemm<T, R><<<grid, 256, 0, p.stream>>>(A, MP, KP, Ny, (const T*)in, (T*)out, ncols); \
+    cheb_gemm<T, R><<<grid, 256, 0, p.stream>>>(A, KP, Ny, Ny, (const T*)in, (T*)out, ncols); \
     break;
     GGEM_CASE(1)
     GGEM_CASE(2)
@@ -235,6 +238,41 @@ hipError_t launch_cheb(Plan& p, const void* in, void* out, int nfields, bool for
   return hipGetLastError();
 }
 
+// out[f][r][c] = sum_k A[r][k] in[f][k][c], r < Mout, k < Kin, c < ncols
+// real columns; A row-major with KP columns and rows padded to a multiple
+// of 144 (nine 16-row tiles per block row).
+template <typename T>
+hipError_t launch_row_gemm(Plan& p, const T* A, int KP, int Kin, int Mout, const void* in,
+                           void* out, long ncols, int nfields) {
+  const unsigned zb = (unsigned)((Mout + 16 * kMaxRowTiles - 1) / (16 * kMaxRowTiles));
+  const int rt = Mout <= 16 * kMaxRowTiles ? (Mout + 15) / 16 : kMaxRowTiles;
+  dim3 grid((unsigned)((ncols + 4 * 16 * kColTiles - 1) / (4 * 16 * kColTiles)), nfields, zb);
+  switch (rt) {
+#define GGEM_CASE(R)                                                                      \
+  case R:                                                                                 \
+    cheb_gemm<T, R><<<grid, 256, 0, p.stream>>>(A, KP, Kin, Mout, (const T*)in, (T*)out, \
+                                                ncols);                                   \
+    break;
+    GGEM_CASE(1)
+    GGEM_CASE(2)
+    GGEM_CASE(3)
+    GGEM_CASE(4)
+    GGEM_CASE(5)
+    GGEM_CASE(6)
+    GGEM_CASE(7)
+    GGEM_CASE(8)
+    GGEM_CASE(9)
+#undef GGEM_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_row_gemm<double>(Plan&, const double*, int, int, int, const void*,
+                                            void*, long, int);
+template hipError_t launch_row_gemm<float>(Plan&, const float*, int, int, int, const void*, void*,
+                                           long, int);
 template hipError_t launch_cheb<double>(Plan&, const void*, void*, int, bool);
 template hipError_t launch_cheb<float>(Plan&, const void*, void*, int, bool);
 
