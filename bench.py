@@ -249,6 +249,37 @@ def roofline_entry(stage, stage_ms, work_units, flop, peak, traffic):
             "flop_per_unit": flop}
 
 
+def step_roofline(c, precision, dl, near_units, spread_units, ms):
+    """Whole-step roofline: T_ideal = sum over the stages of max(flop /
+    peak, bytes / 8 TB/s) with the kernel-counted pairs and updates (the local
+    sum and the spread are ALU-bound) and the grid stages' algorithmic bytes
+    (each field read and written once per pass: z and x FFTs, Chebyshev
+    products, tau coefficients in and out, interpolation); the fraction is
+    T_ideal / T_measured.  The wall data's local sum and the binning are left
+    out (a smaller T_ideal, a lower fraction)."""
+    fp64 = precision == "fp64"
+    peak = (PEAK_FP64_TFLOPS if fp64 else PEAK_FP32_TFLOPS) * 1e12
+    e = 8 if fp64 else 4
+    nf = 6 if dl else 3
+    n3 = c.Ny * c.Nx * c.Nz                  # real nodes per field
+    nh = c.Ny * c.Nx * (c.Nz // 2 + 1)       # complex coefficients per field
+    grid = {
+        "fft_fwd": 3 * (n3 * e + nh * 2 * e) + 3 * (2 * nh * 2 * e),
+        "cheb_fwd": 3 * 2 * nh * 2 * e,
+        "tau": 3 * nh * 2 * e + nf * nh * 2 * e,
+        "cheb_inv": nf * 2 * nh * 2 * e,
+        "fft_inv": nf * (2 * nh * 2 * e) + nf * (nh * 2 * e + n3 * e),
+        "interp": nf * n3 * e + c.nt * 24,
+    }
+    terms = {"near": near_units * (FLOP_NEAR_DL if dl else FLOP_NEAR_SL) / peak * 1e3,
+             "spread": spread_units * FLOP_SPREAD / peak * 1e3}
+    terms.update({k: v / (PEAK_HBM_GBS * 1e9) * 1e3 for k, v in grid.items()})
+    t = sum(terms.values())
+    return {"t_ideal_ms": round(t, 4), "t_measured_ms": round(ms, 4), "frac": round(t / ms, 4),
+            "terms_ms": {k: round(v, 4) for k, v in terms.items()},
+            "grid_bytes": sum(grid.values())}
+
+
 def measure_case(c, args, precision, with_other=True, golden_parts=True):
     """Mixed (or FP64) evaluation of one case: throughput, the roofline of
     the local sum and of the spread, errors against the other precision and
@@ -328,6 +359,7 @@ def measure_case(c, args, precision, with_other=True, golden_parts=True):
     for st, sms in ((stage, stage_ms), (side, side_ms)):
         units, flop = (near_units, flop_near) if st == "near" else (spread_units, FLOP_SPREAD)
         rl[st] = roofline_entry(st, sms, units, flop, peak, measured_traffic(st, c.name, precision))
+    res["roofline_step"] = step_roofline(c, precision, dl, near_units, spread_units, ms)
     res.update(ms=ms, mpts=c.nt / (ms * 1e-3) / 1e6, stage=stage, roofline=rl[stage],
                roofline_other=rl[side], work={"near_pairs": near_units,
                                               "spread_updates": spread_units})
@@ -871,7 +903,7 @@ def bench_single(args):
                      config)
     for k in ("err_vs_oracle", "err_vs_fp64", "fp64_ms_per_step", "fp64_mpoints_per_s",
               "mixed_ms_per_step", "mixed_mpoints_per_s", "speedup_mixed_vs_fp64", "work",
-              "roofline_other"):
+              "roofline_other", "roofline_step"):
         if k in r:
             line[k] = r[k]
     line["roofline"] = r["roofline"]
