@@ -461,8 +461,30 @@ def extra_small(args):
         o = out.cpu().numpy()
         if p == "fp64":
             ref = o
+        # the same call captured once into a HIP graph on a side stream and
+        # replayed (one submission instead of about 30 launches)
+        st = torch.cuda.Stream()
+        plan.set_stream(st)
+        with torch.cuda.stream(st):
+            call()
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=st):
+            call()
+        for _ in range(20):
+            graph.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(200):
+            graph.replay()
+        torch.cuda.synchronize()
+        us_graph = (time.perf_counter() - t0) / 200 * 1e6
+        plan.status()
+        graph_err = float(np.abs(out.cpu().numpy() - o).max())
         res[p] = {"us_per_call_back_to_back": round(ms * 1e3, 2),
-                  "us_per_call_synchronised_median": round(statistics.median(lat), 2)}
+                  "us_per_call_synchronised_median": round(statistics.median(lat), 2),
+                  "us_per_call_graph_replay": round(us_graph, 2),
+                  "graph_replay_max_abs_diff": graph_err}
         if p == "mixed":
             res[p]["rel_l2_vs_fp64"] = rel_l2(o, ref)
         plan.close()

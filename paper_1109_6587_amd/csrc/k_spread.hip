@@ -99,7 +99,7 @@ __device__ inline void lds_wave_sync() {
 //
 // CNT: count the (source, node) pairs within r_c into a.work.
 template <typename T, bool REL, bool CNT>
-__global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
+__global__ void __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1))) spread_tile(SpreadArgs a) {
   using Q = typename V4<T>::t;
   __shared__ double lx[REL ? 1 : 4][64], ly[REL ? 1 : 4][64], lz[REL ? 1 : 4][64];
   // REL: per wave the both-halves list [0, 64) and the low-only and
@@ -107,6 +107,7 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
   __shared__ Q lr[REL ? 4 : 1][REL ? kSlot : 64];
   __shared__ Q lf[4][REL ? kSlot : 64];
   __shared__ T red[NW - 1][6][64];
+  __shared__ int desc0[5 * 64];
   __shared__ unsigned cnt_w[NW];
   const CellGeom& g = a.g;
   const int lane = threadIdx.x & 63;
@@ -226,31 +227,75 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
     }
     n = rem;
   };
-  for (int cy = cy0; cy <= cy1; ++cy) {
-    const double ylo = cy / g.icy - g.H, yhi = (cy + 1) / g.icy - g.H;
-    const double gyc = fmax(0.0, fmax(ylo - by1, by0 - yhi) - eps);
-    for (int cxu = cx0; cxu <= cx1; ++cxu) {
+  // The rows are described in parallel, one lane per row (64 at a time):
+  // its one or two runs of z slabs and their batch counts; an inclusive scan
+  // of the counts numbers the batches in walk order, and the wave then takes
+  // its own batches (walk number mod 4) without visiting the rows one by one.
+  // A sparse tile thus pays one round of bucket loads, not one per row.  The
+  // descriptors go to LDS (registers would cost occupancy): wave 0's to its
+  // own slice, the others' to their reduction slot, which they write only
+  // after their last batch.
+  int* const rd = wave == 0 ? desc0 : reinterpret_cast<int*>(&red[wave - 1][0][0]);
+  const int ncxr = cx1 - cx0 + 1;
+  const int nrows = (cy1 - cy0 + 1) * ncxr;
+  for (int r0 = 0; r0 < nrows; r0 += 64) {
+    int sa0 = 0, sa1 = 0, sb0 = 0, sb1 = 0;
+    if (r0 + lane < nrows) {
+      const int cy = cy0 + (r0 + lane) / ncxr, cxu = cx0 + (r0 + lane) % ncxr;
+      const double ylo = cy / g.icy - g.H, yhi = (cy + 1) / g.icy - g.H;
+      const double gyc = fmax(0.0, fmax(ylo - by1, by0 - yhi) - eps);
       const int cx = ((cxu % g.ncx) + g.ncx) % g.ncx;
       const double xlo = cx / g.icx, xhi = (cx + 1) / g.icx;
       const double gxc = fmax(
           0.0, fabs(min_image_s(0.5 * (xlo + xhi) - cbx, g.Lx, g.invLx)) - 0.5 * (xhi - xlo) - hbx - eps);
       const double h2 = rc2m - (gxc * gxc + gyc * gyc);
-      if (h2 < 0.0) continue;
-      const double hz = sqrt(h2) + eps;
-      int fa = (int)floor((bz0 - hz) * szs), fb = (int)floor((bz1 + hz) * szs);
-      if (fb - fa + 1 >= nzf) {
-        fa = 0;
-        fb = nzf - 1;
+      if (h2 >= 0.0) {
+        const double hz = sqrt(h2) + eps;
+        int fa = (int)floor((bz0 - hz) * szs), fb = (int)floor((bz1 + hz) * szs);
+        if (fb - fa + 1 >= nzf) {
+          fa = 0;
+          fb = nzf - 1;
+        }
+        const int fl0 = ((fa % nzf) + nzf) % nzf, flen = fb - fa + 1;
+        const int row = (cy * g.ncx + cx) * nzf;
+        if (fl0 + flen > nzf) {  // the window wraps: slabs fl0..nzf-1, then 0..
+          sa0 = a.scell[row + fl0];
+          sa1 = a.scell[row + nzf];
+          sb0 = a.scell[row];
+          sb1 = a.scell[row + fl0 + flen - nzf];
+        } else {
+          sa0 = a.scell[row + fl0];
+          sa1 = a.scell[row + fl0 + flen];
+        }
       }
-      const int fl0 = ((fa % nzf) + nzf) % nzf, flen = fb - fa + 1;
-      const int nseg = fl0 + flen > nzf ? 2 : 1;
-      const int row = (cy * g.ncx + cx) * nzf;
-      for (int sg = 0; sg < nseg; ++sg) {
-        const int lo = sg == 0 ? fl0 : 0;
-        const int hi = sg == 0 ? (nseg == 2 ? nzf - 1 : fl0 + flen - 1) : fl0 + flen - 1 - nzf;
-        const int s0 = a.scell[row + lo], s1 = a.scell[row + hi + 1];
-        for (int b = s0; b < s1; b += 64) {
-          if (bc++ % NW != wave) continue;
+    }
+    int bend = ((sa1 - sa0 + 63) >> 6) + ((sb1 - sb0 + 63) >> 6);
+    for (int o = 1; o < 64; o <<= 1) {  // inclusive prefix of the batch counts
+      const int v = __shfl_up(bend, o);
+      if (lane >= o) bend += v;
+    }
+    const int nun = __builtin_amdgcn_readlane(bend, 63);
+    rd[lane] = bend;
+    rd[64 + lane] = sa0;
+    rd[128 + lane] = sa1;
+    rd[192 + lane] = sb0;
+    rd[256 + lane] = sb1;
+    lds_wave_sync();
+    int cc = 0;  // the row of the current batch (uniform, advances monotonically)
+    int rend = __builtin_amdgcn_readfirstlane(rd[0]), rbeg = 0;
+    for (int u = ((wave - bc) % NW + NW) % NW; u < nun; u += NW) {
+      while (u >= rend) {
+        rbeg = rend;
+        rend = __builtin_amdgcn_readfirstlane(rd[++cc]);
+      }
+      const int ra0 = __builtin_amdgcn_readfirstlane(rd[64 + cc]);
+      const int ra1 = __builtin_amdgcn_readfirstlane(rd[128 + cc]);
+      const int na = (ra1 - ra0 + 63) >> 6;
+      const int lb = u - rbeg;
+      const int b = lb < na ? ra0 + 64 * lb : __builtin_amdgcn_readfirstlane(rd[192 + cc]) + 64 * (lb - na);
+      const int s1 = lb < na ? ra1 : __builtin_amdgcn_readfirstlane(rd[256 + cc]);
+      {
+        {
           // the batch's sources within r_c of the tile's box, compacted; REL
           // sorts them by the z half (nodes k_lo..k_lo+3, k_lo+4..k_lo+7)
           // they can reach
@@ -388,6 +433,8 @@ __global__ void __launch_bounds__(TB) spread_tile(SpreadArgs a) {
         }
       }
     }
+    bc += nun;
+    lds_wave_sync();  // the descriptors are read before the next chunk's
   }
   if constexpr (REL) {
     half_pass(64, cl, nrz, fx, fy, fz, true);
