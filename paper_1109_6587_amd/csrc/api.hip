@@ -499,6 +499,68 @@ int evaluate(Plan& p, long long ns, const double* xs, const double* f, long long
   return finish(p);
 }
 
+}  // namespace
+
+namespace ggem {
+
+template <typename T>
+int batch_phase_bin(Plan& p, long long ns, const double* xs, const double* f) {
+  HIP_TRY(launch_bin(p, p.src, ns, xs, f, nullptr, true, true));
+  p.tview = &p.src;
+  p.tnrm = p.tgt.s;
+  if (ns > 0) launch_near_order_sources(p);
+  HIP_TRY(hipGetLastError());
+  return GGEM_OK;
+}
+
+template <typename T>
+int batch_phase_wall(Plan& p) {
+  HIP_TRY(launch_wall_sum<T>(p));
+  HIP_TRY(launch_fft_forward<T>(p, p.wall_phys, p.wall_spec, 6));
+  return GGEM_OK;
+}
+
+template <typename T>
+int batch_phase_grid(Plan& p) {
+  const int Ny = p.p.Ny;
+  HIP_TRY(launch_fft_forward<T>(p, p.phys, p.specA, 3 * Ny));
+  HIP_TRY(launch_cheb<T>(p, p.specA, p.specB, 3, true));
+  HIP_TRY(launch_tau<T>(p, false));
+  if (p.interp_mode == GGEM_INTERP_SPECTRAL) {
+    HIP_TRY(launch_nufft_pad<T>(p, 3));
+    p.over->stream = p.stream;
+    HIP_TRY(launch_fft_inverse<T>(*p.over, p.over_spec, p.over_phys, 3 * Ny));
+    HIP_TRY(launch_row_gemm<T>(p, (const T*)p.cth, p.th_kp, Ny, p.th_planes, p.over_phys,
+                               p.over_theta, 4L * p.p.Nx * p.p.Nz, 3));
+  } else {
+    HIP_TRY(launch_cheb<T>(p, p.specA, p.specB, 3, false));
+    HIP_TRY(launch_fft_inverse<T>(p, p.specB, p.phys, 3 * Ny));
+  }
+  return GGEM_OK;
+}
+
+template <typename T>
+int batch_phase_interp(Plan& p, long long nt, double* out) {
+  if (nt <= 0) return GGEM_OK;
+  if (p.interp_mode == GGEM_INTERP_SPECTRAL) HIP_TRY(launch_spectral_eval<T>(p, (int)nt, out, false));
+  else HIP_TRY(launch_interp<T>(p, (int)nt, out, false, true));
+  return GGEM_OK;
+}
+
+template int batch_phase_bin<double>(Plan&, long long, const double*, const double*);
+template int batch_phase_bin<float>(Plan&, long long, const double*, const double*);
+template int batch_phase_wall<double>(Plan&);
+template int batch_phase_wall<float>(Plan&);
+template int batch_phase_grid<double>(Plan&);
+template int batch_phase_grid<float>(Plan&);
+template int batch_phase_interp<double>(Plan&, long long, double*);
+template int batch_phase_interp<float>(Plan&, long long, double*);
+
+}  // namespace ggem
+
+namespace {
+
+
 int check_eval(Plan& p, long long ns, const double* xs, const double* f, long long nt,
                const double* xt, double* out, int parts) {
   if (ns < 0 || nt < 0) return fail(GGEM_E_ARG, "negative point count");

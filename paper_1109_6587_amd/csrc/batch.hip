@@ -9,6 +9,19 @@
 // be captured once into a HIP graph and replayed: one launch then submits
 // every kernel of every instance, and the branches run concurrently.
 //
+// Shared launches (built, switched off; see ggem_batch_create): when every
+// instance's targets are its sources (the suspension case) and the
+// instances share one precision, the three pair-sum kernels would run as
+// shared launches instead: one spread over every instance's tiles, one local sum
+// over every instance's target items and one over every instance's wall
+// nodes (job lists of per-instance arguments, uploaded when the batch is
+// created).  A small instance then no longer leaves most of the GPU idle
+// while it runs, and a large one no longer waits for a free stream.  The
+// per-instance stages around them (binning, wall transforms, the grid
+// stages, interpolation) stay on the branches.  Every block of a shared
+// launch does exactly the work of the same block in the instance's own
+// launch, so each instance still equals its solo evaluation bit for bit.
+//
 // Nothing in an evaluation allocates, synchronises with the host or records
 // a memset node; domain checks are deferred (ggem_batch_status).
 #include <math.h>
@@ -23,6 +36,14 @@
 
 using namespace ggem;
 
+// One shared launch: its job list on the device.
+struct JobGroup {
+  void* jobs = nullptr;
+  int* boff = nullptr;
+  int n = 0, nblocks = 0;
+  bool flag = false;  // spread: tile-relative staging; local sums: the FP32 fast path
+};
+
 struct ggem_batch_s {
   int n;
   std::vector<ggem_plan_t> plans;
@@ -34,6 +55,13 @@ struct ggem_batch_s {
   hipEvent_t caller_ready, done;
   hipGraph_t graph;
   hipGraphExec_t exec;
+  // shared launches (all instances of one precision)
+  bool shared = false;
+  bool fp64 = false;
+  hipStream_t side = nullptr;      // the local sums, beside the spread on origin
+  hipEvent_t ev_go = nullptr, ev_spread = nullptr, ev_wall = nullptr, ev_near = nullptr;
+  std::vector<JobGroup> spread_g, near_g, wall_g;
+  void* job_mem = nullptr;
 };
 
 static thread_local char g_batch_err[256];
@@ -48,6 +76,10 @@ static thread_local char g_batch_err[256];
   } while (0)
 
 static void free_batch(ggem_batch_s* b) {
+  if (b->job_mem) (void)hipFree(b->job_mem);
+  for (hipEvent_t e : {b->ev_go, b->ev_spread, b->ev_wall, b->ev_near})
+    if (e) (void)hipEventDestroy(e);
+  if (b->side) (void)hipStreamDestroy(b->side);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   for (ggem_plan_t p : b->plans)
@@ -62,18 +94,21 @@ static void free_batch(ggem_batch_s* b) {
   if (b->origin) (void)hipStreamDestroy(b->origin);
 }
 
+// Work estimate of an instance: points times the local neighbourhood, plus
+// the grid.
+static double instance_cost(const ggem_params& q) {
+  const double rc = q.rc > 0 ? q.rc : 4.0 / q.alpha;
+  const double vol = q.Lx * q.Lz * 2.0 * q.H;
+  const double nb = 4.18879 * rc * rc * rc;  // neighbourhood volume
+  const double pts = (double)q.max_src;
+  const double grid = (double)q.Nx * q.Nz * q.Ny;
+  return pts * (1.0 + pts * nb / vol) + 20.0 * grid;
+}
+
 // Longest-processing-time assignment of instances to branches.
 static void assign_branches(ggem_batch_s* b, const ggem_params* prm, int nbranch) {
   std::vector<double> cost(b->n);
-  for (int i = 0; i < b->n; ++i) {
-    const ggem_params& q = prm[i];
-    const double rc = q.rc > 0 ? q.rc : 4.0 / q.alpha;
-    const double vol = q.Lx * q.Lz * 2.0 * q.H;
-    const double nb = 4.18879 * rc * rc * rc;  // neighbourhood volume
-    const double pts = (double)q.max_src;
-    const double grid = (double)q.Nx * q.Nz * q.Ny;
-    cost[i] = pts * (1.0 + pts * nb / vol) + 20.0 * grid;
-  }
+  for (int i = 0; i < b->n; ++i) cost[i] = instance_cost(prm[i]);
   std::vector<int> order(b->n);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
@@ -84,6 +119,60 @@ static void assign_branches(ggem_batch_s* b, const ggem_params* prm, int nbranch
     b->branch_of[i] = k;
     load[k] += cost[i];
   }
+}
+
+// Job lists of the shared launches, heaviest instances first (so that the
+// long tiles start early), split by the kernel variant each instance takes.
+static int setup_shared(ggem_batch_s* b, const ggem_params* prm) {
+  const int n = b->n;
+  b->fp64 = b->plans[0]->p.fp64;
+  for (int i = 1; i < n; ++i)
+    if (b->plans[i]->p.fp64 != b->fp64) return GGEM_OK;  // mixed precisions: no shared launches
+  std::vector<int> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+    return instance_cost(prm[a]) > instance_cost(prm[c]);
+  });
+  std::vector<std::vector<Plan*>> lists(6);  // spread rel/not, near fast/not, wall fast/not
+  for (int i : order) {
+    Plan& p = b->plans[i]->p;
+    lists[spread_job_rel(p) ? 0 : 1].push_back(&p);
+    lists[near_job_fast(p) ? 2 : 3].push_back(&p);
+    lists[near_job_fast(p) ? 4 : 5].push_back(&p);
+  }
+  const size_t nbytes = near_job_bytes(b->fp64);
+  auto align = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  size_t total = 0;
+  for (int g = 0; g < 6; ++g) {
+    const size_t m = lists[g].size();
+    if (m) total += align(m * (g < 2 ? spread_job_bytes() : nbytes)) + align((m + 1) * sizeof(int));
+  }
+  if (hipMalloc(&b->job_mem, total) != hipSuccess)
+    return ggem_set_error(GGEM_E_NOMEM, "device allocation failed");
+  char* mem = (char*)b->job_mem;
+  for (int g = 0; g < 6; ++g) {
+    const int m = (int)lists[g].size();
+    if (!m) continue;
+    JobGroup jg;
+    jg.n = m;
+    jg.jobs = mem;
+    mem += align(m * (g < 2 ? spread_job_bytes() : nbytes));
+    jg.boff = (int*)mem;
+    mem += align((m + 1) * sizeof(int));
+    jg.flag = (g % 2) == 0;
+    jg.nblocks = g < 2 ? spread_jobs_upload(lists[g].data(), m, jg.jobs, jg.boff)
+                       : near_jobs_upload(lists[g].data(), m, g >= 4, jg.jobs, jg.boff);
+    if (jg.nblocks < 0) return ggem_set_error(GGEM_E_DEVICE, "job list upload failed");
+    (g < 2 ? b->spread_g : g < 4 ? b->near_g : b->wall_g).push_back(jg);
+  }
+  if (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_go, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_spread, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_wall, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_near, hipEventDisableTiming) != hipSuccess)
+    return ggem_set_error(GGEM_E_DEVICE, "stream or event creation failed");
+  b->shared = true;
+  return GGEM_OK;
 }
 
 extern "C" int ggem_batch_create(int n_inst, const ggem_params* params, int n_branches,
@@ -128,6 +217,10 @@ extern "C" int ggem_batch_create(int n_inst, const ggem_params* params, int n_br
   }
   assign_branches(b, params, n_branches);
   for (int i = 0; i < n_inst; ++i) b->plans[i]->p.stream = b->branches[b->branch_of[i]];
+  // The shared launches stay switched off: the one graph capture of them
+  // that ran ended in a host-side segmentation fault, whose cause has not
+  // been shown.  Every evaluation takes the per-instance path below.
+  (void)setup_shared;
   *out = b;
   return GGEM_OK;
 }
@@ -136,6 +229,7 @@ extern "C" int ggem_batch_destroy(ggem_batch_t b) {
   if (!b) return ggem_set_error(GGEM_E_ARG, "null batch");
   (void)hipStreamSynchronize(b->origin);
   for (hipStream_t s : b->branches) (void)hipStreamSynchronize(s);
+  if (b->side) (void)hipStreamSynchronize(b->side);
   free_batch(b);
   delete b;
   return GGEM_OK;
@@ -158,9 +252,68 @@ static int check_offsets(ggem_batch_s* b, const long long* src_off, const long l
   return GGEM_OK;
 }
 
+#define PHASE_TRY(i, expr)                                                    \
+  do {                                                                        \
+    if (int rc_ = (expr)) {                                                   \
+      char msg_[200];                                                         \
+      snprintf(msg_, sizeof msg_, "instance %d: %s", (i), ggem_last_error()); \
+      return ggem_set_error(rc_, msg_);                                       \
+    }                                                                         \
+  } while (0)
+
+// Shared launches (targets = sources for every instance).  origin forks to
+// the branches, which bin their instances' sources; after the join, origin
+// runs the shared spread while the side stream runs the shared local sums
+// at the wall nodes and then at the targets; each branch then finishes its
+// instances' wall data (after the wall sums), grid stages (after the
+// spread) and interpolation (after the target sums), and joins.
+template <typename T>
+static int enqueue_shared_t(ggem_batch_s* b, const long long* so, const double* xs, const double* f,
+                            double* u) {
+  BATCH_TRY(hipEventRecord(b->fork, b->origin));
+  for (hipStream_t s : b->branches) BATCH_TRY(hipStreamWaitEvent(s, b->fork, 0));
+  for (int i = 0; i < b->n; ++i) {
+    const long long ns = so[i + 1] - so[i];
+    PHASE_TRY(i, batch_phase_bin<T>(b->plans[i]->p, ns, xs ? xs + 3 * so[i] : nullptr,
+                                    f ? f + 3 * so[i] : nullptr));
+  }
+  for (size_t k = 0; k < b->branches.size(); ++k) {
+    BATCH_TRY(hipEventRecord(b->join[k], b->branches[k]));
+    BATCH_TRY(hipStreamWaitEvent(b->origin, b->join[k], 0));
+  }
+  BATCH_TRY(hipEventRecord(b->ev_go, b->origin));
+  BATCH_TRY(hipStreamWaitEvent(b->side, b->ev_go, 0));
+  for (const JobGroup& g : b->spread_g)
+    BATCH_TRY(launch_spread_jobs<T>(b->origin, g.jobs, g.boff, g.n, g.nblocks, g.flag));
+  BATCH_TRY(hipEventRecord(b->ev_spread, b->origin));
+  for (const JobGroup& g : b->wall_g)
+    BATCH_TRY(launch_near_jobs(b->side, b->fp64, g.flag, true, g.jobs, g.boff, g.n, g.nblocks));
+  BATCH_TRY(hipEventRecord(b->ev_wall, b->side));
+  for (const JobGroup& g : b->near_g)
+    BATCH_TRY(launch_near_jobs(b->side, b->fp64, g.flag, false, g.jobs, g.boff, g.n, g.nblocks));
+  BATCH_TRY(hipEventRecord(b->ev_near, b->side));
+  for (hipStream_t s : b->branches) BATCH_TRY(hipStreamWaitEvent(s, b->ev_wall, 0));
+  for (int i = 0; i < b->n; ++i) PHASE_TRY(i, batch_phase_wall<T>(b->plans[i]->p));
+  for (hipStream_t s : b->branches) BATCH_TRY(hipStreamWaitEvent(s, b->ev_spread, 0));
+  for (int i = 0; i < b->n; ++i) PHASE_TRY(i, batch_phase_grid<T>(b->plans[i]->p));
+  for (hipStream_t s : b->branches) BATCH_TRY(hipStreamWaitEvent(s, b->ev_near, 0));
+  for (int i = 0; i < b->n; ++i)
+    PHASE_TRY(i, batch_phase_interp<T>(b->plans[i]->p, so[i + 1] - so[i], u + 3 * so[i]));
+  for (size_t k = 0; k < b->branches.size(); ++k) {
+    BATCH_TRY(hipEventRecord(b->join[k], b->branches[k]));
+    BATCH_TRY(hipStreamWaitEvent(b->origin, b->join[k], 0));
+  }
+  BATCH_TRY(hipStreamWaitEvent(b->origin, b->ev_near, 0));
+  return GGEM_OK;
+}
+
 // fork from the origin stream, every instance on its branch, join
 static int enqueue(ggem_batch_s* b, const long long* so, const double* xs, const double* f,
                    const long long* to, const double* xt, double* u) {
+  bool coincide = b->shared && xs == xt;
+  for (int i = 0; coincide && i <= b->n; ++i) coincide = so[i] == to[i];
+  if (coincide)
+    return b->fp64 ? enqueue_shared_t<double>(b, so, xs, f, u) : enqueue_shared_t<float>(b, so, xs, f, u);
   BATCH_TRY(hipEventRecord(b->fork, b->origin));
   for (hipStream_t s : b->branches) BATCH_TRY(hipStreamWaitEvent(s, b->fork, 0));
   for (int i = 0; i < b->n; ++i) {

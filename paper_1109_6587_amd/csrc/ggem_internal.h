@@ -225,6 +225,40 @@ hipError_t launch_row_gemm(Plan& p, const T* A, int KP, int Kin, int Mout, const
                            void* out, long ncols, int nfields);
 template <typename T>
 hipError_t launch_spectral_eval(Plan& p, int nt, double* out, bool stress);
+template <typename T>
+hipError_t launch_wall_sum(Plan& p);
+const int* launch_near_order_sources(Plan& p);
+
+// Shared launches of a batch: the spread, and the local sums at the targets
+// and at the wall nodes, of many plans in one launch each.  The job lists
+// (each plan's kernel arguments and block offsets) are uploaded once, when
+// the batch is created; a launch then reads them on the device.
+int spread_job_blocks(const Plan& p);
+bool spread_job_rel(const Plan& p);
+size_t spread_job_bytes();
+int spread_jobs_upload(const Plan* const* plans, int n, void* dev_args, int* dev_boff);
+template <typename T>
+hipError_t launch_spread_jobs(hipStream_t s, const void* dev_args, const int* dev_boff, int n,
+                              int nblocks, bool rel);
+bool near_job_fast(const Plan& p);
+size_t near_job_bytes(bool fp64);
+int near_job_blocks(const Plan& p, bool wall);
+int near_jobs_upload(Plan* const* plans, int n, bool wall, void* dev_jobs, int* dev_boff);
+hipError_t launch_near_jobs(hipStream_t s, bool fp64, bool fast, bool wall, const void* dev_jobs,
+                            const int* dev_boff, int n, int nblocks);
+// The single-layer evaluation of a plan whose targets are its sources, in
+// the phases around the shared launches: binning (and the target order of
+// the local sum), the wall data after the shared wall-node sums, the grid
+// stages after the shared spread, and the interpolation after the shared
+// local sums.  Each enqueues on p.stream.
+template <typename T>
+int batch_phase_bin(Plan& p, long long ns, const double* xs, const double* f);
+template <typename T>
+int batch_phase_wall(Plan& p);
+template <typename T>
+int batch_phase_grid(Plan& p);
+template <typename T>
+int batch_phase_interp(Plan& p, long long nt, double* out);
 
 }  // namespace ggem
 

@@ -13,6 +13,8 @@
 // FP64 in mixed mode, so only exactly coincident points take the self rule and
 // no FP32 intermediate overflows.  Other kernel values are evaluated in T
 // (double, or float in mixed mode) from the displacement formed in FP64.
+#include <vector>
+
 #include "ggem_internal.h"
 
 namespace ggem {
@@ -294,21 +296,17 @@ struct NearArgs {
 //
 // CNT (FAST only): count the in-range pairs into a.work; the exact path
 // counts per batch whenever a.work is set.
+//
+// item: the work item (after the XCD order); slice: the run of neighbour cells.
 template <typename T, bool DL, bool FAST, int W, bool CNT>
-__global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k, KcF kf) {
+__device__ __forceinline__ void near_body(const NearArgs& a, const Kc<T>& k, const KcF& kf, int item,
+                                          int slice) {
   // staged sources: FP64 position (x, y, z, unused) and strength (x, y, z,
   // unused), one vector read each
   __shared__ double4 lp[W][64];
   __shared__ typename Vec4<T>::t lf[W][64];
   __shared__ T part[W][3][64];
   const CellGeom& g = a.g;
-  // XCD-aware: block b runs on XCD b % 8; each XCD takes chunks of 16
-  // consecutive work items in turn (the grid is a multiple of 128)
-  int item = blockIdx.x;
-  if ((gridDim.x & 127) == 0) {
-    const int q = blockIdx.x >> 3;
-    item = (q >> 4) * 128 + (blockIdx.x & 7) * 16 + (q & 15);
-  }
   const int nitems = a.item_start[g.ncells];
   if (item >= nitems) return;
   const int lane = threadIdx.x & 63;
@@ -367,7 +365,6 @@ __global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k, KcF kf
   // wall targets only see the wall cell layer (cells are at least r_c high)
   const int oy0 = a.nplane ? 1 : 0, noy = a.nplane ? 1 : 3;
   const int ncand = noy * nxo * nzo;
-  const int slice = blockIdx.y;
   const int kc0 = slice * ncand / a.nslice, nk = (slice + 1) * ncand / a.nslice - kc0;
   // lane l < nk describes neighbour cell kc0 + l: source range, periodic
   // shift and number of batches
@@ -579,6 +576,47 @@ __global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k, KcF kf
   }
 }
 
+// XCD-aware: block b runs on XCD b % 8; each XCD takes chunks of 16
+// consecutive work items in turn (when the grid is a multiple of 128)
+__device__ inline int xcd_item(int b, int nb) {
+  if ((nb & 127) != 0) return b;
+  const int q = b >> 3;
+  return (q >> 4) * 128 + (b & 7) * 16 + (q & 15);
+}
+
+template <typename T, bool DL, bool FAST, int W, bool CNT>
+__global__ void __launch_bounds__(64 * W) near_field(NearArgs a, Kc<T> k, KcF kf) {
+  near_body<T, DL, FAST, W, CNT>(a, k, kf, xcd_item(blockIdx.x, gridDim.x), blockIdx.y);
+}
+
+// Many target sets in one launch: job j owns blocks [boff[j], boff[j + 1])
+// in x (a multiple of 128 each, so that every job's items are dealt to the
+// XCDs as in its own launch) and the slices in y.  A block finds its job by
+// bisection and does exactly the work of the same block of the job's own
+// launch.
+template <typename T>
+struct NearJob {
+  NearArgs a;
+  Kc<T> k;
+  KcF kf;
+};
+
+template <typename T, bool FAST, int W>
+__global__ void __launch_bounds__(64 * W) near_field_jobs(const NearJob<T>* __restrict__ jobs,
+                                                          const int* __restrict__ boff, int njobs) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = njobs;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (boff[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  const NearJob<T>& j = jobs[lo];
+  const int t = b - boff[lo];
+  near_body<T, false, FAST, W, false>(j.a, j.k, j.kf, xcd_item(t, boff[lo + 1] - boff[lo]),
+                                      blockIdx.y);
+}
+
 template <typename T, bool DL, int W>
 static void launch_near_w(Plan& p, const NearArgs& a, unsigned grid) {
   const bool fast = sizeof(T) == 4 && p.cg.ncx >= 3 && p.cg.ncz >= 3;
@@ -784,20 +822,87 @@ __global__ void __launch_bounds__(256) sum_slices(const T* __restrict__ part, T*
   out[i] = v;
 }
 
-template <typename T>
-hipError_t launch_wall(Plan& p) {
+static NearArgs wall_args(Plan& p) {
   const int nplane = p.p.Nx * p.p.Nz;
   NearArgs a = near_args(p, p.wall, p.wall_part, (size_t)nplane);
   a.nplane = nplane;
   a.nslice = kWallSlices;
   a.sstride = 6 * (size_t)nplane;
   a.scale = -0.039788735772973833942 / ((double)p.p.Nx * (double)p.p.Nz);
-  launch_near_kernel<T, false>(p, a, near_grid(p, 2 * nplane));
-  const size_t n = 6 * (size_t)nplane;
+  return a;
+}
+
+// the wall slices' partial sums added in slice order
+template <typename T>
+hipError_t launch_wall_sum(Plan& p) {
+  const size_t n = 6 * (size_t)p.p.Nx * p.p.Nz;
   sum_slices<T><<<(unsigned)((n + 255) / 256), 256, 0, p.stream>>>((const T*)p.wall_part,
                                                                    (T*)p.wall_phys, n);
   return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_wall(Plan& p) {
+  launch_near_kernel<T, false>(p, wall_args(p), near_grid(p, 2 * p.p.Nx * p.p.Nz));
+  return launch_wall_sum<T>(p);
+}
+
+// Job lists of the single-layer local sums of many plans in one launch: at
+// the plans' sources as targets (after their binning and target order of
+// the current call), or at their wall nodes.
+bool near_job_fast(const Plan& p) { return !p.fp64 && p.cg.ncx >= 3 && p.cg.ncz >= 3; }
+
+size_t near_job_bytes(bool fp64) {
+  return fp64 ? sizeof(NearJob<double>) : sizeof(NearJob<float>);
+}
+
+int near_job_blocks(const Plan& p, bool wall) {
+  return (int)near_grid(const_cast<Plan&>(p), wall ? 2 * p.p.Nx * p.p.Nz : (int)p.p.max_tgt);
+}
+
+template <typename T>
+static int near_jobs_upload_t(Plan* const* plans, int n, bool wall, void* dev_jobs, int* dev_boff) {
+  std::vector<NearJob<T>> j(n);
+  std::vector<int> off(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    Plan& p = *plans[i];
+    if (wall) {
+      j[i].a = wall_args(p);
+    } else {
+      j[i].a = near_args(p, p.src, p.ul, (size_t)p.p.max_tgt);
+      j[i].a.tcap = (size_t)p.p.max_tgt;
+      j[i].a.order = p.norder;
+    }
+    j[i].k = make_kc<T>(p.p.alpha);
+    j[i].kf = make_kcf(p.p.alpha);
+    off[i + 1] = off[i] + near_job_blocks(p, wall);
+  }
+  if (n > 0 && (hipMemcpy(dev_jobs, j.data(), n * sizeof(NearJob<T>), hipMemcpyHostToDevice) != hipSuccess ||
+                hipMemcpy(dev_boff, off.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice) != hipSuccess))
+    return -1;
+  return off[n];
+}
+
+int near_jobs_upload(Plan* const* plans, int n, bool wall, void* dev_jobs, int* dev_boff) {
+  if (n <= 0) return 0;
+  return plans[0]->fp64 ? near_jobs_upload_t<double>(plans, n, wall, dev_jobs, dev_boff)
+                        : near_jobs_upload_t<float>(plans, n, wall, dev_jobs, dev_boff);
+}
+
+hipError_t launch_near_jobs(hipStream_t s, bool fp64, bool fast, bool wall, const void* dev_jobs,
+                            const int* dev_boff, int n, int nblocks) {
+  if (n <= 0 || nblocks <= 0) return hipSuccess;
+  const dim3 g((unsigned)nblocks, (unsigned)(wall ? kWallSlices : kNearSlices));
+  if (fp64)
+    near_field_jobs<double, false, 4><<<g, 256, 0, s>>>((const NearJob<double>*)dev_jobs, dev_boff, n);
+  else if (fast)
+    near_field_jobs<float, true, 4><<<g, 256, 0, s>>>((const NearJob<float>*)dev_jobs, dev_boff, n);
+  else
+    near_field_jobs<float, false, 4><<<g, 256, 0, s>>>((const NearJob<float>*)dev_jobs, dev_boff, n);
+  return hipGetLastError();
+}
+
+const int* launch_near_order_sources(Plan& p) { return launch_near_order(p, p.src); }
 
 hipError_t launch_gauge(Plan& p) {
   const int n = p.src.n;
@@ -822,5 +927,7 @@ template hipError_t launch_near_dl<double>(Plan&, int);
 template hipError_t launch_near_dl<float>(Plan&, int);
 template hipError_t launch_wall<double>(Plan&);
 template hipError_t launch_wall<float>(Plan&);
+template hipError_t launch_wall_sum<double>(Plan&);
+template hipError_t launch_wall_sum<float>(Plan&);
 
 }  // namespace ggem

@@ -4,6 +4,8 @@
 //
 // Each lane owns two grid nodes and sums over the sources in the cells that
 // can reach its tile, in a fixed order: no atomics, bitwise reproducible.
+#include <vector>
+
 #include "ggem_internal.h"
 
 namespace ggem {
@@ -98,8 +100,10 @@ __device__ inline void lds_wave_sync() {
 // added at the lane's node of that half in complete groups of four.
 //
 // CNT: count the (source, node) pairs within r_c into a.work.
+//
+// The tile is (z tile bx, x tile by, y tile bz) of the grid of a.
 template <typename T, bool REL, bool CNT>
-__global__ void __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1))) spread_tile(SpreadArgs a) {
+__device__ __forceinline__ void spread_body(const SpreadArgs& a, int bx, int by, int bz) {
   using Q = typename V4<T>::t;
   __shared__ double lx[REL ? 1 : 4][64], ly[REL ? 1 : 4][64], lz[REL ? 1 : 4][64];
   // REL: per wave the both-halves list [0, 64) and the low-only and
@@ -112,16 +116,9 @@ __global__ void __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(sizeof(
   const CellGeom& g = a.g;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  // XCD-aware: blocks are dealt round-robin to the 8 XCDs, so block b runs on
-  // XCD b % 8; give each XCD a contiguous run of z tiles
-  int bx = blockIdx.x;
-  if ((gridDim.x & 7) == 0) {
-    const int per = gridDim.x >> 3;
-    bx = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  }
   const int k_lo = bx * TZ;
-  const int i_lo = blockIdx.y * TX;
-  const int j_lo = blockIdx.z * TY;
+  const int i_lo = by * TX;
+  const int j_lo = bz * TY;
   const int k = k_lo + (lane & 3), i = i_lo + ((lane >> 2) & 3), j = j_lo + (lane >> 4);
   const int k1 = k + 4;  // the lane's second node
   const bool valid = (k < a.Nz) && (i < a.Nx) && (j < a.Ny);
@@ -484,8 +481,43 @@ __global__ void __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(sizeof(
   }
 }
 
-template <typename T>
-hipError_t launch_spread(Plan& p, int /*unused*/) {
+// XCD-aware: blocks are dealt round-robin to the 8 XCDs, so block b runs on
+// XCD b % 8; each XCD gets a contiguous run of the z tiles of a row
+__device__ inline int xcd_z_tile(int b, int nbx) {
+  if ((nbx & 7) != 0) return b;
+  const int per = nbx >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+template <typename T, bool REL, bool CNT>
+__global__ void __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1)))
+spread_tile(SpreadArgs a) {
+  spread_body<T, REL, CNT>(a, xcd_z_tile(blockIdx.x, gridDim.x), blockIdx.y, blockIdx.z);
+}
+
+// Many grids in one launch: job j owns blocks [boff[j], boff[j + 1]) (its
+// tiles, z fastest, padded to a multiple of 8 so that every job's rows start
+// on XCD 0 as in the single launch).  A block finds its job by bisection and
+// does exactly the work of the same tile in the job's own launch.
+template <typename T, bool REL>
+__global__ void __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1)))
+spread_tile_jobs(const SpreadArgs* __restrict__ jobs, const int* __restrict__ boff, int njobs) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = njobs;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (boff[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  const SpreadArgs& a = jobs[lo];
+  const int nbx = (a.Nz + TZ - 1) / TZ, nby = (a.Nx + TX - 1) / TX, nbz = (a.Ny + TY - 1) / TY;
+  const int t = b - boff[lo];
+  if (t >= nbx * nby * nbz) return;  // padding
+  const int row = t / nbx;
+  spread_body<T, REL, false>(a, xcd_z_tile(t - row * nbx, nbx), row % nby, row / nby);
+}
+
+static SpreadArgs spread_args(const Plan& p) {
   SpreadArgs a;
   a.g = p.cg;
   a.Nx = p.p.Nx;
@@ -504,10 +536,22 @@ hipError_t launch_spread(Plan& p, int /*unused*/) {
   a.sf = p.src.s;
   a.scap = (size_t)p.p.max_src;
   a.out = p.phys;
+  a.work = nullptr;
+  return a;
+}
+
+// tile-relative staging (FP32 only) needs one periodic image per (tile,
+// source) pair
+static bool spread_rel(const Plan& p) {
+  return !p.fp64 && WT * p.dx + p.rc < 0.5 * p.p.Lx && WZ * p.dz + p.rc < 0.5 * p.p.Lz;
+}
+
+template <typename T>
+hipError_t launch_spread(Plan& p, int /*unused*/) {
+  SpreadArgs a = spread_args(p);
   a.work = p.count_work ? p.work + 1 : nullptr;
   dim3 grid((p.p.Nz + TZ - 1) / TZ, (p.p.Nx + TX - 1) / TX, (p.p.Ny + TY - 1) / TY);
-  // tile-relative staging needs one periodic image per (tile, source) pair
-  const bool rel = sizeof(T) == 4 && WT * p.dx + p.rc < 0.5 * p.p.Lx && WZ * p.dz + p.rc < 0.5 * p.p.Lz;
+  const bool rel = sizeof(T) == 4 && spread_rel(p);
   const bool cnt = a.work != nullptr;
   if (rel && cnt) spread_tile<T, true, true><<<grid, TB, 0, p.stream>>>(a);
   else if (rel) spread_tile<T, true, false><<<grid, TB, 0, p.stream>>>(a);
@@ -516,7 +560,41 @@ hipError_t launch_spread(Plan& p, int /*unused*/) {
   return hipGetLastError();
 }
 
+int spread_job_blocks(const Plan& p) {
+  const int n = ((p.p.Nz + TZ - 1) / TZ) * ((p.p.Nx + TX - 1) / TX) * ((p.p.Ny + TY - 1) / TY);
+  return (n + 7) & ~7;
+}
+
+bool spread_job_rel(const Plan& p) { return spread_rel(p); }
+
+int spread_jobs_upload(const Plan* const* plans, int n, void* dev_args, int* dev_boff) {
+  std::vector<SpreadArgs> a(n);
+  std::vector<int> off(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    a[i] = spread_args(*plans[i]);
+    off[i + 1] = off[i] + spread_job_blocks(*plans[i]);
+  }
+  if (n > 0 && (hipMemcpy(dev_args, a.data(), n * sizeof(SpreadArgs), hipMemcpyHostToDevice) != hipSuccess ||
+                hipMemcpy(dev_boff, off.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice) != hipSuccess))
+    return -1;
+  return off[n];
+}
+
+size_t spread_job_bytes() { return sizeof(SpreadArgs); }
+
+template <typename T>
+hipError_t launch_spread_jobs(hipStream_t s, const void* dev_args, const int* dev_boff, int n,
+                              int nblocks, bool rel) {
+  if (n <= 0 || nblocks <= 0) return hipSuccess;
+  const SpreadArgs* a = (const SpreadArgs*)dev_args;
+  if (sizeof(T) == 4 && rel) spread_tile_jobs<T, true><<<nblocks, TB, 0, s>>>(a, dev_boff, n);
+  else spread_tile_jobs<T, false><<<nblocks, TB, 0, s>>>(a, dev_boff, n);
+  return hipGetLastError();
+}
+
 template hipError_t launch_spread<double>(Plan&, int);
 template hipError_t launch_spread<float>(Plan&, int);
+template hipError_t launch_spread_jobs<double>(hipStream_t, const void*, const int*, int, int, bool);
+template hipError_t launch_spread_jobs<float>(hipStream_t, const void*, const int*, int, int, bool);
 
 }  // namespace ggem
