@@ -183,13 +183,57 @@ __global__ void __launch_bounds__(256) interp_staged(InterpArgs a) {
   for (int row = 0; row < 25; ++row) twab[row] = (T)(wy[row / 5] * wx[row % 5]);
   if (nbox * (int)sizeof(T) <= kBoxBytes) {
     const int oj = j0 - 2 - lo[0], oi = i0 - lo[1], ok = k0 - lo[2];
+    // A box of at most 256 x UR nodes is held one register per node and
+    // thread: the next field's loads are issued before this field's sums,
+    // so their memory latency overlaps the arithmetic.  A larger box is
+    // staged in batches of eight loads per thread.
+    constexpr int UR = 32;
+    const bool piped = nbox <= 256 * UR;
+    int off[UR];
+    T v[UR];
+    if (piped) {
+#pragma unroll
+      for (int u = 0; u < UR; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        off[u] = 0;
+        if (e < nbox) {
+          const int kb = e % bk, r = e / bk, ib = r % bi, jb = r / bi;
+          const int gi = wrap1(lo[1] + ib, a.Nx), gk = wrap1(lo[2] + kb, a.Nz);
+          off[u] = ((lo[0] + jb) * a.Nx + gi) * a.Nz + gk;
+          v[u] = g[off[u]];
+        }
+      }
+    }
     for (int c = 0; c < NC; ++c) {
-      for (int e = threadIdx.x; e < nbox; e += 256) {
-        const int kb = e % bk, r = e / bk, ib = r % bi, jb = r / bi;
-        const int gi = wrap1(lo[1] + ib, a.Nx), gk = wrap1(lo[2] + kb, a.Nz);
-        box[e] = g[c * fs + ((size_t)(lo[0] + jb) * a.Nx + gi) * a.Nz + gk];
+      if (piped) {
+#pragma unroll
+        for (int u = 0; u < UR; ++u)
+          if (threadIdx.x + 256 * u < nbox) box[threadIdx.x + 256 * u] = v[u];
+      } else {
+        constexpr int U = 8;
+        for (int e0 = threadIdx.x; e0 < nbox; e0 += 256 * U) {
+          T w[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int e = e0 + 256 * u;
+            if (e < nbox) {
+              const int kb = e % bk, r = e / bk, ib = r % bi, jb = r / bi;
+              const int gi = wrap1(lo[1] + ib, a.Nx), gk = wrap1(lo[2] + kb, a.Nz);
+              w[u] = g[c * fs + ((size_t)(lo[0] + jb) * a.Nx + gi) * a.Nz + gk];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+            if (e0 + 256 * u < nbox) box[e0 + 256 * u] = w[u];
+        }
       }
       __syncthreads();
+      if (piped && c + 1 < NC) {
+        const T* gc = g + (size_t)(c + 1) * fs;
+#pragma unroll
+        for (int u = 0; u < UR; ++u)
+          if (threadIdx.x + 256 * u < nbox) v[u] = gc[off[u]];
+      }
       if (valid) {
         T sum = (T)0;
         for (int row = 0; row < 25; ++row) {
