@@ -521,12 +521,13 @@ def batched(args, steps):
     f = t(np.concatenate([c.f for c in cases]))
     n = int(to[-1])
     out = {p: torch.empty((n, 3), dtype=torch.float64, device=dev) for p in ("mixed", "fp64")}
-    branches, tuned_ms, cached = args.branches, None, None
+    branches, tuned_ms, cached, cells = args.branches, None, None, None
     if branches <= 0:
         from paper_1109_6587_amd.autotune import tune_batch
-        branches, tuned_ms, cached = tune_batch(
+        branches, tuned_ms, cached, cells = tune_batch(
             cases, (so, xs, f, to, xs, out[args.precision]), precision=args.precision, log=log)
-    batches = {p: G.Batch(cases, precision=p, n_branches=branches) for p in out}
+    batches = {p: G.Batch(cases, precision=p, n_branches=branches,
+                          cell_scales=cells if p == args.precision else None) for p in out}
     for p, b in batches.items():
         b.capture(so, xs, f, to, xs, out[p])
         b.replay()
@@ -562,7 +563,8 @@ def batched(args, steps):
     units = {"near": 0, "spread": 0}
     stage_ms = {"near": 0.0, "spread": 0.0}
     for i, c in enumerate(cases):
-        plan = G.Plan.from_case(c, precision=prec, sync_checks=False)
+        plan = G.Plan.from_case(c, precision=prec, sync_checks=False,
+                                cell_scale=cells[i] if cells else 0.0)
         xsi, fi = xs[so[i]:so[i + 1]], f[so[i]:so[i + 1]]
         oi = out[prec][to[i]:to[i + 1]]
         call = lambda: plan.single_layer(xsi, fi, xsi, out=oi)  # noqa: E731
@@ -588,7 +590,8 @@ def batched(args, steps):
             "mpoints_per_s": round(n / (ms * 1e-3) / 1e6, 3), "ms_per_step": round(ms, 5),
             f"{other}_ms_per_step": round(ms_other, 5), "eager_ms_per_step": round(ms_eager, 5),
             "err_vs_fp64": {"rel_l2": err},
-            "autotune": {"ms_by_branches": tuned_ms, "from_cache": cached}}
+            "autotune": {"ms_by_branches": tuned_ms, "from_cache": cached,
+                         "cell_scales": cells}}
 
 
 def fredholm(steps):

@@ -78,6 +78,13 @@ typedef struct {
   int sync_checks;      /* 1: wait and report domain errors; 0: asynchronous  */
   long long max_src;    /* capacity reserved at plan time (sources)           */
   long long max_tgt;    /* capacity reserved at plan time (targets)           */
+  double cell_scale;    /* cells of the cell list at least cell_scale * rc on
+                           a side: 0 or 1 selects rc, the smallest cell the
+                           27-cell neighbourhood of the local sum allows; up
+                           to 4.  A tuning knob only (the set of pairs within
+                           rc, and so the result, is the same at any value):
+                           larger cells mean fewer, fuller cell rows for the
+                           spread and the local sum to walk                   */
 } ggem_params;
 
 /* Create a plan: validates the parameters, precomputes the Gauss-Lobatto

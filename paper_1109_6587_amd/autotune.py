@@ -1,13 +1,19 @@
 """Autotuner for batched evaluations, with an on-disk cache.
 
-The tunable of a batch is its number of branch streams: more branches let
-small instances overlap, fewer keep large instances from competing for the
-compute units.  For a batch (its instances' boxes, grids, split parameters
-and point counts, the precision and the device name) every candidate is
-timed as a captured graph (warm-up replays, then timed replays) and the
-fastest is kept in a JSON cache, so later runs of the same batch shape skip
-the search.  Cache file: $GGEM_AUTOTUNE_CACHE, else
-~/.cache/ggem/autotune.json.
+A batch has two tunables.
+* The cell size of each instance (ggem_params.cell_scale: cells of at least
+  scale * r_c on a side).  Larger cells mean fewer, fuller cell rows for the
+  spread and the local sum to walk, which helps sparse instances; smaller
+  cells cull more candidate pairs, which helps dense ones.  Each instance is
+  timed alone at every candidate scale and keeps its fastest.
+* The number of branch streams: more branches let small instances overlap,
+  fewer keep large instances from competing for the compute units.  Every
+  candidate is timed as a captured graph of the whole batch (warm-up
+  replays, then timed replays), with the tuned cell sizes.
+The result for a batch shape (its instances' boxes, grids, split parameters
+and point counts, the precision and the device name) is kept in a JSON
+cache, so later runs of the same batch shape skip the search.  Cache file:
+$GGEM_AUTOTUNE_CACHE, else ~/.cache/ggem/autotune.json.
 """
 from __future__ import annotations
 
@@ -19,6 +25,7 @@ import time
 from . import ggem as B
 
 CANDIDATES = (1, 2, 4, 8)
+CELL_SCALES = (0.0, 1.5, 2.0)
 
 
 def cache_path():
@@ -56,35 +63,65 @@ def _store(path, data):
     os.replace(tmp, path)
 
 
-def tune_batch(cases, arrays, precision="mixed", candidates=CANDIDATES, warmup=2, reps=5,
-               path=None, log=None):
-    """Best branch count for `cases`; arrays = (src_off, xs, f, tgt_off, xt, u)
-    as for Batch.capture.  Returns (branches, timings in ms, from_cache)."""
+def _time(call, warmup, reps):
     import torch
+    for _ in range(warmup):
+        call()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        call()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps
+
+
+def tune_cells(cases, arrays, precision="mixed", scales=CELL_SCALES, warmup=2, reps=5):
+    """Fastest cell scale of each instance, each evaluated alone (its own
+    plan, eager calls); returns (scales, ms per instance and scale)."""
+    so, xs, f, to, xt, u = arrays
+    best, ms = [], []
+    for i, c in enumerate(cases):
+        a, b = int(so[i]), int(so[i + 1])
+        p, q = int(to[i]), int(to[i + 1])
+        xsi, fi, ui = xs[a:b], f[a:b], u[p:q]
+        xti = xsi if (xt is xs and a == p and b == q) else xt[p:q]
+        row = {}
+        for sc in scales:
+            plan = B.Plan.from_case(c, precision=precision, sync_checks=False, cell_scale=sc)
+            row[str(sc)] = _time(lambda: plan.single_layer(xsi, fi, xti, out=ui), warmup, reps)
+            plan.status()
+            plan.close()
+        ms.append(row)
+        best.append(float(min(row, key=row.get)))
+    return best, ms
+
+
+def tune_batch(cases, arrays, precision="mixed", candidates=CANDIDATES, warmup=2, reps=5,
+               path=None, log=None, scales=CELL_SCALES):
+    """Best cell scales and branch count for `cases`; arrays = (src_off, xs,
+    f, tgt_off, xt, u) as for Batch.capture.  Returns (branches, timings in
+    ms by branch count, from_cache, cell scale per instance)."""
     path = path or cache_path()
     key = batch_key(cases, precision)
     data = _load(path)
-    if key in data:
+    if key in data and "cell_scales" in data[key]:
         ent = data[key]
-        return int(ent["branches"]), ent.get("ms", {}), True
+        return int(ent["branches"]), ent.get("ms", {}), True, [float(v) for v in ent["cell_scales"]]
+    cells, cell_ms = tune_cells(cases, arrays, precision, scales, warmup, reps)
+    if log:
+        log(f"cell scales: {cells}")
     times = {}
     for nb in candidates:
-        b = B.Batch(cases, precision=precision, n_branches=nb)
+        b = B.Batch(cases, precision=precision, n_branches=nb, cell_scales=cells)
         b.capture(*arrays)
-        for _ in range(warmup):
-            b.replay()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            b.replay()
-        torch.cuda.synchronize()
-        times[str(nb)] = (time.perf_counter() - t0) * 1e3 / reps
+        times[str(nb)] = _time(b.replay, warmup, reps)
         b.status()
         b.close()
         if log:
             log(f"branches {nb}: {times[str(nb)]:.3f} ms")
     best = int(min(times, key=times.get))
     data = _load(path)
-    data[key] = {"branches": best, "ms": times, "instances": len(cases), "precision": precision}
+    data[key] = {"branches": best, "ms": times, "instances": len(cases), "precision": precision,
+                 "cell_scales": cells, "cell_ms": cell_ms}
     _store(path, data)
-    return best, times, False
+    return best, times, False, cells

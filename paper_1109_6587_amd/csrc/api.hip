@@ -593,6 +593,7 @@ int init_plan(Plan& p, const ggem_params* prm, hipStream_t stream) {
     return fail(GGEM_E_ARG, "precision must be GGEM_FP64, GGEM_MIXED or GGEM_MIXED_BF16");
   if (q.max_src < 0 || q.max_tgt < 0 || q.max_src > (1LL << 30) || q.max_tgt > (1LL << 30))
     return fail(GGEM_E_ARG, "capacities must be in 0..2^30");
+  if (!(q.cell_scale >= 0.0 && q.cell_scale <= 4.0)) return fail(GGEM_E_ARG, "cell_scale must be in 0..4");
 
   memset(&p, 0, sizeof(Plan));
   p.p = q;
@@ -613,8 +614,9 @@ int init_plan(Plan& p, const ggem_params* prm, hipStream_t stream) {
     p.radx[i] = i < nrx ? rx[i] : 1;
     p.radz[i] = i < nrz ? rz[i] : 1;
   }
-  // cell list: cells strictly larger than rc, at most kMaxCells of them
-  double cs = q.rc * (1.0 + 1e-10);
+  // cell list: cells strictly larger than rc (times the cell scale), at
+  // most kMaxCells of them
+  double cs = q.rc * (q.cell_scale > 1.0 ? q.cell_scale : 1.0) * (1.0 + 1e-10);
   CellGeom& g = p.cg;
   for (;;) {
     g.ncx = (int)floor(q.Lx / cs);

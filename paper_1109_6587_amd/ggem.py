@@ -78,6 +78,7 @@ class Params(ctypes.Structure):
         ("Nx", ctypes.c_int), ("Nz", ctypes.c_int), ("Ny", ctypes.c_int),
         ("precision", ctypes.c_int), ("sync_checks", ctypes.c_int),
         ("max_src", ctypes.c_longlong), ("max_tgt", ctypes.c_longlong),
+        ("cell_scale", ctypes.c_double),
     ]
 
 
@@ -199,12 +200,12 @@ class Plan:
     """A GGEM plan: box, split parameter, grid, precision and capacities."""
 
     def __init__(self, Lx, Lz, H, alpha, Nx, Nz, Ny, rc=0.0, precision="fp64",
-                 max_src=1, max_tgt=1, sync_checks=True, stream=None):
+                 max_src=1, max_tgt=1, sync_checks=True, stream=None, cell_scale=0.0):
         lib = load_library()
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self.params = Params(float(Lx), float(Lz), float(H), float(alpha), float(rc),
                              int(Nx), int(Nz), int(Ny), prec, 1 if sync_checks else 0,
-                             int(max_src), int(max_tgt))
+                             int(max_src), int(max_tgt), float(cell_scale))
         self.Nx, self.Nz, self.Ny = int(Nx), int(Nz), int(Ny)
         self._h = ctypes.c_void_p()
         _check(lib.ggem_plan_create(ctypes.byref(self.params), _stream_handle(stream),
@@ -655,14 +656,19 @@ class Batch:
     ``cases``: objects with Lx, Lz, H, alpha, rc, Nx, Nz, Ny and ns/nt (for
     the capacities), e.g. workloads.SlitCase."""
 
-    def __init__(self, cases, precision="mixed", n_branches=4):
+    def __init__(self, cases, precision="mixed", n_branches=4, cell_scales=None):
+        """cell_scales: one ggem_params.cell_scale per instance (None: 0)."""
         lib = load_library()
         prec = PRECISIONS[precision]
         arr = (Params * len(cases))()
+        if cell_scales is None:
+            cell_scales = [0.0] * len(cases)
+        if len(cell_scales) != len(cases):
+            raise ValueError("cell_scales must have one entry per instance")
         for i, c in enumerate(cases):
             arr[i] = Params(float(c.Lx), float(c.Lz), float(c.H), float(c.alpha), float(c.rc),
                             int(c.Nx), int(c.Nz), int(c.Ny), prec, 0, max(int(c.ns), 1),
-                            max(int(c.nt), 1))
+                            max(int(c.nt), 1), float(cell_scales[i]))
         self.n = len(cases)
         self._h = ctypes.c_void_p()
         _check(lib.ggem_batch_create(self.n, arr, int(n_branches), ctypes.byref(self._h)))

@@ -41,9 +41,22 @@ def test_every_declared_symbol_exported(lib):
     assert sorted(B.EXPORTS) == declared()
 
 
+def test_params_struct_matches_header():
+    """The binding's Params mirrors the fields of ggem_params in order."""
+    txt = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \{(.*?)\} ggem_params;", txt, flags=re.S).group(1)
+    names = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if decl:
+            names += [n.strip().lstrip("*") for n in decl.split(None, 1)[1].split(",")]
+    names = [n.split()[-1] for n in names]
+    assert names == [f for f, _ in B.Params._fields_]
+
+
 def params(**kw):
     p = dict(Lx=8.0, Lz=8.0, H=2.0, alpha=3.0, rc=0.0, Nx=32, Nz=32, Ny=17, precision=B.FP64,
-             sync_checks=1, max_src=10, max_tgt=10)
+             sync_checks=1, max_src=10, max_tgt=10, cell_scale=0.0)
     p.update(kw)
     return B.Params(*[p[f] for f, _ in B.Params._fields_])
 
@@ -59,6 +72,9 @@ def params(**kw):
     (dict(Ny=131), "Ny"),
     (dict(precision=7), "precision"),
     (dict(max_src=-1), "capacities"),
+    (dict(cell_scale=4.5), "cell_scale"),
+    (dict(cell_scale=-1.0), "cell_scale"),
+    (dict(cell_scale=float("nan")), "cell_scale"),
 ])
 def test_plan_create_rejects(lib, bad, needle):
     h = ctypes.c_void_p()

@@ -195,7 +195,20 @@ def test_autotune_caches(tmp_path):
     so, xs, f, to, xt = pack(cases)
     u = torch.empty((int(to[-1]), 3), dtype=torch.float64, device=DEV)
     path = str(tmp_path / "tune.json")
-    best, ms, cached = tune_batch(cases, (so, xs, f, to, xt, u), candidates=(1, 2), path=path)
+    best, ms, cached, cells = tune_batch(cases, (so, xs, f, to, xt, u), candidates=(1, 2),
+                                         path=path, scales=(0.0, 1.5))
     assert not cached and best in (1, 2) and set(ms) == {"1", "2"}
-    best2, _, cached2 = tune_batch(cases, (so, xs, f, to, xt, u), candidates=(1, 2), path=path)
-    assert cached2 and best2 == best
+    assert len(cells) == len(cases) and set(cells) <= {0.0, 1.5}
+    best2, _, cached2, cells2 = tune_batch(cases, (so, xs, f, to, xt, u), candidates=(1, 2),
+                                           path=path, scales=(0.0, 1.5))
+    assert cached2 and best2 == best and cells2 == cells
+    # the tuned batch still equals its instances evaluated alone with the
+    # same cell sizes, bit for bit
+    b = G.Batch(cases, precision="mixed", n_branches=best, cell_scales=cells)
+    b.single_layer(so, xs, f, to, xt, u)
+    b.status()
+    got = u.cpu().numpy()
+    for i, c in enumerate(cases):
+        plan = G.Plan.from_case(c, precision="mixed", cell_scale=cells[i])
+        solo = plan.single_layer(dev(c.xs), dev(c.f), dev(c.xt)).cpu().numpy()
+        assert np.array_equal(got[to[i]:to[i + 1]], solo), i

@@ -130,6 +130,26 @@ def test_single_layer_random_fp64(cfg):
     assert rel_max(u, ref) < TOL64
 
 
+@pytest.mark.parametrize("scale", [1.5, 2.0])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_cell_scale_keeps_the_result(scale, precision):
+    """Larger cells (ggem_params.cell_scale) change only how the pairs are
+    found: single and double layer still match the oracle (1e-10 FP64,
+    1e-5 mixed), on a box with six cells across at the default size."""
+    c = random_case(51, 400, 150, 12.0, 1.5, 2.0, 2.0, 48, 48, 33, dl=True)
+    print(f"case {c.name} cell scale {scale} {precision}", flush=True)
+    g = O.SlitGrid.from_case(c)
+    ref_s = O.single_layer(g, c.xs, c.f, c.xt)
+    ref_d = O.double_layer(g, c.xs, c.f, c.xt, c.normals)
+    plan = G.Plan.from_case(c, precision=precision, cell_scale=scale)
+    u = plan.single_layer(dev(c.xs), dev(c.f), dev(c.xt)).cpu().numpy()
+    v = plan.double_layer(dev(c.xs), dev(c.f), dev(c.xt), dev(c.normals)).cpu().numpy()
+    if precision == "fp64":
+        assert rel_max(u, ref_s) < TOL64 and rel_max(v, ref_d) < TOL64
+    else:
+        assert rel_l2(u, ref_s) < TOLMIX and rel_l2(v, ref_d) < TOLMIX
+
+
 def test_empty_inputs():
     c = random_case(31, 10, 10, 4.0, 1.0, 4.0, 1.0, 16, 16, 9)
     plan = G.Plan.from_case(c)
