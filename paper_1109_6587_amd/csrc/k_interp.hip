@@ -122,9 +122,9 @@ __global__ void __launch_bounds__(256) interp_combine(InterpArgs a) {
 // per block (they share one or two cells).  The box of grid nodes that their
 // stencils cover is staged in LDS one field at a time and every thread sums
 // its 125 nodes from there, in the order of interp_combine.  Blocks whose box
-// exceeds 56 KiB of LDS (targets far apart in the sorted order, e.g. across
+// exceeds 36 KiB of LDS (targets far apart in the sorted order, e.g. across
 // a row of cells) gather from global memory as interp_combine does.
-constexpr int kBoxBytes = 56 * 1024;
+constexpr int kBoxBytes = 36 * 1024;
 
 template <typename T, bool STRESS>
 __global__ void __launch_bounds__(256) interp_staged(InterpArgs a) {
@@ -187,7 +187,7 @@ __global__ void __launch_bounds__(256) interp_staged(InterpArgs a) {
     // thread: the next field's loads are issued before this field's sums,
     // so their memory latency overlaps the arithmetic.  A larger box is
     // staged in batches of eight loads per thread.
-    constexpr int UR = 32;
+    constexpr int UR = 12;
     const bool piped = nbox <= 256 * UR;
     int off[UR];
     T v[UR];
