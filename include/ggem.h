@@ -423,7 +423,8 @@ int ggem_rigid_solve(ggem_rigid_t rigid, long long n_nodes, const double* nodes,
  * yy, zz, xy, xz, yz, float64 device.  The local parts are summed in FP64,
  * the grid fields keep the plan's precision.  Runs on the plan's stream
  * without the second stream.  Errors: GGEM_E_ARG, GGEM_E_CAPACITY (ns above
- * max_src), GGEM_E_DOMAIN (a source or probe outside the slit, reported as
+ * max_src or nt above max_tgt: the probes are binned in the plan's target
+ * workspace), GGEM_E_DOMAIN (a source or probe outside the slit, reported as
  * for the evaluations), GGEM_E_DEVICE. */
 int ggem_probe(ggem_plan_t plan, long long ns, const double* xs, const double* f, long long nt,
                const double* xt, double* u, double* p, double* sigma);

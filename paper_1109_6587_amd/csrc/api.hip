@@ -790,7 +790,7 @@ extern "C" int ggem_probe(ggem_plan_t plan, long long ns, const double* xs, cons
   Plan& p = plan->p;
   if (ns < 0 || nt < 0) return fail(GGEM_E_ARG, "negative point count");
   if (ns > p.p.max_src) return fail(GGEM_E_CAPACITY, "ns=%lld exceeds max_src=%lld", ns, p.p.max_src);
-  if (nt > (1LL << 30)) return fail(GGEM_E_ARG, "too many probes");
+  if (nt > p.p.max_tgt) return fail(GGEM_E_CAPACITY, "nt=%lld probes exceed max_tgt=%lld", nt, p.p.max_tgt);
   if (ns > 0 && (!xs || !f)) return fail(GGEM_E_ARG, "null source array");
   if (nt > 0 && (!xt || !u || !pr || !sigma)) return fail(GGEM_E_ARG, "null probe array");
   return p.fp64 ? probe_eval<double>(p, ns, xs, f, nt, xt, u, pr, sigma)

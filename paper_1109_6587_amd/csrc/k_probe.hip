@@ -8,10 +8,10 @@
 //   sigma^l_jk = (1/8pi) sum_i T^l_jik g_i,
 // a coincident source adding -(4 alpha/sqrt(pi))/(8pi) g to the velocity only.
 // The global parts are the slit solution of Appendix C interpolated with the
-// 4th-order Lagrange stencil of Sec. 3.2.2.  One thread per probe, FP64 sums
-// (the grid fields keep the plan's precision).  The local sums take the
-// probes in the cell order of their binning, so that neighbouring lanes walk
-// the same cells; each probe's own sum is unchanged by that order.
+// 4th-order Lagrange stencil of Sec. 3.2.2.  The local sums run in FP64, one
+// block of four waves per work item of up to 64 probes of one cell of the
+// probes' binning (probe_local); the interpolation takes one thread per
+// probe and sums in FP64 (the grid fields keep the plan's precision).
 //
 // Undisturbed flows (Appendix B), walls at y = -H and y = +H:
 //   simple shear sigma = rate e;  Poiseuille (centre-line velocity U0)
@@ -49,88 +49,168 @@ struct ProbeArgs {
   unsigned* flags;
 };
 
-__global__ void __launch_bounds__(256) probe_local(ProbeArgs a) {
-  const int ts = blockIdx.x * blockDim.x + threadIdx.x;
-  if (ts >= a.nt) return;
-  const int t = a.order[ts];
-  const CellGeom& g = a.g;
-  double px = a.xt[3 * (size_t)t], py = a.xt[3 * (size_t)t + 1], pz = a.xt[3 * (size_t)t + 2];
-  double u[3] = {0, 0, 0}, pr = 0.0, s[6] = {0, 0, 0, 0, 0, 0};
-  const bool finite = isfinite(px) && isfinite(py) && isfinite(pz);
-  if (!finite || !(fabs(py) <= g.H)) {
-    atomicOr(a.flags, finite ? kFlagOutside : kFlagNonFinite);
-  } else {
-    px = wrap_p(px, g.Lx);
-    pz = wrap_p(pz, g.Lz);
-    const int ix = min(g.ncx - 1, max(0, (int)floor(px * g.icx)));
-    const int iy = min(g.ncy - 1, max(0, (int)floor((py + g.H) * g.icy)));
-    const int iz = min(g.ncz - 1, max(0, (int)floor(pz * g.icz)));
-    const int nxo = g.ncx >= 3 ? 3 : g.ncx, nzo = g.ncz >= 3 ? 3 : g.ncz;
-    const double al = a.alpha, a3 = al * al * al / kSqrtPi;
-    double selfx = 0, selfy = 0, selfz = 0;
-    for (int oy = -1; oy <= 1; ++oy) {
-      const int cy = iy + oy;
-      if (cy < 0 || cy >= g.ncy) continue;
-      for (int oxi = 0; oxi < nxo; ++oxi) {
-        const int cx = g.ncx >= 3 ? (ix + oxi - 1 + g.ncx) % g.ncx : oxi;
-        for (int ozi = 0; ozi < nzo; ++ozi) {
-          const int cz = g.ncz >= 3 ? (iz + ozi - 1 + g.ncz) % g.ncz : ozi;
-          const int c = (cy * g.ncx + cx) * g.ncz + cz;
-          for (int j = a.cell_start[c]; j < a.cell_start[c + 1]; ++j) {
-            const double dx = fma(-g.Lx, rint((px - a.sx[j]) * g.invLx), px - a.sx[j]);
-            const double dy = py - a.sy[j];
-            const double dz = fma(-g.Lz, rint((pz - a.sz[j]) * g.invLz), pz - a.sz[j]);
-            double r2;
-            {
+// One pair within r_c (r2 > 0): its terms of u^l, p^l and sigma^l (without
+// the 1/8pi), added to u, pr and s.
+__device__ inline void probe_pair(double dx, double dy, double dz, double r2, double fx, double fy,
+                                  double fz, double al, double a3, double* u, double& pr,
+                                  double* s) {
+  const double r = sqrt(r2), ir2 = 1.0 / r2;
+  const double ec = erfc(al * r), ex = exp(-al * al * r2);
+  const double df = dx * fx + dy * fy + dz * fz;
+  // G^l g = A g + B d (d.g)
+  const double er = ec / r, ce = 2.0 * al / kSqrtPi * ex;
+  const double A = er - ce, B = (er + ce) * ir2;
+  u[0] += A * fx + B * df * dx;
+  u[1] += A * fy + B * df * dy;
+  u[2] += A * fz + B * df * dz;
+  // P^l . g = (2 erfc/r^3 + (4 alpha/sqrt(pi)) (1/r^2 - alpha^2) e) (d.g)
+  pr += (2.0 * er * ir2 + 4.0 * al / kSqrtPi * (ir2 - al * al) * ex) * df;
+  // T^l_jik g_i = C d_j d_k (d.g) + D (d_j g_k + d_k g_j + delta_jk (d.g))
+  const double C = -6.0 * er * ir2 * ir2 - 12.0 * al / kSqrtPi * ex * ir2 * ir2 - 8.0 * a3 * ex * ir2;
+  const double D = 4.0 * a3 * ex;
+  const double d[3] = {dx, dy, dz}, gv[3] = {fx, fy, fz};
+  const int ja[6] = {0, 1, 2, 0, 0, 1}, ka[6] = {0, 1, 2, 1, 2, 2};
+  for (int m = 0; m < 6; ++m) {
+    const int jj = ja[m], kk = ka[m];
+    s[m] += C * d[jj] * d[kk] * df + D * (d[jj] * gv[kk] + d[kk] * gv[jj] + (jj == kk ? df : 0.0));
+  }
+}
+
+// minimum-image displacement and its square, formed as the pair sums decide
+// the cutoff (FP64, fixed association)
+__device__ inline double probe_disp(const CellGeom& g, double px, double py, double pz, double qx,
+                                    double qy, double qz, double& dx, double& dy, double& dz) {
+  dx = fma(-g.Lx, rint((px - qx) * g.invLx), px - qx);
+  dy = py - qy;
+  dz = fma(-g.Lz, rint((pz - qz) * g.invLz), pz - qz);
+  double r2;
+  {
 #pragma clang fp contract(off)
-              r2 = (dx * dx + dy * dy) + dz * dz;
-            }
-            if (r2 > a.rc2) continue;
+    r2 = (dx * dx + dy * dy) + dz * dz;
+  }
+  return r2;
+}
+
+// One block of four waves per work item: up to 64 probes of one cell of the
+// probes' binning, one probe per lane of every wave.  The item's neighbour
+// cells are walked in a fixed order (y, then x, then z offsets) and their
+// sorted sources numbered in batches of 64; wave w takes batches w, w + 4,
+// ..., staged through its own LDS slice.  Every lane first marks its sources
+// within r_c in the batch (a coincident source goes to the self term at
+// once), then evaluates the marked ones in source order, so the expensive
+// pair terms cost a wave only as many steps as its busiest lane has pairs.
+// The four partial sums are added in wave order at the end: the result does
+// not depend on timing.
+constexpr int kProbeWaves = 4;
+
+__global__ void __launch_bounds__(64 * kProbeWaves) probe_local(ProbeArgs a,
+                                                                const int* __restrict__ item_start,
+                                                                const int* __restrict__ item_cell,
+                                                                const int* __restrict__ tcell) {
+  __shared__ double lq[kProbeWaves][3][64], lf[kProbeWaves][3][64];
+  __shared__ double part[kProbeWaves - 1][13][64];
+  const CellGeom& g = a.g;
+  const int item = blockIdx.x;
+  if (item >= item_start[g.ncells]) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int c = item_cell[item];
+  const int t0 = tcell[c] + (item - item_start[c]) * 64;
+  const bool active = t0 + lane < tcell[c + 1];
+  const int t = active ? a.order[t0 + lane] : 0;
+  double px = 0.0, py = 0.0, pz = 0.0;
+  bool ok = false;
+  if (active) {
+    px = a.xt[3 * (size_t)t];
+    py = a.xt[3 * (size_t)t + 1];
+    pz = a.xt[3 * (size_t)t + 2];
+    const bool finite = isfinite(px) && isfinite(py) && isfinite(pz);
+    if (finite && fabs(py) <= g.H) {
+      ok = true;
+      px = wrap_p(px, g.Lx);
+      pz = wrap_p(pz, g.Lz);
+    } else if (wave == 0) {
+      atomicOr(a.flags, finite ? kFlagOutside : kFlagNonFinite);
+    }
+  }
+  const int iz = c % g.ncz, ix = (c / g.ncz) % g.ncx, iy = c / (g.ncz * g.ncx);
+  const int nxo = g.ncx >= 3 ? 3 : g.ncx, nzo = g.ncz >= 3 ? 3 : g.ncz;
+  const double al = a.alpha, a3 = al * al * al / kSqrtPi;
+  // u (3), p, sigma (6), self (3)
+  double acc[13];
+  for (int m = 0; m < 13; ++m) acc[m] = 0.0;
+  int bc = 0;  // batches numbered in walk order (uniform)
+  for (int oy = -1; oy <= 1; ++oy) {
+    const int cy = iy + oy;
+    if (cy < 0 || cy >= g.ncy) continue;
+    for (int oxi = 0; oxi < nxo; ++oxi) {
+      const int cx = g.ncx >= 3 ? (ix + oxi - 1 + g.ncx) % g.ncx : oxi;
+      for (int ozi = 0; ozi < nzo; ++ozi) {
+        const int cz = g.ncz >= 3 ? (iz + ozi - 1 + g.ncz) % g.ncz : ozi;
+        const int cc = (cy * g.ncx + cx) * g.ncz + cz;
+        const int s0 = a.cell_start[cc], s1 = a.cell_start[cc + 1];
+        for (int b = s0; b < s1; b += 64) {
+          if (bc++ % kProbeWaves != wave) continue;
+          const int j = b + lane;
+          __builtin_amdgcn_wave_barrier();
+          if (j < s1) {
+            lq[wave][0][lane] = a.sx[j];
+            lq[wave][1][lane] = a.sy[j];
+            lq[wave][2][lane] = a.sz[j];
             const int src = a.perm[j];
-            const double fx = a.f[3 * (size_t)src], fy = a.f[3 * (size_t)src + 1],
-                         fz = a.f[3 * (size_t)src + 2];
-            if (r2 == 0.0) {
-              selfx += fx;
-              selfy += fy;
-              selfz += fz;
-              continue;
+            lf[wave][0][lane] = a.f[3 * (size_t)src];
+            lf[wave][1][lane] = a.f[3 * (size_t)src + 1];
+            lf[wave][2][lane] = a.f[3 * (size_t)src + 2];
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          const int n = min(64, s1 - b);
+          unsigned long long mask = 0;
+          if (ok) {
+            for (int e = 0; e < n; ++e) {
+              double dx, dy, dz;
+              const double r2 = probe_disp(g, px, py, pz, lq[wave][0][e], lq[wave][1][e],
+                                           lq[wave][2][e], dx, dy, dz);
+              if (r2 > a.rc2) continue;
+              if (r2 == 0.0) {
+                acc[10] += lf[wave][0][e];
+                acc[11] += lf[wave][1][e];
+                acc[12] += lf[wave][2][e];
+                continue;
+              }
+              mask |= 1ull << e;
             }
-            const double r = sqrt(r2), ir2 = 1.0 / r2;
-            const double ec = erfc(al * r), ex = exp(-al * al * r2);
-            const double df = dx * fx + dy * fy + dz * fz;
-            // G^l g = A g + B d (d.g)
-            const double er = ec / r, ce = 2.0 * al / kSqrtPi * ex;
-            const double A = er - ce, B = (er + ce) * ir2;
-            u[0] += A * fx + B * df * dx;
-            u[1] += A * fy + B * df * dy;
-            u[2] += A * fz + B * df * dz;
-            // P^l . g = (2 erfc/r^3 + (4 alpha/sqrt(pi)) (1/r^2 - alpha^2) e) (d.g)
-            pr += (2.0 * er * ir2 + 4.0 * al / kSqrtPi * (ir2 - al * al) * ex) * df;
-            // T^l_jik g_i = C d_j d_k (d.g) + D (d_j g_k + d_k g_j + delta_jk (d.g))
-            const double C = -6.0 * er * ir2 * ir2 - 12.0 * al / kSqrtPi * ex * ir2 * ir2 -
-                             8.0 * a3 * ex * ir2;
-            const double D = 4.0 * a3 * ex;
-            const double d[3] = {dx, dy, dz}, gv[3] = {fx, fy, fz};
-            const int ja[6] = {0, 1, 2, 0, 0, 1}, ka[6] = {0, 1, 2, 1, 2, 2};
-            for (int m = 0; m < 6; ++m) {
-              const int jj = ja[m], kk = ka[m];
-              s[m] += C * d[jj] * d[kk] * df +
-                      D * (d[jj] * gv[kk] + d[kk] * gv[jj] + (jj == kk ? df : 0.0));
-            }
+          }
+          while (mask) {
+            const int e = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            double dx, dy, dz;
+            const double r2 = probe_disp(g, px, py, pz, lq[wave][0][e], lq[wave][1][e],
+                                         lq[wave][2][e], dx, dy, dz);
+            probe_pair(dx, dy, dz, r2, lf[wave][0][e], lf[wave][1][e], lf[wave][2][e], al, a3,
+                       acc, acc[3], acc + 4);
           }
         }
       }
     }
-    const double sc = -4.0 * al / kSqrtPi;
-    u[0] = kInv8Pi * (u[0] + sc * selfx);
-    u[1] = kInv8Pi * (u[1] + sc * selfy);
-    u[2] = kInv8Pi * (u[2] + sc * selfz);
-    pr *= kInv8Pi;
-    for (int m = 0; m < 6; ++m) s[m] *= kInv8Pi;
   }
-  for (int d = 0; d < 3; ++d) a.u[3 * (size_t)t + d] = u[d];
-  a.p[t] = pr;
-  for (int m = 0; m < 6; ++m) a.s[6 * (size_t)t + m] = s[m];
+  if (wave > 0)
+    for (int m = 0; m < 13; ++m) part[wave - 1][m][lane] = acc[m];
+  __syncthreads();
+  if (wave != 0 || !active) return;
+  for (int w = 0; w < kProbeWaves - 1; ++w)
+    for (int m = 0; m < 13; ++m) acc[m] += part[w][m][lane];
+  if (ok) {
+    const double sc = -4.0 * al / kSqrtPi;
+    for (int d = 0; d < 3; ++d) a.u[3 * (size_t)t + d] = kInv8Pi * (acc[d] + sc * acc[10 + d]);
+    a.p[t] = kInv8Pi * acc[3];
+    for (int m = 0; m < 6; ++m) a.s[6 * (size_t)t + m] = kInv8Pi * acc[4 + m];
+  } else {
+    for (int d = 0; d < 3; ++d) a.u[3 * (size_t)t + d] = 0.0;
+    a.p[t] = 0.0;
+    for (int m = 0; m < 6; ++m) a.s[6 * (size_t)t + m] = 0.0;
+  }
 }
 
 struct ProbeInterpArgs {
@@ -138,17 +218,21 @@ struct ProbeInterpArgs {
   double dx, dz, H, Lx, Lz;
   const double* y;     // Gauss-Lobatto nodes
   const double* xt;    // probes (nt, 3)
+  const int* order;    // probes in the cell order of their binning
   const void* grid;    // [ncomp][Ny][Nx][Nz] T
   double* out[2];      // components [0, split) to out[0], [split, ncomp) to out[1]
   int split;
   int stride[2];
 };
 
-// out += the Lagrange interpolant of every grid component at the probe
+// out += the Lagrange interpolant of every grid component at the probe;
+// the threads take the probes in cell order, so that a block's stencils
+// overlap in the caches
 template <typename T>
 __global__ void __launch_bounds__(256) probe_interp(ProbeInterpArgs a) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= a.nt) return;
+  const int ts = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ts >= a.nt) return;
+  const int t = a.order[ts];
   double x = a.xt[3 * (size_t)t], y = a.xt[3 * (size_t)t + 1], z = a.xt[3 * (size_t)t + 2];
   if (!(isfinite(x) && isfinite(z) && fabs(y) <= a.H)) return;  // flagged by probe_local
   x = wrap_p(x, a.Lx);
@@ -222,7 +306,10 @@ hipError_t launch_probe_local(Plan& p, int nt, const double* xt, const double* f
   a.p = pr;
   a.s = sigma;
   a.flags = p.flags;
-  probe_local<<<(nt + 255) / 256, 256, 0, p.stream>>>(a);
+  // an upper bound of the work items: one per 64 probes of a cell
+  const unsigned nitems = (unsigned)((nt + 63) / 64 + p.cg.ncells);
+  probe_local<<<nitems, 64 * kProbeWaves, 0, p.stream>>>(a, p.tgt.item_start, p.tgt.item_cell,
+                                                         p.tgt.cell_start);
   return hipGetLastError();
 }
 
@@ -243,6 +330,7 @@ hipError_t launch_probe_interp(Plan& p, int nt, const double* xt, int ncomp, int
   a.Lz = p.p.Lz;
   a.y = p.y;
   a.xt = xt;
+  a.order = p.tgt.perm;  // binned by launch_probe_local
   a.grid = p.phys;
   a.out[0] = out0;
   a.out[1] = out1;

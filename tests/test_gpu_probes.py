@@ -70,6 +70,13 @@ def test_probe_domain_errors(case):
     with pytest.raises(G.GGEMError):
         G.Plan(g.Lx, g.Lz, g.H, g.alpha, g.Nx, g.Nz, g.Ny, rc=g.rc, max_src=5,
                max_tgt=5).probe(dev(xs), dev(f), dev(xt))
+    # more probes than the target capacity: rejected before any device work
+    small = G.Plan(g.Lx, g.Lz, g.H, g.alpha, g.Nx, g.Nz, g.Ny, rc=g.rc, max_src=len(xs),
+                   max_tgt=len(xt) - 1)
+    with pytest.raises(G.GGEMError) as e:
+        small.probe(dev(xs), dev(f), dev(xt))
+    assert e.value.code == G.ggem.E_CAPACITY and "max_tgt" in str(e.value)
+    small.close()
     plan.close()
 
 
