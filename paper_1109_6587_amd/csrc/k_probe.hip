@@ -225,16 +225,28 @@ struct ProbeInterpArgs {
   int stride[2];
 };
 
-// out += the Lagrange interpolant of every grid component at the probe;
-// the threads take the probes in cell order, so that a block's stencils
-// overlap in the caches
-template <typename T>
+// out += the Lagrange interpolant of every grid component at the probe.
+// The threads take the probes in cell order, so that a block's stencils
+// overlap in the caches.  G lanes per probe (G = 16 for few probes, else 1):
+// lane r of a probe's group takes the stencil rows (y, x) = r, r + G, ... of
+// the 25 rows of five z nodes, and the group adds its partial sums in a fixed
+// tree order.
+template <typename T, int G>
 __global__ void __launch_bounds__(256) probe_interp(ProbeInterpArgs a) {
-  const int ts = blockIdx.x * blockDim.x + threadIdx.x;
-  if (ts >= a.nt) return;
-  const int t = a.order[ts];
-  double x = a.xt[3 * (size_t)t], y = a.xt[3 * (size_t)t + 1], z = a.xt[3 * (size_t)t + 2];
-  if (!(isfinite(x) && isfinite(z) && fabs(y) <= a.H)) return;  // flagged by probe_local
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ts = gid / G, r = gid % G;
+  const bool valid = ts < a.nt;
+  const int t = valid ? a.order[ts] : 0;
+  double x = 0.0, y = 0.0, z = 0.0;
+  if (valid) {
+    x = a.xt[3 * (size_t)t];
+    y = a.xt[3 * (size_t)t + 1];
+    z = a.xt[3 * (size_t)t + 2];
+  }
+  // probes outside the slit are flagged by probe_local and left alone
+  const bool ok = valid && isfinite(x) && isfinite(z) && fabs(y) <= a.H;
+  if (G == 1 && !ok) return;
+  if (!ok) x = y = z = 0.0;
   x = wrap_p(x, a.Lx);
   z = wrap_p(z, a.Lz);
   const int i0 = (int)floor(x / a.dx + 0.5), k0 = (int)floor(z / a.dz + 0.5);
@@ -245,21 +257,24 @@ __global__ void __launch_bounds__(256) probe_interp(ProbeInterpArgs a) {
   const int j0 = min(a.Ny - 3, max(2, (int)rint(acos(y / a.H) * N / M_PI)));
   for (int q = 0; q < 5; ++q) yn[q] = a.y[j0 - 2 + q];
   lagrange5(y, yn, wy);
-  const T* G = (const T*)a.grid;
+  const T* Gr = (const T*)a.grid;
   const size_t plane = (size_t)a.Nx * a.Nz, field = plane * a.Ny;
   for (int c = 0; c < a.ncomp; ++c) {
     double acc = 0.0;
-    for (int jy = 0; jy < 5; ++jy)
-      for (int ix = 0; ix < 5; ++ix) {
-        const int ii = wrap1(i0 - 2 + ix, a.Nx);
-        const T* row = G + c * field + (size_t)(j0 - 2 + jy) * plane + (size_t)ii * a.Nz;
-        double rz = 0.0;
-        for (int kz = 0; kz < 5; ++kz) rz += wz[kz] * (double)row[wrap1(k0 - 2 + kz, a.Nz)];
-        acc += wy[jy] * wx[ix] * rz;
-      }
-    const int o = c < a.split ? 0 : 1;
-    const int cc = c < a.split ? c : c - a.split;
-    a.out[o][(size_t)t * a.stride[o] + cc] += acc;
+    for (int row = r; row < 25; row += G) {
+      const int jy = row / 5, ix = row % 5;
+      const int ii = wrap1(i0 - 2 + ix, a.Nx);
+      const T* rowp = Gr + c * field + (size_t)(j0 - 2 + jy) * plane + (size_t)ii * a.Nz;
+      double rz = 0.0;
+      for (int kz = 0; kz < 5; ++kz) rz += wz[kz] * (double)rowp[wrap1(k0 - 2 + kz, a.Nz)];
+      acc += wy[jy] * wx[ix] * rz;
+    }
+    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_down(acc, o, G);
+    if (ok && r == 0) {
+      const int o = c < a.split ? 0 : 1;
+      const int cc = c < a.split ? c : c - a.split;
+      a.out[o][(size_t)t * a.stride[o] + cc] += acc;
+    }
   }
 }
 
@@ -337,7 +352,10 @@ hipError_t launch_probe_interp(Plan& p, int nt, const double* xt, int ncomp, int
   a.split = split;
   a.stride[0] = stride0;
   a.stride[1] = stride1;
-  probe_interp<T><<<(nt + 255) / 256, 256, 0, p.stream>>>(a);
+  if (nt < 65536)
+    probe_interp<T, 16><<<(unsigned)(((size_t)nt * 16 + 255) / 256), 256, 0, p.stream>>>(a);
+  else
+    probe_interp<T, 1><<<(nt + 255) / 256, 256, 0, p.stream>>>(a);
   return hipGetLastError();
 }
 
