@@ -33,10 +33,10 @@
 //      components with a y-derivative.
 // Vectors are stored [n][mode] so a wave's accesses are coalesced.  With few
 // modes per compute unit each thread's chain of dependent steps is the time,
-// so for Chebyshev order N <= 64 A, B and E keep a parity's column in
-// registers, recompute the sweep factors inline and issue their loads ahead
-// of the sweeps; larger orders use the LDS-column kernels with the plan-time
-// factor tables.
+// so for Chebyshev order N <= 64 (N <= 96 with FP32 inputs) A, B and E keep
+// a parity's column in registers, recompute the sweep factors inline and
+// issue their loads ahead of the sweeps; larger orders use the LDS-column
+// kernels with the plan-time factor tables.
 #include "ggem_internal.h"
 
 namespace ggem {
@@ -418,9 +418,10 @@ __device__ __forceinline__ void pressure_par(const TauArgs& a, const Mode& md, i
                      [&](int n, double2 v) { PA[(size_t)n * S] = v; });
 }
 
-// k = 0 (N <= 64): 2n p_n = c_{n-1} b_{n-1} - b_{n+1} with b = H F_y and
-// p(-H) = gauge, one lane per coefficient n = lane + 1; the wall condition's
-// alternating sum is a fixed-order wave reduction.
+// k = 0: 2n p_n = c_{n-1} b_{n-1} - b_{n+1} with b = H F_y and p(-H) =
+// gauge; lane l takes the coefficients n = l + 1, l + 65, ... (one each for
+// N <= 64), and the wall condition's alternating sum is each lane's running
+// sum, then a fixed-order wave reduction.
 template <typename T>
 __device__ __forceinline__ void pressure_zero(const TauArgs& a) {
   using C = typename CT<T>::t;
@@ -428,14 +429,14 @@ __device__ __forceinline__ void pressure_zero(const TauArgs& a) {
   const size_t S = (size_t)a.nmodes;
   const C* Fy = (const C*)a.in + (size_t)Ny * S;
   double2* PA = a.scr + (size_t)kPA * Ny * S;
-  const int n = threadIdx.x + 1;
   double2 t = z2(0, 0);
-  if (n <= N) {
+  for (int n = threadIdx.x + 1; n <= N; n += 64) {
     const double2 bm = zscale(a.H * (n == 1 ? 2.0 : 1.0), to_z(Fy[(size_t)(n - 1) * S]));
     const double2 bp = (n + 1 <= N - 1) ? zscale(a.H, to_z(Fy[(size_t)(n + 1) * S])) : z2(0, 0);
     const double2 pn = zscale(1.0 / (2.0 * n), zsub(bm, bp));
     PA[(size_t)n * S] = pn;
-    t = (n & 1) ? zscale(-1.0, pn) : pn;
+    if (n <= 64) t = (n & 1) ? zscale(-1.0, pn) : pn;
+    else t = (n & 1) ? zsub(t, pn) : zadd(t, pn);
   }
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
@@ -836,6 +837,15 @@ hipError_t launch_tau(Plan& p, bool stress) {
   if (a.N <= 64) {
     launch_tau_reg<T, 64>(p, a, nb, nc, stress);
     return hipGetLastError();
+  }
+  // FP32 inputs up to order 96 still fit the register form without spills
+  // (about 410 registers for the pressure sweep); FP64 and higher orders use
+  // the LDS columns
+  if constexpr (sizeof(T) == 4) {
+    if (a.N <= 96) {
+      launch_tau_reg<T, 96>(p, a, nb, nc, stress);
+      return hipGetLastError();
+    }
   }
   const size_t lds = tau_lds_bytes(p);
   tau_pressure<T><<<dim3(nb, 2), 64, lds, p.stream>>>(a);
