@@ -33,7 +33,7 @@
 //      components with a y-derivative.
 // Vectors are stored [n][mode] so a wave's accesses are coalesced.  With few
 // modes per compute unit each thread's chain of dependent steps is the time,
-// so for Chebyshev order N <= 64 (N <= 96 with FP32 inputs) A, B and E keep
+// so for Chebyshev order N <= 64 (N <= 128 with FP32 inputs) A, B and E keep
 // a parity's column in registers, recompute the sweep factors inline and
 // issue their loads ahead of the sweeps; larger orders use the LDS-column
 // kernels with the plan-time factor tables.
@@ -839,11 +839,17 @@ hipError_t launch_tau(Plan& p, bool stress) {
     return hipGetLastError();
   }
   // FP32 inputs up to order 96 still fit the register form without spills
-  // (about 410 registers for the pressure sweep); FP64 and higher orders use
-  // the LDS columns
+  // (about 410 registers for the pressure sweep); up to 128 the pressure
+  // sweep spills some 200 registers and is still 2.5x faster than the LDS
+  // form; FP64 (whose sweeps spill far more) and higher orders use the LDS
+  // columns
   if constexpr (sizeof(T) == 4) {
     if (a.N <= 96) {
       launch_tau_reg<T, 96>(p, a, nb, nc, stress);
+      return hipGetLastError();
+    }
+    if (a.N <= 128) {
+      launch_tau_reg<T, 128>(p, a, nb, nc, stress);
       return hipGetLastError();
     }
   }
