@@ -150,6 +150,22 @@ def test_cell_scale_keeps_the_result(scale, precision):
         assert rel_l2(u, ref_s) < TOLMIX and rel_l2(v, ref_d) < TOLMIX
 
 
+@pytest.mark.parametrize("Ny", [77, 121, 129])
+def test_high_order_tau_mixed(Ny):
+    """Chebyshev orders above 64 in mixed precision (the register sweeps up to
+    order 128, the LDS form above): single and double layer against the
+    oracle (1e-5)."""
+    c = random_case(62, 60, 40, 4.0, 1.5, 3.0, 1.3, 16, 16, Ny, dl=True)
+    print(f"case {c.name} Ny={Ny} mixed", flush=True)
+    g = O.SlitGrid.from_case(c)
+    ref_s = O.single_layer(g, c.xs, c.f, c.xt)
+    ref_d = O.double_layer(g, c.xs, c.f, c.xt, c.normals)
+    plan = G.Plan.from_case(c, precision="mixed")
+    u = plan.single_layer(dev(c.xs), dev(c.f), dev(c.xt)).cpu().numpy()
+    v = plan.double_layer(dev(c.xs), dev(c.f), dev(c.xt), dev(c.normals)).cpu().numpy()
+    assert rel_l2(u, ref_s) < TOLMIX and rel_l2(v, ref_d) < TOLMIX
+
+
 def test_empty_inputs():
     c = random_case(31, 10, 10, 4.0, 1.0, 4.0, 1.0, 16, 16, 9)
     plan = G.Plan.from_case(c)
