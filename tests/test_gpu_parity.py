@@ -57,6 +57,22 @@ def test_spread_grid_fp64(c0):
     assert rel_max(F, ref["spread"]) < 1e-12
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+def test_spread_grid_coarse(precision, tol):
+    """A coarse grid (dx = 2.5 r_c) whose tiles reach more than 64 rows of
+    cells, so the spread describes them in two chunks of lanes; sources also
+    outside [0, L) in x and z."""
+    c = random_case(63, 300, 10, 40.0, 12.0, 2.0, 2.0, 8, 8, 9)   # mid tiles: 10 x 7 rows
+    c.xs[::4, 0] -= 40.0
+    c.xs[1::4, 2] += 80.0
+    print(f"case {c.name} coarse spread {precision}", flush=True)
+    g = O.SlitGrid.from_case(c)
+    ref = O.spread(g, g.wrap(c.xs), c.f)
+    plan = G.Plan.from_case(c, precision=precision)
+    F = plan.spread_grid(dev(c.xs), dev(c.f)).cpu().numpy()
+    assert rel_max(F, ref) < tol
+
+
 @pytest.mark.parametrize("part", ["local", "global", "all"])
 def test_single_layer_fp64(c0, part):
     c, g, ref = c0
