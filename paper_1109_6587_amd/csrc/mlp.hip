@@ -169,15 +169,41 @@ __global__ void __launch_bounds__(256) sum_final(int np, const float* __restrict
   if (threadIdx.x == 0) out[0] = red[0] * inv;
 }
 
-// part[z][o] = sum over the samples of chunk z of dZ[s][o]
-__global__ void colsum_partial(int n, int m, const unsigned short* __restrict__ dZ,
-                               float* __restrict__ part) {
-  const int o = blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= m) return;
-  const int s0 = blockIdx.y * kChunk, s1 = min(n, s0 + kChunk);
+// part[z][o] = sum over the samples of chunk z of dZ[s][o].  A block takes
+// 64 columns of one chunk: each of its waves sums 64 consecutive samples
+// with 16 loads in flight per lane, and the wave sums are added in wave
+// order through LDS, so the result does not depend on timing.
+constexpr int kColWaves = kChunk / 64;
+static_assert(kChunk % 64 == 0 && kColWaves <= 16, "one block of at most 1024 threads per chunk");
+
+__global__ void __launch_bounds__(64 * kColWaves) colsum_partial(int n, int m,
+                                                                 const unsigned short* __restrict__ dZ,
+                                                                 float* __restrict__ part) {
+  __shared__ float red[kColWaves][64];
+  const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int o = blockIdx.x * 64 + c;
+  const long r0 = (long)blockIdx.y * kChunk + (long)w * 64;
+  const long r1 = min((long)n, r0 + 64);
+  float acc[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) acc[u] = 0.0f;
+  if (o < m) {
+    for (long i = r0; i < r1; i += 16) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (i + u < r1) acc[u] += bf2f(dZ[(i + u) * m + o]);
+    }
+  }
   float s = 0.0f;
-  for (int i = s0; i < s1; ++i) s += bf2f(dZ[(long)i * m + o]);
-  part[(long)blockIdx.y * m + o] = s;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) s += acc[u];
+  red[w][c] = s;
+  __syncthreads();
+  if (w == 0 && o < m) {
+    float t = 0.0f;
+    for (int k = 0; k < kColWaves; ++k) t += red[k][c];
+    part[(long)blockIdx.y * m + o] = t;
+  }
 }
 
 // dst[i] = sum_z part[z stride + i], z ascending
@@ -466,7 +492,7 @@ static void backward(ggem_mlp_s* m, int n, const float* T) {
     launch_gemm(kF32, a, st);
     reduce_splits<<<nblk(out * in), 256, 0, st>>>(out * in, splits, m->part, (long)out * in,
                                                   m->G + w_off(l));
-    colsum_partial<<<dim3(nblk(out, 128), splits), 128, 0, st>>>(n, out, dz, m->part);
+    colsum_partial<<<dim3(nblk(out, 64), splits), 64 * kColWaves, 0, st>>>(n, out, dz, m->part);
     reduce_splits<<<nblk(out), 256, 0, st>>>(out, splits, m->part, out, m->G + b_off(l));
     if (l == 0) break;
     // dz_{l-1} = (W_l^T dz) * silu'(z_{l-1})
