@@ -46,6 +46,11 @@ __constant__ double kGLt[4] = {0.069431844202973712, 0.33000947820757187, 0.6699
                                0.93056815579702629};
 __constant__ double kGLw[4] = {0.17392742256872693, 0.32607257743127307, 0.32607257743127307,
                                0.17392742256872693};
+// cos and sin of the polar angles (pi/2) t_o at the same nodes
+__constant__ double kPolC[4] = {0.994058492765765, 0.8686241377879603, 0.49547160085329073,
+                                0.10884720005703206};
+__constant__ double kPolS[4] = {0.10884720005703191, 0.49547160085329056, 0.8686241377879602,
+                                0.994058492765765};
 
 __device__ inline double min_img(double d, double L, double invL) {
   return fma(-L, rint(d * invL), d);
@@ -93,8 +98,9 @@ __device__ inline void add_stokeslet(double dx, double dy, double dz, double fx,
   const double r = sqrt(r2);
   const double ec = erfc(alpha * r), ex = exp(-alpha * alpha * r2);
   const double c = 2.0 * alpha / kSqrtPi * ex;
-  const double A = ec / r - c;                 // coefficient of I
-  const double B = (ec / r + c) / r2;          // coefficient of d d^T
+  const double ir = 1.0 / r;
+  const double A = ec * ir - c;                // coefficient of I
+  const double B = (ec * ir + c) * (ir * ir);  // coefficient of d d^T
   const double df = dx * fx + dy * fy + dz * fz;
   acc[0] += w * (A * fx + B * df * dx);
   acc[1] += w * (A * fy + B * df * dy);
@@ -111,8 +117,8 @@ __device__ inline void add_stresslet(double dx, double dy, double dz, double qx,
   const double r = sqrt(r2);
   const double ec = erfc(alpha * r), ex = exp(-alpha * alpha * r2);
   const double a3 = alpha * alpha * alpha / kSqrtPi;
-  const double C = -6.0 * ec / (r2 * r2 * r) - 12.0 * alpha / kSqrtPi * ex / (r2 * r2) -
-                   8.0 * a3 * ex / r2;
+  const double ir = 1.0 / r, ir2 = ir * ir;
+  const double C = -ir2 * (ir2 * (6.0 * ec * ir + 12.0 * alpha / kSqrtPi * ex) + 8.0 * a3 * ex);
   const double D = 4.0 * a3 * ex;
   const double dq = dx * qx + dy * qy + dz * qz, dm = dx * mx + dy * my + dz * mz;
   const double qm = qx * mx + qy * my + qz * mz;
@@ -135,8 +141,7 @@ __device__ void element_point(const double (&e)[3][3], const double (&fe)[3][3],
   const double omega = sqrt(cx * cx + cy * cy + cz * cz);
   double xi, eta, w;
   if (polar) {
-    const double th = 0.5 * M_PI * kGLt[o];
-    const double c = cos(th), s = sin(th);
+    const double c = kPolC[o], s = kPolS[o];
     const double rmax = 1.0 / (c + s);
     const double rho = rmax * kGLt[i];
     xi = rho * c;
